@@ -1,0 +1,258 @@
+"""Oracle query engine (test infrastructure only).
+
+Executes CRISP's dual-mode query (Algorithm 1; Sections 4.3.1-4.3.2) one query
+at a time, in the paper's order and notation:
+
+  1. q' = q R when the index holds a rotation (Section 4.1: the rotation is
+     kept in the index metadata so queries are mapped into the same space).
+  2. For every subspace m: split q'^(m) into its left / right halves, compute
+     Dist_1 and Dist_2 against the two half-codebooks, sort them, and run the
+     Multi-Sequence traversal with a priority queue of (cost, i, j): pop the
+     cheapest cell, count it as one rank, give it weight 2 when the mode flag
+     phi = 1 and rank <= k_size (else 1), add the weight to the score of every
+     id in the cell's CSR posting list, and stop once ``retrieved`` reaches the
+     per-subspace budget.
+  3. Candidates C = {x : V[x] >= tau}, with the robustness fallback that keeps
+     |C| >= k (Section 4.3.2, Stage 1).
+  4. phi = 1: order C by Hamming distance of sign codes (Stage 2).
+  5. Verify: phi = 0 computes the exact L2 distance of every candidate;
+     phi = 1 walks the Hamming order and stops after P = patience_factor * k
+     consecutive candidates that leave the top-k unchanged (Stage 3).  The
+     ADSampling estimator of Stage 3 is not part of this engine: distances
+     are exact (the paper's "Hamming re-ranking with exact L2" variant,
+     Section 6.4).
+  6. Return the top-k.
+
+Readings where the paper is silent (each is also listed in the design notes):
+
+* Budget: budget = max(1, ceil(alpha * N)) ids per subspace; whole cells are
+  added, so the last cell may overshoot it; empty cells still consume a rank.
+* Order of cells: ascending (cost, i, j) where i, j are ranks in the sorted
+  half-distance lists, each sorted by (distance, centroid index).
+* tau is one integer threshold for both modes.
+* Fallback: if fewer than k points reach tau, use the largest s <= tau with at
+  least k points scoring >= s; if even s = 1 has fewer than k, C = {V >= 1}
+  and the output is padded with id -1 / distance +inf.
+* Distance key: the float64 value d_canon defined by ``canonical_sqdist``; the
+  result order is ascending (d_canon, id).  Returned distances are
+  f32(d_canon).
+* Patience: a candidate "updates" the top-k iff the top-k holds fewer than k
+  items or its key is below the current k-th key; the counter of consecutive
+  non-updates resets on an update and the walk stops when it reaches P.
+* Learned budget: the walk additionally stops after ``limit`` candidates.
+"""
+from __future__ import annotations
+
+import heapq
+import math
+
+import numpy as np
+
+from .build import half_distances, rotate_rows
+
+LANES = 64
+
+
+def budget_for(alpha: float, n: int) -> int:
+    """Per-subspace retrieval budget: max(1, ceil(alpha * N)), in float64."""
+    return max(1, int(math.ceil(float(alpha) * float(n))))
+
+
+def rotate_query(index: dict, q: np.ndarray) -> np.ndarray:
+    """q' = q R if the index has a rotation, else q (float32)."""
+    q = np.asarray(q, dtype=np.float32).reshape(-1, index["d"])
+    if index["rotation"] is None:
+        return q.copy()
+    return rotate_rows(q, index["rotation"])
+
+
+def subspace_half_distances(index: dict, qp: np.ndarray) -> np.ndarray:
+    """Dist_1 / Dist_2 of one rotated query for every subspace: (M, 2, K) f64."""
+    m, kh = index["m"], index["k_half"]
+    h = index["d"] // (2 * m)
+    out = np.zeros((m, 2, kh), dtype=np.float64)
+    for sub in range(m):
+        for s in range(2):
+            lo = sub * 2 * h + s * h
+            out[sub, s] = half_distances(qp[None, lo:lo + h], index["centroids"][sub, s])[0]
+    return out
+
+
+def multi_sequence(d1: np.ndarray, d2: np.ndarray, sizes: np.ndarray, budget: int,
+                   k_size: int, phi: int):
+    """Multi-Sequence cell traversal of one subspace (Algorithm 1).
+
+    d1, d2 -- half distances (K,) of the left / right half
+    sizes  -- (K*K,) posting-list length of cell i_L * K + i_R
+    Returns a list of (cell, weight) in visit order.
+    """
+    kh = d1.shape[0]
+    o1 = np.argsort(d1, kind="stable")        # ascending (distance, index)
+    o2 = np.argsort(d2, kind="stable")
+    d1s, d2s = d1[o1], d2[o2]
+    pq = [(d1s[0] + d2s[0], 0, 0)]
+    rank = 0
+    retrieved = 0
+    visited = []
+    while retrieved < budget:
+        cost, i, j = heapq.heappop(pq)
+        cell = int(o1[i]) * kh + int(o2[j])      # Combine(i, j)
+        rank += 1
+        w = 2 if (phi == 1 and rank <= k_size) else 1
+        visited.append((cell, w))
+        retrieved += int(sizes[cell])
+        # next candidates: the right neighbour in this row, and the next row's
+        # first cell when leaving column 0.
+        if j + 1 < kh:
+            heapq.heappush(pq, (d1s[i] + d2s[j + 1], i, j + 1))
+        if j == 0 and i + 1 < kh:
+            heapq.heappush(pq, (d1s[i + 1] + d2s[0], i + 1, 0))
+    return visited
+
+
+def collision_scores(index: dict, activated: list) -> np.ndarray:
+    """V[x] += w for every id of every activated cell (Eq. 1 / Algorithm 1)."""
+    v = np.zeros(index["n"], dtype=np.int64)
+    for sub, cells in enumerate(activated):
+        off = index["offsets"][sub]
+        ids = index["ids"][sub]
+        for cell, w in cells:
+            v[ids[off[cell]:off[cell + 1]]] += w
+    return v
+
+
+def select_candidates(v: np.ndarray, tau: int, k: int):
+    """Threshold + fallback; returns (ascending candidate ids, effective tau)."""
+    def count_ge(s):
+        return int(np.count_nonzero(v >= s))
+    s_eff = tau
+    if count_ge(tau) < k:
+        s_eff = 1
+        for s in range(min(tau, int(v.max(initial=0))), 0, -1):
+            if count_ge(s) >= k:
+                s_eff = s
+                break
+    return np.flatnonzero(v >= s_eff).astype(np.int64), s_eff
+
+
+def hamming(codes_q: np.ndarray, codes_x: np.ndarray) -> np.ndarray:
+    """Popcount of XOR of packed sign codes."""
+    x = np.bitwise_xor(codes_x, codes_q[None, :])
+    return np.unpackbits(x.view(np.uint8), axis=1).sum(axis=1).astype(np.int64)
+
+
+def hamming_order(index: dict, qp: np.ndarray, cand: np.ndarray):
+    """Candidates sorted by (Hamming distance, id) (Section 4.3.2, Stage 2)."""
+    from .build import sign_codes
+    cq = sign_codes(qp[None, :])[0]
+    hd = hamming(cq, index["codes"][cand])
+    order = np.lexsort((cand, hd))
+    return cand[order], hd[order]
+
+
+def canonical_sqdist(qp: np.ndarray, rows: np.ndarray) -> np.ndarray:
+    """d_canon for each row: lane-strided float64 partial sums + tree.
+
+    For lane l in [0, 64): p_l = sum over r ascending of (q'[64 r + l] - x[64 r + l])^2
+    (float64, unfused); then p_l <- p_l + p_{l+s} for s = 32, 16, ..., 1 and
+    l < s; d_canon = p_0.
+    """
+    d = qp.shape[0]
+    q64 = qp.astype(np.float64).reshape(d // LANES, LANES)
+    x64 = np.asarray(rows, dtype=np.float32).astype(np.float64).reshape(-1, d // LANES, LANES)
+    p = np.zeros((x64.shape[0], LANES), dtype=np.float64)
+    for r in range(d // LANES):
+        delta = q64[None, r, :] - x64[:, r, :]
+        sq = delta * delta
+        p = p + sq
+    s = LANES // 2
+    while s >= 1:
+        p[:, :s] = p[:, :s] + p[:, s:2 * s]
+        s //= 2
+    return p[:, 0].copy()
+
+
+def topk_by_key(ids: np.ndarray, dist: np.ndarray, k: int):
+    """Top-k by ascending (d_canon, id), padded with (-1, +inf)."""
+    order = np.lexsort((ids, dist))[:k]
+    out_i = np.full(k, -1, dtype=np.int64)
+    out_d = np.full(k, np.inf, dtype=np.float32)
+    out_i[:order.size] = ids[order]
+    out_d[:order.size] = dist[order].astype(np.float32)
+    return out_i, out_d
+
+
+def patience_walk(ids: np.ndarray, dist: np.ndarray, k: int, patience: int,
+                  limit: int | None = None):
+    """Sequential verification with patience termination.
+
+    Returns (examined prefix length, position of the last update L*, stop
+    position L_stop if the patience rule fired else None).
+    """
+    top = []                      # sorted list of (d, id), at most k entries
+    run = 0
+    last_update = 0
+    stop = None
+    n = ids.size if limit is None else min(ids.size, int(limit))
+    pos = 0
+    for pos in range(1, n + 1):
+        key = (float(dist[pos - 1]), int(ids[pos - 1]))
+        if len(top) < k or key < top[-1]:
+            top.append(key)
+            top.sort()
+            del top[k:]
+            run = 0
+            last_update = pos
+        else:
+            run += 1
+        if run >= patience:
+            stop = pos
+            break
+    return pos, last_update, stop
+
+
+def search_one(index: dict, q: np.ndarray, k: int, *, mode: int, alpha: float,
+               tau: int, patience_factor: int = 40, limit: int | None = None,
+               trace: bool = False):
+    """One query through Algorithm 1.  Returns (ids[k], dists[k], trace)."""
+    n, m = index["n"], index["m"]
+    budget = budget_for(alpha, n)
+    qp = rotate_query(index, q)[0]
+    hd = subspace_half_distances(index, qp)
+    activated = []
+    for sub in range(m):
+        sizes = np.diff(index["offsets"][sub].astype(np.int64))
+        activated.append(multi_sequence(hd[sub, 0], hd[sub, 1], sizes, budget, k, mode))
+    v = collision_scores(index, activated)
+    cand, tau_eff = select_candidates(v, tau, k)
+    tr = {"q_rot": qp, "half_dist": hd, "activated": activated, "scores": v,
+          "candidates": cand, "tau_eff": tau_eff}
+    if mode == 0:
+        dist = canonical_sqdist(qp, index["base"][cand])
+        out_i, out_d = topk_by_key(cand, dist, k)
+        tr.update(order=cand, examined=cand.size)
+    else:
+        order, hdist = hamming_order(index, qp, cand)
+        dist_all = canonical_sqdist(qp, index["base"][order])
+        examined, last_upd, stop = patience_walk(order, dist_all, k, patience_factor * k, limit)
+        out_i, out_d = topk_by_key(order[:examined], dist_all[:examined], k)
+        tr.update(order=order, hamming=hdist, examined=examined, last_update=last_upd,
+                  stop=stop, dist_order=dist_all)
+    return out_i, out_d, (tr if trace else None)
+
+
+def search(index: dict, queries: np.ndarray, k: int, *, mode: int, alpha: float, tau: int,
+           patience_factor: int = 40, limits=None, trace: bool = False):
+    """All queries; returns ids (Q, k) int64, dists (Q, k) f32 and traces."""
+    queries = np.asarray(queries, dtype=np.float32).reshape(-1, index["d"])
+    nq = queries.shape[0]
+    ids = np.full((nq, k), -1, dtype=np.int64)
+    dists = np.full((nq, k), np.inf, dtype=np.float32)
+    traces = []
+    for qi in range(nq):
+        lim = None if limits is None else int(limits[qi])
+        i, d, tr = search_one(index, queries[qi], k, mode=mode, alpha=alpha, tau=tau,
+                              patience_factor=patience_factor, limit=lim, trace=trace)
+        ids[qi], dists[qi] = i, d
+        traces.append(tr)
+    return ids, dists, traces
