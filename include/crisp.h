@@ -1,0 +1,271 @@
+/*
+ * crisp.h -- C ABI of the MI355X (gfx950) CRISP query engine.
+ *
+ * CRISP ("Correlation-Resilient Indexing via Subspace Partitioning",
+ * Dimitropoulos, Michalopoulos, Tsitsigkos, Mamoulis) answers approximate
+ * k-nearest-neighbour queries under squared Euclidean distance with a
+ * subspace-collision index: M subspaces, each split into two halves with a
+ * K-centroid codebook per half; a point's cell in a subspace is the pair of
+ * its nearest half-centroids; per subspace a CSR inverted index lists the ids
+ * of every cell (Section 4.2).  A query (Algorithm 1, Section 4.3) rotates
+ * itself when the index was built with a rotation (Section 4.1), scores its
+ * sub-vectors against the half-codebooks, walks the cells of each subspace in
+ * ascending cost until a per-subspace id budget is met, counts per-point
+ * collisions (Eq. 1; rank-weighted in Optimized Mode), keeps points reaching
+ * a threshold tau, and re-ranks them by exact L2 -- all of them (Guaranteed
+ * Mode) or in Hamming order with patience termination (Optimized Mode).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * * Every call returns crisp_status; CRISP_OK (0) on success.  Nothing throws
+ *   across the ABI.  crisp_last_error() returns a thread-local message for
+ *   the last non-OK status of the calling thread.
+ * * Pointers named "device" are HIP device pointers.  The caller owns every
+ *   input, output and workspace buffer; the library owns only the opaque
+ *   crisp_index host structure.  The library never allocates device memory.
+ * * hip_stream is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *   asynchronously on it; results are valid after the stream is synchronised.
+ *   Launch failures are reported as CRISP_E_HIP; faults inside kernels surface
+ *   at the caller's next synchronisation.
+ * * Arguments are validated before anything is enqueued; on any error no
+ *   output is written.
+ * * Limits: D % 64 == 0, D % (2M) == 0, 1 <= M <= 127 (scores fit in 8 bits),
+ *   1 <= K <= 256, 1 <= N < 2^31.  Violations return CRISP_E_UNSUPPORTED.
+ *
+ * Floating-point definitions shared with the CPU reference
+ * --------------------------------------------------------
+ * * Rotation (Section 3 "Randomized Orthogonal Rotation", Section 4.1):
+ *   x'_j = f32( sum_i x_i R_ij ), float64 accumulation in ascending i.  Both
+ *   factors are float32, so every product is exact in float64.
+ * * Half distance (Algorithm 1, Dist_1 / Dist_2): float64, for t ascending
+ *   acc = acc + (f64(a_t) - f64(c_t))^2, unfused.
+ * * Cell order inside a subspace (Section 4.3.1, Multi-Sequence traversal):
+ *   ascending (d1s[i] + d2s[j], i, j) with i, j the ranks of the left / right
+ *   centroids in their half's (distance, index) order; cell id = iL * K + iR.
+ * * Distance key (Section 4.3.2, Stage 3, exact L2): d_canon in float64,
+ *   lane-strided: p_l = sum_r (q'[64 r + l] - x[64 r + l])^2 for l < 64, then
+ *   p_l += p_{l+s} for s = 32, 16, ..., 1; results ordered by (d_canon, id);
+ *   returned distances are f32(d_canon).  The engine evaluates candidates in
+ *   float32 with a proven error band and recomputes d_canon wherever the band
+ *   could change a decision, so its ids equal those of the definition.
+ */
+#ifndef CRISP_H_
+#define CRISP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CRISP_OK = 0,
+  CRISP_E_INVALID = -1,     /* bad argument (null pointer, out-of-range value) */
+  CRISP_E_WORKSPACE = -2,   /* workspace smaller than the size query returned */
+  CRISP_E_HIP = -3,         /* a HIP runtime call failed */
+  CRISP_E_FORMAT = -4,      /* index arrays inconsistent (CSR check failed) */
+  CRISP_E_UNSUPPORTED = -5  /* shape outside the documented limits */
+} crisp_status;
+
+typedef struct crisp_index crisp_index;   /* opaque; freed by crisp_index_free */
+
+/*
+ * Index arrays (Section 4.2).  All pointers are device pointers BORROWED for
+ * the lifetime of the index; the caller keeps them alive and unchanged.
+ *   rotation  -- float32 [D][D] row-major, x' = x R; NULL when the correlation
+ *                check did not fire (Section 4.1).
+ *   centroids -- float32 [M][2][K][h], h = D / (2M); half 0 covers the first h
+ *                dimensions of subspace m (dims m*2h .. m*2h+h-1).
+ *   offsets   -- int32 [M][K*K + 1]; offsets[m][0] = 0, non-decreasing,
+ *                offsets[m][K*K] = N ("Offsets", size K^2 + 1).
+ *   ids       -- int32 [M][N]; cell-major, ascending inside a cell ("Vector IDs").
+ *   base      -- float32 [N][D] row-major, in rotated space when rotated.
+ *   codes     -- uint64 [N][D/64], bit (i % 64) of word (i / 64) = [base_i > 0]
+ *                (Section 3, Binary Quantization).  Required for Optimized Mode.
+ */
+typedef struct {
+  int64_t n;
+  int32_t d, m, k_half;
+  const float *rotation;
+  const float *centroids;
+  const int32_t *offsets;
+  const int32_t *ids;
+  const float *base;
+  const uint64_t *codes;
+} crisp_index_desc;
+
+/*
+ * Bytes of the device buffer crisp_index_load needs for derived per-index
+ * tables (per cell and id tile, where each posting list crosses tile
+ * boundaries).  tile_ids: ids per collision-counting tile (a power of two in
+ * [4096, 131072]; 0 = library default).
+ */
+crisp_status crisp_index_derived_bytes(const crisp_index_desc *desc, int32_t tile_ids,
+                                       size_t *bytes);
+
+/*
+ * Validates the CSR arrays on the device (offsets monotone with the documented
+ * end points; every id in range and ascending inside its cell) and builds the
+ * derived tables into `derived` (device, caller-owned, at least the bytes
+ * returned above, kept alive until crisp_index_free).  Synchronises
+ * hip_stream once to read the validation result.  Returns CRISP_E_FORMAT if
+ * the arrays are inconsistent.
+ */
+crisp_status crisp_index_load(const crisp_index_desc *desc, int32_t tile_ids, void *derived,
+                              size_t derived_bytes, void *hip_stream, crisp_index **out);
+
+crisp_status crisp_index_free(crisp_index *index);
+
+/*
+ * Search parameters (Table 1; Section 4.3.2; Section 6 parameter ranges).
+ *   mode            -- 0 Guaranteed (phi = 0), 1 Optimized (phi = 1).
+ *   alpha           -- retrieval fraction per subspace, 0 < alpha <= 1:
+ *                      budget = max(1, ceil(alpha * N)) ids per subspace.
+ *   tau             -- integer collision threshold, 0 <= tau <= 2M.
+ *   patience_factor -- Optimized Mode stops after patience_factor * k
+ *                      consecutive non-updating verifications (paper: 40).
+ *   limits          -- optional device int32 [nq]: per-query cap on the number
+ *                      of candidates verified in Optimized Mode (the learned
+ *                      budget); values < 1 mean "no cap".  NULL = none.
+ *   max_chunk       -- queries processed per internal chunk (0 = default);
+ *                      the workspace scales with it.
+ */
+typedef struct {
+  int32_t mode;
+  double alpha;
+  int32_t tau;
+  int32_t patience_factor;
+  const int32_t *limits;
+  int32_t max_chunk;
+} crisp_search_params;
+
+/*
+ * Optional stage outputs for verification (device pointers, each may be NULL).
+ * Sizes are per query; rows are laid out query-major for all nq queries.
+ *   q_rot       float32 [nq][D]        rotated query (A0)
+ *   half_dist   float64 [nq][M][2][K]  Dist_1 / Dist_2 (A1)
+ *   n_cells     int32  [nq][M]         activated cells per subspace (A2)
+ *   cells       int32  [nq][M][K*K]    activated cell | weight << 24, any order
+ *   retrieved   int32  [nq][M]         ids in the activated cells of subspace m
+ *   hist        int32  [nq][2M+1]      number of points with each score
+ *   tau_eff     int32  [nq]            threshold after the fallback rule
+ *   n_cand      int32  [nq]            |C|
+ *   cand        int32  [nq][N]         candidates, ascending id (first n_cand)
+ *   cand_score  uint8  [nq][N]         their scores
+ *   order       int32  [nq][N]         candidates in (Hamming, id) order (mode 1)
+ *   hamming     int32  [nq][N]         their Hamming distances (mode 1)
+ *   examined    int32  [nq]            candidates verified
+ *   last_update int32  [nq]            1-based position of the last top-k update
+ *   stopped     int32  [nq]            1 if the patience rule ended the walk
+ */
+typedef struct {
+  float *q_rot;
+  double *half_dist;
+  int32_t *n_cells;
+  int32_t *cells;
+  int32_t *retrieved;
+  int32_t *hist;
+  int32_t *tau_eff;
+  int32_t *n_cand;
+  int32_t *cand;
+  uint8_t *cand_score;
+  int32_t *order;
+  int32_t *hamming;
+  int32_t *examined;
+  int32_t *last_update;
+  int32_t *stopped;
+} crisp_taps;
+
+/* Bytes of workspace crisp_search needs for this index, batch and parameters. */
+crisp_status crisp_search_workspace_bytes(const crisp_index *index, int64_t nq, int32_t k,
+                                          const crisp_search_params *params, size_t *bytes);
+
+/*
+ * Algorithm 1 for a batch of queries.
+ *   queries -- device float32 [nq][D] (original, unrotated space)
+ *   ids     -- device int64 [nq][k], ascending (d_canon, id); -1 padding
+ *   dists   -- device float32 [nq][k], f32(d_canon) squared L2; +inf padding
+ *   workspace -- device, >= crisp_search_workspace_bytes(...)
+ *   taps    -- NULL, or stage outputs to fill (see crisp_taps)
+ * Padding occurs only when fewer than k points collide at all.
+ * 1 <= k <= min(N, 1024); nq >= 0 (nq == 0 is a no-op).
+ */
+crisp_status crisp_search(crisp_index *index, const float *queries, int64_t nq, int32_t k,
+                          const crisp_search_params *params, int64_t *ids, float *dists,
+                          void *workspace, size_t ws_bytes, const crisp_taps *taps,
+                          void *hip_stream);
+
+/*
+ * Row rotation x' = x R with the float64 ascending-order definition above
+ * (Section 3; used for queries, and for the data set when building).
+ *   x -- device float32 [rows][d]; r -- device float32 [d][d]; out -- device
+ *   float32 [rows][d] (must not alias x).
+ */
+crisp_status crisp_rotate_rows(const float *x, int64_t rows, int32_t d, const float *r,
+                               float *out, void *hip_stream);
+
+/* ---- Index build on the GPU (Sections 3, 4.1, 4.2) ---------------------- */
+
+/*
+ * Centred sample covariance (Section 4.1): cov_ij = sum_s (x_si - mu_i)
+ * (x_sj - mu_j) / (S - 1) over the sampled rows, accumulated in float64.
+ *   x -- device float32 [n][d]; rows -- device int64 [s] sampled row indices;
+ *   cov -- device float64 [d*d + d]: the [d][d] covariance followed by the d
+ *   column means.  s >= 2.
+ */
+crisp_status crisp_build_covariance(const float *x, int64_t n, int32_t d, const int64_t *rows,
+                                    int64_t s, double *cov, void *hip_stream);
+
+/*
+ * One Lloyd assignment on sampled rows of one half (k-means, Section 3):
+ * label[i] = argmin_c halfdist(x[rows[i]][col0 .. col0+h), cent[c]) with the
+ * lowest index on ties.
+ *   x -- device float32 [n][d]; rows -- device int64 [s] (NULL: rows 0..s-1);
+ *   cent -- device float32 [k][h]; label -- device int32 [s].
+ */
+crisp_status crisp_build_assign(const float *x, int64_t n, int32_t d, int32_t col0, int32_t h,
+                                const int64_t *rows, int64_t s, const float *cent, int32_t k,
+                                int32_t *label, void *hip_stream);
+
+/*
+ * Lloyd update: cent[c] = f32( (float64 sum of the member rows in the order
+ * listed) / count ) for every non-empty cluster; empty clusters keep their
+ * centroid.  member_off -- device int32 [k + 1], members -- device int32
+ * sample positions grouped by cluster (ascending inside a cluster, as
+ * crisp_build_csr produces from the labels); row = rows[member] (rows NULL:
+ * row = member).
+ */
+crisp_status crisp_build_update(const float *x, int64_t n, int32_t d, int32_t col0, int32_t h,
+                                const int64_t *rows, const int32_t *member_off,
+                                const int32_t *members, int32_t k, float *cent, void *hip_stream);
+
+/*
+ * Stable counting sort of cell labels into CSR (Section 4.2): offsets int32
+ * [cells + 1], ids int32 [n] (cell-major, ascending ids inside a cell).
+ * cell_of -- device int32 [n] in [0, cells); scratch -- device int32 of at
+ * least crisp_build_csr_scratch(n, cells) ints.
+ */
+int64_t crisp_build_csr_scratch(int64_t n, int32_t cells);
+crisp_status crisp_build_csr(const int32_t *cell_of, int64_t n, int32_t cells, int32_t *offsets,
+                             int32_t *ids, int32_t *scratch, void *hip_stream);
+
+/* cell_of[i] = left[i] * k + right[i] (Combine). */
+crisp_status crisp_build_combine(const int32_t *left, const int32_t *right, int64_t n, int32_t k,
+                                 int32_t *cell_of, void *hip_stream);
+
+/* Sign codes (Section 3): codes uint64 [n][d/64] from x float32 [n][d]. */
+crisp_status crisp_build_codes(const float *x, int64_t n, int32_t d, uint64_t *codes,
+                               void *hip_stream);
+
+/* Thread-local message for the last non-OK status. */
+const char *crisp_last_error(void);
+
+/* Library version string. */
+const char *crisp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CRISP_H_ */

@@ -250,7 +250,10 @@ def search(index: dict, queries: np.ndarray, k: int, *, mode: int, alpha: float,
     dists = np.full((nq, k), np.inf, dtype=np.float32)
     traces = []
     for qi in range(nq):
-        lim = None if limits is None else int(limits[qi])
+        # a per-query limit below 1 means "no limit" (the engine's convention)
+        lim = None
+        if limits is not None and int(limits[qi]) >= 1:
+            lim = int(limits[qi])
         i, d, tr = search_one(index, queries[qi], k, mode=mode, alpha=alpha, tau=tau,
                               patience_factor=patience_factor, limit=lim, trace=trace)
         ids[qi], dists[qi] = i, d

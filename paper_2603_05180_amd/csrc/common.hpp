@@ -1,0 +1,113 @@
+// Shared device helpers for the CRISP gfx950 kernels.
+//
+// The whole library is compiled with -ffp-contract=off: every float64
+// expression that defines a canonical value (rotation, half distance,
+// distance key) is evaluated exactly as written, one rounding per operation.
+// Fused multiply-adds appear only where they are spelled out (fmaf in the
+// float32 first-pass distance, whose error is bounded separately).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "crisp.h"
+
+namespace crisp {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+__device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
+
+__device__ __forceinline__ int wave_sum_i32(int v) {
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, kWave);
+  return v;
+}
+
+__device__ __forceinline__ long long wave_sum_i64(long long v) {
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, kWave);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum_f32(float v) {
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, kWave);
+  return v;
+}
+
+// Inclusive prefix sum across the 64 lanes.
+__device__ __forceinline__ int wave_incl_scan_i32(int v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int s = 1; s < kWave; s <<= 1) {
+    int u = __shfl_up(v, s, kWave);
+    if (lane >= s) v += u;
+  }
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long lanes_below_mask() {
+  const int lane = lane_id();
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Bits of a non-negative double: monotone as an unsigned integer.
+__device__ __forceinline__ unsigned long long dbits(double x) {
+  return static_cast<unsigned long long>(__double_as_longlong(x));
+}
+__device__ __forceinline__ double from_dbits(unsigned long long b) {
+  return __longlong_as_double(static_cast<long long>(b));
+}
+
+// Block-wide exclusive scan of `n` ints held in LDS (in place), n <= 4096.
+// Returns the total.  All threads of the block must call it.
+__device__ inline int block_exclusive_scan(int *a, int n, int *tmp /* >= blockDim/64 + 1 ints */) {
+  const int tid = threadIdx.x;
+  const int nt = blockDim.x;
+  const int per = (n + nt - 1) / nt;
+  const int b = tid * per;
+  int local = 0;
+  for (int i = 0; i < per; ++i)
+    if (b + i < n) local += a[b + i];
+  int incl = wave_incl_scan_i32(local);
+  if (lane_id() == kWave - 1) tmp[wave_id()] = incl;
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    const int nw = nt / kWave;
+    for (int w = 0; w < nw; ++w) {
+      int t = tmp[w];
+      tmp[w] = run;
+      run += t;
+    }
+    tmp[nw] = run;
+  }
+  __syncthreads();
+  int run = tmp[wave_id()] + incl - local;
+  for (int i = 0; i < per; ++i) {
+    if (b + i < n) {
+      int t = a[b + i];
+      a[b + i] = run;
+      run += t;
+    }
+  }
+  int total = tmp[nt / kWave];
+  __syncthreads();
+  return total;
+}
+
+// Largest j in [0, n) with a[j] <= v, for non-decreasing a with a[0] <= v.
+__device__ __forceinline__ int upper_bound_minus1(const int *a, int n, int v) {
+  int lo = 0, hi = n;  // first index with a[idx] > v
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] <= v) lo = mid + 1; else hi = mid;
+  }
+  return lo - 1;
+}
+
+}  // namespace crisp

@@ -1,0 +1,444 @@
+// C ABI of the CRISP engine: validation, workspace layout and launch order.
+// Every entry point is declared and documented in include/crisp.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "build_kernels.hpp"
+#include "common.hpp"
+#include "query_kernels.hpp"
+
+using namespace crisp;
+
+namespace {
+
+thread_local std::string g_err;
+
+crisp_status fail(crisp_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+crisp_status fail(crisp_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(CRISP_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));  \
+  } while (0)
+
+#define LAUNCH_TRY(name)                                                                     \
+  do {                                                                                       \
+    hipError_t e_ = hipGetLastError();                                                       \
+    if (e_ != hipSuccess) return fail(CRISP_E_HIP, "launch %s: %s", name, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kDefaultTile = 32768;
+constexpr int kDefaultChunk = 1024;
+
+inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+inline unsigned grid1(long long n, int block) {
+  long long g = (n + block - 1) / block;
+  return static_cast<unsigned>(std::max<long long>(1, std::min<long long>(g, 0x7fffffffll)));
+}
+
+crisp_status check_shape(int64_t n, int32_t d, int32_t m, int32_t k) {
+  if (n < 1 || d < 1 || m < 1 || k < 1) return fail(CRISP_E_INVALID, "n, d, m, k must be positive");
+  if (n >= (int64_t(1) << 31)) return fail(CRISP_E_UNSUPPORTED, "N must be < 2^31");
+  if (d % 64 != 0) return fail(CRISP_E_UNSUPPORTED, "D must be a multiple of 64");
+  if (d > 8192) return fail(CRISP_E_UNSUPPORTED, "D must be <= 8192");
+  if (m > 127) return fail(CRISP_E_UNSUPPORTED, "M must be <= 127");
+  if (d % (2 * m) != 0) return fail(CRISP_E_UNSUPPORTED, "D must be a multiple of 2M");
+  if (k > 256) return fail(CRISP_E_UNSUPPORTED, "K must be <= 256");
+  return CRISP_OK;
+}
+
+int resolve_tile(int32_t tile_ids) { return tile_ids > 0 ? tile_ids : kDefaultTile; }
+
+}  // namespace
+
+struct crisp_index {
+  int64_t n;
+  int d, m, k, h, ncells, tile, ntiles;
+  const float *rot, *cent, *base;
+  const int32_t *off, *ids;
+  const uint64_t *codes;
+  int32_t *tile_off;
+};
+
+// Workspace layout for one chunk of qc queries.
+struct Layout {
+  size_t qrot, hdist, ptab, ncell, cells, retr, tilecnt, hist, flag, taueff, ncand, segids, segscore, cand,
+      score, regA, regB, regC, examined, lastupd, stopped, total;
+};
+
+static Layout make_layout(const crisp_index *ix, long long qc) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+  const long long n = ix->n;
+  L.qrot = take(qc * ix->d * 4);
+  L.hdist = take(qc * ix->m * 2 * ix->k * 8);
+  L.ptab = take(ix->k > 64 ? qc * ix->m * ix->k * (ix->k + 1) * 4 : 0);
+  L.ncell = take(qc * ix->m * 4);
+  L.cells = take(qc * ix->m * ix->ncells * 4);
+  L.retr = take(qc * ix->m * 4);
+  L.tilecnt = take(qc * ix->ntiles * 4);
+  L.hist = take(qc * (2 * ix->m + 1) * 4);
+  L.flag = take(qc * 4);
+  L.taueff = take(qc * 4);
+  L.ncand = take(qc * 4);
+  L.segids = take(qc * n * 4);     // per-tile segments; later the Hamming order
+  L.segscore = take(qc * n);
+  L.cand = take(qc * n * 4);
+  L.score = take(qc * n);
+  L.regA = take(qc * n * 4);       // mode 0: first-pass distances; mode 1: Hamming per candidate
+  L.regB = take(qc * n * 4);       // mode 0: survivor positions;    mode 1: sorted Hamming
+  L.regC = take(qc * n * 8);       // mode 0: survivor keys
+  L.examined = take(qc * 4);
+  L.lastupd = take(qc * 4);
+  L.stopped = take(qc * 4);
+  L.total = o;
+  return L;
+}
+
+static long long chunk_of(const crisp_search_params *p, long long nq) {
+  long long c = (p && p->max_chunk > 0) ? p->max_chunk : kDefaultChunk;
+  return std::max<long long>(1, std::min<long long>(c, std::max<long long>(nq, 1)));
+}
+
+extern "C" {
+
+const char *crisp_last_error(void) { return g_err.c_str(); }
+const char *crisp_version(void) { return "crisp-gfx950 0.1"; }
+
+crisp_status crisp_index_derived_bytes(const crisp_index_desc *desc, int32_t tile_ids, size_t *bytes) {
+  if (!desc || !bytes) return fail(CRISP_E_INVALID, "null argument");
+  crisp_status s = check_shape(desc->n, desc->d, desc->m, desc->k_half);
+  if (s != CRISP_OK) return s;
+  int tile = resolve_tile(tile_ids);
+  if (tile < 4096 || tile > 131072 || (tile & (tile - 1)))
+    return fail(CRISP_E_INVALID, "tile_ids must be a power of two in [4096, 131072]");
+  long long ntiles = (desc->n + tile - 1) / tile;
+  if (ntiles > 1024) return fail(CRISP_E_UNSUPPORTED, "N / tile_ids must be <= 1024");
+  long long ncells = static_cast<long long>(desc->k_half) * desc->k_half;
+  *bytes = align_up(static_cast<size_t>(desc->m) * ncells * (ntiles + 1) * 4) + 256;
+  return CRISP_OK;
+}
+
+crisp_status crisp_index_load(const crisp_index_desc *desc, int32_t tile_ids, void *derived, size_t derived_bytes,
+                              void *hip_stream, crisp_index **out) {
+  if (!desc || !out || !derived) return fail(CRISP_E_INVALID, "null argument");
+  size_t need = 0;
+  crisp_status s = crisp_index_derived_bytes(desc, tile_ids, &need);
+  if (s != CRISP_OK) return s;
+  if (derived_bytes < need) return fail(CRISP_E_WORKSPACE, "derived buffer %zu < %zu bytes", derived_bytes, need);
+  if (!desc->centroids || !desc->offsets || !desc->ids || !desc->base)
+    return fail(CRISP_E_INVALID, "centroids, offsets, ids and base are required");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int tile = resolve_tile(tile_ids);
+  const int ncells = desc->k_half * desc->k_half;
+  const int ntiles = static_cast<int>((desc->n + tile - 1) / tile);
+  int32_t *tile_off = static_cast<int32_t *>(derived);
+  int32_t *err = reinterpret_cast<int32_t *>(static_cast<char *>(derived) + need - 256);
+  const long long cellsm = static_cast<long long>(desc->m) * ncells;
+  k_fill<int32_t><<<1, 64, 0, st>>>(err, 1, 0);
+  LAUNCH_TRY("k_fill");
+  k_validate_csr<<<grid1(cellsm, 256), 256, 0, st>>>(desc->offsets, desc->ids, desc->m, ncells, desc->n, err);
+  LAUNCH_TRY("k_validate_csr");
+  int32_t herr = 0;
+  HIP_TRY(hipMemcpyAsync(&herr, err, sizeof herr, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (herr) return fail(CRISP_E_FORMAT, "CSR arrays inconsistent (offsets/ids)");
+  // Only validated offsets are used to address the id arrays.
+  k_tile_offsets<<<grid1(cellsm, 256), 256, 0, st>>>(desc->offsets, desc->ids, desc->m, ncells, desc->n, ntiles,
+                                                      tile, tile_off);
+  LAUNCH_TRY("k_tile_offsets");
+  crisp_index *ix = new (std::nothrow) crisp_index{};
+  if (!ix) return fail(CRISP_E_INVALID, "out of host memory");
+  ix->n = desc->n; ix->d = desc->d; ix->m = desc->m; ix->k = desc->k_half;
+  ix->h = desc->d / (2 * desc->m); ix->ncells = ncells; ix->tile = tile; ix->ntiles = ntiles;
+  ix->rot = desc->rotation; ix->cent = desc->centroids; ix->base = desc->base;
+  ix->off = desc->offsets; ix->ids = desc->ids; ix->codes = desc->codes; ix->tile_off = tile_off;
+  *out = ix;
+  return CRISP_OK;
+}
+
+crisp_status crisp_index_free(crisp_index *index) {
+  delete index;
+  return CRISP_OK;
+}
+
+static crisp_status check_params(const crisp_index *ix, int64_t nq, int32_t k, const crisp_search_params *p) {
+  if (!ix || !p) return fail(CRISP_E_INVALID, "null argument");
+  if (nq < 0) return fail(CRISP_E_INVALID, "nq must be >= 0");
+  if (k < 1 || k > 1024 || k > ix->n) return fail(CRISP_E_INVALID, "k must be in [1, min(N, 1024)]");
+  if (p->mode != 0 && p->mode != 1) return fail(CRISP_E_INVALID, "mode must be 0 or 1");
+  if (!(p->alpha > 0.0) || p->alpha > 1.0) return fail(CRISP_E_INVALID, "alpha must be in (0, 1]");
+  if (p->tau < 0 || p->tau > 2 * ix->m) return fail(CRISP_E_INVALID, "tau must be in [0, 2M]");
+  if (p->mode == 1 && p->patience_factor < 1) return fail(CRISP_E_INVALID, "patience_factor must be >= 1");
+  if (p->mode == 1 && !ix->codes) return fail(CRISP_E_UNSUPPORTED, "Optimized Mode needs sign codes");
+  if (p->max_chunk < 0) return fail(CRISP_E_INVALID, "max_chunk must be >= 0");
+  return CRISP_OK;
+}
+
+crisp_status crisp_search_workspace_bytes(const crisp_index *index, int64_t nq, int32_t k,
+                                          const crisp_search_params *params, size_t *bytes) {
+  if (!bytes) return fail(CRISP_E_INVALID, "null argument");
+  crisp_status s = check_params(index, nq, k, params);
+  if (s != CRISP_OK) return s;
+  *bytes = make_layout(index, chunk_of(params, nq)).total;
+  return CRISP_OK;
+}
+
+static crisp_status tap_copy(void *dst, const void *src, size_t bytes, hipStream_t st) {
+  if (!dst || bytes == 0) return CRISP_OK;
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
+  return CRISP_OK;
+}
+
+crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int32_t k,
+                          const crisp_search_params *p, int64_t *ids, float *dists, void *workspace,
+                          size_t ws_bytes, const crisp_taps *taps, void *hip_stream) {
+  crisp_status s = check_params(ix, nq, k, p);
+  if (s != CRISP_OK) return s;
+  if (nq == 0) return CRISP_OK;
+  if (!queries || !ids || !dists || !workspace) return fail(CRISP_E_INVALID, "null argument");
+  const long long qc = chunk_of(p, nq);
+  const Layout L = make_layout(ix, qc);
+  if (ws_bytes < L.total) return fail(CRISP_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  char *ws = static_cast<char *>(workspace);
+  float *qrot = reinterpret_cast<float *>(ws + L.qrot);
+  double *hdist = reinterpret_cast<double *>(ws + L.hdist);
+  int32_t *ptab = reinterpret_cast<int32_t *>(ws + L.ptab);
+  int32_t *ncell = reinterpret_cast<int32_t *>(ws + L.ncell);
+  int32_t *cells = reinterpret_cast<int32_t *>(ws + L.cells);
+  int32_t *retr = reinterpret_cast<int32_t *>(ws + L.retr);
+  int32_t *tilecnt = reinterpret_cast<int32_t *>(ws + L.tilecnt);
+  int32_t *hist = reinterpret_cast<int32_t *>(ws + L.hist);
+  int32_t *flag = reinterpret_cast<int32_t *>(ws + L.flag);
+  int32_t *taueff = reinterpret_cast<int32_t *>(ws + L.taueff);
+  int32_t *ncand = reinterpret_cast<int32_t *>(ws + L.ncand);
+  int32_t *segids = reinterpret_cast<int32_t *>(ws + L.segids);
+  uint8_t *segscore = reinterpret_cast<uint8_t *>(ws + L.segscore);
+  int32_t *cand = reinterpret_cast<int32_t *>(ws + L.cand);
+  uint8_t *score = reinterpret_cast<uint8_t *>(ws + L.score);
+  int32_t *regA = reinterpret_cast<int32_t *>(ws + L.regA);
+  int32_t *regB = reinterpret_cast<int32_t *>(ws + L.regB);
+  double *regC = reinterpret_cast<double *>(ws + L.regC);
+  int32_t *exam = reinterpret_cast<int32_t *>(ws + L.examined);
+  int32_t *lastu = reinterpret_cast<int32_t *>(ws + L.lastupd);
+  int32_t *stopd = reinterpret_cast<int32_t *>(ws + L.stopped);
+
+  const int d = ix->d, m = ix->m, kh = ix->k, nb = 2 * m + 1;
+  const long long n = ix->n;
+  const int budget = static_cast<int>(std::max<double>(1.0, std::ceil(p->alpha * static_cast<double>(n))));
+  const int patience = p->mode == 1 ? p->patience_factor * k : 0;
+  const size_t count_lds = static_cast<size_t>((ix->tile + 3) / 4) * 4;
+  const size_t order_lds = static_cast<size_t>(d + 1) * 4;
+  const size_t rerank_lds = static_cast<size_t>(d) * 4 + static_cast<size_t>(k) * 12;
+
+  for (long long q0 = 0; q0 < nq; q0 += qc) {
+    const int cq = static_cast<int>(std::min<long long>(qc, nq - q0));
+    const float *qin = queries + q0 * d;
+    // A0
+    if (ix->rot) {
+      dim3 g(d / kRotBN, (cq + kRotBM - 1) / kRotBM);
+      k_rotate_rows<<<g, 256, 0, st>>>(qin, cq, d, ix->rot, qrot);
+      LAUNCH_TRY("k_rotate_rows");
+    } else {
+      k_copy_f32<<<grid1(static_cast<long long>(cq) * d, 256), 256, 0, st>>>(qin, qrot, static_cast<long long>(cq) * d);
+      LAUNCH_TRY("k_copy_f32");
+    }
+    // A1
+    {
+      long long tot = static_cast<long long>(cq) * m * 2 * kh;
+      k_half_dist<<<grid1(tot, 256), 256, 0, st>>>(qrot, cq, d, m, kh, ix->h, ix->cent, hdist);
+      LAUNCH_TRY("k_half_dist");
+    }
+    // A2
+    {
+      dim3 g(m, cq);
+      k_select_cells<<<g, 64, 0, st>>>(hdist, m, kh, ix->off, budget, k, p->mode, ptab, ncell, cells, retr);
+      LAUNCH_TRY("k_select_cells");
+    }
+    // A3 / A4
+    k_fill<int32_t><<<grid1(static_cast<long long>(cq) * nb, 256), 256, 0, st>>>(hist, static_cast<long long>(cq) * nb, 0);
+    LAUNCH_TRY("k_fill");
+    {
+      dim3 g(ix->ntiles, cq);
+      k_count<<<g, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
+                                                   ix->ntiles, ix->tile, 0, p->tau, flag, taueff, segids, segscore,
+                                                   tilecnt, hist);
+      LAUNCH_TRY("k_count pass 0");
+      k_flag<<<grid1(cq, 256), 256, 0, st>>>(tilecnt, ix->ntiles, cq, k, p->tau, flag, taueff, hist, nb);
+      LAUNCH_TRY("k_flag");
+      k_count<<<g, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
+                                                   ix->ntiles, ix->tile, 1, p->tau, flag, taueff, segids, segscore,
+                                                   tilecnt, hist);
+      LAUNCH_TRY("k_count pass 1");
+      k_tau_eff<<<grid1(cq, 256), 256, 0, st>>>(flag, cq, k, p->tau, nb, hist, taueff, tilecnt, ix->ntiles);
+      LAUNCH_TRY("k_tau_eff");
+      k_count<<<g, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
+                                                   ix->ntiles, ix->tile, 2, p->tau, flag, taueff, segids, segscore,
+                                                   tilecnt, hist);
+      LAUNCH_TRY("k_count pass 2");
+      k_compact<<<cq, 256, 0, st>>>(segids, segscore, tilecnt, ix->ntiles, ix->tile, n, cand, score, ncand);
+      LAUNCH_TRY("k_compact");
+    }
+    const int32_t *lim = p->limits ? p->limits + q0 : nullptr;
+    if (p->mode == 1) {
+      // A5
+      k_hamming_order<<<cq, kOrderThreads, order_lds, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, segids, regB);
+      LAUNCH_TRY("k_hamming_order");
+      // A6 / A7
+      k_rerank<<<cq, kRerankThreads, rerank_lds, st>>>(1, qrot, d, ix->base, ncand, segids, n, k, patience, lim,
+                                                       reinterpret_cast<float *>(regA), regB, regC, ids + q0 * k,
+                                                       dists + q0 * k, exam, lastu, stopd);
+      LAUNCH_TRY("k_rerank");
+    } else {
+      k_rerank<<<cq, kRerankThreads, rerank_lds, st>>>(0, qrot, d, ix->base, ncand, cand, n, k, patience, lim,
+                                                       reinterpret_cast<float *>(regA), regB, regC, ids + q0 * k,
+                                                       dists + q0 * k, exam, lastu, stopd);
+      LAUNCH_TRY("k_rerank");
+    }
+    if (taps) {
+      const size_t qn = static_cast<size_t>(cq) * static_cast<size_t>(n);
+      if ((s = tap_copy(taps->q_rot ? taps->q_rot + q0 * d : nullptr, qrot, size_t(cq) * d * 4, st))) return s;
+      if ((s = tap_copy(taps->half_dist ? taps->half_dist + q0 * m * 2 * kh : nullptr, hdist, size_t(cq) * m * 2 * kh * 8, st))) return s;
+      if ((s = tap_copy(taps->n_cells ? taps->n_cells + q0 * m : nullptr, ncell, size_t(cq) * m * 4, st))) return s;
+      if ((s = tap_copy(taps->cells ? taps->cells + q0 * m * ix->ncells : nullptr, cells, size_t(cq) * m * ix->ncells * 4, st))) return s;
+      if ((s = tap_copy(taps->retrieved ? taps->retrieved + q0 * m : nullptr, retr, size_t(cq) * m * 4, st))) return s;
+      if ((s = tap_copy(taps->hist ? taps->hist + q0 * nb : nullptr, hist, size_t(cq) * nb * 4, st))) return s;
+      if ((s = tap_copy(taps->tau_eff ? taps->tau_eff + q0 : nullptr, taueff, size_t(cq) * 4, st))) return s;
+      if ((s = tap_copy(taps->n_cand ? taps->n_cand + q0 : nullptr, ncand, size_t(cq) * 4, st))) return s;
+      if ((s = tap_copy(taps->cand ? taps->cand + q0 * n : nullptr, cand, qn * 4, st))) return s;
+      if ((s = tap_copy(taps->cand_score ? taps->cand_score + q0 * n : nullptr, score, qn, st))) return s;
+      if (p->mode == 1) {
+        if ((s = tap_copy(taps->order ? taps->order + q0 * n : nullptr, segids, qn * 4, st))) return s;
+        if ((s = tap_copy(taps->hamming ? taps->hamming + q0 * n : nullptr, regB, qn * 4, st))) return s;
+      }
+      if ((s = tap_copy(taps->examined ? taps->examined + q0 : nullptr, exam, size_t(cq) * 4, st))) return s;
+      if ((s = tap_copy(taps->last_update ? taps->last_update + q0 : nullptr, lastu, size_t(cq) * 4, st))) return s;
+      if ((s = tap_copy(taps->stopped ? taps->stopped + q0 : nullptr, stopd, size_t(cq) * 4, st))) return s;
+    }
+  }
+  return CRISP_OK;
+}
+
+crisp_status crisp_rotate_rows(const float *x, int64_t rows, int32_t d, const float *r, float *out, void *hip_stream) {
+  if (!x || !r || !out) return fail(CRISP_E_INVALID, "null argument");
+  if (rows < 0 || d < 64 || d % 64 != 0) return fail(CRISP_E_UNSUPPORTED, "rows >= 0, D a positive multiple of 64");
+  if (rows == 0) return CRISP_OK;
+  if ((rows + kRotBM - 1) / kRotBM > 65535) return fail(CRISP_E_UNSUPPORTED, "too many rows for one call");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  dim3 g(d / kRotBN, static_cast<unsigned>((rows + kRotBM - 1) / kRotBM));
+  k_rotate_rows<<<g, 256, 0, st>>>(x, rows, d, r, out);
+  LAUNCH_TRY("k_rotate_rows");
+  return CRISP_OK;
+}
+
+crisp_status crisp_build_covariance(const float *x, int64_t n, int32_t d, const int64_t *rows, int64_t s, double *cov,
+                                    void *hip_stream) {
+  if (!x || !rows || !cov) return fail(CRISP_E_INVALID, "null argument");
+  if (n < 1 || s < 2 || d < 64 || d % 64 != 0) return fail(CRISP_E_INVALID, "need s >= 2 and D a multiple of 64");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  double *mean = cov + static_cast<long long>(d) * d;  // caller provides d*d + d doubles
+  k_sample_mean<<<grid1(d, 256), 256, 0, st>>>(x, d, rows, s, mean);
+  LAUNCH_TRY("k_sample_mean");
+  dim3 g(d / 64, d / 64);
+  k_covariance<<<g, 256, 0, st>>>(x, d, rows, s, mean, cov);
+  LAUNCH_TRY("k_covariance");
+  return CRISP_OK;
+}
+
+crisp_status crisp_build_assign(const float *x, int64_t n, int32_t d, int32_t col0, int32_t h, const int64_t *rows,
+                                int64_t s, const float *cent, int32_t k, int32_t *label, void *hip_stream) {
+  if (!x || !cent || !label) return fail(CRISP_E_INVALID, "null argument");
+  if (k < 1 || h < 1 || col0 < 0 || col0 + h > d || s < 0) return fail(CRISP_E_INVALID, "bad half or sizes");
+  if (static_cast<size_t>(k) * h * 4 > 64 * 1024) return fail(CRISP_E_UNSUPPORTED, "K * h too large");
+  if (s == 0) return CRISP_OK;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  k_assign<<<grid1(s, 256), 256, static_cast<size_t>(k) * h * 4, st>>>(x, d, col0, h, rows, s, cent, k, label);
+  LAUNCH_TRY("k_assign");
+  return CRISP_OK;
+}
+
+crisp_status crisp_build_update(const float *x, int64_t n, int32_t d, int32_t col0, int32_t h, const int64_t *rows,
+                                const int32_t *member_off, const int32_t *members, int32_t k, float *cent,
+                                void *hip_stream) {
+  if (!x || !member_off || !members || !cent) return fail(CRISP_E_INVALID, "null argument");
+  if (k < 1 || h < 1 || col0 < 0 || col0 + h > d) return fail(CRISP_E_INVALID, "bad half or sizes");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  k_update<<<grid1(static_cast<long long>(k) * h, 256), 256, 0, st>>>(x, d, col0, h, rows, member_off, members, k, cent);
+  LAUNCH_TRY("k_update");
+  return CRISP_OK;
+}
+
+static long long csr_block(int64_t n, int32_t cells) {
+  long long blk = 256;
+  while ((n + blk - 1) / blk * static_cast<long long>(cells) > (16ll << 20)) blk *= 2;
+  return blk;
+}
+
+int64_t crisp_build_csr_scratch(int64_t n, int32_t cells) {
+  long long blk = csr_block(n, cells);
+  return (n + blk - 1) / blk * static_cast<long long>(cells) + cells;
+}
+
+crisp_status crisp_build_csr(const int32_t *cell_of, int64_t n, int32_t cells, int32_t *offsets, int32_t *ids,
+                             int32_t *scratch, void *hip_stream) {
+  if (!cell_of || !offsets || !ids || !scratch) return fail(CRISP_E_INVALID, "null argument");
+  if (n < 1 || cells < 1) return fail(CRISP_E_INVALID, "n and cells must be positive");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const long long blk = csr_block(n, cells);
+  const long long nblk = (n + blk - 1) / blk;
+  int32_t *table = scratch;
+  int32_t *totals = scratch + nblk * cells;
+  k_fill<int32_t><<<grid1(nblk * cells, 256), 256, 0, st>>>(table, nblk * cells, 0);
+  LAUNCH_TRY("k_fill");
+  k_csr_count<<<grid1(n, 256), 256, 0, st>>>(cell_of, n, cells, static_cast<int>(blk), table);
+  LAUNCH_TRY("k_csr_count");
+  k_csr_scan_blocks<<<grid1(cells, 256), 256, 0, st>>>(table, static_cast<int>(nblk), cells, totals);
+  LAUNCH_TRY("k_csr_scan_blocks");
+  k_csr_offsets<<<1, 1024, 0, st>>>(totals, cells, offsets);
+  LAUNCH_TRY("k_csr_offsets");
+  k_csr_place<<<grid1(nblk, 64), 64, 0, st>>>(cell_of, n, cells, static_cast<int>(blk), offsets, table, ids);
+  LAUNCH_TRY("k_csr_place");
+  return CRISP_OK;
+}
+
+crisp_status crisp_build_combine(const int32_t *left, const int32_t *right, int64_t n, int32_t k, int32_t *cell_of,
+                                 void *hip_stream) {
+  if (!left || !right || !cell_of) return fail(CRISP_E_INVALID, "null argument");
+  if (n < 0 || k < 1) return fail(CRISP_E_INVALID, "bad sizes");
+  if (n == 0) return CRISP_OK;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  k_combine<<<grid1(n, 256), 256, 0, st>>>(left, right, n, k, cell_of);
+  LAUNCH_TRY("k_combine");
+  return CRISP_OK;
+}
+
+crisp_status crisp_build_codes(const float *x, int64_t n, int32_t d, uint64_t *codes, void *hip_stream) {
+  if (!x || !codes) return fail(CRISP_E_INVALID, "null argument");
+  if (n < 0 || d < 64 || d % 64 != 0) return fail(CRISP_E_UNSUPPORTED, "D must be a positive multiple of 64");
+  if (n == 0) return CRISP_OK;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  long long waves = n * (d / 64);
+  k_codes<<<grid1(waves, 4), 256, 0, st>>>(x, n, d, codes);
+  LAUNCH_TRY("k_codes");
+  return CRISP_OK;
+}
+
+}  // extern "C"

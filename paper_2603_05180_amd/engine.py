@@ -1,0 +1,276 @@
+"""Python binding of the CRISP engine.
+
+Marshals torch device tensors into the C ABI of ``libcrisp.so`` and runs
+every step on the GPU: the query path (rotation, half distances, cell
+selection, collision counting, candidate selection, Hamming order, re-rank)
+and the index build's data-sized steps (sample covariance, row rotation,
+k-means assignment and update, CSR counting sort, sign codes).  The build
+performs two D x D dense factorisations on the host with numpy -- the
+eigenvalues of the sample covariance for the correlation check (Section 4.1)
+and the QR factor of the Gaussian matrix that becomes the rotation
+(Section 3) -- which involve no data-sized arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import CrispError, IndexDesc, SearchParams, Taps, check, lib
+
+__all__ = ["Index", "build_index", "CrispError", "budget_for", "TAU_CEV"]
+
+TAU_CEV = 0.85
+KMEANS_ITERS = 25
+CEV_SAMPLE_CAP = 100_000
+KMEANS_SAMPLE_CAP = 100_000
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def budget_for(alpha: float, n: int) -> int:
+    return max(1, int(math.ceil(float(alpha) * float(n))))
+
+
+class Index:
+    """A CRISP index resident on the GPU (the arrays of Section 4.2).
+
+    ``arrays`` maps the names of ``crisp_index_desc`` to tensors (device or
+    host; host arrays are copied to ``device``).  The index keeps them alive.
+    """
+
+    def __init__(self, arrays: dict, *, tile_ids: int = 0, device: str = "cuda:0", stream=None):
+        self.device = torch.device(device)
+        dev = {}
+        for name in ("rotation", "centroids", "offsets", "ids", "base", "codes"):
+            v = arrays.get(name)
+            if v is None:
+                dev[name] = None
+                continue
+            if isinstance(v, np.ndarray):
+                if name == "codes":
+                    v = torch.from_numpy(np.ascontiguousarray(v).view(np.int64))
+                else:
+                    v = torch.from_numpy(np.ascontiguousarray(v))
+            dev[name] = v.to(self.device).contiguous()
+        self.arrays = dev
+        self.n = int(arrays["n"])
+        self.d = int(arrays["d"])
+        self.m = int(arrays["m"])
+        self.k_half = int(arrays["k_half"])
+        self.rotated = dev["rotation"] is not None
+        self._desc = IndexDesc(self.n, self.d, self.m, self.k_half, _ptr(dev["rotation"]),
+                               _ptr(dev["centroids"]), _ptr(dev["offsets"]), _ptr(dev["ids"]),
+                               _ptr(dev["base"]), _ptr(dev["codes"]))
+        nbytes = ctypes.c_size_t(0)
+        check(lib.crisp_index_derived_bytes(ctypes.byref(self._desc), int(tile_ids), ctypes.byref(nbytes)))
+        self._derived = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p(0)
+        check(lib.crisp_index_load(ctypes.byref(self._desc), int(tile_ids), _ptr(self._derived),
+                                   nbytes.value, _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self._ws = None
+
+    # ------------------------------------------------------------------
+    def free(self):
+        if self._h is not None and self._h.value:
+            lib.crisp_index_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def params(self, *, mode=0, alpha=0.01, tau=1, patience_factor=40, limits=None, max_chunk=0):
+        return SearchParams(int(mode), float(alpha), int(tau), int(patience_factor), _ptr(limits), int(max_chunk))
+
+    def workspace_bytes(self, nq: int, k: int, params: SearchParams) -> int:
+        b = ctypes.c_size_t(0)
+        check(lib.crisp_search_workspace_bytes(self._h, int(nq), int(k), ctypes.byref(params), ctypes.byref(b)))
+        return b.value
+
+    def workspace(self, nq: int, k: int, params: SearchParams) -> torch.Tensor:
+        need = self.workspace_bytes(nq, k, params)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def alloc_taps(self, nq: int, mode: int) -> dict:
+        n, m, kh, d = self.n, self.m, self.k_half, self.d
+        z = dict(device=self.device)
+        t = {
+            "q_rot": torch.empty(nq, d, dtype=torch.float32, **z),
+            "half_dist": torch.empty(nq, m, 2, kh, dtype=torch.float64, **z),
+            "n_cells": torch.empty(nq, m, dtype=torch.int32, **z),
+            "cells": torch.empty(nq, m, kh * kh, dtype=torch.int32, **z),
+            "retrieved": torch.empty(nq, m, dtype=torch.int32, **z),
+            "hist": torch.empty(nq, 2 * m + 1, dtype=torch.int32, **z),
+            "tau_eff": torch.empty(nq, dtype=torch.int32, **z),
+            "n_cand": torch.empty(nq, dtype=torch.int32, **z),
+            "cand": torch.empty(nq, n, dtype=torch.int32, **z),
+            "cand_score": torch.empty(nq, n, dtype=torch.uint8, **z),
+            "examined": torch.empty(nq, dtype=torch.int32, **z),
+            "last_update": torch.empty(nq, dtype=torch.int32, **z),
+            "stopped": torch.empty(nq, dtype=torch.int32, **z),
+        }
+        if mode == 1:
+            t["order"] = torch.empty(nq, n, dtype=torch.int32, **z)
+            t["hamming"] = torch.empty(nq, n, dtype=torch.int32, **z)
+        return t
+
+    def search(self, queries: torch.Tensor, k: int, *, mode: int = 0, alpha: float = 0.01, tau: int = 1,
+               patience_factor: int = 40, limits: torch.Tensor | None = None, max_chunk: int = 0,
+               taps: dict | None = None, out: tuple | None = None, stream=None):
+        """Algorithm 1 for a batch; returns (ids int64 [nq, k], dists f32 [nq, k])."""
+        if queries.device != self.device or queries.dtype != torch.float32 or not queries.is_contiguous():
+            raise ValueError("queries must be a contiguous float32 tensor on the index device")
+        if queries.dim() != 2 or queries.shape[1] != self.d:
+            raise ValueError(f"queries must have shape [nq, {self.d}]")
+        if limits is not None and (limits.dtype != torch.int32 or limits.device != self.device
+                                   or limits.numel() != queries.shape[0]):
+            raise ValueError("limits must be an int32 device tensor with one entry per query")
+        nq = int(queries.shape[0])
+        p = self.params(mode=mode, alpha=alpha, tau=tau, patience_factor=patience_factor,
+                        limits=limits, max_chunk=max_chunk)
+        ws = self.workspace(nq, k, p)
+        if out is None:
+            ids = torch.empty(nq, k, dtype=torch.int64, device=self.device)
+            dists = torch.empty(nq, k, dtype=torch.float32, device=self.device)
+        else:
+            ids, dists = out
+        tp = None
+        if taps is not None:
+            tp = Taps(*[_ptr(taps.get(f)) for f in _lib.TAP_FIELDS])
+        check(lib.crisp_search(self._h, _ptr(queries), nq, int(k), ctypes.byref(p), _ptr(ids), _ptr(dists),
+                               _ptr(ws), ws.numel(), ctypes.byref(tp) if tp is not None else None,
+                               _stream(stream)))
+        return ids, dists
+
+
+# ----------------------------------------------------------------------------
+# Index build on the GPU
+# ----------------------------------------------------------------------------
+def rotate_rows(x: torch.Tensor, r: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """x' = x R (float64 ascending accumulation per output), in chunks of rows."""
+    if out is None:
+        out = torch.empty_like(x)
+    rows, d = x.shape
+    step = 64 * 65535
+    for r0 in range(0, rows, step):
+        r1 = min(rows, r0 + step)
+        check(lib.crisp_rotate_rows(ctypes.c_void_p(x[r0:r1].data_ptr()), r1 - r0, d, _ptr(r),
+                                    ctypes.c_void_p(out[r0:r1].data_ptr()), _stream(stream)))
+    return out
+
+
+def sample_cev(x: torch.Tensor, rows: np.ndarray, stream=None) -> float:
+    """Correlation check of Section 4.1 on the sampled rows."""
+    n, d = x.shape
+    rows_t = torch.from_numpy(np.ascontiguousarray(rows, dtype=np.int64)).to(x.device)
+    cov = torch.empty(d * d + d, dtype=torch.float64, device=x.device)
+    check(lib.crisp_build_covariance(_ptr(x), n, d, _ptr(rows_t), rows_t.numel(), _ptr(cov), _stream(stream)))
+    c = cov[: d * d].reshape(d, d).cpu().numpy()
+    lam = np.linalg.eigvalsh(c)[::-1]
+    top = int(math.floor(0.2 * d))
+    return float(lam[:top].sum() / lam.sum())
+
+
+def _csr(cell_of: torch.Tensor, cells: int, stream=None):
+    n = cell_of.numel()
+    off = torch.empty(cells + 1, dtype=torch.int32, device=cell_of.device)
+    ids = torch.empty(n, dtype=torch.int32, device=cell_of.device)
+    scratch = torch.empty(int(lib.crisp_build_csr_scratch(n, cells)), dtype=torch.int32, device=cell_of.device)
+    check(lib.crisp_build_csr(_ptr(cell_of), n, cells, _ptr(off), _ptr(ids), _ptr(scratch), _stream(stream)))
+    return off, ids
+
+
+def _kmeans_half(x, col0, h, rows_t, init_pos, k, iters, stream=None):
+    """Lloyd's k-means on the sampled rows of one half; returns f32 [k, h]."""
+    n, d = x.shape
+    s = rows_t.numel()
+    dev = x.device
+    cent = torch.empty(k, h, dtype=torch.float32, device=dev)
+    # Initial centroids = the sampled rows at init_pos, via a one-member update.
+    init_off = torch.arange(k + 1, dtype=torch.int32, device=dev)
+    init_mem = torch.from_numpy(np.ascontiguousarray(init_pos, dtype=np.int32)).to(dev)
+    check(lib.crisp_build_update(_ptr(x), n, d, col0, h, _ptr(rows_t), _ptr(init_off), _ptr(init_mem), k,
+                                 _ptr(cent), _stream(stream)))
+    label = torch.empty(s, dtype=torch.int32, device=dev)
+    for _ in range(iters):
+        check(lib.crisp_build_assign(_ptr(x), n, d, col0, h, _ptr(rows_t), s, _ptr(cent), k, _ptr(label),
+                                     _stream(stream)))
+        moff, mem = _csr(label, k, stream)
+        check(lib.crisp_build_update(_ptr(x), n, d, col0, h, _ptr(rows_t), _ptr(moff), _ptr(mem), k,
+                                     _ptr(cent), _stream(stream)))
+    return cent
+
+
+def build_index(x: torch.Tensor, m: int, k_half: int, *, g, cev_rows: np.ndarray, km_rows: np.ndarray,
+                km_init: np.ndarray, force_rotation: bool | None = None, iters: int = KMEANS_ITERS,
+                keep_input: bool = True, stream=None) -> dict:
+    """Build a CRISP index from device data ``x`` (float32 [N, D]).
+
+    g        -- the D x D Gaussian matrix (numpy, or a callable returning it),
+                used only if the rotation fires
+    cev_rows, km_rows, km_init -- sampled rows / initial centroid positions
+    keep_input -- when False and the rotation fires, ``x`` is overwritten by
+                the rotated rows in chunks (peak device memory ~ N D floats)
+    Returns the arrays of crisp_index_desc as device tensors plus "cev".
+    """
+    n, d = x.shape
+    dev = x.device
+    if d % (2 * m) or d % 64:
+        raise ValueError("D must be a multiple of 2M and of 64")
+    h = d // (2 * m)
+    cev = sample_cev(x, cev_rows, stream)
+    rotate = (cev > TAU_CEV) if force_rotation is None else bool(force_rotation)
+    rot = None
+    base = x
+    if rotate:
+        gm = g() if callable(g) else g
+        q, _ = np.linalg.qr(np.asarray(gm, dtype=np.float64))
+        rot = torch.from_numpy(q.astype(np.float32)).to(dev)
+        if keep_input:
+            base = rotate_rows(x, rot, stream=stream)
+        else:
+            step = 1 << 16
+            buf = torch.empty(min(step, n), d, dtype=torch.float32, device=dev)
+            for r0 in range(0, n, step):
+                r1 = min(n, r0 + step)
+                rotate_rows(x[r0:r1], rot, out=buf[: r1 - r0], stream=stream)
+                x[r0:r1].copy_(buf[: r1 - r0])
+            base = x
+    rows_t = torch.from_numpy(np.ascontiguousarray(km_rows, dtype=np.int64)).to(dev)
+    cent = torch.empty(m, 2, k_half, h, dtype=torch.float32, device=dev)
+    offsets = torch.empty(m, k_half * k_half + 1, dtype=torch.int32, device=dev)
+    ids = torch.empty(m, n, dtype=torch.int32, device=dev)
+    lab = [torch.empty(n, dtype=torch.int32, device=dev) for _ in range(2)]
+    cell = torch.empty(n, dtype=torch.int32, device=dev)
+    for sub in range(m):
+        for s in range(2):
+            col0 = sub * 2 * h + s * h
+            c = _kmeans_half(base, col0, h, rows_t, km_init, k_half, iters, stream)
+            cent[sub, s].copy_(c)
+            check(lib.crisp_build_assign(_ptr(base), n, d, col0, h, None, n, _ptr(cent[sub, s]), k_half,
+                                         _ptr(lab[s]), _stream(stream)))
+        check(lib.crisp_build_combine(_ptr(lab[0]), _ptr(lab[1]), n, k_half, _ptr(cell), _stream(stream)))
+        off_s, ids_s = _csr(cell, k_half * k_half, stream)
+        offsets[sub].copy_(off_s)
+        ids[sub].copy_(ids_s)
+    codes = torch.empty(n, d // 64, dtype=torch.int64, device=dev)
+    check(lib.crisp_build_codes(_ptr(base), n, d, _ptr(codes), _stream(stream)))
+    return {"n": n, "d": d, "m": m, "k_half": k_half, "cev": cev, "rotation": rot, "centroids": cent,
+            "offsets": offsets, "ids": ids, "base": base, "codes": codes}

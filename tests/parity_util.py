@@ -1,0 +1,80 @@
+"""Helpers that compare the GPU engine stage by stage with the oracle."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import synth
+from oracle import build as obuild
+from oracle import query as oquery
+
+
+def make_workload(base: str, **kw):
+    w = synth.WORKLOADS[base].scaled(**kw)
+    p = synth.mixture_params(w)
+    x = synth.rows(w, w.seed_data, 0, w.n, p)
+    q = synth.rows(w, w.seed_query, 0, w.n_query, p)
+    return w, x, q
+
+
+def oracle_index(w, x, **kw):
+    return obuild.build_index_for(w, x, **kw)
+
+
+def gpu_index(idx, tile_ids=0):
+    from paper_2603_05180_amd import engine
+    return engine.Index(idx, tile_ids=tile_ids)
+
+
+def run_gpu(gidx, q: np.ndarray, k: int, *, mode, alpha, tau, patience_factor=40, limits=None, max_chunk=0):
+    qt = torch.from_numpy(np.ascontiguousarray(q, dtype=np.float32)).to(gidx.device)
+    taps = gidx.alloc_taps(q.shape[0], mode)
+    lim = None
+    if limits is not None:
+        lim = torch.from_numpy(np.asarray(limits, dtype=np.int32)).to(gidx.device)
+    ids, d = gidx.search(qt, k, mode=mode, alpha=alpha, tau=tau, patience_factor=patience_factor,
+                         limits=lim, max_chunk=max_chunk, taps=taps)
+    torch.cuda.synchronize()
+    return ids.cpu().numpy(), d.cpu().numpy(), {kk: v.cpu().numpy() for kk, v in taps.items()}
+
+
+def compare(idx, q, k, *, mode, alpha, tau, patience_factor=40, limits=None, gpu=None, max_chunk=0,
+            tile_ids=0, check_stages=True):
+    """Run both sides; assert bit-exact stages and results.  Returns a summary."""
+    g = gpu if gpu is not None else gpu_index(idx, tile_ids)
+    gi, gd, tp = run_gpu(g, q, k, mode=mode, alpha=alpha, tau=tau, patience_factor=patience_factor,
+                         limits=limits, max_chunk=max_chunk)
+    oi, od, tr = oquery.search(idx, q, k, mode=mode, alpha=alpha, tau=tau, patience_factor=patience_factor,
+                               limits=limits, trace=True)
+    m, kh, n = idx["m"], idx["k_half"], idx["n"]
+    for qi in range(q.shape[0]):
+        t = tr[qi]
+        if check_stages:
+            assert np.array_equal(tp["q_rot"][qi].view(np.uint32), t["q_rot"].view(np.uint32)), f"q_rot q={qi}"
+            assert np.array_equal(tp["half_dist"][qi].view(np.uint64), t["half_dist"].view(np.uint64)), \
+                f"half_dist q={qi}"
+            for sub in range(m):
+                nc = int(tp["n_cells"][qi, sub])
+                got = sorted((int(v) & 0xFFFFFF, int(v) >> 24) for v in tp["cells"][qi, sub, :nc])
+                ref = sorted(t["activated"][sub])
+                assert got == ref, f"cells q={qi} m={sub}"
+                sizes = np.diff(idx["offsets"][sub].astype(np.int64))
+                assert int(tp["retrieved"][qi, sub]) == int(sum(sizes[c] for c, _ in ref))
+            assert int(tp["tau_eff"][qi]) == t["tau_eff"], f"tau_eff q={qi}"
+            nc = int(tp["n_cand"][qi])
+            assert nc == t["candidates"].size, f"|C| q={qi}"
+            assert np.array_equal(tp["cand"][qi, :nc], t["candidates"]), f"cand q={qi}"
+            assert np.array_equal(tp["cand_score"][qi, :nc].astype(np.int64), t["scores"][t["candidates"]])
+            floor = max(t["tau_eff"], 1)
+            v = t["scores"]
+            hist = np.bincount(v[v >= floor], minlength=2 * m + 1)
+            assert np.array_equal(tp["hist"][qi], hist), f"hist q={qi}"
+            if mode == 1:
+                assert np.array_equal(tp["order"][qi, :nc], t["order"]), f"order q={qi}"
+                assert np.array_equal(tp["hamming"][qi, :nc], t["hamming"]), f"hamming q={qi}"
+                assert int(tp["examined"][qi]) == t["examined"], f"examined q={qi}"
+                assert int(tp["last_update"][qi]) == t["last_update"], f"last_update q={qi}"
+                assert int(tp["stopped"][qi]) == (0 if t["stop"] is None else 1), f"stopped q={qi}"
+    assert np.array_equal(gi, oi), "ids"
+    assert np.array_equal(gd.view(np.uint32), od.view(np.uint32)), "dists"
+    return {"n_cand": [t["candidates"].size for t in tr], "gpu": g}

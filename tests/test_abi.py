@@ -1,0 +1,46 @@
+"""The C-ABI library loads and exports every function include/crisp.h declares (CPU, no compute)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    with open(os.path.join(ROOT, "include", "crisp.h")) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(crisp_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2603_05180_amd import _lib
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib.EXPORTED)
+
+
+def test_version_and_error_string_without_gpu():
+    from paper_2603_05180_amd import _lib
+    assert _lib.lib.crisp_version().startswith(b"crisp-gfx950")
+    assert isinstance(_lib.lib.crisp_last_error(), bytes)
+
+
+def test_null_arguments_are_rejected_before_any_launch():
+    from paper_2603_05180_amd import _lib
+    size = ctypes.c_size_t(0)
+    assert _lib.lib.crisp_index_derived_bytes(None, 0, ctypes.byref(size)) == -1
+    desc = _lib.IndexDesc(1000, 100, 4, 8, None, None, None, None, None, None)
+    assert _lib.lib.crisp_index_derived_bytes(ctypes.byref(desc), 0, ctypes.byref(size)) == -5   # D % 64
+    desc = _lib.IndexDesc(1000, 128, 4, 8, None, None, None, None, None, None)
+    assert _lib.lib.crisp_index_derived_bytes(ctypes.byref(desc), 0, ctypes.byref(size)) == 0
+    assert size.value > 0
+    assert _lib.lib.crisp_index_derived_bytes(ctypes.byref(desc), 5000, ctypes.byref(size)) == -1  # not 2^k
+    desc = _lib.IndexDesc(1000, 128, 4, 300, None, None, None, None, None, None)
+    assert _lib.lib.crisp_index_derived_bytes(ctypes.byref(desc), 0, ctypes.byref(size)) == -5
+    assert _lib.lib.crisp_search(None, None, 1, 1, None, None, None, None, 0, None, None) == -1
+    assert _lib.lib.crisp_rotate_rows(None, 1, 64, None, None, None) == -1
+    assert _lib.lib.crisp_build_csr(None, 1, 1, None, None, None, None) == -1

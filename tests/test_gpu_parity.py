@@ -1,0 +1,98 @@
+"""GPU engine vs oracle, element by element, through the C ABI (needs an MI355X).
+
+Indexes are built by the oracle (CPU) and loaded by the engine as data, so
+the two sides search the same index.  Every stage is compared bit for bit:
+rotated queries, half distances, activated cells and weights, candidate
+lists and scores, threshold after the fallback, Hamming order, verified
+prefix, and the final ids and float32 distances.
+"""
+import numpy as np
+import pytest
+
+from parity_util import compare, gpu_index, make_workload, oracle_index
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    w, x, q = make_workload("cfg1")
+    idx = oracle_index(w, x)
+    return w, x, q, idx
+
+
+@pytest.mark.parametrize("mode,alpha,tau", [(0, 0.05, 4), (0, 0.02, 6), (1, 0.05, 4), (1, 0.1, 6)])
+def test_cfg1_full(cfg1, mode, alpha, tau):
+    """Plain Guaranteed / Optimized Mode at the CPU-fast size (N=10k, D=128, 100 queries)."""
+    w, x, q, idx = cfg1
+    print(f"cfg1 mode={mode} alpha={alpha} tau={tau}", flush=True)
+    compare(idx, q, w.k, mode=mode, alpha=alpha, tau=tau)
+
+
+def test_cfg1_ragged_tiles_and_chunks(cfg1):
+    """4096-id tiles (N=10k: 3 tiles, ragged tail) and 7-query chunks."""
+    w, x, q, idx = cfg1
+    print("cfg1 tiles=4096 chunk=7", flush=True)
+    compare(idx, q[:30], w.k, mode=1, alpha=0.05, tau=4, tile_ids=4096, max_chunk=7)
+    compare(idx, q[:30], w.k, mode=0, alpha=0.05, tau=4, tile_ids=4096, max_chunk=7)
+
+
+def test_fallback_and_degenerate_thresholds(cfg1):
+    w, x, q, idx = cfg1
+    g = gpu_index(idx)
+    print("fallback tau=16", flush=True)
+    s = compare(idx, q[:20], w.k, mode=0, alpha=0.002, tau=16, gpu=g)          # forces the fallback
+    assert min(s["n_cand"]) >= w.k
+    print("tau=0", flush=True)
+    compare(idx, q[:5], w.k, mode=0, alpha=0.01, tau=0, gpu=g)                 # every point a candidate
+    print("alpha=1", flush=True)
+    compare(idx, q[:5], w.k, mode=1, alpha=1.0, tau=8, gpu=g)                  # every cell activated
+    print("k=1", flush=True)
+    compare(idx, q[:10], 1, mode=1, alpha=0.02, tau=3, gpu=g)
+    print("k=100", flush=True)
+    compare(idx, q[:10], 100, mode=0, alpha=0.02, tau=3, gpu=g)
+    print("single query", flush=True)
+    compare(idx, q[:1], w.k, mode=1, alpha=0.03, tau=2, gpu=g, patience_factor=1)
+
+
+def test_padding_when_too_few_points_collide():
+    w, x, q = make_workload("cfg1", n=600, d=64, m=2, k_half=4, n_query=6)
+    idx = oracle_index(w, x)
+    print("padding", flush=True)
+    compare(idx, q, 50, mode=0, alpha=0.001, tau=2)
+
+
+def test_learned_prefix_limits(cfg1):
+    w, x, q, idx = cfg1
+    lim = np.array([1, 5, 17, 0, 200, 3] * 5, dtype=np.int32)
+    print("limits", flush=True)
+    compare(idx, q[:30], w.k, mode=1, alpha=0.05, tau=4, limits=lim)
+
+
+@pytest.mark.parametrize("k_half", [1, 64, 80])
+def test_codebook_sizes(k_half):
+    """K = 1 (one cell), K = 64 (4096 cells), K = 80 (prefix tables in device memory)."""
+    w, x, q = make_workload("cfg1", n=4000, d=128, m=4, k_half=k_half, n_query=12)
+    idx = oracle_index(w, x)
+    print(f"K={k_half}", flush=True)
+    for mode in (0, 1):
+        compare(idx, q, 10, mode=mode, alpha=0.03, tau=2)
+
+
+def test_rotated_index():
+    """Correlated data: the rotation fires, queries are rotated on the GPU."""
+    w, x, q = make_workload("cfg3", n=3000, d=256, m=8, k_half=6, rank=16, n_query=16)
+    idx = oracle_index(w, x)
+    assert idx["rotation"] is not None
+    print("rotated", flush=True)
+    for mode in (0, 1):
+        compare(idx, q, 10, mode=mode, alpha=0.05, tau=3)
+
+
+def test_wide_rows_several_tiles():
+    """D = 1024 (float4 path), 5 tiles of 4096 with a ragged tail."""
+    w, x, q = make_workload("cfg3", n=18000, d=1024, m=16, k_half=8, rank=32, n_query=10)
+    idx = oracle_index(w, x)
+    print("D=1024", flush=True)
+    for mode in (0, 1):
+        compare(idx, q, 10, mode=mode, alpha=0.02, tau=4, tile_ids=4096)
