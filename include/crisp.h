@@ -258,6 +258,30 @@ crisp_status crisp_build_combine(const int32_t *left, const int32_t *right, int6
 crisp_status crisp_build_codes(const float *x, int64_t n, int32_t d, uint64_t *codes,
                                void *hip_stream);
 
+/* ---- Stage timing ------------------------------------------------------ */
+
+/*
+ * GPU time per query stage, measured with HIP events recorded on the search
+ * stream around each stage's launches.  Stages: 0 rotation (A0), 1 half
+ * distances (A1), 2 cell selection (A2), 3 collision counting, fallback and
+ * candidate lists (A3/A4), 4 Hamming order (A5), 5 re-rank (A6/A7).
+ */
+typedef struct {
+  double ms[8];
+  int64_t intervals[8];
+  int64_t dropped;       /* intervals not timed because the event pool was full */
+} crisp_profile;
+
+/*
+ * Starts timing the index's subsequent crisp_search calls: creates a pool of
+ * 2 * max_intervals HIP events (host-side driver objects; no device memory).
+ * Calls that overlap on several streams are timed per stream interval.
+ */
+crisp_status crisp_profile_begin(crisp_index *index, int32_t max_intervals);
+
+/* Waits for the recorded events, writes the sums to *out, releases the pool. */
+crisp_status crisp_profile_end(crisp_index *index, crisp_profile *out);
+
 /* Thread-local message for the last non-OK status. */
 const char *crisp_last_error(void);
 

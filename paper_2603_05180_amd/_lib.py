@@ -36,6 +36,12 @@ class SearchParams(ctypes.Structure):
                 ("patience_factor", c_int32), ("limits", c_void_p), ("max_chunk", c_int32)]
 
 
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("intervals", c_int64 * 8), ("dropped", c_int64)]
+
+
+STAGES = ["rotate", "half_dist", "select", "count", "hamming_order", "rerank"]
+
 TAP_FIELDS = ["q_rot", "half_dist", "n_cells", "cells", "retrieved", "hist", "tau_eff", "n_cand",
               "cand", "cand_score", "order", "hamming", "examined", "last_update", "stopped"]
 
@@ -71,6 +77,8 @@ _SIGS = {
     "crisp_build_csr": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "crisp_build_combine": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
     "crisp_build_codes": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
+    "crisp_profile_begin": (c_int32, [c_void_p, c_int32]),
+    "crisp_profile_end": (c_int32, [c_void_p, ctypes.POINTER(Profile)]),
 }
 
 for _name, (_res, _args) in _SIGS.items():

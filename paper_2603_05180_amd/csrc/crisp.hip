@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "build_kernels.hpp"
 #include "common.hpp"
@@ -74,7 +75,35 @@ struct crisp_index {
   const int32_t *off, *ids;
   const uint64_t *codes;
   int32_t *tile_off;
+  // stage timing (crisp_profile_begin / crisp_profile_end)
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;
+  std::vector<int> prof_stage;
+  size_t prof_used = 0;
+  int64_t prof_dropped = 0;
 };
+
+namespace {
+// Records a start event on construction and a stop event on stop() when the
+// index is being profiled and the pool has room.
+struct StageTimer {
+  crisp_index *ix;
+  hipStream_t st;
+  long slot = -1;
+  StageTimer(crisp_index *ix_, int stage, hipStream_t st_) : ix(ix_), st(st_) {
+    if (!ix->prof_on) return;
+    if (ix->prof_used + 2 > ix->prof_ev.size()) { ++ix->prof_dropped; return; }
+    slot = static_cast<long>(ix->prof_used);
+    ix->prof_used += 2;
+    ix->prof_stage[slot / 2] = stage;
+    (void)hipEventRecord(ix->prof_ev[slot], st);
+  }
+  void stop() {
+    if (slot >= 0) (void)hipEventRecord(ix->prof_ev[slot + 1], st);
+    slot = -1;
+  }
+};
+}  // namespace
 
 // Workspace layout for one chunk of qc queries.
 struct Layout {
@@ -175,6 +204,8 @@ crisp_status crisp_index_load(const crisp_index_desc *desc, int32_t tile_ids, vo
 }
 
 crisp_status crisp_index_free(crisp_index *index) {
+  if (index)
+    for (auto &e : index->prof_ev) (void)hipEventDestroy(e);
   delete index;
   return CRISP_OK;
 }
@@ -253,6 +284,7 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
     const int cq = static_cast<int>(std::min<long long>(qc, nq - q0));
     const float *qin = queries + q0 * d;
     // A0
+    StageTimer t0(ix, 0, st);
     if (ix->rot) {
       dim3 g(d / kRotBN, (cq + kRotBM - 1) / kRotBM);
       k_rotate_rows<<<g, 256, 0, st>>>(qin, cq, d, ix->rot, qrot);
@@ -261,19 +293,25 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
       k_copy_f32<<<grid1(static_cast<long long>(cq) * d, 256), 256, 0, st>>>(qin, qrot, static_cast<long long>(cq) * d);
       LAUNCH_TRY("k_copy_f32");
     }
+    t0.stop();
     // A1
     {
+      StageTimer t1(ix, 1, st);
       long long tot = static_cast<long long>(cq) * m * 2 * kh;
       k_half_dist<<<grid1(tot, 256), 256, 0, st>>>(qrot, cq, d, m, kh, ix->h, ix->cent, hdist);
       LAUNCH_TRY("k_half_dist");
+      t1.stop();
     }
     // A2
     {
+      StageTimer t2(ix, 2, st);
       dim3 g(m, cq);
       k_select_cells<<<g, 64, 0, st>>>(hdist, m, kh, ix->off, budget, k, p->mode, ptab, ncell, cells, retr);
       LAUNCH_TRY("k_select_cells");
+      t2.stop();
     }
     // A3 / A4
+    StageTimer t3(ix, 3, st);
     k_fill<int32_t><<<grid1(static_cast<long long>(cq) * nb, 256), 256, 0, st>>>(hist, static_cast<long long>(cq) * nb, 0);
     LAUNCH_TRY("k_fill");
     {
@@ -297,21 +335,28 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
       k_compact<<<cq, 256, 0, st>>>(segids, segscore, tilecnt, ix->ntiles, ix->tile, n, cand, score, ncand);
       LAUNCH_TRY("k_compact");
     }
+    t3.stop();
     const int32_t *lim = p->limits ? p->limits + q0 : nullptr;
     if (p->mode == 1) {
       // A5
+      StageTimer t4(ix, 4, st);
       k_hamming_order<<<cq, kOrderThreads, order_lds, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, segids, regB);
       LAUNCH_TRY("k_hamming_order");
+      t4.stop();
       // A6 / A7
+      StageTimer t5(ix, 5, st);
       k_rerank<<<cq, kRerankThreads, rerank_lds, st>>>(1, qrot, d, ix->base, ncand, segids, n, k, patience, lim,
                                                        reinterpret_cast<float *>(regA), regB, regC, ids + q0 * k,
                                                        dists + q0 * k, exam, lastu, stopd);
       LAUNCH_TRY("k_rerank");
+      t5.stop();
     } else {
+      StageTimer t5(ix, 5, st);
       k_rerank<<<cq, kRerankThreads, rerank_lds, st>>>(0, qrot, d, ix->base, ncand, cand, n, k, patience, lim,
                                                        reinterpret_cast<float *>(regA), regB, regC, ids + q0 * k,
                                                        dists + q0 * k, exam, lastu, stopd);
       LAUNCH_TRY("k_rerank");
+      t5.stop();
     }
     if (taps) {
       const size_t qn = static_cast<size_t>(cq) * static_cast<size_t>(n);
@@ -335,6 +380,41 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
     }
   }
   return CRISP_OK;
+}
+
+crisp_status crisp_profile_begin(crisp_index *ix, int32_t max_intervals) {
+  if (!ix || max_intervals < 1) return fail(CRISP_E_INVALID, "bad argument");
+  if (ix->prof_on) return fail(CRISP_E_INVALID, "profiling already active");
+  ix->prof_ev.assign(static_cast<size_t>(max_intervals) * 2, nullptr);
+  ix->prof_stage.assign(static_cast<size_t>(max_intervals), 0);
+  for (auto &e : ix->prof_ev) HIP_TRY(hipEventCreate(&e));
+  ix->prof_used = 0;
+  ix->prof_dropped = 0;
+  ix->prof_on = true;
+  return CRISP_OK;
+}
+
+crisp_status crisp_profile_end(crisp_index *ix, crisp_profile *out) {
+  if (!ix || !out) return fail(CRISP_E_INVALID, "null argument");
+  if (!ix->prof_on) return fail(CRISP_E_INVALID, "profiling not active");
+  std::memset(out, 0, sizeof *out);
+  crisp_status rc = CRISP_OK;
+  for (size_t i = 0; i + 1 < ix->prof_used; i += 2) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(ix->prof_ev[i + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ix->prof_ev[i], ix->prof_ev[i + 1]);
+    if (e != hipSuccess) { rc = fail(CRISP_E_HIP, "event timing: %s", hipGetErrorString(e)); break; }
+    int stg = ix->prof_stage[i / 2];
+    out->ms[stg] += ms;
+    out->intervals[stg] += 1;
+  }
+  out->dropped = ix->prof_dropped;
+  for (auto &e : ix->prof_ev) (void)hipEventDestroy(e);
+  ix->prof_ev.clear();
+  ix->prof_stage.clear();
+  ix->prof_used = 0;
+  ix->prof_on = false;
+  return rc;
 }
 
 crisp_status crisp_rotate_rows(const float *x, int64_t rows, int32_t d, const float *r, float *out, void *hip_stream) {

@@ -609,39 +609,75 @@ __device__ __forceinline__ Band band_of(float df, int d) {
   return Band{v - v * eps - absb, v + v * eps + absb};
 }
 
-// float32 distance of one row, whole wave; result in every lane.
+// float32 distance of one row, whole wave; result in every lane.  Loads are
+// issued eight at a time before they are consumed so that several are in
+// flight per lane.
 __device__ __forceinline__ float row_dist_f32(const float *__restrict__ sq, const float *__restrict__ x, int d) {
   const int lane = lane_id();
   float acc = 0.0f;
   if ((d & 255) == 0) {
     const float4 *xr = reinterpret_cast<const float4 *>(x);
     const float4 *qq = reinterpret_cast<const float4 *>(sq);
-    for (int r = lane; r < d / 4; r += kWave) {
-      float4 a = xr[r];
-      float4 b = qq[r];
-      float e0 = b.x - a.x, e1 = b.y - a.y, e2 = b.z - a.z, e3 = b.w - a.w;
-      acc = fmaf(e0, e0, acc);
-      acc = fmaf(e1, e1, acc);
-      acc = fmaf(e2, e2, acc);
-      acc = fmaf(e3, e3, acc);
+    const int nv = d / 4;
+    for (int r0 = lane; r0 < nv; r0 += kWave * 8) {
+      float4 a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int r = r0 + u * kWave;
+        a[u] = (r < nv) ? xr[r] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int r = r0 + u * kWave;
+        if (r < nv) {
+          float4 b = qq[r];
+          float e0 = b.x - a[u].x, e1 = b.y - a[u].y, e2 = b.z - a[u].z, e3 = b.w - a[u].w;
+          acc = fmaf(e0, e0, acc);
+          acc = fmaf(e1, e1, acc);
+          acc = fmaf(e2, e2, acc);
+          acc = fmaf(e3, e3, acc);
+        }
+      }
     }
   } else {
-    for (int e = lane; e < d; e += kWave) {
-      float t = sq[e] - x[e];
-      acc = fmaf(t, t, acc);
+    for (int e0 = lane; e0 < d; e0 += kWave * 8) {
+      float a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int e = e0 + u * kWave;
+        a[u] = (e < d) ? x[e] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int e = e0 + u * kWave;
+        if (e < d) {
+          float t = sq[e] - a[u];
+          acc = fmaf(t, t, acc);
+        }
+      }
     }
   }
   return wave_sum_f32(acc);
 }
 
-// d_canon of one row, whole wave; result in every lane.
+// d_canon of one row, whole wave; result in every lane.  Loads are batched
+// sixteen at a time; the float64 accumulation order is the definition's.
 __device__ __forceinline__ double row_dist_canon(const float *__restrict__ sq, const float *__restrict__ x, int d) {
   const int lane = lane_id();
+  const int nr = d / kWave;
   double p = 0.0;
-  for (int r = 0; r < d / kWave; ++r) {
-    double t = static_cast<double>(sq[r * kWave + lane]) - static_cast<double>(x[r * kWave + lane]);
-    double s2 = t * t;
-    p = p + s2;
+  for (int r0 = 0; r0 < nr; r0 += 16) {
+    float xv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) xv[u] = (r0 + u < nr) ? x[(r0 + u) * kWave + lane] : 0.f;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      if (r0 + u < nr) {
+        double t = static_cast<double>(sq[(r0 + u) * kWave + lane]) - static_cast<double>(xv[u]);
+        double s2 = t * t;
+        p = p + s2;
+      }
+    }
   }
 #pragma unroll
   for (int s = 32; s >= 1; s >>= 1) {

@@ -93,6 +93,16 @@ class Index:
         except Exception:
             pass
 
+    def profile_begin(self, max_intervals: int = 4096):
+        check(lib.crisp_profile_begin(self._h, int(max_intervals)))
+
+    def profile_end(self) -> dict:
+        """Per-stage GPU milliseconds and interval counts since profile_begin."""
+        pr = _lib.Profile()
+        check(lib.crisp_profile_end(self._h, ctypes.byref(pr)))
+        return {name: {"ms": pr.ms[i], "intervals": pr.intervals[i]} for i, name in enumerate(_lib.STAGES)} | \
+            {"dropped": pr.dropped}
+
     def params(self, *, mode=0, alpha=0.01, tau=1, patience_factor=40, limits=None, max_chunk=0):
         return SearchParams(int(mode), float(alpha), int(tau), int(patience_factor), _ptr(limits), int(max_chunk))
 
