@@ -42,12 +42,13 @@
  * * Cell order inside a subspace (Section 4.3.1, Multi-Sequence traversal):
  *   ascending (d1s[i] + d2s[j], i, j) with i, j the ranks of the left / right
  *   centroids in their half's (distance, index) order; cell id = iL * K + iR.
- * * Distance key (Section 4.3.2, Stage 3, exact L2): d_canon in float64,
- *   lane-strided: p_l = sum_r (q'[64 r + l] - x[64 r + l])^2 for l < 64, then
- *   p_l += p_{l+s} for s = 32, 16, ..., 1; results ordered by (d_canon, id);
- *   returned distances are f32(d_canon).  The engine evaluates candidates in
- *   float32 with a proven error band and recomputes d_canon wherever the band
- *   could change a decision, so its ids equal those of the definition.
+ * * Distance key (Section 4.3.2, Stage 3, exact L2): d_canon in float64.
+ *   Dimensions are cut into groups of four; group g goes to lane g % 64;
+ *   lane l sums (q'_i - x_i)^2 over its groups in ascending g, the four
+ *   dimensions of a group in order (unfused); then p_l += p_{l+s} for
+ *   s = 32, 16, ..., 1 and d_canon = p_0.  Results are ordered by
+ *   (d_canon, id); returned distances are f32(d_canon).  Every verified
+ *   candidate's key is computed exactly so.
  */
 #ifndef CRISP_H_
 #define CRISP_H_

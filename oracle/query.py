@@ -151,20 +151,28 @@ def hamming_order(index: dict, qp: np.ndarray, cand: np.ndarray):
 
 
 def canonical_sqdist(qp: np.ndarray, rows: np.ndarray) -> np.ndarray:
-    """d_canon for each row: lane-strided float64 partial sums + tree.
+    """d_canon for each row: 64 lane partial sums + a halving tree (float64).
 
-    For lane l in [0, 64): p_l = sum over r ascending of (q'[64 r + l] - x[64 r + l])^2
-    (float64, unfused); then p_l <- p_l + p_{l+s} for s = 32, 16, ..., 1 and
-    l < s; d_canon = p_0.
+    The dimensions are cut into groups of four consecutive ones; group g goes
+    to lane g % 64.  Lane l sums (q'[i] - x[i])^2 over its groups in ascending
+    g and over the four dimensions of a group in order (float64, unfused);
+    then p_l <- p_l + p_{l+s} for s = 32, 16, ..., 1 and l < s; d_canon = p_0.
+    Dimensions are zero-padded to a multiple of 256, which adds exact zeros.
     """
     d = qp.shape[0]
-    q64 = qp.astype(np.float64).reshape(d // LANES, LANES)
-    x64 = np.asarray(rows, dtype=np.float32).astype(np.float64).reshape(-1, d // LANES, LANES)
-    p = np.zeros((x64.shape[0], LANES), dtype=np.float64)
-    for r in range(d // LANES):
-        delta = q64[None, r, :] - x64[:, r, :]
-        sq = delta * delta
-        p = p + sq
+    pad = (-d) % (4 * LANES)
+    q64 = np.concatenate([qp.astype(np.float64), np.zeros(pad)])
+    x64 = np.asarray(rows, dtype=np.float32).astype(np.float64).reshape(-1, d)
+    x64 = np.concatenate([x64, np.zeros((x64.shape[0], pad))], axis=1)
+    r_groups = (d + pad) // (4 * LANES)
+    q4 = q64.reshape(r_groups, LANES, 4)
+    x4 = x64.reshape(-1, r_groups, LANES, 4)
+    p = np.zeros((x4.shape[0], LANES), dtype=np.float64)
+    for r in range(r_groups):
+        for c in range(4):
+            delta = q4[None, r, :, c] - x4[:, r, :, c]
+            sq = delta * delta
+            p = p + sq
     s = LANES // 2
     while s >= 1:
         p[:, :s] = p[:, :s] + p[:, s:2 * s]

@@ -43,7 +43,7 @@ crisp_status fail(crisp_status s, const char *fmt, ...) {
     if (e_ != hipSuccess) return fail(CRISP_E_HIP, "launch %s: %s", name, hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int kDefaultTile = 32768;
+constexpr int kDefaultTile = 65536;
 constexpr int kDefaultChunk = 1024;
 
 inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
@@ -75,6 +75,7 @@ struct crisp_index {
   const int32_t *off, *ids;
   const uint64_t *codes;
   int32_t *tile_off;
+  float *cent_t;  // [M][2][h][K]
   // stage timing (crisp_profile_begin / crisp_profile_end)
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;
@@ -122,7 +123,7 @@ static Layout make_layout(const crisp_index *ix, long long qc) {
   L.ncell = take(qc * ix->m * 4);
   L.cells = take(qc * ix->m * ix->ncells * 4);
   L.retr = take(qc * ix->m * 4);
-  L.tilecnt = take(qc * ix->ntiles * 4);
+  L.tilecnt = take(qc * ix->ntiles * kCountWaves * 4);
   L.hist = take(qc * (2 * ix->m + 1) * 4);
   L.flag = take(qc * 4);
   L.taueff = take(qc * 4);
@@ -131,9 +132,9 @@ static Layout make_layout(const crisp_index *ix, long long qc) {
   L.segscore = take(qc * n);
   L.cand = take(qc * n * 4);
   L.score = take(qc * n);
-  L.regA = take(qc * n * 4);       // mode 0: first-pass distances; mode 1: Hamming per candidate
-  L.regB = take(qc * n * 4);       // mode 0: survivor positions;    mode 1: sorted Hamming
-  L.regC = take(qc * n * 8);       // mode 0: survivor keys
+  L.regA = take(qc * n * 4);       // mode 1: Hamming distance per candidate
+  L.regB = take(qc * n * 4);       // mode 1: Hamming distances in order
+  L.regC = take(qc * n * 8);       // mode 0: float64 keys of the candidates
   L.examined = take(qc * 4);
   L.lastupd = take(qc * 4);
   L.stopped = take(qc * 4);
@@ -161,7 +162,9 @@ crisp_status crisp_index_derived_bytes(const crisp_index_desc *desc, int32_t til
   long long ntiles = (desc->n + tile - 1) / tile;
   if (ntiles > 1024) return fail(CRISP_E_UNSUPPORTED, "N / tile_ids must be <= 1024");
   long long ncells = static_cast<long long>(desc->k_half) * desc->k_half;
-  *bytes = align_up(static_cast<size_t>(desc->m) * ncells * (ntiles + 1) * 4) + 256;
+  const size_t h = static_cast<size_t>(desc->d) / (2 * desc->m);
+  *bytes = align_up(static_cast<size_t>(desc->m) * ncells * (ntiles + 1) * 4) +
+           align_up(static_cast<size_t>(desc->m) * 2 * desc->k_half * h * 4) + 256;
   return CRISP_OK;
 }
 
@@ -193,12 +196,21 @@ crisp_status crisp_index_load(const crisp_index_desc *desc, int32_t tile_ids, vo
   k_tile_offsets<<<grid1(cellsm, 256), 256, 0, st>>>(desc->offsets, desc->ids, desc->m, ncells, desc->n, ntiles,
                                                       tile, tile_off);
   LAUNCH_TRY("k_tile_offsets");
+  const int hh = desc->d / (2 * desc->m);
+  float *cent_t = reinterpret_cast<float *>(static_cast<char *>(derived) +
+                                            align_up(static_cast<size_t>(desc->m) * ncells * (ntiles + 1) * 4));
+  const long long ncent = static_cast<long long>(desc->m) * 2 * desc->k_half * hh;
+  k_transpose_centroids<<<grid1(ncent, 256), 256, 0, st>>>(desc->centroids, desc->m, desc->k_half, hh, cent_t);
+  LAUNCH_TRY("k_transpose_centroids");
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_count), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              tile));
   crisp_index *ix = new (std::nothrow) crisp_index{};
   if (!ix) return fail(CRISP_E_INVALID, "out of host memory");
   ix->n = desc->n; ix->d = desc->d; ix->m = desc->m; ix->k = desc->k_half;
   ix->h = desc->d / (2 * desc->m); ix->ncells = ncells; ix->tile = tile; ix->ntiles = ntiles;
   ix->rot = desc->rotation; ix->cent = desc->centroids; ix->base = desc->base;
   ix->off = desc->offsets; ix->ids = desc->ids; ix->codes = desc->codes; ix->tile_off = tile_off;
+  ix->cent_t = cent_t;
   *out = ix;
   return CRISP_OK;
 }
@@ -276,7 +288,8 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
   const long long n = ix->n;
   const int budget = static_cast<int>(std::max<double>(1.0, std::ceil(p->alpha * static_cast<double>(n))));
   const int patience = p->mode == 1 ? p->patience_factor * k : 0;
-  const size_t count_lds = static_cast<size_t>((ix->tile + 3) / 4) * 4;
+  const size_t count_lds = static_cast<size_t>(ix->tile);
+  const int nseg = ix->ntiles * kCountWaves;
   const size_t order_lds = static_cast<size_t>(d + 1) * 4;
   const size_t rerank_lds = static_cast<size_t>(d) * 4 + static_cast<size_t>(k) * 12;
 
@@ -294,19 +307,13 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
       LAUNCH_TRY("k_copy_f32");
     }
     t0.stop();
-    // A1
-    {
-      StageTimer t1(ix, 1, st);
-      long long tot = static_cast<long long>(cq) * m * 2 * kh;
-      k_half_dist<<<grid1(tot, 256), 256, 0, st>>>(qrot, cq, d, m, kh, ix->h, ix->cent, hdist);
-      LAUNCH_TRY("k_half_dist");
-      t1.stop();
-    }
-    // A2
+    // A1 + A2
     {
       StageTimer t2(ix, 2, st);
       dim3 g(m, cq);
-      k_select_cells<<<g, 64, 0, st>>>(hdist, m, kh, ix->off, budget, k, p->mode, ptab, ncell, cells, retr);
+      k_select_cells<<<g, 64, select_lds_bytes(kh, ix->h), st>>>(qrot, d, ix->cent_t, m, kh, ix->h, ix->off,
+                                                                  budget, k, p->mode, hdist, ptab, ncell, cells,
+                                                                  retr);
       LAUNCH_TRY("k_select_cells");
       t2.stop();
     }
@@ -320,19 +327,20 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
                                                    ix->ntiles, ix->tile, 0, p->tau, flag, taueff, segids, segscore,
                                                    tilecnt, hist);
       LAUNCH_TRY("k_count pass 0");
-      k_flag<<<grid1(cq, 256), 256, 0, st>>>(tilecnt, ix->ntiles, cq, k, p->tau, flag, taueff, hist, nb);
+      k_flag<<<grid1(cq, 4), 256, 0, st>>>(tilecnt, nseg, cq, k, p->tau, flag, taueff, hist, nb);
       LAUNCH_TRY("k_flag");
       k_count<<<g, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
                                                    ix->ntiles, ix->tile, 1, p->tau, flag, taueff, segids, segscore,
                                                    tilecnt, hist);
       LAUNCH_TRY("k_count pass 1");
-      k_tau_eff<<<grid1(cq, 256), 256, 0, st>>>(flag, cq, k, p->tau, nb, hist, taueff, tilecnt, ix->ntiles);
+      k_tau_eff<<<grid1(cq, 256), 256, 0, st>>>(flag, cq, k, p->tau, nb, hist, taueff, tilecnt, nseg);
       LAUNCH_TRY("k_tau_eff");
       k_count<<<g, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
                                                    ix->ntiles, ix->tile, 2, p->tau, flag, taueff, segids, segscore,
                                                    tilecnt, hist);
       LAUNCH_TRY("k_count pass 2");
-      k_compact<<<cq, 256, 0, st>>>(segids, segscore, tilecnt, ix->ntiles, ix->tile, n, cand, score, ncand);
+      k_compact<<<cq, kCompactThreads, 0, st>>>(segids, segscore, tilecnt, nseg, ix->tile / kCountWaves, n, cand,
+                                                 score, ncand);
       LAUNCH_TRY("k_compact");
     }
     t3.stop();
@@ -346,15 +354,13 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
       // A6 / A7
       StageTimer t5(ix, 5, st);
       k_rerank<<<cq, kRerankThreads, rerank_lds, st>>>(1, qrot, d, ix->base, ncand, segids, n, k, patience, lim,
-                                                       reinterpret_cast<float *>(regA), regB, regC, ids + q0 * k,
-                                                       dists + q0 * k, exam, lastu, stopd);
+                                                       regC, ids + q0 * k, dists + q0 * k, exam, lastu, stopd);
       LAUNCH_TRY("k_rerank");
       t5.stop();
     } else {
       StageTimer t5(ix, 5, st);
       k_rerank<<<cq, kRerankThreads, rerank_lds, st>>>(0, qrot, d, ix->base, ncand, cand, n, k, patience, lim,
-                                                       reinterpret_cast<float *>(regA), regB, regC, ids + q0 * k,
-                                                       dists + q0 * k, exam, lastu, stopd);
+                                                       regC, ids + q0 * k, dists + q0 * k, exam, lastu, stopd);
       LAUNCH_TRY("k_rerank");
       t5.stop();
     }

@@ -85,32 +85,13 @@ __global__ void k_fill(T *__restrict__ dst, long long n, T v) {
 }
 
 // ---------------------------------------------------------------------------
-// A1: half distances, one thread per (query, subspace, half, centroid).
-// ---------------------------------------------------------------------------
-__global__ void k_half_dist(const float *__restrict__ qrot, int nq, int d, int m, int k, int h,
-                            const float *__restrict__ cent, double *__restrict__ out) {
-  long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  long long total = static_cast<long long>(nq) * m * 2 * k;
-  if (t >= total) return;
-  int c = static_cast<int>(t % k);
-  long long r = t / k;
-  int s = static_cast<int>(r % 2);
-  r /= 2;
-  int sub = static_cast<int>(r % m);
-  int q = static_cast<int>(r / m);
-  const float *qa = qrot + static_cast<long long>(q) * d + sub * 2 * h + s * h;
-  const float *ca = cent + ((static_cast<long long>(sub) * 2 + s) * k + c) * h;
-  double acc = 0.0;
-  for (int i = 0; i < h; ++i) {
-    double delta = static_cast<double>(qa[i]) - static_cast<double>(ca[i]);
-    double sq = delta * delta;
-    acc = acc + sq;
-  }
-  out[t] = acc;
-}
-
-// ---------------------------------------------------------------------------
-// A2: cell selection.  One wavefront per (query, subspace).
+// A1 + A2: half distances and cell selection.  One wavefront per
+// (query, subspace).
+//
+// Dist_1 / Dist_2 are computed from the rotated sub-vector (staged in LDS)
+// and a load-time transposed copy of the half-codebooks ([M][2][h][K], so the
+// lanes of a wave read consecutive centroids), accumulated over the h
+// coordinates in ascending order exactly as defined.
 //
 // The heap of Algorithm 1 pops cells in ascending key (cost, i, j) with
 // cost = d1s[i] + d2s[j]; since cost is monotone in i and in j the popped
@@ -123,41 +104,79 @@ __global__ void k_half_dist(const float *__restrict__ qrot, int nq, int d, int m
 // ordered by (i, j).  The k_size-th key (rank weights) is found the same way
 // counting cells instead of ids.
 // ---------------------------------------------------------------------------
-struct SelectShared {
-  double d1s[256], d2s[256];
-  int o1[256], o2[256];
-  int ptab[64 * 65];  // row prefix sizes when K <= 64
-  int rowcnt[256];
-  int roww[256];
-  int misc[8];
+struct SelectLds {
+  double *d1s, *d2s, *hd;
+  int *o1, *o2, *rowcnt, *roww, *ptab;
+  float *qs;
 };
 
-__device__ __forceinline__ int row_count_le(const SelectShared &S, int k, int i, double th) {
-  const double a = S.d1s[i];
+__host__ __device__ inline size_t select_lds_bytes(int k, int h) {
+  size_t b = 0;
+  b += 8 * static_cast<size_t>(k) * 4;                      // d1s, d2s, hd (2k)
+  b += 4 * static_cast<size_t>(k) * 4;                      // o1, o2, rowcnt, roww
+  b += (k <= 64) ? 4 * static_cast<size_t>(k) * (k + 1) : 0;  // ptab
+  b += 4 * 2 * static_cast<size_t>(h);                      // qs
+  return (b + 15) / 16 * 16;
+}
+
+__device__ __forceinline__ int row_count_le(const double *d1s, const double *d2s, int k, int i, double th) {
+  const double a = d1s[i];
   int lo = 0, hi = k;
   while (lo < hi) {
     int mid = (lo + hi) >> 1;
-    if (a + S.d2s[mid] <= th) lo = mid + 1; else hi = mid;
+    if (a + d2s[mid] <= th) lo = mid + 1; else hi = mid;
   }
   return lo;
 }
 
-__global__ void __launch_bounds__(64) k_select_cells(const double *__restrict__ hdist, int m, int k,
-                                                     const int32_t *__restrict__ offsets, int budget,
-                                                     int ksize, int phi, int32_t *__restrict__ ptab_g,
-                                                     int32_t *__restrict__ ncell, int32_t *__restrict__ cells_out,
+__global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ qrot, int d,
+                                                     const float *__restrict__ cent_t, int m, int k, int h,
+                                                     const int32_t *__restrict__ offsets, int budget, int ksize,
+                                                     int phi, double *__restrict__ hdist_out,
+                                                     int32_t *__restrict__ ptab_g, int32_t *__restrict__ ncell,
+                                                     int32_t *__restrict__ cells_out,
                                                      int32_t *__restrict__ retrieved) {
-  __shared__ SelectShared S;
+  extern __shared__ __align__(16) unsigned char dyn[];
+  SelectLds S;
+  {
+    unsigned char *p = dyn;
+    S.d1s = reinterpret_cast<double *>(p); p += 8 * k;
+    S.d2s = reinterpret_cast<double *>(p); p += 8 * k;
+    S.hd = reinterpret_cast<double *>(p); p += 16 * k;
+    S.o1 = reinterpret_cast<int *>(p); p += 4 * k;
+    S.o2 = reinterpret_cast<int *>(p); p += 4 * k;
+    S.rowcnt = reinterpret_cast<int *>(p); p += 4 * k;
+    S.roww = reinterpret_cast<int *>(p); p += 4 * k;
+    S.ptab = reinterpret_cast<int *>(p); p += (k <= 64) ? 4 * k * (k + 1) : 0;
+    S.qs = reinterpret_cast<float *>(p);
+  }
   const int sub = blockIdx.x, q = blockIdx.y, lane = threadIdx.x;
   const int ncells = k * k;
-  const double *h1 = hdist + ((static_cast<long long>(q) * m + sub) * 2) * k;
-  const double *h2 = h1 + k;
-  // Sort both halves by (distance, index) via ranks.
+  const float *qa = qrot + static_cast<long long>(q) * d + sub * 2 * h;
+  for (int t = lane; t < 2 * h; t += kWave) S.qs[t] = qa[t];
+  __syncthreads();
+  // ---- Dist_1 / Dist_2 -----------------------------------------------------
+  double *hout = hdist_out + (static_cast<long long>(q) * m + sub) * 2 * k;
+  for (int s = 0; s < 2; ++s) {
+    const float *ct = cent_t + static_cast<long long>(sub * 2 + s) * h * k;
+    for (int c = lane; c < k; c += kWave) {
+      double acc = 0.0;
+      for (int t = 0; t < h; ++t) {
+        double delta = static_cast<double>(S.qs[s * h + t]) - static_cast<double>(ct[t * k + c]);
+        double sq = delta * delta;
+        acc = acc + sq;
+      }
+      S.hd[s * k + c] = acc;
+      hout[s * k + c] = acc;
+    }
+  }
+  __syncthreads();
+  // ---- sort both halves by (distance, index) via ranks -----------------------
   for (int c = lane; c < k; c += kWave) {
-    double v1 = h1[c], v2 = h2[c];
+    double v1 = S.hd[c], v2 = S.hd[k + c];
     int r1 = 0, r2 = 0;
     for (int c2 = 0; c2 < k; ++c2) {
-      double u1 = h1[c2], u2 = h2[c2];
+      double u1 = S.hd[c2], u2 = S.hd[k + c2];
       r1 += (u1 < v1) || (u1 == v1 && c2 < c);
       r2 += (u2 < v2) || (u2 == v2 && c2 < c);
     }
@@ -181,26 +200,26 @@ __global__ void __launch_bounds__(64) k_select_cells(const double *__restrict__ 
   auto size_le = [&](unsigned long long bits) -> int {
     double th = from_dbits(bits);
     int tot = 0;
-    for (int i = lane; i < k; i += kWave) tot += P[i * (k + 1) + row_count_le(S, k, i, th)];
+    for (int i = lane; i < k; i += kWave) tot += P[i * (k + 1) + row_count_le(S.d1s, S.d2s, k, i, th)];
     return wave_sum_i32(tot);
   };
   auto count_le = [&](unsigned long long bits) -> int {
     double th = from_dbits(bits);
     int tot = 0;
-    for (int i = lane; i < k; i += kWave) tot += row_count_le(S, k, i, th);
+    for (int i = lane; i < k; i += kWave) tot += row_count_le(S.d1s, S.d2s, k, i, th);
     return wave_sum_i32(tot);
   };
 
   // ---- budget cutoff -------------------------------------------------------
   const unsigned long long top_bits = dbits(S.d1s[k - 1] + S.d2s[k - 1]);
-  unsigned long long lo = 0, hi = top_bits;
+  unsigned long long lo = dbits(S.d1s[0] + S.d2s[0]), hi = top_bits;
+  if (lo > 0) --lo;  // the smallest key itself may be the cutoff
   while (lo < hi) {
     unsigned long long mid = lo + ((hi - lo) >> 1);
     if (size_le(mid) >= budget) hi = mid; else lo = mid + 1;
   }
   const unsigned long long cstar = hi;
   const int s_lt = (cstar > 0) ? size_le(cstar - 1) : 0;
-  // Ties at cost == cstar, walked in (i, j) order.
   int istar = -1, jstar = -1;
   {
     int carry = 0;
@@ -208,8 +227,8 @@ __global__ void __launch_bounds__(64) k_select_cells(const double *__restrict__ 
       int i = r0 + lane;
       int tlo = 0, thi = 0, tsz = 0;
       if (i < k) {
-        thi = row_count_le(S, k, i, from_dbits(cstar));
-        tlo = (cstar > 0) ? row_count_le(S, k, i, from_dbits(cstar - 1)) : 0;
+        thi = row_count_le(S.d1s, S.d2s, k, i, from_dbits(cstar));
+        tlo = (cstar > 0) ? row_count_le(S.d1s, S.d2s, k, i, from_dbits(cstar - 1)) : 0;
         tsz = P[i * (k + 1) + thi] - P[i * (k + 1) + tlo];
       }
       int incl = wave_incl_scan_i32(tsz) + carry;
@@ -230,12 +249,11 @@ __global__ void __launch_bounds__(64) k_select_cells(const double *__restrict__ 
       carry = __shfl(incl, kWave - 1, kWave);
     }
   }
-  // Activated cells per row.
   for (int i = lane; i < k; i += kWave) {
     int n;
-    if (i < istar) n = row_count_le(S, k, i, from_dbits(cstar));
+    if (i < istar) n = row_count_le(S.d1s, S.d2s, k, i, from_dbits(cstar));
     else if (i == istar) n = jstar + 1;
-    else n = (cstar > 0) ? row_count_le(S, k, i, from_dbits(cstar - 1)) : 0;
+    else n = (cstar > 0) ? row_count_le(S.d1s, S.d2s, k, i, from_dbits(cstar - 1)) : 0;
     S.rowcnt[i] = n;
   }
   __syncthreads();
@@ -251,7 +269,8 @@ __global__ void __launch_bounds__(64) k_select_cells(const double *__restrict__ 
   if (phi == 1 && ksize >= total) {
     for (int i = lane; i < k; i += kWave) S.roww[i] = S.rowcnt[i];
   } else if (phi == 1) {
-    unsigned long long lo2 = 0, hi2 = top_bits;
+    unsigned long long lo2 = dbits(S.d1s[0] + S.d2s[0]), hi2 = top_bits;
+    if (lo2 > 0) --lo2;
     while (lo2 < hi2) {
       unsigned long long mid = lo2 + ((hi2 - lo2) >> 1);
       if (count_le(mid) >= ksize) hi2 = mid; else lo2 = mid + 1;
@@ -264,8 +283,8 @@ __global__ void __launch_bounds__(64) k_select_cells(const double *__restrict__ 
       int i = r0 + lane;
       int tlo = 0, thi = 0;
       if (i < k) {
-        thi = row_count_le(S, k, i, from_dbits(ck));
-        tlo = (ck > 0) ? row_count_le(S, k, i, from_dbits(ck - 1)) : 0;
+        thi = row_count_le(S.d1s, S.d2s, k, i, from_dbits(ck));
+        tlo = (ck > 0) ? row_count_le(S.d1s, S.d2s, k, i, from_dbits(ck - 1)) : 0;
       }
       int tc = thi - tlo;
       int incl = wave_incl_scan_i32(tc) + carry;
@@ -281,9 +300,9 @@ __global__ void __launch_bounds__(64) k_select_cells(const double *__restrict__ 
     }
     for (int i = lane; i < k; i += kWave) {
       int n;
-      if (i < ik) n = row_count_le(S, k, i, from_dbits(ck));
+      if (i < ik) n = row_count_le(S.d1s, S.d2s, k, i, from_dbits(ck));
       else if (i == ik) n = jk + 1;
-      else n = (ck > 0) ? row_count_le(S, k, i, from_dbits(ck - 1)) : 0;
+      else n = (ck > 0) ? row_count_le(S.d1s, S.d2s, k, i, from_dbits(ck - 1)) : 0;
       S.roww[i] = n;
     }
   } else {
@@ -313,18 +332,23 @@ __global__ void __launch_bounds__(64) k_select_cells(const double *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// A3/A4: collision counting in LDS.  One block per (id tile, query).
-// The tile's uint8 counters are packed four per dword and incremented with
-// ds_add_u32 of (w << 8 * (id & 3)); scores never exceed 2M <= 254.
-// Work items are (subspace, activated cell) pairs; each contributes the
-// slice of the cell's posting list that falls inside the tile (from the
-// load-time cell x tile table), flattened over the block by a prefix sum.
+// A3/A4: collision counting in LDS.  One 1024-thread block per (id tile,
+// query).  The tile's uint8 counters are packed four per dword and
+// incremented with ds_add_u32 of (w << 8 * (id & 3)); scores never exceed
+// 2M <= 254.  Work items are (subspace, activated cell) pairs; each
+// contributes the slice of the cell's posting list inside the tile (from the
+// load-time cell x tile table); waves take whole slices round robin and
+// stride them with four coalesced id loads in flight per lane.
+// Each of the 16 waves then scans its sixteenth of the counters (16 per lane
+// per step) and writes the ids reaching the threshold, in ascending order, to
+// its own segment; segment counts go to seg_cnt[q][tile][wave].
 //
-// pass 0: threshold tau, write the tile's candidates, histogram of scores >= tau
+// pass 0: threshold tau, write candidates, histogram of scores >= max(tau, 1)
 // pass 1: queries flagged for the fallback only: histogram of scores >= 1
 // pass 2: queries flagged only: threshold tau_eff, write candidates
 // ---------------------------------------------------------------------------
-constexpr int kCountThreads = 256;
+constexpr int kCountThreads = 1024;
+constexpr int kCountWaves = kCountThreads / kWave;
 constexpr int kItems = 1024;
 
 struct CountShared {
@@ -333,8 +357,7 @@ struct CountShared {
   unsigned char w[kItems];
   int mbase[129];
   int hist[256];
-  int tmp[kCountThreads / kWave + 1];
-  int wtot[kCountThreads / kWave + 1];
+  int tmp[kCountWaves + 1];
 };
 
 __global__ void __launch_bounds__(kCountThreads) k_count(
@@ -342,23 +365,30 @@ __global__ void __launch_bounds__(kCountThreads) k_count(
     const int32_t *__restrict__ offsets, const int32_t *__restrict__ ids, long long n,
     const int32_t *__restrict__ tile_off, int ntiles, int tile_ids, int pass, int tau,
     const int32_t *__restrict__ flag, const int32_t *__restrict__ tau_eff,
-    int32_t *__restrict__ seg_ids, uint8_t *__restrict__ seg_score, int32_t *__restrict__ tile_cnt,
+    int32_t *__restrict__ seg_ids, uint8_t *__restrict__ seg_score, int32_t *__restrict__ seg_cnt,
     int32_t *__restrict__ hist) {
-  extern __shared__ uint32_t cnt[];
+  extern __shared__ __align__(16) uint32_t cnt[];
   __shared__ CountShared S;
   const int tile = blockIdx.x, q = blockIdx.y, tid = threadIdx.x;
   if (pass != 0 && flag[q] == 0) return;
   const long long t0 = static_cast<long long>(tile) * tile_ids;
   const int tlen = static_cast<int>(min(static_cast<long long>(tile_ids), n - t0));
-  const int ndw = (tlen + 3) >> 2;
+  const int ndw = tile_ids >> 2;  // counters allocated for a full tile
   const int thr = (pass == 0) ? tau : (pass == 1 ? 1 : tau_eff[q]);
-  for (int i = tid; i < ndw; i += kCountThreads) cnt[i] = 0u;
+  uint4 *cnt4 = reinterpret_cast<uint4 *>(cnt);
+  for (int i = tid; i < (ndw >> 2); i += kCountThreads) cnt4[i] = make_uint4(0u, 0u, 0u, 0u);
   for (int i = tid; i < 256; i += kCountThreads) S.hist[i] = 0;
-  if (tid == 0) {
-    S.mbase[0] = 0;
-    for (int s = 0; s < m; ++s) S.mbase[s + 1] = S.mbase[s] + ncell[static_cast<long long>(q) * m + s];
+  {
+    // Per-subspace activated-cell counts -> prefix mbase[0..m] (m <= 127:
+    // waves 0 and 1 load and scan them in parallel).
+    const int v = (tid < m) ? ncell[static_cast<long long>(q) * m + tid] : 0;
+    const int incl = wave_incl_scan_i32(v);
+    if (tid == kWave - 1) S.tmp[0] = incl;
+    __syncthreads();
+    if (tid < 2 * kWave) S.mbase[tid + 1] = incl + (tid >= kWave ? S.tmp[0] : 0);
+    if (tid == 0) S.mbase[0] = 0;
+    __syncthreads();
   }
-  __syncthreads();
   const int total_items = S.mbase[m];
   for (int b0 = 0; b0 < total_items; b0 += kItems) {
     const int nb = min(kItems, total_items - b0);
@@ -382,81 +412,72 @@ __global__ void __launch_bounds__(kCountThreads) k_count(
       S.w[it] = static_cast<unsigned char>(w);
     }
     __syncthreads();
-    const int tot = block_exclusive_scan(S.pref, kItems, S.tmp);
-    if (tid == 0) S.pref[kItems] = tot;
-    __syncthreads();
-    for (int p = tid; p < tot; p += kCountThreads) {
-      int j = upper_bound_minus1(S.pref, kItems + 1, p);
-      int id = ids[S.start[j] + (p - S.pref[j])];
-      int loc = id - static_cast<int>(t0);
-      if (static_cast<unsigned>(loc) < static_cast<unsigned>(tlen))
-        atomicAdd(&cnt[loc >> 2], static_cast<uint32_t>(S.w[j]) << ((loc & 3) * 8));
+    // Waves take whole items (posting-list slices) round robin; each lane
+    // strides the slice with four coalesced loads in flight.
+    for (int it = wave_id(); it < nb; it += kCountWaves) {
+      const long long st = S.start[it];
+      const int len = S.pref[it];
+      const uint32_t wgt = S.w[it];
+      for (int p0 = lane_id(); p0 < len; p0 += 4 * kWave) {
+        int idv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int p = p0 + u * kWave;
+          idv[u] = ids[st + (p < len ? p : len - 1)];   // clamped: every load is issued
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int loc = idv[u] - static_cast<int>(t0);
+          if (p0 + u * kWave < len && static_cast<unsigned>(loc) < static_cast<unsigned>(tlen))
+            atomicAdd(&cnt[loc >> 2], wgt << ((loc & 3) * 8));
+        }
+      }
     }
     __syncthreads();
   }
 
-  // ---- scan: threshold, histogram, ordered compaction -----------------------
+  // ---- scan: threshold, histogram, ordered per-wave compaction --------------
   const int lane = lane_id(), wv = wave_id();
-  const int nw = kCountThreads / kWave;
-  const int per = ((ndw + nw - 1) / nw + kWave - 1) / kWave * kWave;
-  const int dw0 = wv * per, dw1 = min(ndw, dw0 + per);
+  const int per_wave = ndw / kCountWaves;            // dwords per wave (multiple of 4)
+  const int dw0 = wv * per_wave;
   const unsigned long long below = lanes_below_mask();
-  int wcount = 0;
-  for (int dw = dw0; dw < dw1; dw += kWave) {
-    int i = dw + lane;
+  int32_t *dst = seg_ids + static_cast<long long>(q) * n + t0 + static_cast<long long>(dw0) * 4;
+  uint8_t *dsc = seg_score + static_cast<long long>(q) * n + t0 + static_cast<long long>(dw0) * 4;
+  int run = 0;
+  for (int v0 = 0; v0 < per_wave; v0 += 4 * kWave) {
+    const int dwl = v0 + 4 * lane;                 // this lane's first dword within the wave range
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (dwl < per_wave) v = cnt4[(dw0 + dwl) >> 2];
+    const uint32_t words[4] = {v.x, v.y, v.z, v.w};
+    const int idbase = (dw0 + dwl) * 4;            // tile-local id of the first counter
     int c = 0;
-    if (i < dw1) {
-      uint32_t v = cnt[i];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        int sc = (v >> (8 * b)) & 255;
-        bool valid = (i * 4 + b) < tlen;
-        if (valid && sc >= thr) {
-          ++c;
-          if (pass != 2 && sc >= 1) atomicAdd(&S.hist[sc], 1);
-        }
-      }
+    for (int e = 0; e < 16; ++e) {
+      int sc = (words[e >> 2] >> (8 * (e & 3))) & 255;
+      bool sel = (dwl < per_wave) && (idbase + e < tlen) && sc >= thr;
+      c += sel ? 1 : 0;
+      if (sel && pass != 2 && sc >= 1) atomicAdd(&S.hist[sc], 1);
     }
-    wcount += wave_sum_i32(c);
-  }
-  if (lane == 0) S.wtot[wv] = wcount;
-  __syncthreads();
-  if (tid == 0) {
-    int run = 0;
-    for (int w = 0; w < nw; ++w) { int t = S.wtot[w]; S.wtot[w] = run; run += t; }
-    S.wtot[nw] = run;
-  }
-  __syncthreads();
-  if (pass != 1) {
-    int32_t *dst = seg_ids + static_cast<long long>(q) * n + t0;
-    uint8_t *dsc = seg_score + static_cast<long long>(q) * n + t0;
-    int run = S.wtot[wv];
-    for (int dw = dw0; dw < dw1; dw += kWave) {
-      int i = dw + lane;
-      uint32_t v = (i < dw1) ? cnt[i] : 0u;
-      int c = 0;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        int sc = (v >> (8 * b)) & 255;
-        c += (i < dw1 && (i * 4 + b) < tlen && sc >= thr) ? 1 : 0;
-      }
-      unsigned long long b0m = __ballot(c & 1), b1m = __ballot(c & 2), b2m = __ballot(c & 4);
-      int pre = __popcll(b0m & below) + 2 * __popcll(b1m & below) + 4 * __popcll(b2m & below);
-      int wt = __popcll(b0m) + 2 * __popcll(b1m) + 4 * __popcll(b2m);
+    if (pass != 1) {
+      unsigned long long b0m = __ballot(c & 1), b1m = __ballot(c & 2), b2m = __ballot(c & 4),
+                         b3m = __ballot(c & 8), b4m = __ballot(c & 16);
+      int pre = __popcll(b0m & below) + 2 * __popcll(b1m & below) + 4 * __popcll(b2m & below) +
+                8 * __popcll(b3m & below) + 16 * __popcll(b4m & below);
+      int wt = __popcll(b0m) + 2 * __popcll(b1m) + 4 * __popcll(b2m) + 8 * __popcll(b3m) + 16 * __popcll(b4m);
       int pos = run + pre;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        int sc = (v >> (8 * b)) & 255;
-        if (i < dw1 && (i * 4 + b) < tlen && sc >= thr) {
-          dst[pos] = static_cast<int32_t>(t0) + i * 4 + b;
+      for (int e = 0; e < 16; ++e) {
+        int sc = (words[e >> 2] >> (8 * (e & 3))) & 255;
+        if ((dwl < per_wave) && (idbase + e < tlen) && sc >= thr) {
+          dst[pos] = static_cast<int32_t>(t0) + idbase + e;
           dsc[pos] = static_cast<uint8_t>(sc);
           ++pos;
         }
       }
       run += wt;
     }
-    if (tid == 0) tile_cnt[static_cast<long long>(q) * ntiles + tile] = S.wtot[nw];
   }
+  if (pass != 1 && lane == 0) seg_cnt[(static_cast<long long>(q) * ntiles + tile) * kCountWaves + wv] = run;
   if (pass != 2) {
     __syncthreads();
     const int nb = 2 * m + 1;
@@ -465,26 +486,31 @@ __global__ void __launch_bounds__(kCountThreads) k_count(
   }
 }
 
-// Per query: |C| at tau; flag the fallback when fewer than k points reach it.
-__global__ void k_flag(const int32_t *__restrict__ tile_cnt, int ntiles, int nq, int k, int tau,
+// Per query (one wavefront): |C| at tau; flag the fallback when fewer than k
+// points reach it.
+__global__ void k_flag(const int32_t *__restrict__ seg_cnt, int nseg, int nq, int k, int tau,
                        int32_t *__restrict__ flag, int32_t *__restrict__ tau_eff, int32_t *__restrict__ hist,
                        int nbins) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.x * (blockDim.x / kWave) + wave_id();
   if (q >= nq) return;
+  const int lane = lane_id();
   int tot = 0;
-  for (int t = 0; t < ntiles; ++t) tot += tile_cnt[static_cast<long long>(q) * ntiles + t];
-  int f = (tot < k && tau > 1) ? 1 : 0;
-  flag[q] = f;
-  tau_eff[q] = tau;
+  for (int t = lane; t < nseg; t += kWave) tot += seg_cnt[static_cast<long long>(q) * nseg + t];
+  tot = wave_sum_i32(tot);
+  const int f = (tot < k && tau > 1) ? 1 : 0;
+  if (lane == 0) {
+    flag[q] = f;
+    tau_eff[q] = tau;
+  }
   if (f)
-    for (int s = 0; s < nbins; ++s) hist[static_cast<long long>(q) * nbins + s] = 0;
+    for (int s = lane; s < nbins; s += kWave) hist[static_cast<long long>(q) * nbins + s] = 0;
 }
 
 // Flagged queries: tau_eff = largest s <= tau with at least k points scoring
 // >= s, else 1; keep the histogram only from tau_eff up.
 __global__ void k_tau_eff(const int32_t *__restrict__ flag, int nq, int k, int tau, int nbins,
                           int32_t *__restrict__ hist, int32_t *__restrict__ tau_eff,
-                          int32_t *__restrict__ tile_cnt, int ntiles) {
+                          int32_t *__restrict__ seg_cnt, int nseg) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq || flag[q] == 0) return;
   int32_t *hq = hist + static_cast<long long>(q) * nbins;
@@ -497,40 +523,56 @@ __global__ void k_tau_eff(const int32_t *__restrict__ flag, int nq, int k, int t
   }
   tau_eff[q] = se;
   for (int s = 0; s < se; ++s) hq[s] = 0;
-  for (int t = 0; t < ntiles; ++t) tile_cnt[static_cast<long long>(q) * ntiles + t] = 0;
+  for (int t = 0; t < nseg; ++t) seg_cnt[static_cast<long long>(q) * nseg + t] = 0;
 }
 
-// Concatenate the per-tile candidate segments into one ascending list.
-__global__ void k_compact(const int32_t *__restrict__ seg_ids, const uint8_t *__restrict__ seg_score,
-                          const int32_t *__restrict__ tile_cnt, int ntiles, int tile_ids, long long n,
-                          int32_t *__restrict__ cand, uint8_t *__restrict__ score, int32_t *__restrict__ ncand) {
-  __shared__ int base[1025];
-  const int q = blockIdx.x;
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int t = 0; t < ntiles; ++t) { base[t] = run; run += tile_cnt[static_cast<long long>(q) * ntiles + t]; }
-    base[ntiles] = run;
-    ncand[q] = run;
-  }
-  __syncthreads();
+// Concatenate the per-(tile, wave) candidate segments into one ascending list.
+constexpr int kCompactThreads = 256;
+
+__global__ void __launch_bounds__(kCompactThreads) k_compact(
+    const int32_t *__restrict__ seg_ids, const uint8_t *__restrict__ seg_score, const int32_t *__restrict__ seg_cnt,
+    int nseg, int seg_len, long long n, int32_t *__restrict__ cand, uint8_t *__restrict__ score,
+    int32_t *__restrict__ ncand) {
+  __shared__ int base[kCompactThreads + 1];
+  __shared__ int tmp[kCompactThreads / kWave + 1];
+  __shared__ int carry;
+  const int q = blockIdx.x, tid = threadIdx.x;
   const long long qo = static_cast<long long>(q) * n;
-  for (int t = 0; t < ntiles; ++t) {
-    int c = base[t + 1] - base[t];
-    long long src = qo + static_cast<long long>(t) * tile_ids;
-    for (int i = threadIdx.x; i < c; i += blockDim.x) {
-      cand[qo + base[t] + i] = seg_ids[src + i];
-      score[qo + base[t] + i] = seg_score[src + i];
+  const int32_t *sc = seg_cnt + static_cast<long long>(q) * nseg;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (int s0 = 0; s0 < nseg; s0 += kCompactThreads) {
+    const int ns = min(kCompactThreads, nseg - s0);
+    base[tid] = (tid < ns) ? sc[s0 + tid] : 0;
+    __syncthreads();
+    const int tot = block_exclusive_scan(base, kCompactThreads, tmp);
+    // copy the ns segments: each wave takes segments round robin
+    for (int s = wave_id(); s < ns; s += kCompactThreads / kWave) {
+      const int c = (s + 1 < kCompactThreads ? base[s + 1] : tot) - base[s];
+      const long long src = qo + static_cast<long long>(s0 + s) * seg_len;
+      const long long dpos = qo + carry + base[s];
+      for (int i = lane_id(); i < c; i += kWave) {
+        cand[dpos + i] = seg_ids[src + i];
+        score[dpos + i] = seg_score[src + i];
+      }
     }
+    __syncthreads();
+    if (tid == 0) carry += tot;
+    __syncthreads();
   }
+  if (tid == 0) ncand[q] = carry;
 }
 
 // ---------------------------------------------------------------------------
 // A5: Hamming order.  One block per query.  The query's sign code is built by
-// ballots over q' (bit i%64 of word i/64 = [q'_i > 0]); each candidate's
-// distance is popcount(xor) over its code row; candidates (ascending id) are
-// placed by a stable counting sort on the distance, giving (hamming, id) order.
+// ballots over q' (bit i%64 of word i/64 = [q'_i > 0]).  Candidate code rows
+// are read by 8 lanes each (64 contiguous bytes per step) and popcount(xor)
+// reduced over those lanes; the candidates (ascending id)
+// are then placed by a stable counting sort on the distance, which gives
+// (hamming, id) order.
 // ---------------------------------------------------------------------------
 constexpr int kOrderThreads = 256;
+constexpr int kOrderWaves = kOrderThreads / kWave;
 
 __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
     const float *__restrict__ qrot, int d, const uint64_t *__restrict__ codes, const int32_t *__restrict__ ncand,
@@ -539,23 +581,72 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
   extern __shared__ int bins[];          // d + 1
   __shared__ uint64_t qc[128];
   __shared__ int chunk[kOrderThreads];
-  __shared__ int tmp[kOrderThreads / kWave + 1];
+  __shared__ int tmp[kOrderWaves + 1];
   const int q = blockIdx.x, tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   const int words = d / 64;
   const int nc = ncand[q];
   const long long qo = static_cast<long long>(q) * n;
-  for (int w = wv; w < words; w += kOrderThreads / kWave) {
+  for (int w = wv; w < words; w += kOrderWaves) {
     unsigned long long b = __ballot(qrot[static_cast<long long>(q) * d + w * 64 + lane] > 0.0f);
     if (lane == 0) qc[w] = b;
   }
   for (int i = tid; i <= d; i += kOrderThreads) bins[i] = 0;
   __syncthreads();
-  for (int i = tid; i < nc; i += kOrderThreads) {
-    const uint64_t *row = codes + static_cast<long long>(cand[qo + i]) * words;
-    int hsum = 0;
-    for (int w = 0; w < words; ++w) hsum += __popcll(qc[w] ^ row[w]);
-    hm_tmp[qo + i] = hsum;
-    atomicAdd(&bins[hsum], 1);
+  // L = min(8, words) lanes per code row (words is a power of two below 8);
+  // lane `sub` of a row reads words sub, sub + L, ... so the L lanes of a row
+  // read L consecutive words per step.  Candidate ids are staged in LDS 256 at
+  // a time; a wave covers 64 / L rows per step, two steps per round.
+  const int L = words >= 8 ? 8 : words;
+  const int rows_per = kWave / L;
+  const int sub = lane % L, rsel = lane / L;
+  const int steps = (words + L - 1) / L;
+  for (int b0 = 0; b0 < nc; b0 += kOrderThreads) {
+    const int nb = min(kOrderThreads, nc - b0);
+    chunk[tid] = cand[qo + b0 + (tid < nb ? tid : 0)];
+    __syncthreads();
+    for (int r = 0; r < kWave; r += 2 * rows_per) {
+      int v[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int loc = r + u * rows_per + rsel;
+        const int il = wv * kWave + loc;
+        const bool ok = loc < kWave && il < nb;
+        const uint64_t *row = codes + static_cast<long long>(chunk[ok ? il : 0]) * words;
+        int hs = 0;
+        int j = 0;
+        for (; j + 8 <= steps; j += 8) {
+          uint64_t cw[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int w = sub + (j + e) * L;
+            cw[e] = row[w < words ? w : 0];
+          }
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int w = sub + (j + e) * L;
+            hs += (w < words) ? __popcll(qc[w] ^ cw[e]) : 0;
+          }
+        }
+        for (; j < steps; ++j) {
+          const int w = sub + j * L;
+          const uint64_t c = row[w < words ? w : 0];
+          hs += (w < words) ? __popcll(qc[w] ^ c) : 0;
+        }
+        v[u] = hs;
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        int vv = v[u];
+        for (int s2 = L >> 1; s2 >= 1; s2 >>= 1) vv += __shfl_xor(vv, s2, kWave);
+        const int loc = r + u * rows_per + rsel;
+        const int il = wv * kWave + loc;
+        if (sub == 0 && loc < kWave && il < nb) {
+          hm_tmp[qo + b0 + il] = vv;
+          atomicAdd(&bins[vv], 1);
+        }
+      }
+    }
+    __syncthreads();
   }
   __syncthreads();
   block_exclusive_scan(bins, d + 1, tmp);
@@ -585,100 +676,58 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
 // ---------------------------------------------------------------------------
 // A6/A7: re-rank.  One block (4 waves) per query; q' staged in LDS.
 //
-// First pass per candidate: float32 squared distance, each lane summing D/64
-// terms with fmaf, then a 6-level butterfly.  Its distance to the float64 key
-// d_canon is at most eps * d_f + abs with eps = (D/64 + 16) 2^-24 (recursive
-// summation of non-negative terms: one rounding for the difference, the
-// D/64 + 6 additions on any term's path, and the float64 key's own error),
-// abs = 4 D 2^-149 for gradual underflow.  Whenever that band could change a
-// comparison, d_canon is recomputed exactly as defined.
+// Every verified row gets its exact float64 key d_canon, computed as defined
+// (4-element groups dealt round-robin to the 64 lanes, each lane summing its
+// groups in order, then a halving tree), one wavefront per row with up to 16
+// sixteen-byte loads in flight per lane.  The
+// extra float64 arithmetic is far below the row's HBM time on MI355X, and it
+// leaves no approximate comparison anywhere: Guaranteed Mode selects the
+// top-k of all candidate keys (radix select on the key bits, ties by id);
+// Optimized Mode walks the Hamming order chunk by chunk, computing a chunk's
+// keys in parallel and applying the patience rule to them in order.
 // ---------------------------------------------------------------------------
 constexpr int kRerankThreads = 256;
 constexpr int kRerankWaves = kRerankThreads / kWave;
 constexpr int kChunk = 256;
 
-struct Band {
-  double lo, hi;
-};
-
-__device__ __forceinline__ Band band_of(float df, int d) {
-  const double eps = (d / 64 + 16) * 5.9604644775390625e-08;  // 2^-24
-  const double absb = 4.0 * d * 1.401298464324817e-45;        // 2^-149
-  if (!(df <= 3.0e38f)) return Band{0.0, __longlong_as_double(0x7ff0000000000000LL)};
-  double v = static_cast<double>(df);
-  return Band{v - v * eps - absb, v + v * eps + absb};
-}
-
-// float32 distance of one row, whole wave; result in every lane.  Loads are
-// issued eight at a time before they are consumed so that several are in
-// flight per lane.
-__device__ __forceinline__ float row_dist_f32(const float *__restrict__ sq, const float *__restrict__ x, int d) {
-  const int lane = lane_id();
-  float acc = 0.0f;
-  if ((d & 255) == 0) {
-    const float4 *xr = reinterpret_cast<const float4 *>(x);
-    const float4 *qq = reinterpret_cast<const float4 *>(sq);
-    const int nv = d / 4;
-    for (int r0 = lane; r0 < nv; r0 += kWave * 8) {
-      float4 a[8];
+template <int B>
+__device__ __forceinline__ double canon_partial(const float4 *__restrict__ qq, const float4 *__restrict__ xr, int nv,
+                                                int lane) {
+  double p = 0.0;
+  for (int r0 = 0; r0 * kWave < nv; r0 += B) {
+    float4 xv[B];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        int r = r0 + u * kWave;
-        a[u] = (r < nv) ? xr[r] : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        int r = r0 + u * kWave;
-        if (r < nv) {
-          float4 b = qq[r];
-          float e0 = b.x - a[u].x, e1 = b.y - a[u].y, e2 = b.z - a[u].z, e3 = b.w - a[u].w;
-          acc = fmaf(e0, e0, acc);
-          acc = fmaf(e1, e1, acc);
-          acc = fmaf(e2, e2, acc);
-          acc = fmaf(e3, e3, acc);
-        }
-      }
+    for (int u = 0; u < B; ++u) {
+      const int g = (r0 + u) * kWave + lane;
+      xv[u] = xr[g < nv ? g : 0];              // clamped: every load is issued
     }
-  } else {
-    for (int e0 = lane; e0 < d; e0 += kWave * 8) {
-      float a[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        int e = e0 + u * kWave;
-        a[u] = (e < d) ? x[e] : 0.f;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        int e = e0 + u * kWave;
-        if (e < d) {
-          float t = sq[e] - a[u];
-          acc = fmaf(t, t, acc);
-        }
-      }
+    for (int u = 0; u < B; ++u) {
+      const int g = (r0 + u) * kWave + lane;
+      const bool ok = g < nv;
+      const float4 qv = qq[ok ? g : 0];
+      const double t0 = ok ? static_cast<double>(qv.x) - static_cast<double>(xv[u].x) : 0.0;
+      const double t1 = ok ? static_cast<double>(qv.y) - static_cast<double>(xv[u].y) : 0.0;
+      const double t2 = ok ? static_cast<double>(qv.z) - static_cast<double>(xv[u].z) : 0.0;
+      const double t3 = ok ? static_cast<double>(qv.w) - static_cast<double>(xv[u].w) : 0.0;
+      double s0 = t0 * t0; p = p + s0;
+      double s1 = t1 * t1; p = p + s1;
+      double s2 = t2 * t2; p = p + s2;
+      double s3 = t3 * t3; p = p + s3;
     }
   }
-  return wave_sum_f32(acc);
+  return p;
 }
 
-// d_canon of one row, whole wave; result in every lane.  Loads are batched
-// sixteen at a time; the float64 accumulation order is the definition's.
+// d_canon of one row, whole wave; result in every lane.  Lane l owns the
+// 4-element groups g = l, l + 64, ... (one 16-byte load each, all of a batch
+// issued before use); groups past the end contribute exact zeros.
 __device__ __forceinline__ double row_dist_canon(const float *__restrict__ sq, const float *__restrict__ x, int d) {
   const int lane = lane_id();
-  const int nr = d / kWave;
-  double p = 0.0;
-  for (int r0 = 0; r0 < nr; r0 += 16) {
-    float xv[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) xv[u] = (r0 + u < nr) ? x[(r0 + u) * kWave + lane] : 0.f;
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      if (r0 + u < nr) {
-        double t = static_cast<double>(sq[(r0 + u) * kWave + lane]) - static_cast<double>(xv[u]);
-        double s2 = t * t;
-        p = p + s2;
-      }
-    }
-  }
+  const int nv = d >> 2;
+  const float4 *qq = reinterpret_cast<const float4 *>(sq);
+  const float4 *xr = reinterpret_cast<const float4 *>(x);
+  double p = (nv <= 4 * kWave) ? canon_partial<4>(qq, xr, nv, lane) : canon_partial<16>(qq, xr, nv, lane);
 #pragma unroll
   for (int s = 32; s >= 1; s >>= 1) {
     double v = __shfl_down(p, s, kWave);
@@ -692,21 +741,25 @@ __device__ __forceinline__ bool key_less(double da, int ia, double db, int ib) {
 }
 
 struct RerankShared {
-  float df[kChunk];
+  double dk[kChunk];
+  int sid[kChunk];
+  int plist[kChunk];
   int hist[256];
   int misc[16];
-  unsigned int umisc[4];
+  unsigned long long umisc[2];
+  double bd;
+  int bid;
 };
 
 __global__ void __launch_bounds__(kRerankThreads) k_rerank(
     int mode, const float *__restrict__ qrot, int d, const float *__restrict__ base,
     const int32_t *__restrict__ ncand, const int32_t *__restrict__ list, long long n, int k, int patience,
-    const int32_t *__restrict__ limits, float *__restrict__ dws, int32_t *__restrict__ sidx,
-    double *__restrict__ sd, int64_t *__restrict__ out_ids, float *__restrict__ out_d,
-    int32_t *__restrict__ examined, int32_t *__restrict__ last_upd, int32_t *__restrict__ stopped) {
+    const int32_t *__restrict__ limits, double *__restrict__ dkey, int64_t *__restrict__ out_ids,
+    float *__restrict__ out_d, int32_t *__restrict__ examined, int32_t *__restrict__ last_upd,
+    int32_t *__restrict__ stopped) {
   extern __shared__ __align__(16) unsigned char dyn[];
-  float *sq = reinterpret_cast<float *>(dyn);                          // d floats
-  double *top_d = reinterpret_cast<double *>(dyn + static_cast<size_t>(d) * 4);   // k doubles
+  float *sq = reinterpret_cast<float *>(dyn);                                          // d floats
+  double *top_d = reinterpret_cast<double *>(dyn + static_cast<size_t>(d) * 4);        // k doubles
   int *top_i = reinterpret_cast<int *>(dyn + static_cast<size_t>(d) * 4 + static_cast<size_t>(k) * 8);
   __shared__ RerankShared S;
   const int q = blockIdx.x, tid = threadIdx.x, lane = lane_id(), wv = wave_id();
@@ -720,67 +773,81 @@ __global__ void __launch_bounds__(kRerankThreads) k_rerank(
   if (mode == 0) {
     // ---- Guaranteed: every candidate --------------------------------------
     for (int i = wv; i < nc; i += kRerankWaves) {
-      float df = row_dist_f32(sq, base + static_cast<long long>(list[qo + i]) * d, d);
-      if (lane == 0) dws[qo + i] = df;
+      double dc = row_dist_canon(sq, base + static_cast<long long>(list[qo + i]) * d, d);
+      if (lane == 0) dkey[qo + i] = dc;
     }
     __syncthreads();
-    // k-th smallest first-pass distance (radix select on the float bits).
-    double ucut = __longlong_as_double(0x7ff0000000000000LL);
+    // k-th smallest key value (radix select over the float64 bit pattern).
+    unsigned long long prefix = 0ull, mask = 0ull;
+    int kk = min(k, nc);
     if (nc > k) {
-      unsigned int prefix = 0u, mask = 0u;
-      int kk = k;
-      for (int shift = 24; shift >= 0; shift -= 8) {
+      for (int shift = 56; shift >= 0; shift -= 8) {
         for (int b = tid; b < 256; b += kRerankThreads) S.hist[b] = 0;
         __syncthreads();
         for (int i = tid; i < nc; i += kRerankThreads) {
-          unsigned int bits = __float_as_uint(dws[qo + i]);
+          unsigned long long bits = dbits(dkey[qo + i]);
           if ((bits & mask) == prefix) atomicAdd(&S.hist[(bits >> shift) & 255], 1);
         }
         __syncthreads();
         if (tid == 0) {
           int cum = 0, b = 0;
-          for (; b < 256; ++b) {
+          for (; b < 255; ++b) {
             if (cum + S.hist[b] >= kk) break;
             cum += S.hist[b];
           }
-          S.umisc[0] = prefix | (static_cast<unsigned int>(b) << shift);
+          S.umisc[0] = prefix | (static_cast<unsigned long long>(b) << shift);
           S.misc[0] = kk - cum;
         }
         __syncthreads();
         prefix = S.umisc[0];
         kk = S.misc[0];
-        mask |= 255u << shift;
+        mask |= 255ull << shift;
         __syncthreads();
       }
-      ucut = band_of(__uint_as_float(prefix), d).hi;
     }
-    // Survivors: lower band <= the k-th smallest upper band.
-    if (tid == 0) S.misc[1] = 0;
+    // Collect the keys below the k-th value, then the first kk ids equal to it
+    // (the list is ascending in id).  nc <= k: every candidate.
+    if (tid == 0) { S.misc[1] = 0; S.misc[2] = 0; }
     __syncthreads();
-    for (int i = tid; i < nc; i += kRerankThreads) {
-      if (band_of(dws[qo + i], d).lo <= ucut) {
+    const double vk = from_dbits(prefix);
+    const int need_eq = (nc > k) ? kk : 0;
+    for (int i0 = 0; i0 < nc; i0 += kRerankThreads) {
+      const int i = i0 + tid;
+      double di = (i < nc) ? dkey[qo + i] : 0.0;
+      bool lt = (i < nc) && (nc <= k || di < vk);
+      bool eq = (i < nc) && (nc > k) && (di == vk);
+      // order-preserving rank among equal keys in this block of 256
+      int eq_before = 0;
+      {
+        unsigned long long bm = __ballot(eq);
+        eq_before = __popcll(bm & lanes_below_mask());
+        if (lane == kWave - 1) S.hist[wv] = __popcll(bm);
+      }
+      __syncthreads();
+      int wbase = 0;
+      for (int w = 0; w < wv; ++w) wbase += S.hist[w];
+      int eq_total_block = 0;
+      for (int w = 0; w < kRerankWaves; ++w) eq_total_block += S.hist[w];
+      const int eq_seen = S.misc[2 + 0];
+      __syncthreads();
+      if (lt || (eq && eq_seen + wbase + eq_before < need_eq)) {
         int p = atomicAdd(&S.misc[1], 1);
-        sidx[qo + p] = i;
+        top_d[p] = di;
+        top_i[p] = list[qo + i];
       }
+      __syncthreads();
+      if (tid == 0) S.misc[2] = eq_seen + eq_total_block;
+      __syncthreads();
     }
-    __syncthreads();
     const int ns = S.misc[1];
-    for (int j = wv; j < ns; j += kRerankWaves) {
-      int id = list[qo + sidx[qo + j]];
-      double dc = row_dist_canon(sq, base + static_cast<long long>(id) * d, d);
-      if (lane == 0) sd[qo + j] = dc;
-    }
-    __syncthreads();
+    // Order the (<= k) selected keys by (d, id).
     for (int j = tid; j < ns; j += kRerankThreads) {
-      double dj = sd[qo + j];
-      int ij = list[qo + sidx[qo + j]];
+      double dj = top_d[j];
+      int ij = top_i[j];
       int rank = 0;
-      for (int t = 0; t < ns; ++t) {
-        double dt = sd[qo + t];
-        int it = list[qo + sidx[qo + t]];
-        rank += key_less(dt, it, dj, ij) ? 1 : 0;
-      }
-      if (rank < k) { oi[rank] = ij; od[rank] = static_cast<float>(dj); }
+      for (int t = 0; t < ns; ++t) rank += key_less(top_d[t], top_i[t], dj, ij) ? 1 : 0;
+      oi[rank] = ij;
+      od[rank] = static_cast<float>(dj);
     }
     for (int r = ns + tid; r < k; r += kRerankThreads) {
       oi[r] = -1;
@@ -802,68 +869,93 @@ __global__ void __launch_bounds__(kRerankThreads) k_rerank(
   }
   if (tid == 0) { S.misc[2] = 0; S.misc[3] = 0; S.misc[4] = 0; S.misc[5] = 0; S.misc[6] = 0; }
   __syncthreads();
-  int tn = 0, run = 0, last = 0, stop = 0, pos = 0;
   for (int c0 = 0; c0 < lim; c0 += kChunk) {
     const int cnt = min(kChunk, lim - c0);
+    // (a) exact keys of the chunk, in parallel
     for (int t = wv; t < cnt; t += kRerankWaves) {
-      float df = row_dist_f32(sq, base + static_cast<long long>(list[qo + c0 + t]) * d, d);
-      if (lane == 0) S.df[t] = df;
+      const int id = list[qo + c0 + t];
+      double dc = row_dist_canon(sq, base + static_cast<long long>(id) * d, d);
+      if (lane == 0) { S.dk[t] = dc; S.sid[t] = id; }
     }
     __syncthreads();
-    if (wv == 0) {
-      tn = S.misc[2]; run = S.misc[3]; last = S.misc[4];
-      pos = c0;
-      for (int t = 0; t < cnt; ++t) {
-        const int id = list[qo + c0 + t];
-        const Band bd = band_of(S.df[t], d);
-        bool upd;
-        bool have = false;
-        double dc = 0.0;
-        if (tn < k) {
-          upd = true;
-        } else {
-          const double kd = top_d[k - 1];
-          const int kid = top_i[k - 1];
-          if (bd.hi < kd) upd = true;
-          else if (bd.lo > kd) upd = false;
-          else {
-            dc = row_dist_canon(sq, base + static_cast<long long>(id) * d, d);
-            have = true;
-            upd = key_less(dc, id, kd, kid);
-          }
+    // (b) candidates that can update the top-k.  With a full top-k, only keys
+    // below its k-th key at the chunk start; while it fills, the first `free`
+    // candidates always update and later ones only below the k-th key of
+    // (top-k so far + those `free`), which bounds the k-th key from then on.
+    const int tn0 = S.misc[2];
+    const int free_slots = max(0, k - tn0);
+    if (tid == 0) {
+      if (tn0 >= k) {
+        S.bd = top_d[k - 1]; S.bid = top_i[k - 1];
+      } else if (cnt > free_slots) {
+        double bd = -1.0; int bid = -1;
+        for (int e = 0; e < tn0; ++e)
+          if (!key_less(top_d[e], top_i[e], bd, bid)) { bd = top_d[e]; bid = top_i[e]; }
+        for (int e = 0; e < free_slots; ++e)
+          if (!key_less(S.dk[e], S.sid[e], bd, bid)) { bd = S.dk[e]; bid = S.sid[e]; }
+        S.bd = bd; S.bid = bid;
+      }
+    }
+    __syncthreads();
+    {
+      const int t = tid;
+      const bool pot = t < cnt && (t < free_slots || key_less(S.dk[t], S.sid[t], S.bd, S.bid));
+      const unsigned long long bm = __ballot(pot);
+      if (lane == 0) S.hist[wv] = __popcll(bm);
+      __syncthreads();
+      int before = 0;
+      for (int w = 0; w < wv; ++w) before += S.hist[w];
+      if (pot) S.plist[before + __popcll(bm & lanes_below_mask())] = t;
+      if (tid == 0) {
+        int tot = 0;
+        for (int w = 0; w < kRerankWaves; ++w) tot += S.hist[w];
+        S.misc[7] = tot;
+      }
+    }
+    __syncthreads();
+    // (c) the patience rule in order over those candidates; every candidate
+    // between two of them is a non-update and only advances the run.
+    if (tid == 0) {
+      int tn = S.misc[2], run = S.misc[3], last = S.misc[4], stop = 0, pos = c0 + cnt, prev = -1;
+      const int np = S.misc[7];
+      for (int e = 0; e <= np; ++e) {
+        const int t = (e < np) ? S.plist[e] : cnt;
+        const int gap = t - prev - 1;
+        if (gap > 0 && run + gap >= patience) {
+          pos = c0 + prev + 1 + (patience - run);
+          stop = 1;
+          break;
         }
-        pos = c0 + t + 1;
-        if (upd) {
-          if (!have) dc = row_dist_canon(sq, base + static_cast<long long>(id) * d, d);
-          if (lane == 0) {
-            int p = (tn < k) ? tn : k - 1;
-            while (p > 0 && key_less(dc, id, top_d[p - 1], top_i[p - 1])) {
-              top_d[p] = top_d[p - 1];
-              top_i[p] = top_i[p - 1];
-              --p;
-            }
-            top_d[p] = dc;
-            top_i[p] = id;
+        run += gap;
+        if (e == np) break;
+        const int id = S.sid[t];
+        const double dc = S.dk[t];
+        if (tn < k || key_less(dc, id, top_d[k - 1], top_i[k - 1])) {
+          int p = (tn < k) ? tn : k - 1;
+          while (p > 0 && key_less(dc, id, top_d[p - 1], top_i[p - 1])) {
+            top_d[p] = top_d[p - 1];
+            top_i[p] = top_i[p - 1];
+            --p;
           }
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+          top_d[p] = dc;
+          top_i[p] = id;
           if (tn < k) ++tn;
           run = 0;
-          last = pos;
-        } else {
-          ++run;
+          last = c0 + t + 1;
+        } else if (++run >= patience) {
+          pos = c0 + t + 1;
+          stop = 1;
+          break;
         }
-        if (run >= patience) { stop = 1; break; }
+        prev = t;
       }
-      if (lane == 0) {
-        S.misc[2] = tn; S.misc[3] = run; S.misc[4] = last; S.misc[5] = stop; S.misc[6] = pos;
-      }
+      S.misc[2] = tn; S.misc[3] = run; S.misc[4] = last; S.misc[5] = stop; S.misc[6] = pos;
     }
     __syncthreads();
     if (S.misc[5]) break;
   }
   __syncthreads();
-  tn = S.misc[2];
+  const int tn = S.misc[2];
   for (int r = tid; r < k; r += kRerankThreads) {
     if (r < tn) { oi[r] = top_i[r]; od[r] = static_cast<float>(top_d[r]); }
     else { oi[r] = -1; od[r] = __int_as_float(0x7f800000); }
@@ -873,6 +965,18 @@ __global__ void __launch_bounds__(kRerankThreads) k_rerank(
     last_upd[q] = S.misc[4];
     stopped[q] = S.misc[5];
   }
+}
+
+// Transposed half-codebooks for the scoring wavefronts: [M][2][K][h] -> [M][2][h][K].
+__global__ void k_transpose_centroids(const float *__restrict__ cent, int m, int k, int h, float *__restrict__ cent_t) {
+  long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  long long total = static_cast<long long>(m) * 2 * k * h;
+  if (t >= total) return;
+  int i = static_cast<int>(t % h);
+  long long r = t / h;
+  int c = static_cast<int>(r % k);
+  long long ms = r / k;
+  cent_t[(ms * h + i) * k + c] = cent[t];
 }
 
 // ---------------------------------------------------------------------------

@@ -106,14 +106,18 @@ def test_hamming_against_sign_comparison():
     assert np.array_equal(got, ref)
 
 
-def test_canonical_sqdist_exact_bound():
-    rng = np.random.default_rng(10)
-    q = rng.standard_normal(128).astype(np.float32)
-    x = rng.standard_normal((5, 128)).astype(np.float32)
+@pytest.mark.parametrize("d", [64, 192, 512])
+def test_canonical_sqdist_exact_bound(d):
+    """The distance key is within the float64 summation bound of the exact
+    rational value (lane sums of at most 4 ceil(d/256) terms + a 6-level tree)."""
+    rng = np.random.default_rng(10 + d)
+    q = rng.standard_normal(d).astype(np.float32)
+    x = rng.standard_normal((5, d)).astype(np.float32)
     got = query.canonical_sqdist(q, x)
+    depth = 4 * ((d + 255) // 256) + 6 + 2
     for i in range(5):
-        ex = sum((Fraction(float(q[t])) - Fraction(float(x[i, t]))) ** 2 for t in range(128))
-        assert abs(Fraction(got[i]) - ex) <= Fraction(2 * 10) * Fraction(2.0 ** -53) * ex
+        ex = sum((Fraction(float(q[t])) - Fraction(float(x[i, t]))) ** 2 for t in range(d))
+        assert abs(Fraction(got[i]) - ex) <= Fraction(depth) * Fraction(2.0 ** -53) * ex
     assert np.allclose(got, ((q[None].astype(np.float64) - x) ** 2).sum(1), rtol=1e-14)
 
 
