@@ -44,7 +44,7 @@ crisp_status fail(crisp_status s, const char *fmt, ...) {
   } while (0)
 
 constexpr int kDefaultTile = 65536;
-constexpr int kDefaultChunk = 1024;
+constexpr int kDefaultChunk = 2048;
 
 inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 

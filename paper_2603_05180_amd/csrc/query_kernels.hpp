@@ -16,57 +16,88 @@
 namespace crisp {
 
 // ---------------------------------------------------------------------------
-// A0: rotation.  64x64 output tile per 256-thread block, 4x4 per thread,
-// k staged through LDS 16 at a time.  Every output accumulates its D
-// products in ascending k in float64 (products of two float32 are exact in
-// float64, so the fused form equals the unfused definition).
+// A0: rotation.  128x64 output tile per 256-thread block, 8x4 outputs per
+// thread; the k dimension is staged through LDS 16 at a time, converted to
+// float64 once on the way in, with the next slab prefetched into registers.
+// Every output accumulates its D products in ascending k in float64
+// (products of two float32 are exact in float64, so the fused form equals
+// the unfused definition).
 // ---------------------------------------------------------------------------
-constexpr int kRotBM = 64, kRotBN = 64, kRotBK = 16;
+constexpr int kRotBM = 128, kRotBN = 64, kRotBK = 16;
 
 __global__ void __launch_bounds__(256) k_rotate_rows(const float *__restrict__ x, long long rows, int d,
                                                      const float *__restrict__ r, float *__restrict__ out) {
-  __shared__ float sa[kRotBK][kRotBM + 1];
-  __shared__ float sb[kRotBK][kRotBN];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  // Rows padded by two doubles: the transposing stores of a wave then fall in
+  // distinct banks, and 16-byte reads stay aligned.
+  __shared__ __align__(16) double sa[kRotBK][kRotBM + 2];
+  __shared__ __align__(16) double sb[kRotBK][kRotBN + 2];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
   const long long row0 = static_cast<long long>(blockIdx.y) * kRotBM;
   const int col0 = blockIdx.x * kRotBN;
-  double acc[4][4];
+  double acc[8][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 8; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int k0 = 0; k0 < d; k0 += kRotBK) {
-    // A tile: 64 rows x 16 k; 1024 values, 4 per thread.
-    for (int e = threadIdx.x; e < kRotBM * kRotBK; e += 256) {
-      int rr = e / kRotBK, kk = e % kRotBK;
+  float ra[8], rb[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int idx = tid + e * 256;
+      const int rr = idx >> 4, kk = idx & 15;
       long long gr = row0 + rr;
-      sa[kk][rr] = (gr < rows) ? x[gr * d + k0 + kk] : 0.0f;
+      gr = gr < rows ? gr : rows - 1;            // clamped; such rows are never stored
+      ra[e] = x[gr * d + k0 + kk];
     }
-    for (int e = threadIdx.x; e < kRotBK * kRotBN; e += 256) {
-      int kk = e / kRotBN, cc = e % kRotBN;
-      sb[kk][cc] = r[static_cast<long long>(k0 + kk) * d + col0 + cc];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + e * 256;
+      const int kk = idx >> 6, cc = idx & 63;
+      rb[e] = r[static_cast<long long>(k0 + kk) * d + col0 + cc];
+    }
+  };
+  gload(0);
+  for (int k0 = 0; k0 < d; k0 += kRotBK) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int idx = tid + e * 256;
+      sa[idx & 15][idx >> 4] = static_cast<double>(ra[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + e * 256;
+      sb[idx >> 6][idx & 63] = static_cast<double>(rb[e]);
     }
     __syncthreads();
+    if (k0 + kRotBK < d) gload(k0 + kRotBK);
 #pragma unroll
     for (int kk = 0; kk < kRotBK; ++kk) {
-      double a[4], b[4];
+      double a[8], b[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = static_cast<double>(sa[kk][ty * 4 + i]);
+      for (int i = 0; i < 8; i += 2) {
+        const double2 v = *reinterpret_cast<const double2 *>(&sa[kk][ty * 8 + i]);
+        a[i] = v.x; a[i + 1] = v.y;
+      }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = static_cast<double>(sb[kk][tx * 4 + j]);
+      for (int j = 0; j < 4; j += 2) {
+        const double2 v = *reinterpret_cast<const double2 *>(&sb[kk][tx * 4 + j]);
+        b[j] = v.x; b[j + 1] = v.y;
+      }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 8; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    long long gr = row0 + ty * 4 + i;
+  for (int i = 0; i < 8; ++i) {
+    const long long gr = row0 + ty * 8 + i;
     if (gr < rows) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) out[gr * d + col0 + tx * 4 + j] = static_cast<float>(acc[i][j]);
+      float4 o = make_float4(static_cast<float>(acc[i][0]), static_cast<float>(acc[i][1]),
+                             static_cast<float>(acc[i][2]), static_cast<float>(acc[i][3]));
+      *reinterpret_cast<float4 *>(&out[gr * d + col0 + tx * 4]) = o;
     }
   }
 }
@@ -567,9 +598,8 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(
 // A5: Hamming order.  One block per query.  The query's sign code is built by
 // ballots over q' (bit i%64 of word i/64 = [q'_i > 0]).  Candidate code rows
 // are read by 8 lanes each (64 contiguous bytes per step) and popcount(xor)
-// reduced over those lanes; the candidates (ascending id)
-// are then placed by a stable counting sort on the distance, which gives
-// (hamming, id) order.
+// reduced over those lanes; a stable counting sort by distance (ballot
+// matching inside a wavefront) then gives the (hamming, id) order.
 // ---------------------------------------------------------------------------
 constexpr int kOrderThreads = 256;
 constexpr int kOrderWaves = kOrderThreads / kWave;
@@ -650,26 +680,42 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
   }
   __syncthreads();
   block_exclusive_scan(bins, d + 1, tmp);
-  for (int b0 = 0; b0 < nc; b0 += kOrderThreads) {
-    const int i = b0 + tid;
-    const int cnt = min(kOrderThreads, nc - b0);
-    const int hv = (i < nc) ? hm_tmp[qo + i] : -1;
-    chunk[tid] = hv;
-    __syncthreads();
-    int before = 0, after = 0;
-    for (int t = 0; t < cnt; ++t) {
-      int u = chunk[t];
-      before += (t < tid && u == hv);
-      after += (t > tid && u == hv);
+  // bins[h] = first position of distance h.  One wavefront places the
+  // candidates in ascending id order, 64 per step: a lane's rank among the
+  // step's lanes with the same distance comes from 14 ballots on the bits of
+  // h, the lowest such lane advances bins[h]; this is a stable counting sort.
+  if (wv == 0 && nc > 0) {
+    const unsigned long long below = lanes_below_mask();
+    for (int b0 = 0; b0 < nc; b0 += 4 * kWave) {
+      int hv[4], idv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = b0 + u * kWave + lane;
+        const int ic = i < nc ? i : nc - 1;       // clamped: every load is issued
+        hv[u] = hm_tmp[qo + ic];
+        idv[u] = cand[qo + ic];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool valid = b0 + u * kWave + lane < nc;
+        const int h = hv[u];
+        unsigned long long same = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 14; ++bit) {
+          const bool on = (h >> bit) & 1;
+          const unsigned long long bb = __ballot(on);
+          same &= on ? bb : ~bb;
+        }
+        if (valid) {
+          const int pos = bins[h] + __popcll(same & below);
+          order[qo + pos] = idv[u];
+          ham_sorted[qo + pos] = h;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (valid && (same & below) == 0) bins[h] += __popcll(same);
+        __builtin_amdgcn_wave_barrier();
+      }
     }
-    if (i < nc) {
-      int pos = bins[hv] + before;
-      order[qo + pos] = cand[qo + i];
-      ham_sorted[qo + pos] = hv;
-    }
-    __syncthreads();
-    if (i < nc && after == 0) bins[hv] += before + 1;
-    __syncthreads();
   }
 }
 
