@@ -18,4 +18,4 @@ brute   -- exact k-nearest-neighbour ground truth
 theory  -- the Guaranteed-Mode recall lower bound (Theorem 1)
 mlp     -- reference forward/backward/Adam for the learned candidate budget
 """
-from . import build, query, brute, theory  # noqa: F401
+from . import build, query, brute, theory, mlp  # noqa: F401
