@@ -131,6 +131,10 @@ crisp_status crisp_index_free(crisp_index *index);
  *                      budget); values < 1 mean "no cap".  NULL = none.
  *   max_chunk       -- queries processed per internal chunk (0 = default);
  *                      the workspace scales with it.
+ *   budget_source   -- 0: patience rule only; 1: Optimized Mode also stops
+ *                      at the prefix predicted by the model set with
+ *                      crisp_set_budget_model (explicit `limits` take
+ *                      precedence).
  */
 typedef struct {
   int32_t mode;
@@ -139,6 +143,7 @@ typedef struct {
   int32_t patience_factor;
   const int32_t *limits;
   int32_t max_chunk;
+  int32_t budget_source;
 } crisp_search_params;
 
 /*
@@ -159,6 +164,8 @@ typedef struct {
  *   examined    int32  [nq]            candidates verified
  *   last_update int32  [nq]            1-based position of the last top-k update
  *   stopped     int32  [nq]            1 if the patience rule ended the walk
+ *   features    float32 [nq][F]        learned-budget features (mode 1), F = 17 + 3M + 13
+ *   limits      int32  [nq]            predicted verification limits (budget_source 1)
  */
 typedef struct {
   float *q_rot;
@@ -176,6 +183,8 @@ typedef struct {
   int32_t *examined;
   int32_t *last_update;
   int32_t *stopped;
+  float *features;
+  int32_t *limits;
 } crisp_taps;
 
 /* Bytes of workspace crisp_search needs for this index, batch and parameters. */
@@ -259,13 +268,55 @@ crisp_status crisp_build_combine(const int32_t *left, const int32_t *right, int6
 crisp_status crisp_build_codes(const float *x, int64_t n, int32_t d, uint64_t *codes,
                                void *hip_stream);
 
+/* ---- Learned verification budget (Optimized Mode) ----------------------- */
+
+/*
+ * An addition on top of the patience rule of Section 4.3.2 (Stage 3): a
+ * 2-layer MLP (64 hidden units, ReLU) predicts y = log(L*), L* being the
+ * 1-based position of the last top-k update of the plain walk, from F =
+ * 17 + 3M + 13 per-query features (log1p |C|; log1p of the counts at the 16
+ * highest score levels; per subspace (c2-c1)/c1, (c_cut-c1)/c1 and log1p of
+ * the cheapest cell's size; Hamming distances at positions 1, 2, 4, ...,
+ * 2048 (clamped to |C|) and at the median position, over D).  The walk stops at min(patience stop, clamp(ceil(exp(y + delta)),
+ * k, |C|)).  Inference rounds the standardised features and W1 to bfloat16
+ * and runs on MFMA with float32 accumulation.
+ *
+ * Parameters: one float32 array of crisp_mlp_param_count(F) values laid out
+ * w1 [F][64] | b1 [64] | w2 [64] | b2 [1].
+ */
+int32_t crisp_feature_count(int32_t m);
+int32_t crisp_mlp_param_count(int32_t f);
+
+/*
+ * Uses `params`, `feat_mean`, `feat_std` (device float32, borrowed until
+ * replaced or cleared) for searches with budget_source = 1; features are
+ * standardised as (f - mean) / std.  params == NULL clears the model.
+ */
+crisp_status crisp_set_budget_model(crisp_index *index, const float *params, int32_t f, const float *feat_mean,
+                                    const float *feat_std, double delta);
+
+/*
+ * Training kernels (float32, device pointers).  x [b][f] standardised
+ * features, t [b] targets; pre [b][64] pre-activations and y [b] outputs of
+ * the forward pass; grad has the parameter layout (mean squared error,
+ * sums over the batch in sample order); Adam with beta1 0.9, beta2 0.999,
+ * eps 1e-8, step >= 1, moments m1, m2 zero-initialised by the caller.
+ */
+crisp_status crisp_mlp_forward(const float *x, int64_t b, int32_t f, const float *params, float *pre, float *y,
+                               void *hip_stream);
+crisp_status crisp_mlp_backward(const float *x, const float *t, int64_t b, int32_t f, const float *params,
+                                const float *pre, const float *y, float *grad, void *hip_stream);
+crisp_status crisp_mlp_adam(float *params, const float *grad, float *m1, float *m2, int32_t f, int32_t step,
+                            float lr, void *hip_stream);
+
 /* ---- Stage timing ------------------------------------------------------ */
 
 /*
  * GPU time per query stage, measured with HIP events recorded on the search
- * stream around each stage's launches.  Stages: 0 rotation (A0), 1 half
- * distances (A1), 2 cell selection (A2), 3 collision counting, fallback and
- * candidate lists (A3/A4), 4 Hamming order (A5), 5 re-rank (A6/A7).
+ * stream around each stage's launches.  Stages: 0 rotation (A0), 1 unused,
+ * 2 half distances + cell selection (A1/A2), 3 collision counting, fallback
+ * and candidate lists (A3/A4), 4 Hamming order (A5), 5 re-rank (A6/A7),
+ * 6 learned-budget features and inference.
  */
 typedef struct {
   double ms[8];

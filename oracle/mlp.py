@@ -9,15 +9,17 @@ earlier of the patience stop and the predicted prefix.
 Label: L* = 1-based position of the last top-k update in the plain walk (the
 shortest prefix that reproduces the plain result).  Target y = log(L*).
 
-Features (float32, F = 1 + 16 + 3M + 3), from the query's own intermediates:
+Features (float32, F = 1 + 16 + 3M + 13), from the query's own intermediates:
   * log1p(|C|)
   * log1p of the number of points at each of the 16 highest score levels
     2M, 2M-1, ..., 2M-15 (only levels >= max(tau_eff, 1) are counted)
   * per subspace m: (c2 - c1) / c1, (c_cut - c1) / c1 and log1p(size of the
     cheapest cell), where c1, c2 are the two smallest cell costs and c_cut the
     cost of the last activated cell (c1 floored at 1e-30 in the divisions)
-  * the Hamming distances at positions 1, k and min(4k, |C|) of the Hamming
-    order, divided by D (0 when |C| = 0)
+  * the Hamming distances at positions 1, 2, 4, ..., 2048 (each clamped to
+    |C|) and at position ceil(|C| / 2) of the Hamming order, divided by D
+    (0 when |C| = 0): how sharply the sign codes separate the front of the
+    order from the bulk
 
 Network: y = w2 . relu(W1^T f + b1) + b2, 64 hidden units.  Training is plain
 mean squared error on log L* with Adam (Kingma & Ba); inference rounds f and
@@ -32,8 +34,11 @@ import numpy as np
 HIDDEN = 64
 
 
+HAMMING_POSITIONS = [1 << i for i in range(12)]
+
+
 def n_features(m: int) -> int:
-    return 1 + 16 + 3 * m + 3
+    return 1 + 16 + 3 * m + len(HAMMING_POSITIONS) + 1
 
 
 def subspace_stats(index: dict, hd: np.ndarray, activated: list) -> np.ndarray:
@@ -77,9 +82,9 @@ def features(index: dict, trace: dict, k: int) -> np.ndarray:
     base = 17 + 3 * m
     if hm is not None and hm.size > 0:
         n = hm.size
-        f[base] = hm[0] / d
-        f[base + 1] = hm[min(k, n) - 1] / d
-        f[base + 2] = hm[min(4 * k, n) - 1] / d
+        for j, pos in enumerate(HAMMING_POSITIONS):
+            f[base + j] = hm[min(pos, n) - 1] / d
+        f[base + len(HAMMING_POSITIONS)] = hm[(n + 1) // 2 - 1] / d
     return f.astype(np.float32)
 
 

@@ -33,17 +33,19 @@ class IndexDesc(ctypes.Structure):
 
 class SearchParams(ctypes.Structure):
     _fields_ = [("mode", c_int32), ("alpha", c_double), ("tau", c_int32),
-                ("patience_factor", c_int32), ("limits", c_void_p), ("max_chunk", c_int32)]
+                ("patience_factor", c_int32), ("limits", c_void_p), ("max_chunk", c_int32),
+                ("budget_source", c_int32)]
 
 
 class Profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 8), ("intervals", c_int64 * 8), ("dropped", c_int64)]
 
 
-STAGES = ["rotate", "half_dist", "select", "count", "hamming_order", "rerank"]
+STAGES = ["rotate", "unused", "select", "count", "hamming_order", "rerank", "budget"]
 
 TAP_FIELDS = ["q_rot", "half_dist", "n_cells", "cells", "retrieved", "hist", "tau_eff", "n_cand",
-              "cand", "cand_score", "order", "hamming", "examined", "last_update", "stopped"]
+              "cand", "cand_score", "order", "hamming", "examined", "last_update", "stopped", "features",
+              "limits"]
 
 
 class Taps(ctypes.Structure):
@@ -78,6 +80,14 @@ _SIGS = {
     "crisp_build_combine": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
     "crisp_build_codes": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
     "crisp_profile_begin": (c_int32, [c_void_p, c_int32]),
+    "crisp_feature_count": (c_int32, [c_int32]),
+    "crisp_mlp_param_count": (c_int32, [c_int32]),
+    "crisp_set_budget_model": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_double]),
+    "crisp_mlp_forward": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "crisp_mlp_backward": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                     c_void_p]),
+    "crisp_mlp_adam": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, ctypes.c_float,
+                                 c_void_p]),
     "crisp_profile_end": (c_int32, [c_void_p, ctypes.POINTER(Profile)]),
 }
 

@@ -12,6 +12,7 @@
 
 #include "build_kernels.hpp"
 #include "common.hpp"
+#include "learned_kernels.hpp"
 #include "query_kernels.hpp"
 
 using namespace crisp;
@@ -76,6 +77,10 @@ struct crisp_index {
   const uint64_t *codes;
   int32_t *tile_off;
   float *cent_t;  // [M][2][h][K]
+  // learned budget model (borrowed device pointers; null when unset)
+  const float *mlp_params = nullptr, *mlp_mean = nullptr, *mlp_std = nullptr;
+  int mlp_nf = 0;
+  double mlp_delta = 0.0;
   // stage timing (crisp_profile_begin / crisp_profile_end)
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;
@@ -109,7 +114,7 @@ struct StageTimer {
 // Workspace layout for one chunk of qc queries.
 struct Layout {
   size_t qrot, hdist, ptab, ncell, cells, retr, tilecnt, hist, flag, taueff, ncand, segids, segscore, cand,
-      score, regA, regB, regC, examined, lastupd, stopped, total;
+      score, regA, regB, regC, examined, lastupd, stopped, sstat, feat, lim, total;
 };
 
 static Layout make_layout(const crisp_index *ix, long long qc) {
@@ -138,6 +143,9 @@ static Layout make_layout(const crisp_index *ix, long long qc) {
   L.examined = take(qc * 4);
   L.lastupd = take(qc * 4);
   L.stopped = take(qc * 4);
+  L.sstat = take(qc * ix->m * 4 * 8);
+  L.feat = take(qc * n_features(ix->m) * 4);
+  L.lim = take(qc * 4);
   L.total = o;
   return L;
 }
@@ -232,6 +240,9 @@ static crisp_status check_params(const crisp_index *ix, int64_t nq, int32_t k, c
   if (p->mode == 1 && p->patience_factor < 1) return fail(CRISP_E_INVALID, "patience_factor must be >= 1");
   if (p->mode == 1 && !ix->codes) return fail(CRISP_E_UNSUPPORTED, "Optimized Mode needs sign codes");
   if (p->max_chunk < 0) return fail(CRISP_E_INVALID, "max_chunk must be >= 0");
+  if (p->budget_source != 0 && p->budget_source != 1) return fail(CRISP_E_INVALID, "budget_source must be 0 or 1");
+  if (p->budget_source == 1 && p->mode != 1) return fail(CRISP_E_INVALID, "the learned budget applies to Optimized Mode");
+  if (p->budget_source == 1 && !ix->mlp_params) return fail(CRISP_E_INVALID, "no budget model set");
   return CRISP_OK;
 }
 
@@ -283,6 +294,10 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
   int32_t *exam = reinterpret_cast<int32_t *>(ws + L.examined);
   int32_t *lastu = reinterpret_cast<int32_t *>(ws + L.lastupd);
   int32_t *stopd = reinterpret_cast<int32_t *>(ws + L.stopped);
+  double *sstat = reinterpret_cast<double *>(ws + L.sstat);
+  float *feat = reinterpret_cast<float *>(ws + L.feat);
+  int32_t *llim = reinterpret_cast<int32_t *>(ws + L.lim);
+  const int nf = n_features(ix->m);
 
   const int d = ix->d, m = ix->m, kh = ix->k, nb = 2 * m + 1;
   const long long n = ix->n;
@@ -313,7 +328,7 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
       dim3 g(m, cq);
       k_select_cells<<<g, 64, select_lds_bytes(kh, ix->h), st>>>(qrot, d, ix->cent_t, m, kh, ix->h, ix->off,
                                                                   budget, k, p->mode, hdist, ptab, ncell, cells,
-                                                                  retr);
+                                                                  retr, sstat);
       LAUNCH_TRY("k_select_cells");
       t2.stop();
     }
@@ -351,6 +366,19 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
       k_hamming_order<<<cq, kOrderThreads, order_lds, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, segids, regB);
       LAUNCH_TRY("k_hamming_order");
       t4.stop();
+      // learned budget: features, then bfloat16 MFMA inference -> limits
+      if (p->budget_source == 1 || (taps && taps->features)) {
+        StageTimer t6(ix, 6, st);
+        k_features<<<grid1(cq, 256), 256, 0, st>>>(cq, m, d, k, 1, ncand, hist, taueff, sstat, regB, n, feat);
+        LAUNCH_TRY("k_features");
+        if (p->budget_source == 1) {
+          k_mlp_limits<<<(cq + 15) / 16, 64, 0, st>>>(cq, nf, feat, ix->mlp_mean, ix->mlp_std, ix->mlp_params,
+                                                      ix->mlp_delta, k, ncand, llim, nullptr);
+          LAUNCH_TRY("k_mlp_limits");
+          if (!lim) lim = llim;
+        }
+        t6.stop();
+      }
       // A6 / A7
       StageTimer t5(ix, 5, st);
       k_rerank<<<cq, kRerankThreads, rerank_lds, st>>>(1, qrot, d, ix->base, ncand, segids, n, k, patience, lim,
@@ -383,8 +411,67 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
       if ((s = tap_copy(taps->examined ? taps->examined + q0 : nullptr, exam, size_t(cq) * 4, st))) return s;
       if ((s = tap_copy(taps->last_update ? taps->last_update + q0 : nullptr, lastu, size_t(cq) * 4, st))) return s;
       if ((s = tap_copy(taps->stopped ? taps->stopped + q0 : nullptr, stopd, size_t(cq) * 4, st))) return s;
+      if (p->mode == 1 && (s = tap_copy(taps->features ? taps->features + q0 * nf : nullptr, feat,
+                                        size_t(cq) * nf * 4, st))) return s;
+      if (p->budget_source == 1 && (s = tap_copy(taps->limits ? taps->limits + q0 : nullptr, llim,
+                                                 size_t(cq) * 4, st))) return s;
     }
   }
+  return CRISP_OK;
+}
+
+int32_t crisp_mlp_param_count(int32_t f) { return f > 0 ? mlp_param_count(f) : -1; }
+
+int32_t crisp_feature_count(int32_t m) { return m > 0 ? n_features(m) : -1; }
+
+crisp_status crisp_set_budget_model(crisp_index *ix, const float *params, int32_t f, const float *feat_mean,
+                                    const float *feat_std, double delta) {
+  if (!ix) return fail(CRISP_E_INVALID, "null index");
+  if (!params) {
+    ix->mlp_params = ix->mlp_mean = ix->mlp_std = nullptr;
+    ix->mlp_nf = 0;
+    return CRISP_OK;
+  }
+  if (f != n_features(ix->m)) return fail(CRISP_E_INVALID, "model has %d features, the index needs %d", f,
+                                          n_features(ix->m));
+  if (!feat_mean || !feat_std) return fail(CRISP_E_INVALID, "feature mean and std are required");
+  if (!std::isfinite(delta)) return fail(CRISP_E_INVALID, "delta must be finite");
+  ix->mlp_params = params; ix->mlp_mean = feat_mean; ix->mlp_std = feat_std; ix->mlp_nf = f; ix->mlp_delta = delta;
+  return CRISP_OK;
+}
+
+crisp_status crisp_mlp_forward(const float *x, int64_t b, int32_t f, const float *params, float *pre, float *y,
+                               void *hip_stream) {
+  if (!x || !params || !pre || !y) return fail(CRISP_E_INVALID, "null argument");
+  if (b < 1 || f < 1) return fail(CRISP_E_INVALID, "b and f must be positive");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  k_mlp_fwd<<<static_cast<unsigned>(b), kHidden, 0, st>>>(static_cast<int>(b), f, x, params, pre, y);
+  LAUNCH_TRY("k_mlp_fwd");
+  return CRISP_OK;
+}
+
+crisp_status crisp_mlp_backward(const float *x, const float *t, int64_t b, int32_t f, const float *params,
+                                const float *pre, const float *y, float *grad, void *hip_stream) {
+  if (!x || !t || !params || !pre || !y || !grad) return fail(CRISP_E_INVALID, "null argument");
+  if (b < 1 || f < 1) return fail(CRISP_E_INVALID, "b and f must be positive");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int np = mlp_param_count(f);
+  k_mlp_bwd<<<grid1(np, 128), 128, 0, st>>>(static_cast<int>(b), f, x, t, params, pre, y, grad);
+  LAUNCH_TRY("k_mlp_bwd");
+  return CRISP_OK;
+}
+
+crisp_status crisp_mlp_adam(float *params, const float *grad, float *m1, float *m2, int32_t f, int32_t step,
+                            float lr, void *hip_stream) {
+  if (!params || !grad || !m1 || !m2) return fail(CRISP_E_INVALID, "null argument");
+  if (f < 1 || step < 1 || !(lr > 0.f)) return fail(CRISP_E_INVALID, "f >= 1, step >= 1, lr > 0");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int np = mlp_param_count(f);
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = static_cast<float>(1.0 - std::pow(0.9, step));
+  const float c2 = static_cast<float>(1.0 - std::pow(0.999, step));
+  k_mlp_adam<<<grid1(np, 256), 256, 0, st>>>(np, params, grad, m1, m2, lr, b1, b2, 1e-8f, c1, c2);
+  LAUNCH_TRY("k_mlp_adam");
   return CRISP_OK;
 }
 

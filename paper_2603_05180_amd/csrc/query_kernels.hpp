@@ -166,7 +166,8 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
                                                      int phi, double *__restrict__ hdist_out,
                                                      int32_t *__restrict__ ptab_g, int32_t *__restrict__ ncell,
                                                      int32_t *__restrict__ cells_out,
-                                                     int32_t *__restrict__ retrieved) {
+                                                     int32_t *__restrict__ retrieved,
+                                                     double *__restrict__ sstat) {
   extern __shared__ __align__(16) unsigned char dyn[];
   SelectLds S;
   {
@@ -359,6 +360,19 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
   if (lane == 0) {
     ncell[static_cast<long long>(q) * m + sub] = total;
     retrieved[static_cast<long long>(q) * m + sub] = retr;
+    // statistics for the learned budget: two smallest cell costs, the
+    // cutoff cost, and the size of the cheapest cell
+    double *st = sstat + (static_cast<long long>(q) * m + sub) * 4;
+    const double c1 = S.d1s[0] + S.d2s[0];
+    double c2 = c1;
+    if (k > 1) {
+      const double a = S.d1s[0] + S.d2s[1], b = S.d1s[1] + S.d2s[0];
+      c2 = a < b ? a : b;
+    }
+    st[0] = c1;
+    st[1] = c2;
+    st[2] = from_dbits(cstar);
+    st[3] = static_cast<double>(P[1]);
   }
 }
 

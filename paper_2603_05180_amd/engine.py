@@ -103,8 +103,20 @@ class Index:
         return {name: {"ms": pr.ms[i], "intervals": pr.intervals[i]} for i, name in enumerate(_lib.STAGES)} | \
             {"dropped": pr.dropped}
 
-    def params(self, *, mode=0, alpha=0.01, tau=1, patience_factor=40, limits=None, max_chunk=0):
-        return SearchParams(int(mode), float(alpha), int(tau), int(patience_factor), _ptr(limits), int(max_chunk))
+    def params(self, *, mode=0, alpha=0.01, tau=1, patience_factor=40, limits=None, max_chunk=0, budget_source=0):
+        return SearchParams(int(mode), float(alpha), int(tau), int(patience_factor), _ptr(limits), int(max_chunk),
+                            int(budget_source))
+
+    @property
+    def n_features(self) -> int:
+        return int(lib.crisp_feature_count(self.m))
+
+    def set_budget_model(self, params: torch.Tensor | None, mean: torch.Tensor | None = None,
+                         std: torch.Tensor | None = None, delta: float = 0.0):
+        """Learned verification budget for budget_source=1 (tensors are kept alive here)."""
+        self._model = (params, mean, std)
+        check(lib.crisp_set_budget_model(self._h, _ptr(params), self.n_features, _ptr(mean), _ptr(std),
+                                         float(delta)))
 
     def workspace_bytes(self, nq: int, k: int, params: SearchParams) -> int:
         b = ctypes.c_size_t(0)
@@ -139,11 +151,13 @@ class Index:
         if mode == 1:
             t["order"] = torch.empty(nq, n, dtype=torch.int32, **z)
             t["hamming"] = torch.empty(nq, n, dtype=torch.int32, **z)
+            t["features"] = torch.empty(nq, self.n_features, dtype=torch.float32, **z)
+            t["limits"] = torch.empty(nq, dtype=torch.int32, **z)
         return t
 
     def search(self, queries: torch.Tensor, k: int, *, mode: int = 0, alpha: float = 0.01, tau: int = 1,
                patience_factor: int = 40, limits: torch.Tensor | None = None, max_chunk: int = 0,
-               taps: dict | None = None, out: tuple | None = None, stream=None):
+               budget_source: int = 0, taps: dict | None = None, out: tuple | None = None, stream=None):
         """Algorithm 1 for a batch; returns (ids int64 [nq, k], dists f32 [nq, k])."""
         if queries.device != self.device or queries.dtype != torch.float32 or not queries.is_contiguous():
             raise ValueError("queries must be a contiguous float32 tensor on the index device")
@@ -154,7 +168,7 @@ class Index:
             raise ValueError("limits must be an int32 device tensor with one entry per query")
         nq = int(queries.shape[0])
         p = self.params(mode=mode, alpha=alpha, tau=tau, patience_factor=patience_factor,
-                        limits=limits, max_chunk=max_chunk)
+                        limits=limits, max_chunk=max_chunk, budget_source=budget_source)
         ws = self.workspace(nq, k, p)
         if out is None:
             ids = torch.empty(nq, k, dtype=torch.int64, device=self.device)

@@ -71,4 +71,7 @@ def test_features_follow_their_definitions():
         d1, d2 = tr["half_dist"][0]
         costs = sorted(d1[i] + d2[j] for i in range(5) for j in range(5))
         assert f[17] == np.float32((costs[1] - costs[0]) / costs[0])
-        assert f[-3] == np.float32(tr["hamming"][0] / 64)
+        hm = tr["hamming"]
+        assert f[17 + 3 * 4] == np.float32(hm[0] / 64)
+        assert f[17 + 3 * 4 + 3] == np.float32(hm[min(8, hm.size) - 1] / 64)
+        assert f[-1] == np.float32(hm[(hm.size + 1) // 2 - 1] / 64)
