@@ -119,6 +119,20 @@ crisp_status crisp_index_load(const crisp_index_desc *desc, int32_t tile_ids, vo
 crisp_status crisp_index_free(crisp_index *index);
 
 /*
+ * Mixed-precision verification (Section 4.3.2, Stage 3 reads rows at full
+ * width; this halves the bytes of rows that cannot enter the result).
+ * crisp_index_bf16_bytes: bytes of the buffer crisp_index_enable_bf16 needs
+ * (2 N D for a bfloat16 copy of the rows, round to nearest even, then 4 N for
+ * a per-row float32 upper bound of ||x - bf16(x)||).
+ * crisp_index_enable_bf16: fills `buffer` (device, caller-owned, 16-byte
+ * aligned, kept alive while searches use precision 1) from the index rows on
+ * hip_stream and lets searches use precision = 1.  buffer == NULL disables it.
+ * The rows must be finite.
+ */
+crisp_status crisp_index_bf16_bytes(const crisp_index *index, size_t *bytes);
+crisp_status crisp_index_enable_bf16(crisp_index *index, void *buffer, size_t bytes, void *hip_stream);
+
+/*
  * Search parameters (Table 1; Section 4.3.2; Section 6 parameter ranges).
  *   mode            -- 0 Guaranteed (phi = 0), 1 Optimized (phi = 1).
  *   alpha           -- retrieval fraction per subspace, 0 < alpha <= 1:
@@ -135,6 +149,13 @@ crisp_status crisp_index_free(crisp_index *index);
  *                      at the prefix predicted by the model set with
  *                      crisp_set_budget_model (explicit `limits` take
  *                      precedence).
+ *   precision       -- 0: every verified row is read in float32.  1: every
+ *                      verified row is first read from the bfloat16 copy
+ *                      (crisp_index_enable_bf16) to bound its distance, and
+ *                      in float32 only where the bound cannot exclude it
+ *                      from the result.  Both give identical ids and
+ *                      distances (every deciding comparison uses the exact
+ *                      float64 key); 1 reads fewer bytes.
  */
 typedef struct {
   int32_t mode;
@@ -144,6 +165,7 @@ typedef struct {
   const int32_t *limits;
   int32_t max_chunk;
   int32_t budget_source;
+  int32_t precision;
 } crisp_search_params;
 
 /*
@@ -166,6 +188,8 @@ typedef struct {
  *   stopped     int32  [nq]            1 if the patience rule ended the walk
  *   features    float32 [nq][F]        learned-budget features (mode 1), F = 17 + 3M + 13
  *   limits      int32  [nq]            predicted verification limits (budget_source 1)
+ *   refined     int32  [nq]            verified rows read in float32 (precision 0:
+ *                                      every one; 1: those the bfloat16 bound kept)
  */
 typedef struct {
   float *q_rot;
@@ -185,6 +209,7 @@ typedef struct {
   int32_t *stopped;
   float *features;
   int32_t *limits;
+  int32_t *refined;
 } crisp_taps;
 
 /* Bytes of workspace crisp_search needs for this index, batch and parameters. */

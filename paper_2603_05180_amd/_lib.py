@@ -34,7 +34,7 @@ class IndexDesc(ctypes.Structure):
 class SearchParams(ctypes.Structure):
     _fields_ = [("mode", c_int32), ("alpha", c_double), ("tau", c_int32),
                 ("patience_factor", c_int32), ("limits", c_void_p), ("max_chunk", c_int32),
-                ("budget_source", c_int32)]
+                ("budget_source", c_int32), ("precision", c_int32)]
 
 
 class Profile(ctypes.Structure):
@@ -45,7 +45,7 @@ STAGES = ["rotate", "unused", "select", "count", "hamming_order", "rerank", "bud
 
 TAP_FIELDS = ["q_rot", "half_dist", "n_cells", "cells", "retrieved", "hist", "tau_eff", "n_cand",
               "cand", "cand_score", "order", "hamming", "examined", "last_update", "stopped", "features",
-              "limits"]
+              "limits", "refined"]
 
 
 class Taps(ctypes.Structure):
@@ -65,6 +65,8 @@ _SIGS = {
     "crisp_index_load": (c_int32, [ctypes.POINTER(IndexDesc), c_int32, c_void_p, c_size_t, c_void_p,
                                    ctypes.POINTER(c_void_p)]),
     "crisp_index_free": (c_int32, [c_void_p]),
+    "crisp_index_bf16_bytes": (c_int32, [c_void_p, ctypes.POINTER(c_size_t)]),
+    "crisp_index_enable_bf16": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
     "crisp_search_workspace_bytes": (c_int32, [c_void_p, c_int64, c_int32, ctypes.POINTER(SearchParams),
                                                ctypes.POINTER(c_size_t)]),
     "crisp_search": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, ctypes.POINTER(SearchParams), c_void_p,

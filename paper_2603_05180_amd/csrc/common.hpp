@@ -55,6 +55,13 @@ __device__ __forceinline__ unsigned long long lanes_below_mask() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// bfloat16 bits of a finite float32, round to nearest even.
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+
 // Bits of a non-negative double: monotone as an unsigned integer.
 __device__ __forceinline__ unsigned long long dbits(double x) {
   return static_cast<unsigned long long>(__double_as_longlong(x));

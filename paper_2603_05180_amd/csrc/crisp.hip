@@ -75,6 +75,8 @@ struct crisp_index {
   const float *rot, *cent, *base;
   const int32_t *off, *ids;
   const uint64_t *codes;
+  const uint16_t *base16 = nullptr;  // bfloat16 copy of the rows (crisp_index_enable_bf16)
+  const float *rerr = nullptr;       // per-row bound of the bfloat16 rounding error
   int32_t *tile_off;
   float *cent_t;  // [M][2][h][K]
   // learned budget model (borrowed device pointers; null when unset)
@@ -114,7 +116,7 @@ struct StageTimer {
 // Workspace layout for one chunk of qc queries.
 struct Layout {
   size_t qrot, hdist, ptab, ncell, cells, retr, tilecnt, hist, flag, taueff, ncand, segids, segscore, cand,
-      score, regA, regB, regC, examined, lastupd, stopped, sstat, feat, lim, total;
+      score, regA, regB, regC, examined, lastupd, stopped, refined, sstat, feat, lim, total;
 };
 
 static Layout make_layout(const crisp_index *ix, long long qc) {
@@ -143,6 +145,7 @@ static Layout make_layout(const crisp_index *ix, long long qc) {
   L.examined = take(qc * 4);
   L.lastupd = take(qc * 4);
   L.stopped = take(qc * 4);
+  L.refined = take(qc * 4);
   L.sstat = take(qc * ix->m * 4 * 8);
   L.feat = take(qc * n_features(ix->m) * 4);
   L.lim = take(qc * 4);
@@ -212,6 +215,12 @@ crisp_status crisp_index_load(const crisp_index_desc *desc, int32_t tile_ids, vo
   LAUNCH_TRY("k_transpose_centroids");
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_count), hipFuncAttributeMaxDynamicSharedMemorySize,
                               tile));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rerank<false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              static_cast<int>(rerank_lds(desc->d, 1024, false).total)));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rerank<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              static_cast<int>(rerank_lds(desc->d, 1024, true).total)));
   crisp_index *ix = new (std::nothrow) crisp_index{};
   if (!ix) return fail(CRISP_E_INVALID, "out of host memory");
   ix->n = desc->n; ix->d = desc->d; ix->m = desc->m; ix->k = desc->k_half;
@@ -220,6 +229,35 @@ crisp_status crisp_index_load(const crisp_index_desc *desc, int32_t tile_ids, vo
   ix->off = desc->offsets; ix->ids = desc->ids; ix->codes = desc->codes; ix->tile_off = tile_off;
   ix->cent_t = cent_t;
   *out = ix;
+  return CRISP_OK;
+}
+
+crisp_status crisp_index_bf16_bytes(const crisp_index *ix, size_t *bytes) {
+  if (!ix || !bytes) return fail(CRISP_E_INVALID, "null argument");
+  *bytes = align_up(static_cast<size_t>(ix->n) * ix->d * 2) + align_up(static_cast<size_t>(ix->n) * 4);
+  return CRISP_OK;
+}
+
+crisp_status crisp_index_enable_bf16(crisp_index *ix, void *buffer, size_t bytes, void *hip_stream) {
+  if (!ix) return fail(CRISP_E_INVALID, "null index");
+  if (!buffer) {
+    ix->base16 = nullptr;
+    ix->rerr = nullptr;
+    return CRISP_OK;
+  }
+  size_t need = 0;
+  crisp_status s = crisp_index_bf16_bytes(ix, &need);
+  if (s != CRISP_OK) return s;
+  if (bytes < need) return fail(CRISP_E_WORKSPACE, "bfloat16 buffer %zu < %zu bytes", bytes, need);
+  if (reinterpret_cast<uintptr_t>(buffer) % 16 != 0) return fail(CRISP_E_INVALID, "buffer must be 16-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  uint16_t *b16 = static_cast<uint16_t *>(buffer);
+  float *err = reinterpret_cast<float *>(static_cast<char *>(buffer) +
+                                         align_up(static_cast<size_t>(ix->n) * ix->d * 2));
+  k_base_bf16<<<grid1(ix->n, 256 / kWave), 256, 0, st>>>(ix->base, ix->n, ix->d, b16, err);
+  LAUNCH_TRY("k_base_bf16");
+  ix->base16 = b16;
+  ix->rerr = err;
   return CRISP_OK;
 }
 
@@ -243,6 +281,8 @@ static crisp_status check_params(const crisp_index *ix, int64_t nq, int32_t k, c
   if (p->budget_source != 0 && p->budget_source != 1) return fail(CRISP_E_INVALID, "budget_source must be 0 or 1");
   if (p->budget_source == 1 && p->mode != 1) return fail(CRISP_E_INVALID, "the learned budget applies to Optimized Mode");
   if (p->budget_source == 1 && !ix->mlp_params) return fail(CRISP_E_INVALID, "no budget model set");
+  if (p->precision != 0 && p->precision != 1) return fail(CRISP_E_INVALID, "precision must be 0 or 1");
+  if (p->precision == 1 && !ix->base16) return fail(CRISP_E_INVALID, "precision 1 needs crisp_index_enable_bf16");
   return CRISP_OK;
 }
 
@@ -294,6 +334,7 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
   int32_t *exam = reinterpret_cast<int32_t *>(ws + L.examined);
   int32_t *lastu = reinterpret_cast<int32_t *>(ws + L.lastupd);
   int32_t *stopd = reinterpret_cast<int32_t *>(ws + L.stopped);
+  int32_t *refd = reinterpret_cast<int32_t *>(ws + L.refined);
   double *sstat = reinterpret_cast<double *>(ws + L.sstat);
   float *feat = reinterpret_cast<float *>(ws + L.feat);
   int32_t *llim = reinterpret_cast<int32_t *>(ws + L.lim);
@@ -306,7 +347,12 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
   const size_t count_lds = static_cast<size_t>(ix->tile);
   const int nseg = ix->ntiles * kCountWaves;
   const size_t order_lds = static_cast<size_t>(d + 1) * 4;
-  const size_t rerank_lds = static_cast<size_t>(d) * 4 + static_cast<size_t>(k) * 12;
+  const bool bf16 = p->precision == 1;
+  const size_t rr_lds = rerank_lds(d, k, bf16).total;
+  // float32 error factor of the bfloat16 row distance: gamma_{L+10}, L = terms per lane
+  const double lterms = static_cast<double>((d / 8 + kWave - 1) / kWave * 8 + 10) * 5.9604644775390625e-08;
+  const double gam = lterms / (1.0 - lterms);
+  auto rerank_kernel = bf16 ? k_rerank<true> : k_rerank<false>;
 
   for (long long q0 = 0; q0 < nq; q0 += qc) {
     const int cq = static_cast<int>(std::min<long long>(qc, nq - q0));
@@ -381,14 +427,18 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
       }
       // A6 / A7
       StageTimer t5(ix, 5, st);
-      k_rerank<<<cq, kRerankThreads, rerank_lds, st>>>(1, qrot, d, ix->base, ncand, segids, n, k, patience, lim,
-                                                       regC, ids + q0 * k, dists + q0 * k, exam, lastu, stopd);
+      rerank_kernel<<<cq, kRerankThreads, rr_lds, st>>>(1, qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
+                                                        segids, n, k, patience, lim, regC, nullptr, nullptr,
+                                                        ids + q0 * k,
+                                                        dists + q0 * k, exam, lastu, stopd, refd);
       LAUNCH_TRY("k_rerank");
       t5.stop();
     } else {
       StageTimer t5(ix, 5, st);
-      k_rerank<<<cq, kRerankThreads, rerank_lds, st>>>(0, qrot, d, ix->base, ncand, cand, n, k, patience, lim,
-                                                       regC, ids + q0 * k, dists + q0 * k, exam, lastu, stopd);
+      rerank_kernel<<<cq, kRerankThreads, rr_lds, st>>>(0, qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
+                                                        cand, n, k, patience, lim, regC,
+                                                        reinterpret_cast<float *>(regA), regB, ids + q0 * k,
+                                                        dists + q0 * k, exam, lastu, stopd, refd);
       LAUNCH_TRY("k_rerank");
       t5.stop();
     }
@@ -411,6 +461,7 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
       if ((s = tap_copy(taps->examined ? taps->examined + q0 : nullptr, exam, size_t(cq) * 4, st))) return s;
       if ((s = tap_copy(taps->last_update ? taps->last_update + q0 : nullptr, lastu, size_t(cq) * 4, st))) return s;
       if ((s = tap_copy(taps->stopped ? taps->stopped + q0 : nullptr, stopd, size_t(cq) * 4, st))) return s;
+      if ((s = tap_copy(taps->refined ? taps->refined + q0 : nullptr, refd, size_t(cq) * 4, st))) return s;
       if (p->mode == 1 && (s = tap_copy(taps->features ? taps->features + q0 * nf : nullptr, feat,
                                         size_t(cq) * nf * 4, st))) return s;
       if (p->budget_source == 1 && (s = tap_copy(taps->limits ? taps->limits + q0 : nullptr, llim,

@@ -57,11 +57,7 @@ __global__ void k_features(int nq, int m, int d, int k, int have_ham, const int3
 typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ short bf16_rne(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return static_cast<short>(u >> 16);
-}
+__device__ __forceinline__ short bf16_rne(float x) { return static_cast<short>(bf16_bits(x)); }
 
 // Inference: one wavefront per 16 queries.  x_norm = (f - mean) / std in
 // float32, rounded to bfloat16 with W1; h = relu(x W1 + b1) on

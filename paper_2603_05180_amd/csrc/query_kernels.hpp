@@ -1,14 +1,15 @@
 // Query-path kernels of the CRISP engine (Algorithm 1, Sections 4.3.1-4.3.2).
 //
 //   k_rotate_rows   (A0) x' = x R, float64 ascending-i accumulation per output
-//   k_half_dist     (A1) Dist_1 / Dist_2 for every (query, subspace, half, centroid)
-//   k_select_cells  (A2) Multi-Sequence cell set + rank weights per (query, subspace)
+//   k_select_cells  (A1/A2) Dist_1 / Dist_2 of every half-centroid, then the
+//                   Multi-Sequence cell set + rank weights per (query, subspace)
 //   k_count         (A3/A4) LDS collision counters per (query, id tile),
 //                   threshold, ordered compaction, score histogram
 //   k_flag / k_tau_eff / k_compact (A4) fallback rule and candidate lists
 //   k_hamming_order (A5) Hamming distance + stable counting sort
-//   k_rerank        (A6/A7) float32 first pass with a proven band, float64
-//                   re-check where the band matters, top-k / patience walk
+//   k_rerank        (A6/A7) exact float64 keys, top-k / patience walk; the
+//                   bfloat16 variant first bounds every row from a bfloat16
+//                   copy and reads float32 rows only where the bound matters
 #pragma once
 
 #include "common.hpp"
@@ -636,11 +637,11 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
   }
   for (int i = tid; i <= d; i += kOrderThreads) bins[i] = 0;
   __syncthreads();
-  // L = min(8, words) lanes per code row (words is a power of two below 8);
-  // lane `sub` of a row reads words sub, sub + L, ... so the L lanes of a row
-  // read L consecutive words per step.  Candidate ids are staged in LDS 256 at
-  // a time; a wave covers 64 / L rows per step, two steps per round.
-  const int L = words >= 8 ? 8 : words;
+  // L = the largest power of two <= min(8, words) lanes per code row; lane
+  // `sub` of a row reads words sub, sub + L, ... so the L lanes of a row read
+  // L consecutive words per step.  Candidate ids are staged in LDS 256 at a
+  // time; a wave covers 64 / L rows per step, two steps per round.
+  const int L = words >= 8 ? 8 : words >= 4 ? 4 : words >= 2 ? 2 : 1;
   const int rows_per = kWave / L;
   const int sub = lane % L, rsel = lane / L;
   const int steps = (words + L - 1) / L;
@@ -811,16 +812,250 @@ struct RerankShared {
   int bid;
 };
 
+// ---------------------------------------------------------------------------
+// Mixed precision: a bfloat16 first pass whose every decision is certified.
+//
+// Row x has a bfloat16 copy x~ (round to nearest even) and a stored
+// e_x >= ||x - x~||.  The float32 value t of ||q' - x~||^2 (each lane sums
+// L <= ceil(D/512) * 8 fused squares in order, then a 6-level tree; every
+// term is >= 0) satisfies |t - ||q' - x~||^2| <= g ||q' - x~||^2 with
+// g = gamma_{L+10} = (L+10)u / (1 - (L+10)u), u = 2^-24.  The triangle
+// inequality then gives
+//     (sqrt(t (1 - g)) - e_x)_+^2  <=  ||q' - x||^2  <=  (sqrt(t (1 + 2g)) + e_x)^2.
+// d_canon is within a relative 2^-45 of ||q' - x||^2 for D <= 8192; both
+// bounds are widened by a relative 2^-36 (that, plus the float64 rounding of
+// the bound) and an absolute 2^-100 (float32 subnormals flushed to zero), so
+// lb <= d_canon <= ub holds for every row.  A row is read in float32 only if
+// its lower bound does not exclude it; all comparisons that decide a result
+// use d_canon, so the results equal the float32-only path bit for bit.
+// ---------------------------------------------------------------------------
+constexpr double kBoundRel = 1.0 / 68719476736.0;          // 2^-36
+constexpr double kBoundAbs = 7.888609052210118e-31;         // 2^-100
+
+// ||q' - x~||^2 in float32 for the bfloat16 row x16; whole wave, result in
+// every lane (an xor butterfly adds the same pair in both lanes).
+__device__ __forceinline__ float row_dist_bf16(const float *__restrict__ sq, const uint16_t *__restrict__ x16, int d) {
+  const int lane = lane_id();
+  const int nv = d >> 3;  // 16-byte groups of eight bfloat16
+  const uint4 *xr = reinterpret_cast<const uint4 *>(x16);
+  const float4 *qq = reinterpret_cast<const float4 *>(sq);
+  constexpr int B = 8;
+  float p = 0.f;
+  for (int r0 = 0; r0 * kWave < nv; r0 += B) {
+    uint4 xv[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int g = (r0 + u) * kWave + lane;
+      xv[u] = xr[g < nv ? g : 0];  // clamped: every load is issued
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int g = (r0 + u) * kWave + lane;
+      const bool ok = g < nv;
+      const int gg = ok ? g : 0;
+      const float4 qa = qq[2 * gg], qb = qq[2 * gg + 1];
+      const uint32_t w[4] = {xv[u].x, xv[u].y, xv[u].z, xv[u].w};
+      const float qs[8] = {qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, qb.z, qb.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float lo = __uint_as_float(w[e] << 16);
+        const float hi = __uint_as_float(w[e] & 0xFFFF0000u);
+        const float t0 = ok ? qs[2 * e] - lo : 0.f;
+        const float t1 = ok ? qs[2 * e + 1] - hi : 0.f;
+        p = fmaf(t0, t0, p);
+        p = fmaf(t1, t1, p);
+      }
+    }
+  }
+  return wave_sum_f32(p);
+}
+
+__device__ __forceinline__ void bf16_bounds(float t32, float ex, double g, double &lb, double &ub) {
+  const double t = static_cast<double>(t32);
+  const double e = static_cast<double>(ex);
+  const double slo = sqrt(fmax(0.0, t * (1.0 - g))) - e;
+  lb = (slo > 0.0 ? slo * slo : 0.0) * (1.0 - kBoundRel) - kBoundAbs;
+  const double shi = sqrt(t * (1.0 + 2.0 * g)) + e;
+  ub = shi * shi * (1.0 + kBoundRel) + kBoundAbs;
+}
+
+// Max-heap of doubles (the k smallest values seen; top = the k-th smallest).
+__device__ inline void heap_push(double *h, int &n, double v) {
+  int i = n++;
+  while (i > 0) {
+    const int p = (i - 1) >> 1;
+    if (h[p] >= v) break;
+    h[i] = h[p];
+    i = p;
+  }
+  h[i] = v;
+}
+__device__ inline void heap_replace_top(double *h, int n, double v) {
+  int i = 0;
+  for (;;) {
+    int c = 2 * i + 1;
+    if (c >= n) break;
+    if (c + 1 < n && h[c + 1] > h[c]) ++c;
+    if (h[c] <= v) break;
+    h[i] = h[c];
+    i = c;
+  }
+  h[i] = v;
+}
+
+// One wavefront per row: bfloat16 copy and an upper bound of ||x - x~||
+// (float64 sum of exact squared differences, widened, rounded up to float).
+__global__ void __launch_bounds__(256) k_base_bf16(const float *__restrict__ base, long long n, int d,
+                                                    uint16_t *__restrict__ b16, float *__restrict__ err) {
+  const long long row = static_cast<long long>(blockIdx.x) * (256 / kWave) + wave_id();
+  if (row >= n) return;
+  const int lane = lane_id();
+  const float *x = base + row * d;
+  uint16_t *y = b16 + row * d;
+  double s = 0.0;
+  for (int i = lane; i < d; i += kWave) {
+    const float v = x[i];
+    const uint16_t b = bf16_bits(v);
+    y[i] = b;
+    const double diff = static_cast<double>(v) - static_cast<double>(__uint_as_float(static_cast<uint32_t>(b) << 16));
+    s = s + diff * diff;
+  }
+#pragma unroll
+  for (int sh = 32; sh >= 1; sh >>= 1) s = s + __shfl_xor(s, sh, kWave);
+  if (lane == 0) {
+    const double e = sqrt(s) * (1.0 + kBoundRel);
+    float f = static_cast<float>(e);
+    if (static_cast<double>(f) < e) f = nextafterf(f, __int_as_float(0x7f800000));
+    err[row] = f;
+  }
+}
+
+// Dynamic LDS of k_rerank: q' (D floats) | top-k keys (k doubles) | top-k ids
+// (k ints) | [bfloat16 pass] heap (k doubles), lower / upper bounds and
+// certification flags of a chunk.
+struct RerankLds {
+  size_t top_d, top_i, heap, lb, ub, pc, total;
+};
+__host__ __device__ inline RerankLds rerank_lds(int d, int k, bool bf16) {
+  RerankLds L{};
+  size_t o = static_cast<size_t>(d) * 4;
+  L.top_d = o; o += static_cast<size_t>(k) * 8;
+  L.top_i = o; o += static_cast<size_t>(k) * 4;
+  o = (o + 15) & ~static_cast<size_t>(15);
+  if (bf16) {
+    L.heap = o; o += static_cast<size_t>(k) * 8;
+    L.lb = o; o += kChunk * 8;
+    L.ub = o; o += kChunk * 8;
+    L.pc = o; o += kChunk * 4;
+  }
+  L.total = o;
+  return L;
+}
+
+// kk-th smallest (1-based, kk <= n) of n non-negative doubles: radix select
+// over the bit pattern, 8 bits per round.  Whole block.  Returns the value
+// and, in *need_eq, how many entries equal to it are among the kk smallest.
+__device__ inline double radix_kth(const double *__restrict__ keys, int n, int kk, RerankShared &S, int *need_eq) {
+  const int tid = threadIdx.x;
+  unsigned long long prefix = 0ull, mask = 0ull;
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    for (int b = tid; b < 256; b += kRerankThreads) S.hist[b] = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += kRerankThreads) {
+      const unsigned long long bits = dbits(keys[i]);
+      if ((bits & mask) == prefix) atomicAdd(&S.hist[(bits >> shift) & 255], 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int cum = 0, b = 0;
+      for (; b < 255; ++b) {
+        if (cum + S.hist[b] >= kk) break;
+        cum += S.hist[b];
+      }
+      S.umisc[0] = prefix | (static_cast<unsigned long long>(b) << shift);
+      S.misc[0] = kk - cum;
+    }
+    __syncthreads();
+    prefix = S.umisc[0];
+    kk = S.misc[0];
+    mask |= 255ull << shift;
+    __syncthreads();
+  }
+  *need_eq = kk;
+  return from_dbits(prefix);
+}
+
+// Top-k by (key, id) of n keys whose ids are ascending in list order; writes
+// the k results (padded with id -1 / +inf).  Whole block.
+__device__ inline void select_topk(const double *__restrict__ keys, const int32_t *__restrict__ kid, int n, int k,
+                                   RerankShared &S, double *top_d, int *top_i, int64_t *__restrict__ oi,
+                                   float *__restrict__ od) {
+  const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
+  double vk = 0.0;
+  int need_eq = 0;
+  if (n > k) vk = radix_kth(keys, n, k, S, &need_eq);
+  // Keys below the k-th value, then the first need_eq ids equal to it.
+  if (tid == 0) { S.misc[1] = 0; S.misc[2] = 0; }
+  __syncthreads();
+  for (int i0 = 0; i0 < n; i0 += kRerankThreads) {
+    const int i = i0 + tid;
+    const double di = (i < n) ? keys[i] : 0.0;
+    const bool lt = (i < n) && (n <= k || di < vk);
+    const bool eq = (i < n) && (n > k) && (di == vk);
+    const unsigned long long bm = __ballot(eq);
+    const int eq_before = __popcll(bm & lanes_below_mask());
+    if (lane == kWave - 1) S.hist[wv] = __popcll(bm);
+    __syncthreads();
+    int wbase = 0;
+    for (int w = 0; w < wv; ++w) wbase += S.hist[w];
+    int eq_total_block = 0;
+    for (int w = 0; w < kRerankWaves; ++w) eq_total_block += S.hist[w];
+    const int eq_seen = S.misc[2];
+    __syncthreads();
+    if (lt || (eq && eq_seen + wbase + eq_before < need_eq)) {
+      const int p = atomicAdd(&S.misc[1], 1);
+      top_d[p] = di;
+      top_i[p] = kid[i];
+    }
+    __syncthreads();
+    if (tid == 0) S.misc[2] = eq_seen + eq_total_block;
+    __syncthreads();
+  }
+  const int ns = S.misc[1];
+  for (int j = tid; j < ns; j += kRerankThreads) {
+    const double dj = top_d[j];
+    const int ij = top_i[j];
+    int rank = 0;
+    for (int t = 0; t < ns; ++t) rank += key_less(top_d[t], top_i[t], dj, ij) ? 1 : 0;
+    oi[rank] = ij;
+    od[rank] = static_cast<float>(dj);
+  }
+  for (int r = ns + tid; r < k; r += kRerankThreads) {
+    oi[r] = -1;
+    od[r] = __int_as_float(0x7f800000);
+  }
+}
+
+// kBf16 = false: every verified row read in float32.  kBf16 = true: every
+// row first in bfloat16; float32 only where the bounds cannot exclude it.
+template <bool kBf16>
 __global__ void __launch_bounds__(kRerankThreads) k_rerank(
     int mode, const float *__restrict__ qrot, int d, const float *__restrict__ base,
+    const uint16_t *__restrict__ base16, const float *__restrict__ rerr, double gam,
     const int32_t *__restrict__ ncand, const int32_t *__restrict__ list, long long n, int k, int patience,
-    const int32_t *__restrict__ limits, double *__restrict__ dkey, int64_t *__restrict__ out_ids,
-    float *__restrict__ out_d, int32_t *__restrict__ examined, int32_t *__restrict__ last_upd,
-    int32_t *__restrict__ stopped) {
+    const int32_t *__restrict__ limits, double *__restrict__ dkey, float *__restrict__ lbuf,
+    int32_t *__restrict__ rbuf, int64_t *__restrict__ out_ids, float *__restrict__ out_d,
+    int32_t *__restrict__ examined, int32_t *__restrict__ last_upd, int32_t *__restrict__ stopped,
+    int32_t *__restrict__ refined) {
   extern __shared__ __align__(16) unsigned char dyn[];
-  float *sq = reinterpret_cast<float *>(dyn);                                          // d floats
-  double *top_d = reinterpret_cast<double *>(dyn + static_cast<size_t>(d) * 4);        // k doubles
-  int *top_i = reinterpret_cast<int *>(dyn + static_cast<size_t>(d) * 4 + static_cast<size_t>(k) * 8);
+  const RerankLds LL = rerank_lds(d, k, kBf16);
+  float *sq = reinterpret_cast<float *>(dyn);
+  double *top_d = reinterpret_cast<double *>(dyn + LL.top_d);
+  int *top_i = reinterpret_cast<int *>(dyn + LL.top_i);
+  double *heap = reinterpret_cast<double *>(dyn + LL.heap);
+  double *xlb = reinterpret_cast<double *>(dyn + LL.lb);
+  double *xub = reinterpret_cast<double *>(dyn + LL.ub);
+  int *xpc = reinterpret_cast<int *>(dyn + LL.pc);
   __shared__ RerankShared S;
   const int q = blockIdx.x, tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   const long long qo = static_cast<long long>(q) * n;
@@ -832,91 +1067,68 @@ __global__ void __launch_bounds__(kRerankThreads) k_rerank(
 
   if (mode == 0) {
     // ---- Guaranteed: every candidate --------------------------------------
-    for (int i = wv; i < nc; i += kRerankWaves) {
-      double dc = row_dist_canon(sq, base + static_cast<long long>(list[qo + i]) * d, d);
-      if (lane == 0) dkey[qo + i] = dc;
-    }
-    __syncthreads();
-    // k-th smallest key value (radix select over the float64 bit pattern).
-    unsigned long long prefix = 0ull, mask = 0ull;
-    int kk = min(k, nc);
-    if (nc > k) {
-      for (int shift = 56; shift >= 0; shift -= 8) {
-        for (int b = tid; b < 256; b += kRerankThreads) S.hist[b] = 0;
-        __syncthreads();
-        for (int i = tid; i < nc; i += kRerankThreads) {
-          unsigned long long bits = dbits(dkey[qo + i]);
-          if ((bits & mask) == prefix) atomicAdd(&S.hist[(bits >> shift) & 255], 1);
+    const int32_t *kid = list + qo;
+    int nk = nc;
+    if constexpr (kBf16) {
+      // Bounds of every candidate; the k-th smallest upper bound T caps the
+      // k-th key, so only rows with lower bound <= T can be in the top-k.
+      for (int i = wv; i < nc; i += kRerankWaves) {
+        const int id = list[qo + i];
+        const float t = row_dist_bf16(sq, base16 + static_cast<long long>(id) * d, d);
+        if (lane == 0) {
+          double lb, ub;
+          bf16_bounds(t, rerr[id], gam, lb, ub);
+          dkey[qo + i] = ub;
+          float lf = static_cast<float>(lb);
+          if (static_cast<double>(lf) > lb) lf = nextafterf(lf, -__int_as_float(0x7f800000));
+          lbuf[qo + i] = lf;
         }
+      }
+      __syncthreads();
+      double thr = __longlong_as_double(0x7ff0000000000000ll);
+      if (nc > k) {
+        int unused;
+        thr = radix_kth(dkey + qo, nc, k, S, &unused);
+      }
+      // Refinement set, in list order (ascending id).
+      if (tid == 0) S.misc[3] = 0;
+      __syncthreads();
+      for (int i0 = 0; i0 < nc; i0 += kRerankThreads) {
+        const int i = i0 + tid;
+        const bool keep = i < nc && static_cast<double>(lbuf[qo + i]) <= thr;
+        const unsigned long long bm = __ballot(keep);
+        if (lane == 0) S.hist[wv] = __popcll(bm);
+        __syncthreads();
+        int before = S.misc[3];
+        for (int w = 0; w < wv; ++w) before += S.hist[w];
+        if (keep) rbuf[qo + before + __popcll(bm & lanes_below_mask())] = list[qo + i];
         __syncthreads();
         if (tid == 0) {
-          int cum = 0, b = 0;
-          for (; b < 255; ++b) {
-            if (cum + S.hist[b] >= kk) break;
-            cum += S.hist[b];
-          }
-          S.umisc[0] = prefix | (static_cast<unsigned long long>(b) << shift);
-          S.misc[0] = kk - cum;
+          int tot = 0;
+          for (int w = 0; w < kRerankWaves; ++w) tot += S.hist[w];
+          S.misc[3] += tot;
         }
         __syncthreads();
-        prefix = S.umisc[0];
-        kk = S.misc[0];
-        mask |= 255ull << shift;
-        __syncthreads();
+      }
+      nk = S.misc[3];
+      kid = rbuf + qo;
+      for (int j = wv; j < nk; j += kRerankWaves) {
+        const double dc = row_dist_canon(sq, base + static_cast<long long>(kid[j]) * d, d);
+        if (lane == 0) dkey[qo + j] = dc;
+      }
+    } else {
+      for (int i = wv; i < nc; i += kRerankWaves) {
+        const double dc = row_dist_canon(sq, base + static_cast<long long>(list[qo + i]) * d, d);
+        if (lane == 0) dkey[qo + i] = dc;
       }
     }
-    // Collect the keys below the k-th value, then the first kk ids equal to it
-    // (the list is ascending in id).  nc <= k: every candidate.
-    if (tid == 0) { S.misc[1] = 0; S.misc[2] = 0; }
     __syncthreads();
-    const double vk = from_dbits(prefix);
-    const int need_eq = (nc > k) ? kk : 0;
-    for (int i0 = 0; i0 < nc; i0 += kRerankThreads) {
-      const int i = i0 + tid;
-      double di = (i < nc) ? dkey[qo + i] : 0.0;
-      bool lt = (i < nc) && (nc <= k || di < vk);
-      bool eq = (i < nc) && (nc > k) && (di == vk);
-      // order-preserving rank among equal keys in this block of 256
-      int eq_before = 0;
-      {
-        unsigned long long bm = __ballot(eq);
-        eq_before = __popcll(bm & lanes_below_mask());
-        if (lane == kWave - 1) S.hist[wv] = __popcll(bm);
-      }
-      __syncthreads();
-      int wbase = 0;
-      for (int w = 0; w < wv; ++w) wbase += S.hist[w];
-      int eq_total_block = 0;
-      for (int w = 0; w < kRerankWaves; ++w) eq_total_block += S.hist[w];
-      const int eq_seen = S.misc[2 + 0];
-      __syncthreads();
-      if (lt || (eq && eq_seen + wbase + eq_before < need_eq)) {
-        int p = atomicAdd(&S.misc[1], 1);
-        top_d[p] = di;
-        top_i[p] = list[qo + i];
-      }
-      __syncthreads();
-      if (tid == 0) S.misc[2] = eq_seen + eq_total_block;
-      __syncthreads();
-    }
-    const int ns = S.misc[1];
-    // Order the (<= k) selected keys by (d, id).
-    for (int j = tid; j < ns; j += kRerankThreads) {
-      double dj = top_d[j];
-      int ij = top_i[j];
-      int rank = 0;
-      for (int t = 0; t < ns; ++t) rank += key_less(top_d[t], top_i[t], dj, ij) ? 1 : 0;
-      oi[rank] = ij;
-      od[rank] = static_cast<float>(dj);
-    }
-    for (int r = ns + tid; r < k; r += kRerankThreads) {
-      oi[r] = -1;
-      od[r] = __int_as_float(0x7f800000);
-    }
+    select_topk(dkey + qo, kid, nk, k, S, top_d, top_i, oi, od);
     if (tid == 0) {
       examined[q] = nc;
       last_upd[q] = 0;
       stopped[q] = 0;
+      if (refined) refined[q] = nk;
     }
     return;
   }
@@ -924,26 +1136,67 @@ __global__ void __launch_bounds__(kRerankThreads) k_rerank(
   // ---- Optimized: Hamming order with patience ------------------------------
   int lim = nc;
   if (limits != nullptr) {
-    int l = limits[q];
+    const int l = limits[q];
     if (l > 0 && l < lim) lim = l;
   }
-  if (tid == 0) { S.misc[2] = 0; S.misc[3] = 0; S.misc[4] = 0; S.misc[5] = 0; S.misc[6] = 0; }
+  if (tid == 0) { S.misc[2] = 0; S.misc[3] = 0; S.misc[4] = 0; S.misc[5] = 0; S.misc[6] = 0; S.misc[8] = 0; }
   __syncthreads();
   for (int c0 = 0; c0 < lim; c0 += kChunk) {
     const int cnt = min(kChunk, lim - c0);
-    // (a) exact keys of the chunk, in parallel
-    for (int t = wv; t < cnt; t += kRerankWaves) {
-      const int id = list[qo + c0 + t];
-      double dc = row_dist_canon(sq, base + static_cast<long long>(id) * d, d);
-      if (lane == 0) { S.dk[t] = dc; S.sid[t] = id; }
+    const int tn0 = S.misc[2];
+    const int free_slots = max(0, k - tn0);
+    if constexpr (kBf16) {
+      // (a) bounds of the chunk from the bfloat16 rows
+      for (int t = wv; t < cnt; t += kRerankWaves) {
+        const int id = list[qo + c0 + t];
+        const float tt = row_dist_bf16(sq, base16 + static_cast<long long>(id) * d, d);
+        if (lane == 0) {
+          double lb, ub;
+          bf16_bounds(tt, rerr[id], gam, lb, ub);
+          xlb[t] = lb;
+          xub[t] = ub;
+          S.sid[t] = id;
+        }
+      }
+      __syncthreads();
+      // When candidate t is walked, the k-th key is at most the k-th smallest
+      // of (the top-k keys at the chunk start, upper bounds of the chunk
+      // before t); a row whose lower bound exceeds that cannot update.
+      if (tid == 0) {
+        int hs = 0;
+        for (int e = tn0 - 1; e >= 0; --e) heap[hs++] = top_d[e];  // descending order is a max-heap
+        int np = 0;
+        for (int t = 0; t < cnt; ++t) {
+          const bool full = hs >= k;
+          const bool cert = !full || xlb[t] <= heap[0];
+          xpc[t] = cert ? 1 : 0;
+          if (cert) S.plist[np++] = t;
+          const double u = xub[t];
+          if (!full) heap_push(heap, hs, u);
+          else if (u < heap[0]) heap_replace_top(heap, hs, u);
+        }
+        S.misc[7] = np;
+      }
+      __syncthreads();
+      const int np = S.misc[7];
+      for (int e = wv; e < np; e += kRerankWaves) {
+        const int t = S.plist[e];
+        const double dc = row_dist_canon(sq, base + static_cast<long long>(S.sid[t]) * d, d);
+        if (lane == 0) S.dk[t] = dc;
+      }
+    } else {
+      // (a) exact keys of the chunk, in parallel
+      for (int t = wv; t < cnt; t += kRerankWaves) {
+        const int id = list[qo + c0 + t];
+        const double dc = row_dist_canon(sq, base + static_cast<long long>(id) * d, d);
+        if (lane == 0) { S.dk[t] = dc; S.sid[t] = id; }
+      }
     }
     __syncthreads();
     // (b) candidates that can update the top-k.  With a full top-k, only keys
     // below its k-th key at the chunk start; while it fills, the first `free`
     // candidates always update and later ones only below the k-th key of
     // (top-k so far + those `free`), which bounds the k-th key from then on.
-    const int tn0 = S.misc[2];
-    const int free_slots = max(0, k - tn0);
     if (tid == 0) {
       if (tn0 >= k) {
         S.bd = top_d[k - 1]; S.bid = top_i[k - 1];
@@ -959,7 +1212,9 @@ __global__ void __launch_bounds__(kRerankThreads) k_rerank(
     __syncthreads();
     {
       const int t = tid;
-      const bool pot = t < cnt && (t < free_slots || key_less(S.dk[t], S.sid[t], S.bd, S.bid));
+      bool pot = t < cnt;
+      if constexpr (kBf16) pot = pot && xpc[t] != 0;
+      pot = pot && (t < free_slots || key_less(S.dk[t], S.sid[t], S.bd, S.bid));
       const unsigned long long bm = __ballot(pot);
       if (lane == 0) S.hist[wv] = __popcll(bm);
       __syncthreads();
@@ -1012,6 +1267,13 @@ __global__ void __launch_bounds__(kRerankThreads) k_rerank(
       S.misc[2] = tn; S.misc[3] = run; S.misc[4] = last; S.misc[5] = stop; S.misc[6] = pos;
     }
     __syncthreads();
+    if constexpr (kBf16) {
+      // float32 rows inside the verified prefix
+      const bool f = tid < cnt && c0 + tid < S.misc[6] && xpc[tid] != 0;
+      const unsigned long long bm = __ballot(f);
+      if (lane == 0 && bm) atomicAdd(&S.misc[8], __popcll(bm));
+      __syncthreads();
+    }
     if (S.misc[5]) break;
   }
   __syncthreads();
@@ -1024,6 +1286,7 @@ __global__ void __launch_bounds__(kRerankThreads) k_rerank(
     examined[q] = S.misc[6];
     last_upd[q] = S.misc[4];
     stopped[q] = S.misc[5];
+    if (refined) refined[q] = kBf16 ? S.misc[8] : S.misc[6];
   }
 }
 

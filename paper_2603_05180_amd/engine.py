@@ -103,9 +103,28 @@ class Index:
         return {name: {"ms": pr.ms[i], "intervals": pr.intervals[i]} for i, name in enumerate(_lib.STAGES)} | \
             {"dropped": pr.dropped}
 
-    def params(self, *, mode=0, alpha=0.01, tau=1, patience_factor=40, limits=None, max_chunk=0, budget_source=0):
+    def params(self, *, mode=0, alpha=0.01, tau=1, patience_factor=40, limits=None, max_chunk=0, budget_source=0,
+               precision=0):
         return SearchParams(int(mode), float(alpha), int(tau), int(patience_factor), _ptr(limits), int(max_chunk),
-                            int(budget_source))
+                            int(budget_source), int(precision))
+
+    def enable_bf16(self, stream=None) -> torch.Tensor:
+        """bfloat16 copy of the rows + per-row error bounds for precision=1
+        (the buffer is kept alive by the index)."""
+        b = ctypes.c_size_t(0)
+        check(lib.crisp_index_bf16_bytes(self._h, ctypes.byref(b)))
+        buf = torch.empty(b.value, dtype=torch.uint8, device=self.device)
+        check(lib.crisp_index_enable_bf16(self._h, _ptr(buf), b.value, _stream(stream)))
+        self._bf16 = buf
+        return buf
+
+    def bf16_rows(self) -> tuple[torch.Tensor, torch.Tensor]:
+        """Views of the bfloat16 copy [N, D] and the row error bounds [N]."""
+        n, d = self.n, self.d
+        off = (n * d * 2 + 255) // 256 * 256
+        rows = self._bf16[: n * d * 2].view(torch.bfloat16).view(n, d)
+        err = self._bf16[off: off + 4 * n].view(torch.float32)
+        return rows, err
 
     @property
     def n_features(self) -> int:
@@ -147,6 +166,7 @@ class Index:
             "examined": torch.empty(nq, dtype=torch.int32, **z),
             "last_update": torch.empty(nq, dtype=torch.int32, **z),
             "stopped": torch.empty(nq, dtype=torch.int32, **z),
+            "refined": torch.empty(nq, dtype=torch.int32, **z),
         }
         if mode == 1:
             t["order"] = torch.empty(nq, n, dtype=torch.int32, **z)
@@ -157,7 +177,8 @@ class Index:
 
     def search(self, queries: torch.Tensor, k: int, *, mode: int = 0, alpha: float = 0.01, tau: int = 1,
                patience_factor: int = 40, limits: torch.Tensor | None = None, max_chunk: int = 0,
-               budget_source: int = 0, taps: dict | None = None, out: tuple | None = None, stream=None):
+               budget_source: int = 0, precision: int = 0, taps: dict | None = None, out: tuple | None = None,
+               stream=None):
         """Algorithm 1 for a batch; returns (ids int64 [nq, k], dists f32 [nq, k])."""
         if queries.device != self.device or queries.dtype != torch.float32 or not queries.is_contiguous():
             raise ValueError("queries must be a contiguous float32 tensor on the index device")
@@ -168,7 +189,7 @@ class Index:
             raise ValueError("limits must be an int32 device tensor with one entry per query")
         nq = int(queries.shape[0])
         p = self.params(mode=mode, alpha=alpha, tau=tau, patience_factor=patience_factor,
-                        limits=limits, max_chunk=max_chunk, budget_source=budget_source)
+                        limits=limits, max_chunk=max_chunk, budget_source=budget_source, precision=precision)
         ws = self.workspace(nq, k, p)
         if out is None:
             ids = torch.empty(nq, k, dtype=torch.int64, device=self.device)

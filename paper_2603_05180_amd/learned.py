@@ -5,9 +5,11 @@ The label of a query is L*, the 1-based position of the last top-k update of
 the plain patience walk (read from the engine's `last_update` tap); the
 network predicts log L* from the features the engine computes during the
 same search.  At search time the walk stops at the earlier of the patience
-stop and clamp(ceil(exp(y + delta)), k, |C|); delta is chosen on held-out
-queries so that a target fraction of them keeps a prefix >= L* (for those
-the result equals the plain result exactly).
+stop and clamp(ceil(exp(y + delta)), k, |C|).  The margin delta is the
+smallest value (found by bisection) at which held-out queries keep a given
+fraction of their plain top-k: the plain result is the judge.  A prefix
+never loses a plain result it contains, so that fraction is non-decreasing
+in delta and bisection finds the threshold.
 """
 from __future__ import annotations
 
@@ -33,18 +35,22 @@ def _st():
 
 def collect(index: engine.Index, queries: torch.Tensor, k: int, *, alpha: float, tau: int, patience_factor: int = 40,
             batch: int = 8192):
-    """Plain Optimized-Mode searches with taps: features, L*, verified prefix, |C|."""
+    """Plain Optimized-Mode searches with taps: features, L*, verified prefix,
+    |C| and the plain top-k ids."""
     nq = queries.shape[0]
     dev = queries.device
     f = index.n_features
     out = {"features": torch.empty(nq, f, dtype=torch.float32, device=dev),
            "last_update": torch.empty(nq, dtype=torch.int32, device=dev),
            "examined": torch.empty(nq, dtype=torch.int32, device=dev),
-           "n_cand": torch.empty(nq, dtype=torch.int32, device=dev)}
+           "n_cand": torch.empty(nq, dtype=torch.int32, device=dev),
+           "ids": torch.empty(nq, k, dtype=torch.int64, device=dev)}
+    dists = torch.empty(nq, k, dtype=torch.float32, device=dev)
     for q0 in range(0, nq, batch):
         q1 = min(nq, q0 + batch)
-        taps = {key: v[q0:q1] for key, v in out.items()}
-        index.search(queries[q0:q1], k, mode=1, alpha=alpha, tau=tau, patience_factor=patience_factor, taps=taps)
+        taps = {key: v[q0:q1] for key, v in out.items() if key != "ids"}
+        index.search(queries[q0:q1], k, mode=1, alpha=alpha, tau=tau, patience_factor=patience_factor, taps=taps,
+                     out=(out["ids"][q0:q1], dists[q0:q1]))
     torch.cuda.synchronize()
     return out
 
@@ -111,11 +117,34 @@ class BudgetModel:
                 log(f"epoch {ep + 1}/{epochs}: mse {mse:.4f}")
         return self
 
-    def calibrate(self, x: torch.Tensor, l_star: torch.Tensor, target: float = 0.99) -> float:
-        """delta = the `target` quantile of log L* - y over held-out queries."""
-        y, _ = self.forward(x)
-        gap = (torch.log(l_star.double().clamp(min=1.0)) - y.double()).cpu().numpy()
-        self.delta = float(np.quantile(gap, target)) if gap.size else 0.0
+    def calibrate(self, index: engine.Index, queries: torch.Tensor, plain_ids: torch.Tensor, k: int, *,
+                  floor: float = 0.998, lo: float = -2.0, hi: float = 6.0, iters: int = 14, batch: int = 8192,
+                  **search_kw) -> float:
+        """Smallest delta in [lo, hi] (to within (hi - lo) / 2^iters) at which
+        the learned searches of `queries` keep at least `floor` of the plain
+        top-k ids `plain_ids`; `hi` if none does."""
+        def kept(delta):
+            self.delta = delta
+            self.install(index)
+            hit = 0.0
+            for q0 in range(0, queries.shape[0], batch):
+                q1 = min(queries.shape[0], q0 + batch)
+                ids, _ = index.search(queries[q0:q1], k, mode=1, budget_source=1, **search_kw)
+                hit += float((ids[:, :, None] == plain_ids[q0:q1, None, :]).any(-1).sum())
+            return hit / max(1, plain_ids.numel())
+
+        if kept(lo) >= floor:
+            return self.delta
+        if kept(hi) < floor:
+            return self.delta
+        for _ in range(iters):
+            mid = 0.5 * (lo + hi)
+            if kept(mid) >= floor:
+                hi = mid
+            else:
+                lo = mid
+        self.delta = hi
+        self.install(index)
         return self.delta
 
     def install(self, index: engine.Index):
@@ -123,20 +152,21 @@ class BudgetModel:
 
 
 def train_budget(index: engine.Index, train_queries: torch.Tensor, k: int, *, alpha: float, tau: int,
-                 patience_factor: int = 40, epochs: int = 30, holdout: float = 0.1, target: float = 0.99,
+                 patience_factor: int = 40, epochs: int = 30, holdout: float = 0.1, floor: float = 0.998,
                  seed: int = 0, log=None) -> BudgetModel:
-    """Collect plain traces, train, calibrate on a held-out split, install."""
-    tr = collect(index, train_queries, k, alpha=alpha, tau=tau, patience_factor=patience_factor)
-    keep = (tr["last_update"] >= 1).nonzero().squeeze(1)
+    """Collect plain traces, train on all but the first `holdout` fraction of
+    the queries, calibrate delta on that held-out part, install."""
+    kw = dict(alpha=alpha, tau=tau, patience_factor=patience_factor)
+    tr = collect(index, train_queries, k, **kw)
+    nq = train_queries.shape[0]
+    nval = max(1, int(nq * holdout))
+    keep = (tr["last_update"][nval:] >= 1).nonzero().squeeze(1) + nval
     feats = tr["features"].index_select(0, keep)
     lstar = tr["last_update"].index_select(0, keep)
-    n = feats.shape[0]
-    nval = max(1, int(n * holdout))
     model = BudgetModel(index.n_features, device=feats.device, seed=seed)
-    model.fit_standardisation(feats[nval:])
-    x = model.standardise(feats)
-    t = torch.log(lstar.float())
-    model.train(x[nval:], t[nval:], epochs=epochs, seed=seed, log=log)
-    model.calibrate(x[:nval], lstar[:nval], target)
-    model.install(index)
+    model.fit_standardisation(feats)
+    model.train(model.standardise(feats), torch.log(lstar.float()), epochs=epochs, seed=seed, log=log)
+    model.calibrate(index, train_queries[:nval], tr["ids"][:nval], k, floor=floor, **kw)
+    if log is not None:
+        log(f"delta {model.delta:.4f} (floor {floor} of the plain top-{k} on {nval} held-out queries)")
     return model

@@ -26,24 +26,25 @@ def gpu_index(idx, tile_ids=0):
     return engine.Index(idx, tile_ids=tile_ids)
 
 
-def run_gpu(gidx, q: np.ndarray, k: int, *, mode, alpha, tau, patience_factor=40, limits=None, max_chunk=0):
+def run_gpu(gidx, q: np.ndarray, k: int, *, mode, alpha, tau, patience_factor=40, limits=None, max_chunk=0,
+            precision=0):
     qt = torch.from_numpy(np.ascontiguousarray(q, dtype=np.float32)).to(gidx.device)
     taps = gidx.alloc_taps(q.shape[0], mode)
     lim = None
     if limits is not None:
         lim = torch.from_numpy(np.asarray(limits, dtype=np.int32)).to(gidx.device)
     ids, d = gidx.search(qt, k, mode=mode, alpha=alpha, tau=tau, patience_factor=patience_factor,
-                         limits=lim, max_chunk=max_chunk, taps=taps)
+                         limits=lim, max_chunk=max_chunk, precision=precision, taps=taps)
     torch.cuda.synchronize()
     return ids.cpu().numpy(), d.cpu().numpy(), {kk: v.cpu().numpy() for kk, v in taps.items()}
 
 
 def compare(idx, q, k, *, mode, alpha, tau, patience_factor=40, limits=None, gpu=None, max_chunk=0,
-            tile_ids=0, check_stages=True):
+            tile_ids=0, check_stages=True, precision=0):
     """Run both sides; assert bit-exact stages and results.  Returns a summary."""
     g = gpu if gpu is not None else gpu_index(idx, tile_ids)
     gi, gd, tp = run_gpu(g, q, k, mode=mode, alpha=alpha, tau=tau, patience_factor=patience_factor,
-                         limits=limits, max_chunk=max_chunk)
+                         limits=limits, max_chunk=max_chunk, precision=precision)
     oi, od, tr = oquery.search(idx, q, k, mode=mode, alpha=alpha, tau=tau, patience_factor=patience_factor,
                                limits=limits, trace=True)
     m, kh, n = idx["m"], idx["k_half"], idx["n"]
@@ -77,4 +78,4 @@ def compare(idx, q, k, *, mode, alpha, tau, patience_factor=40, limits=None, gpu
                 assert int(tp["stopped"][qi]) == (0 if t["stop"] is None else 1), f"stopped q={qi}"
     assert np.array_equal(gi, oi), "ids"
     assert np.array_equal(gd.view(np.uint32), od.view(np.uint32)), "dists"
-    return {"n_cand": [t["candidates"].size for t in tr], "gpu": g}
+    return {"n_cand": [t["candidates"].size for t in tr], "gpu": g, "taps": tp, "ids": gi, "dists": gd}

@@ -96,3 +96,14 @@ def test_wide_rows_several_tiles():
     print("D=1024", flush=True)
     for mode in (0, 1):
         compare(idx, q, 10, mode=mode, alpha=0.02, tau=4, tile_ids=4096)
+
+
+@pytest.mark.parametrize("d,m", [(192, 4), (320, 5), (448, 7)])
+def test_code_widths_not_a_power_of_two(d, m):
+    """3, 5 and 7 sign-code words per row: the Hamming kernel's lanes per row
+    must still cover every word exactly once."""
+    w, x, q = make_workload("cfg3", n=2500, d=d, m=m, k_half=6, rank=8, n_query=12)
+    idx = oracle_index(w, x)
+    print(f"D={d} M={m}", flush=True)
+    for mode in (0, 1):
+        compare(idx, q, 10, mode=mode, alpha=0.05, tau=3)
