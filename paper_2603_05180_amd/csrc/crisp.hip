@@ -215,12 +215,15 @@ crisp_status crisp_index_load(const crisp_index_desc *desc, int32_t tile_ids, vo
   LAUNCH_TRY("k_transpose_centroids");
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_count), hipFuncAttributeMaxDynamicSharedMemorySize,
                               tile));
-  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rerank<false>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              static_cast<int>(rerank_lds(desc->d, 1024, false).total)));
-  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rerank<true>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              static_cast<int>(rerank_lds(desc->d, 1024, true).total)));
+  {
+    const void *rr[4] = {reinterpret_cast<const void *>(&k_rerank<0, false>),
+                         reinterpret_cast<const void *>(&k_rerank<0, true>),
+                         reinterpret_cast<const void *>(&k_rerank<1, false>),
+                         reinterpret_cast<const void *>(&k_rerank<1, true>)};
+    for (int i = 0; i < 4; ++i)
+      HIP_TRY(hipFuncSetAttribute(rr[i], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  static_cast<int>(rerank_lds(desc->d, 1024, (i & 1) != 0).total)));
+  }
   crisp_index *ix = new (std::nothrow) crisp_index{};
   if (!ix) return fail(CRISP_E_INVALID, "out of host memory");
   ix->n = desc->n; ix->d = desc->d; ix->m = desc->m; ix->k = desc->k_half;
@@ -352,7 +355,8 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
   // float32 error factor of the bfloat16 row distance: gamma_{L+10}, L = terms per lane
   const double lterms = static_cast<double>((d / 8 + kWave - 1) / kWave * 8 + 10) * 5.9604644775390625e-08;
   const double gam = lterms / (1.0 - lterms);
-  auto rerank_kernel = bf16 ? k_rerank<true> : k_rerank<false>;
+  auto rerank0 = bf16 ? k_rerank<0, true> : k_rerank<0, false>;
+  auto rerank1 = bf16 ? k_rerank<1, true> : k_rerank<1, false>;
 
   for (long long q0 = 0; q0 < nq; q0 += qc) {
     const int cq = static_cast<int>(std::min<long long>(qc, nq - q0));
@@ -427,7 +431,7 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
       }
       // A6 / A7
       StageTimer t5(ix, 5, st);
-      rerank_kernel<<<cq, kRerankThreads, rr_lds, st>>>(1, qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
+      rerank1<<<cq, kRerankThreads, rr_lds, st>>>(qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
                                                         segids, n, k, patience, lim, regC, nullptr, nullptr,
                                                         ids + q0 * k,
                                                         dists + q0 * k, exam, lastu, stopd, refd);
@@ -435,7 +439,7 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
       t5.stop();
     } else {
       StageTimer t5(ix, 5, st);
-      rerank_kernel<<<cq, kRerankThreads, rr_lds, st>>>(0, qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
+      rerank0<<<cq, kRerankThreads, rr_lds, st>>>(qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
                                                         cand, n, k, patience, lim, regC,
                                                         reinterpret_cast<float *>(regA), regB, ids + q0 * k,
                                                         dists + q0 * k, exam, lastu, stopd, refd);

@@ -783,12 +783,15 @@ __device__ __forceinline__ double canon_partial(const float4 *__restrict__ qq, c
 // d_canon of one row, whole wave; result in every lane.  Lane l owns the
 // 4-element groups g = l, l + 64, ... (one 16-byte load each, all of a batch
 // issued before use); groups past the end contribute exact zeros.
+// kWide = false keeps at most 4 loads in flight per lane (fewer registers,
+// for kernels that read few rows this way).
+template <bool kWide = true>
 __device__ __forceinline__ double row_dist_canon(const float *__restrict__ sq, const float *__restrict__ x, int d) {
   const int lane = lane_id();
   const int nv = d >> 2;
   const float4 *qq = reinterpret_cast<const float4 *>(sq);
   const float4 *xr = reinterpret_cast<const float4 *>(x);
-  double p = (nv <= 4 * kWave) ? canon_partial<4>(qq, xr, nv, lane) : canon_partial<16>(qq, xr, nv, lane);
+  double p = (!kWide || nv <= 4 * kWave) ? canon_partial<4>(qq, xr, nv, lane) : canon_partial<16>(qq, xr, nv, lane);
 #pragma unroll
   for (int s = 32; s >= 1; s >>= 1) {
     double v = __shfl_down(p, s, kWave);
@@ -832,42 +835,51 @@ struct RerankShared {
 constexpr double kBoundRel = 1.0 / 68719476736.0;          // 2^-36
 constexpr double kBoundAbs = 7.888609052210118e-31;         // 2^-100
 
-// ||q' - x~||^2 in float32 for the bfloat16 row x16; whole wave, result in
-// every lane (an xor butterfly adds the same pair in both lanes).
-__device__ __forceinline__ float row_dist_bf16(const float *__restrict__ sq, const uint16_t *__restrict__ x16, int d) {
+// ||q' - x~||^2 in float32 for two bfloat16 rows at once (2 x 8 sixteen-byte
+// loads in flight per lane: one row alone leaves the wave latency-bound);
+// whole wave, results in every lane (an xor butterfly adds the same pair in
+// both lanes).
+__device__ __forceinline__ float2 row_dist_bf16_x2(const float *__restrict__ sq, const uint16_t *__restrict__ xa16,
+                                                   const uint16_t *__restrict__ xb16, int d) {
   const int lane = lane_id();
   const int nv = d >> 3;  // 16-byte groups of eight bfloat16
-  const uint4 *xr = reinterpret_cast<const uint4 *>(x16);
+  const uint4 *xa = reinterpret_cast<const uint4 *>(xa16);
+  const uint4 *xb = reinterpret_cast<const uint4 *>(xb16);
   const float4 *qq = reinterpret_cast<const float4 *>(sq);
   constexpr int B = 8;
-  float p = 0.f;
+  float pa = 0.f, pb = 0.f;
   for (int r0 = 0; r0 * kWave < nv; r0 += B) {
-    uint4 xv[B];
+    uint4 va[B], vb[B];
 #pragma unroll
     for (int u = 0; u < B; ++u) {
       const int g = (r0 + u) * kWave + lane;
-      xv[u] = xr[g < nv ? g : 0];  // clamped: every load is issued
+      const int gg = g < nv ? g : 0;  // clamped: every load is issued
+      va[u] = xa[gg];
+      vb[u] = xb[gg];
     }
 #pragma unroll
     for (int u = 0; u < B; ++u) {
       const int g = (r0 + u) * kWave + lane;
       const bool ok = g < nv;
       const int gg = ok ? g : 0;
-      const float4 qa = qq[2 * gg], qb = qq[2 * gg + 1];
-      const uint32_t w[4] = {xv[u].x, xv[u].y, xv[u].z, xv[u].w};
-      const float qs[8] = {qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, qb.z, qb.w};
+      const float4 q0 = qq[2 * gg], q1 = qq[2 * gg + 1];
+      const float qs[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+      const uint32_t wa[4] = {va[u].x, va[u].y, va[u].z, va[u].w};
+      const uint32_t wb[4] = {vb[u].x, vb[u].y, vb[u].z, vb[u].w};
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const float lo = __uint_as_float(w[e] << 16);
-        const float hi = __uint_as_float(w[e] & 0xFFFF0000u);
-        const float t0 = ok ? qs[2 * e] - lo : 0.f;
-        const float t1 = ok ? qs[2 * e + 1] - hi : 0.f;
-        p = fmaf(t0, t0, p);
-        p = fmaf(t1, t1, p);
+        const float a0 = ok ? qs[2 * e] - __uint_as_float(wa[e] << 16) : 0.f;
+        const float a1 = ok ? qs[2 * e + 1] - __uint_as_float(wa[e] & 0xFFFF0000u) : 0.f;
+        const float b0 = ok ? qs[2 * e] - __uint_as_float(wb[e] << 16) : 0.f;
+        const float b1 = ok ? qs[2 * e + 1] - __uint_as_float(wb[e] & 0xFFFF0000u) : 0.f;
+        pa = fmaf(a0, a0, pa);
+        pa = fmaf(a1, a1, pa);
+        pb = fmaf(b0, b0, pb);
+        pb = fmaf(b1, b1, pb);
       }
     }
   }
-  return wave_sum_f32(p);
+  return make_float2(wave_sum_f32(pa), wave_sum_f32(pb));
 }
 
 __device__ __forceinline__ void bf16_bounds(float t32, float ex, double g, double &lb, double &ub) {
@@ -1036,11 +1048,12 @@ __device__ inline void select_topk(const double *__restrict__ keys, const int32_
   }
 }
 
-// kBf16 = false: every verified row read in float32.  kBf16 = true: every
-// row first in bfloat16; float32 only where the bounds cannot exclude it.
-template <bool kBf16>
+// kMode: 0 Guaranteed, 1 Optimized.  kBf16 = false: every verified row read
+// in float32.  kBf16 = true: every row first in bfloat16; float32 only where
+// the bounds cannot exclude it.
+template <int kMode, bool kBf16>
 __global__ void __launch_bounds__(kRerankThreads) k_rerank(
-    int mode, const float *__restrict__ qrot, int d, const float *__restrict__ base,
+    const float *__restrict__ qrot, int d, const float *__restrict__ base,
     const uint16_t *__restrict__ base16, const float *__restrict__ rerr, double gam,
     const int32_t *__restrict__ ncand, const int32_t *__restrict__ list, long long n, int k, int patience,
     const int32_t *__restrict__ limits, double *__restrict__ dkey, float *__restrict__ lbuf,
@@ -1065,23 +1078,26 @@ __global__ void __launch_bounds__(kRerankThreads) k_rerank(
   int64_t *oi = out_ids + static_cast<long long>(q) * k;
   float *od = out_d + static_cast<long long>(q) * k;
 
-  if (mode == 0) {
+  if constexpr (kMode == 0) {
     // ---- Guaranteed: every candidate --------------------------------------
     const int32_t *kid = list + qo;
     int nk = nc;
     if constexpr (kBf16) {
       // Bounds of every candidate; the k-th smallest upper bound T caps the
       // k-th key, so only rows with lower bound <= T can be in the top-k.
-      for (int i = wv; i < nc; i += kRerankWaves) {
-        const int id = list[qo + i];
-        const float t = row_dist_bf16(sq, base16 + static_cast<long long>(id) * d, d);
-        if (lane == 0) {
+      for (int i = 2 * wv; i < nc; i += 2 * kRerankWaves) {
+        const int ida = list[qo + i];
+        const int idb = list[qo + min(i + 1, nc - 1)];
+        const float2 t = row_dist_bf16_x2(sq, base16 + static_cast<long long>(ida) * d,
+                                          base16 + static_cast<long long>(idb) * d, d);
+        if (lane < 2 && i + lane < nc) {
+          const int id = lane ? idb : ida;
           double lb, ub;
-          bf16_bounds(t, rerr[id], gam, lb, ub);
-          dkey[qo + i] = ub;
+          bf16_bounds(lane ? t.y : t.x, rerr[id], gam, lb, ub);
+          dkey[qo + i + lane] = ub;
           float lf = static_cast<float>(lb);
           if (static_cast<double>(lf) > lb) lf = nextafterf(lf, -__int_as_float(0x7f800000));
-          lbuf[qo + i] = lf;
+          lbuf[qo + i + lane] = lf;
         }
       }
       __syncthreads();
@@ -1113,7 +1129,7 @@ __global__ void __launch_bounds__(kRerankThreads) k_rerank(
       nk = S.misc[3];
       kid = rbuf + qo;
       for (int j = wv; j < nk; j += kRerankWaves) {
-        const double dc = row_dist_canon(sq, base + static_cast<long long>(kid[j]) * d, d);
+        const double dc = row_dist_canon<false>(sq, base + static_cast<long long>(kid[j]) * d, d);
         if (lane == 0) dkey[qo + j] = dc;
       }
     } else {
@@ -1133,160 +1149,165 @@ __global__ void __launch_bounds__(kRerankThreads) k_rerank(
     return;
   }
 
-  // ---- Optimized: Hamming order with patience ------------------------------
-  int lim = nc;
-  if (limits != nullptr) {
-    const int l = limits[q];
-    if (l > 0 && l < lim) lim = l;
-  }
-  if (tid == 0) { S.misc[2] = 0; S.misc[3] = 0; S.misc[4] = 0; S.misc[5] = 0; S.misc[6] = 0; S.misc[8] = 0; }
-  __syncthreads();
-  for (int c0 = 0; c0 < lim; c0 += kChunk) {
-    const int cnt = min(kChunk, lim - c0);
-    const int tn0 = S.misc[2];
-    const int free_slots = max(0, k - tn0);
-    if constexpr (kBf16) {
-      // (a) bounds of the chunk from the bfloat16 rows
-      for (int t = wv; t < cnt; t += kRerankWaves) {
-        const int id = list[qo + c0 + t];
-        const float tt = row_dist_bf16(sq, base16 + static_cast<long long>(id) * d, d);
-        if (lane == 0) {
-          double lb, ub;
-          bf16_bounds(tt, rerr[id], gam, lb, ub);
-          xlb[t] = lb;
-          xub[t] = ub;
-          S.sid[t] = id;
-        }
-      }
-      __syncthreads();
-      // When candidate t is walked, the k-th key is at most the k-th smallest
-      // of (the top-k keys at the chunk start, upper bounds of the chunk
-      // before t); a row whose lower bound exceeds that cannot update.
-      if (tid == 0) {
-        int hs = 0;
-        for (int e = tn0 - 1; e >= 0; --e) heap[hs++] = top_d[e];  // descending order is a max-heap
-        int np = 0;
-        for (int t = 0; t < cnt; ++t) {
-          const bool full = hs >= k;
-          const bool cert = !full || xlb[t] <= heap[0];
-          xpc[t] = cert ? 1 : 0;
-          if (cert) S.plist[np++] = t;
-          const double u = xub[t];
-          if (!full) heap_push(heap, hs, u);
-          else if (u < heap[0]) heap_replace_top(heap, hs, u);
-        }
-        S.misc[7] = np;
-      }
-      __syncthreads();
-      const int np = S.misc[7];
-      for (int e = wv; e < np; e += kRerankWaves) {
-        const int t = S.plist[e];
-        const double dc = row_dist_canon(sq, base + static_cast<long long>(S.sid[t]) * d, d);
-        if (lane == 0) S.dk[t] = dc;
-      }
-    } else {
-      // (a) exact keys of the chunk, in parallel
-      for (int t = wv; t < cnt; t += kRerankWaves) {
-        const int id = list[qo + c0 + t];
-        const double dc = row_dist_canon(sq, base + static_cast<long long>(id) * d, d);
-        if (lane == 0) { S.dk[t] = dc; S.sid[t] = id; }
-      }
+  if constexpr (kMode == 1) {
+    // ---- Optimized: Hamming order with patience ------------------------------
+    int lim = nc;
+    if (limits != nullptr) {
+      const int l = limits[q];
+      if (l > 0 && l < lim) lim = l;
     }
+    if (tid == 0) { S.misc[2] = 0; S.misc[3] = 0; S.misc[4] = 0; S.misc[5] = 0; S.misc[6] = 0; S.misc[8] = 0; }
     __syncthreads();
-    // (b) candidates that can update the top-k.  With a full top-k, only keys
-    // below its k-th key at the chunk start; while it fills, the first `free`
-    // candidates always update and later ones only below the k-th key of
-    // (top-k so far + those `free`), which bounds the k-th key from then on.
-    if (tid == 0) {
-      if (tn0 >= k) {
-        S.bd = top_d[k - 1]; S.bid = top_i[k - 1];
-      } else if (cnt > free_slots) {
-        double bd = -1.0; int bid = -1;
-        for (int e = 0; e < tn0; ++e)
-          if (!key_less(top_d[e], top_i[e], bd, bid)) { bd = top_d[e]; bid = top_i[e]; }
-        for (int e = 0; e < free_slots; ++e)
-          if (!key_less(S.dk[e], S.sid[e], bd, bid)) { bd = S.dk[e]; bid = S.sid[e]; }
-        S.bd = bd; S.bid = bid;
-      }
-    }
-    __syncthreads();
-    {
-      const int t = tid;
-      bool pot = t < cnt;
-      if constexpr (kBf16) pot = pot && xpc[t] != 0;
-      pot = pot && (t < free_slots || key_less(S.dk[t], S.sid[t], S.bd, S.bid));
-      const unsigned long long bm = __ballot(pot);
-      if (lane == 0) S.hist[wv] = __popcll(bm);
-      __syncthreads();
-      int before = 0;
-      for (int w = 0; w < wv; ++w) before += S.hist[w];
-      if (pot) S.plist[before + __popcll(bm & lanes_below_mask())] = t;
-      if (tid == 0) {
-        int tot = 0;
-        for (int w = 0; w < kRerankWaves; ++w) tot += S.hist[w];
-        S.misc[7] = tot;
-      }
-    }
-    __syncthreads();
-    // (c) the patience rule in order over those candidates; every candidate
-    // between two of them is a non-update and only advances the run.
-    if (tid == 0) {
-      int tn = S.misc[2], run = S.misc[3], last = S.misc[4], stop = 0, pos = c0 + cnt, prev = -1;
-      const int np = S.misc[7];
-      for (int e = 0; e <= np; ++e) {
-        const int t = (e < np) ? S.plist[e] : cnt;
-        const int gap = t - prev - 1;
-        if (gap > 0 && run + gap >= patience) {
-          pos = c0 + prev + 1 + (patience - run);
-          stop = 1;
-          break;
-        }
-        run += gap;
-        if (e == np) break;
-        const int id = S.sid[t];
-        const double dc = S.dk[t];
-        if (tn < k || key_less(dc, id, top_d[k - 1], top_i[k - 1])) {
-          int p = (tn < k) ? tn : k - 1;
-          while (p > 0 && key_less(dc, id, top_d[p - 1], top_i[p - 1])) {
-            top_d[p] = top_d[p - 1];
-            top_i[p] = top_i[p - 1];
-            --p;
+    for (int c0 = 0; c0 < lim; c0 += kChunk) {
+      const int cnt = min(kChunk, lim - c0);
+      const int tn0 = S.misc[2];
+      const int free_slots = max(0, k - tn0);
+      if constexpr (kBf16) {
+        // (a) bounds of the chunk from the bfloat16 rows
+        for (int t = 2 * wv; t < cnt; t += 2 * kRerankWaves) {
+          const int ida = list[qo + c0 + t];
+          const int idb = list[qo + c0 + min(t + 1, cnt - 1)];
+          const float2 tt = row_dist_bf16_x2(sq, base16 + static_cast<long long>(ida) * d,
+                                             base16 + static_cast<long long>(idb) * d, d);
+          if (lane < 2 && t + lane < cnt) {
+            const int id = lane ? idb : ida;
+            double lb, ub;
+            bf16_bounds(lane ? tt.y : tt.x, rerr[id], gam, lb, ub);
+            xlb[t + lane] = lb;
+            xub[t + lane] = ub;
+            S.sid[t + lane] = id;
           }
-          top_d[p] = dc;
-          top_i[p] = id;
-          if (tn < k) ++tn;
-          run = 0;
-          last = c0 + t + 1;
-        } else if (++run >= patience) {
-          pos = c0 + t + 1;
-          stop = 1;
-          break;
         }
-        prev = t;
+        __syncthreads();
+        // When candidate t is walked, the k-th key is at most the k-th smallest
+        // of (the top-k keys at the chunk start, upper bounds of the chunk
+        // before t); a row whose lower bound exceeds that cannot update.
+        if (tid == 0) {
+          int hs = 0;
+          for (int e = tn0 - 1; e >= 0; --e) heap[hs++] = top_d[e];  // descending order is a max-heap
+          int np = 0;
+          for (int t = 0; t < cnt; ++t) {
+            const bool full = hs >= k;
+            const bool cert = !full || xlb[t] <= heap[0];
+            xpc[t] = cert ? 1 : 0;
+            if (cert) S.plist[np++] = t;
+            const double u = xub[t];
+            if (!full) heap_push(heap, hs, u);
+            else if (u < heap[0]) heap_replace_top(heap, hs, u);
+          }
+          S.misc[7] = np;
+        }
+        __syncthreads();
+        const int np = S.misc[7];
+        for (int e = wv; e < np; e += kRerankWaves) {
+          const int t = S.plist[e];
+          const double dc = row_dist_canon<false>(sq, base + static_cast<long long>(S.sid[t]) * d, d);
+          if (lane == 0) S.dk[t] = dc;
+        }
+      } else {
+        // (a) exact keys of the chunk, in parallel
+        for (int t = wv; t < cnt; t += kRerankWaves) {
+          const int id = list[qo + c0 + t];
+          const double dc = row_dist_canon(sq, base + static_cast<long long>(id) * d, d);
+          if (lane == 0) { S.dk[t] = dc; S.sid[t] = id; }
+        }
       }
-      S.misc[2] = tn; S.misc[3] = run; S.misc[4] = last; S.misc[5] = stop; S.misc[6] = pos;
+      __syncthreads();
+      // (b) candidates that can update the top-k.  With a full top-k, only keys
+      // below its k-th key at the chunk start; while it fills, the first `free`
+      // candidates always update and later ones only below the k-th key of
+      // (top-k so far + those `free`), which bounds the k-th key from then on.
+      if (tid == 0) {
+        if (tn0 >= k) {
+          S.bd = top_d[k - 1]; S.bid = top_i[k - 1];
+        } else if (cnt > free_slots) {
+          double bd = -1.0; int bid = -1;
+          for (int e = 0; e < tn0; ++e)
+            if (!key_less(top_d[e], top_i[e], bd, bid)) { bd = top_d[e]; bid = top_i[e]; }
+          for (int e = 0; e < free_slots; ++e)
+            if (!key_less(S.dk[e], S.sid[e], bd, bid)) { bd = S.dk[e]; bid = S.sid[e]; }
+          S.bd = bd; S.bid = bid;
+        }
+      }
+      __syncthreads();
+      {
+        const int t = tid;
+        bool pot = t < cnt;
+        if constexpr (kBf16) pot = pot && xpc[t] != 0;
+        pot = pot && (t < free_slots || key_less(S.dk[t], S.sid[t], S.bd, S.bid));
+        const unsigned long long bm = __ballot(pot);
+        if (lane == 0) S.hist[wv] = __popcll(bm);
+        __syncthreads();
+        int before = 0;
+        for (int w = 0; w < wv; ++w) before += S.hist[w];
+        if (pot) S.plist[before + __popcll(bm & lanes_below_mask())] = t;
+        if (tid == 0) {
+          int tot = 0;
+          for (int w = 0; w < kRerankWaves; ++w) tot += S.hist[w];
+          S.misc[7] = tot;
+        }
+      }
+      __syncthreads();
+      // (c) the patience rule in order over those candidates; every candidate
+      // between two of them is a non-update and only advances the run.
+      if (tid == 0) {
+        int tn = S.misc[2], run = S.misc[3], last = S.misc[4], stop = 0, pos = c0 + cnt, prev = -1;
+        const int np = S.misc[7];
+        for (int e = 0; e <= np; ++e) {
+          const int t = (e < np) ? S.plist[e] : cnt;
+          const int gap = t - prev - 1;
+          if (gap > 0 && run + gap >= patience) {
+            pos = c0 + prev + 1 + (patience - run);
+            stop = 1;
+            break;
+          }
+          run += gap;
+          if (e == np) break;
+          const int id = S.sid[t];
+          const double dc = S.dk[t];
+          if (tn < k || key_less(dc, id, top_d[k - 1], top_i[k - 1])) {
+            int p = (tn < k) ? tn : k - 1;
+            while (p > 0 && key_less(dc, id, top_d[p - 1], top_i[p - 1])) {
+              top_d[p] = top_d[p - 1];
+              top_i[p] = top_i[p - 1];
+              --p;
+            }
+            top_d[p] = dc;
+            top_i[p] = id;
+            if (tn < k) ++tn;
+            run = 0;
+            last = c0 + t + 1;
+          } else if (++run >= patience) {
+            pos = c0 + t + 1;
+            stop = 1;
+            break;
+          }
+          prev = t;
+        }
+        S.misc[2] = tn; S.misc[3] = run; S.misc[4] = last; S.misc[5] = stop; S.misc[6] = pos;
+      }
+      __syncthreads();
+      if constexpr (kBf16) {
+        // float32 rows inside the verified prefix
+        const bool f = tid < cnt && c0 + tid < S.misc[6] && xpc[tid] != 0;
+        const unsigned long long bm = __ballot(f);
+        if (lane == 0 && bm) atomicAdd(&S.misc[8], __popcll(bm));
+        __syncthreads();
+      }
+      if (S.misc[5]) break;
     }
     __syncthreads();
-    if constexpr (kBf16) {
-      // float32 rows inside the verified prefix
-      const bool f = tid < cnt && c0 + tid < S.misc[6] && xpc[tid] != 0;
-      const unsigned long long bm = __ballot(f);
-      if (lane == 0 && bm) atomicAdd(&S.misc[8], __popcll(bm));
-      __syncthreads();
+    const int tn = S.misc[2];
+    for (int r = tid; r < k; r += kRerankThreads) {
+      if (r < tn) { oi[r] = top_i[r]; od[r] = static_cast<float>(top_d[r]); }
+      else { oi[r] = -1; od[r] = __int_as_float(0x7f800000); }
     }
-    if (S.misc[5]) break;
-  }
-  __syncthreads();
-  const int tn = S.misc[2];
-  for (int r = tid; r < k; r += kRerankThreads) {
-    if (r < tn) { oi[r] = top_i[r]; od[r] = static_cast<float>(top_d[r]); }
-    else { oi[r] = -1; od[r] = __int_as_float(0x7f800000); }
-  }
-  if (tid == 0) {
-    examined[q] = S.misc[6];
-    last_upd[q] = S.misc[4];
-    stopped[q] = S.misc[5];
-    if (refined) refined[q] = kBf16 ? S.misc[8] : S.misc[6];
+    if (tid == 0) {
+      examined[q] = S.misc[6];
+      last_upd[q] = S.misc[4];
+      stopped[q] = S.misc[5];
+      if (refined) refined[q] = kBf16 ? S.misc[8] : S.misc[6];
+    }
   }
 }
 
