@@ -413,7 +413,12 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
     if (p->mode == 1) {
       // A5
       StageTimer t4(ix, 4, st);
-      k_hamming_order<<<cq, kOrderThreads, order_lds, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, segids, regB);
+      if (hamming_vec(d / 64) == 2)
+        k_hamming_order<2><<<cq, kOrderThreads, order_lds, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, segids,
+                                                                 regB);
+      else
+        k_hamming_order<1><<<cq, kOrderThreads, order_lds, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, segids,
+                                                                 regB);
       LAUNCH_TRY("k_hamming_order");
       t4.stop();
       // learned budget: features, then bfloat16 MFMA inference -> limits

@@ -126,7 +126,9 @@ __global__ void k_fill(T *__restrict__ dst, long long n, T v) {
 // coordinates in ascending order exactly as defined.
 //
 // The heap of Algorithm 1 pops cells in ascending key (cost, i, j) with
-// cost = d1s[i] + d2s[j]; since cost is monotone in i and in j the popped
+// cost = d1s[i] + d2s[j].  For K <= 64 the pops are replayed directly (one
+// lane per sorted row, a wavefront argmin per pop) while they number at most
+// kPopCap.  Otherwise: since cost is monotone in i and in j the popped
 // prefix is exactly {cells with key <= key of the cutoff cell}.  The cutoff
 // is the smallest key whose prefix holds >= budget ids.  It is found by
 // bisection over the bit patterns of the float64 cost (monotone for
@@ -136,9 +138,11 @@ __global__ void k_fill(T *__restrict__ dst, long long n, T v) {
 // ordered by (i, j).  The k_size-th key (rank weights) is found the same way
 // counting cells instead of ids.
 // ---------------------------------------------------------------------------
+constexpr int kPopCap = 256;  // cells the direct enumeration may pop before bisection takes over
+
 struct SelectLds {
   double *d1s, *d2s, *hd;
-  int *o1, *o2, *rowcnt, *roww, *ptab;
+  int *o1, *o2, *rowcnt, *roww, *ptab, *pops;
   float *qs;
 };
 
@@ -147,6 +151,7 @@ __host__ __device__ inline size_t select_lds_bytes(int k, int h) {
   b += 8 * static_cast<size_t>(k) * 4;                      // d1s, d2s, hd (2k)
   b += 4 * static_cast<size_t>(k) * 4;                      // o1, o2, rowcnt, roww
   b += (k <= 64) ? 4 * static_cast<size_t>(k) * (k + 1) : 0;  // ptab
+  b += (k <= 64) ? 4 * static_cast<size_t>(kPopCap) : 0;      // pops
   b += 4 * 2 * static_cast<size_t>(h);                      // qs
   return (b + 15) / 16 * 16;
 }
@@ -181,6 +186,7 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
     S.rowcnt = reinterpret_cast<int *>(p); p += 4 * k;
     S.roww = reinterpret_cast<int *>(p); p += 4 * k;
     S.ptab = reinterpret_cast<int *>(p); p += (k <= 64) ? 4 * k * (k + 1) : 0;
+    S.pops = reinterpret_cast<int *>(p); p += (k <= 64) ? 4 * kPopCap : 0;
     S.qs = reinterpret_cast<float *>(p);
   }
   const int sub = blockIdx.x, q = blockIdx.y, lane = threadIdx.x;
@@ -218,6 +224,75 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
   }
   __syncthreads();
   const int32_t *off = offsets + static_cast<long long>(sub) * (ncells + 1);
+  int32_t *dst = cells_out + (static_cast<long long>(q) * m + sub) * ncells;
+  double *st = sstat + (static_cast<long long>(q) * m + sub) * 4;
+  const double c1 = S.d1s[0] + S.d2s[0];
+  double c2 = c1;
+  if (k > 1) {
+    const double a = S.d1s[0] + S.d2s[1], b = S.d1s[1] + S.d2s[0];
+    c2 = a < b ? a : b;
+  }
+
+  // ---- direct enumeration (K <= 64: lane i owns sorted row i) ---------------
+  // Each step pops the smallest (cost, i) over the rows' next cells (within
+  // a row cost and j ascend together), i.e. exactly the heap's order, until
+  // the budget is met; typical budgets need a handful of cells.  If kPopCap
+  // cells do not meet it, the bisection below decides instead.
+  if (k <= kWave) {
+    const bool row = lane < k;
+    const double a = row ? S.d1s[lane] : 0.0;
+    const int cbase = row ? S.o1[lane] * k : 0;
+    int j = 0;
+    int cell = row ? cbase + S.o2[0] : 0;
+    int size = row ? off[cell + 1] - off[cell] : 0;
+    double cost = row ? a + S.d2s[0] : __longlong_as_double(0x7ff0000000000000ll);
+    const int big = 1 << 30;
+    int npop = 0, retr = 0;
+    double ccut = 0.0;
+    bool met = false;
+    while (npop < kPopCap) {
+      double bc = cost;
+      int bi = (row && j < k) ? lane : big;
+#pragma unroll
+      for (int sh = 32; sh >= 1; sh >>= 1) {
+        const double oc = __shfl_xor(bc, sh, kWave);
+        const int oi = __shfl_xor(bi, sh, kWave);
+        if (oc < bc || (oc == bc && oi < bi)) { bc = oc; bi = oi; }
+      }
+      const int psz = __shfl(size, bi, kWave);
+      const int pcell = __shfl(cell, bi, kWave);
+      if (lane == 0) S.pops[npop] = pcell | ((phi == 1 && npop < ksize ? 2 : 1) << 24);
+      ++npop;
+      retr += psz;
+      ccut = bc;
+      if (lane == bi) {
+        ++j;
+        if (j < k) {
+          cell = cbase + S.o2[j];
+          size = off[cell + 1] - off[cell];
+          cost = a + S.d2s[j];
+        } else {
+          cost = __longlong_as_double(0x7ff0000000000000ll);
+        }
+      }
+      if (retr >= budget) { met = true; break; }
+    }
+    if (met) {
+      __syncthreads();
+      for (int t = lane; t < npop; t += kWave) dst[t] = S.pops[t];
+      if (lane == 0) {
+        ncell[static_cast<long long>(q) * m + sub] = npop;
+        retrieved[static_cast<long long>(q) * m + sub] = retr;
+        st[0] = c1;
+        st[1] = c2;
+        st[2] = ccut;
+        const int c0 = S.o1[0] * k + S.o2[0];
+        st[3] = static_cast<double>(off[c0 + 1] - off[c0]);
+      }
+      return;
+    }
+  }
+
   int *P = (k <= 64) ? S.ptab : (ptab_g + (static_cast<long long>(q) * m + sub) * k * (k + 1));
   for (int i = lane; i < k; i += kWave) {
     int base = S.o1[i] * k, acc = 0;
@@ -344,7 +419,6 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
   __syncthreads();
 
   // ---- emit (cell | weight << 24), rows in order ----------------------------
-  int32_t *dst = cells_out + (static_cast<long long>(q) * m + sub) * ncells;
   int carry = 0;
   for (int r0 = 0; r0 < k; r0 += kWave) {
     int i = r0 + lane;
@@ -363,13 +437,6 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
     retrieved[static_cast<long long>(q) * m + sub] = retr;
     // statistics for the learned budget: two smallest cell costs, the
     // cutoff cost, and the size of the cheapest cell
-    double *st = sstat + (static_cast<long long>(q) * m + sub) * 4;
-    const double c1 = S.d1s[0] + S.d2s[0];
-    double c2 = c1;
-    if (k > 1) {
-      const double a = S.d1s[0] + S.d2s[1], b = S.d1s[1] + S.d2s[0];
-      c2 = a < b ? a : b;
-    }
     st[0] = c1;
     st[1] = c2;
     st[2] = from_dbits(cstar);
@@ -386,8 +453,9 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
 // load-time cell x tile table); waves take whole slices round robin and
 // stride them with four coalesced id loads in flight per lane.
 // Each of the 16 waves then scans its sixteenth of the counters (16 per lane
-// per step) and writes the ids reaching the threshold, in ascending order, to
-// its own segment; segment counts go to seg_cnt[q][tile][wave].
+// per step, compared four at a time in 16-bit fields) and writes the ids
+// reaching the threshold, in ascending order, to its own segment; segment
+// counts go to seg_cnt[q][tile][wave].
 //
 // pass 0: threshold tau, write candidates, histogram of scores >= max(tau, 1)
 // pass 1: queries flagged for the fallback only: histogram of scores >= 1
@@ -421,6 +489,7 @@ __global__ void __launch_bounds__(kCountThreads) k_count(
   const int tlen = static_cast<int>(min(static_cast<long long>(tile_ids), n - t0));
   const int ndw = tile_ids >> 2;  // counters allocated for a full tile
   const int thr = (pass == 0) ? tau : (pass == 1 ? 1 : tau_eff[q]);
+  const int lane = lane_id();
   uint4 *cnt4 = reinterpret_cast<uint4 *>(cnt);
   for (int i = tid; i < (ndw >> 2); i += kCountThreads) cnt4[i] = make_uint4(0u, 0u, 0u, 0u);
   for (int i = tid; i < 256; i += kCountThreads) S.hist[i] = 0;
@@ -449,33 +518,58 @@ __global__ void __launch_bounds__(kCountThreads) k_count(
         int cell = packed & 0xFFFFFF;
         w = packed >> 24;
         const int32_t *to = tile_off + (static_cast<long long>(s) * ncells + cell) * (ntiles + 1);
-        int a = to[tile];
+        const int a = to[tile];
         len = to[tile + 1] - a;
-        start = static_cast<long long>(s) * n + offsets[static_cast<long long>(s) * (ncells + 1) + cell] + a;
+        start = static_cast<long long>(s) * n + a;
       }
       S.pref[it] = len;
       S.start[it] = start;
       S.w[it] = static_cast<unsigned char>(w);
     }
     __syncthreads();
-    // Waves take whole items (posting-list slices) round robin; each lane
-    // strides the slice with four coalesced loads in flight.
-    for (int it = wave_id(); it < nb; it += kCountWaves) {
-      const long long st = S.start[it];
-      const int len = S.pref[it];
-      const uint32_t wgt = S.w[it];
-      for (int p0 = lane_id(); p0 < len; p0 += 4 * kWave) {
-        int idv[4];
+    // Waves take whole items (posting-list slices, a few dozen ids each on
+    // average) round robin, kG at a time: the first 64 ids of kG slices are
+    // loaded together, then any longer slice is strided with four coalesced
+    // loads in flight per lane.
+    constexpr int kG = 8;
+    for (int it0 = wave_id(); it0 < nb; it0 += kG * kCountWaves) {
+      int idv[kG], lenv[kG];
+      long long stv[kG];
+      uint32_t wgv[kG];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int p = p0 + u * kWave;
-          idv[u] = ids[st + (p < len ? p : len - 1)];   // clamped: every load is issued
-        }
+      for (int u = 0; u < kG; ++u) {
+        const int it = it0 + u * kCountWaves;
+        const bool ok = it < nb;
+        lenv[u] = ok ? S.pref[it] : 0;
+        stv[u] = ok ? S.start[it] : 0;
+        wgv[u] = ok ? S.w[it] : 0u;
+        // clamped: every load is issued, an empty slice reads element 0
+        const long long a = lenv[u] > 0 ? stv[u] + (lane < lenv[u] ? lane : lenv[u] - 1) : 0;
+        idv[u] = ids[a];
+      }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int loc = idv[u] - static_cast<int>(t0);
-          if (p0 + u * kWave < len && static_cast<unsigned>(loc) < static_cast<unsigned>(tlen))
-            atomicAdd(&cnt[loc >> 2], wgt << ((loc & 3) * 8));
+      for (int u = 0; u < kG; ++u) {
+        const int loc = idv[u] - static_cast<int>(t0);
+        if (lane < lenv[u] && static_cast<unsigned>(loc) < static_cast<unsigned>(tlen))
+          atomicAdd(&cnt[loc >> 2], wgv[u] << ((loc & 3) * 8));
+      }
+#pragma unroll 1
+      for (int u = 0; u < kG; ++u) {
+        const long long st = stv[u];
+        const int len = lenv[u];
+        for (int p0 = kWave + lane; p0 < len; p0 += 4 * kWave) {
+          int iv[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int p = p0 + e * kWave;
+            iv[e] = ids[st + (p < len ? p : len - 1)];   // clamped: every load is issued
+          }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int loc = iv[e] - static_cast<int>(t0);
+            if (p0 + e * kWave < len && static_cast<unsigned>(loc) < static_cast<unsigned>(tlen))
+              atomicAdd(&cnt[loc >> 2], wgv[u] << ((loc & 3) * 8));
+          }
         }
       }
     }
@@ -483,44 +577,52 @@ __global__ void __launch_bounds__(kCountThreads) k_count(
   }
 
   // ---- scan: threshold, histogram, ordered per-wave compaction --------------
-  const int lane = lane_id(), wv = wave_id();
+  const int wv = wave_id();
   const int per_wave = ndw / kCountWaves;            // dwords per wave (multiple of 4)
   const int dw0 = wv * per_wave;
   const unsigned long long below = lanes_below_mask();
   int32_t *dst = seg_ids + static_cast<long long>(q) * n + t0 + static_cast<long long>(dw0) * 4;
   uint8_t *dsc = seg_score + static_cast<long long>(q) * n + t0 + static_cast<long long>(dw0) * 4;
   int run = 0;
+  // Bytes >= thr, four at a time: the even and odd bytes of a dword sit in
+  // 16-bit fields, and adding 256 - thr to a field sets its bit 8 exactly
+  // when the byte is >= thr (no carry leaves the field).
+  const uint32_t add = static_cast<uint32_t>(0x100 - thr) * 0x00010001u;
   for (int v0 = 0; v0 < per_wave; v0 += 4 * kWave) {
     const int dwl = v0 + 4 * lane;                 // this lane's first dword within the wave range
     uint4 v = make_uint4(0u, 0u, 0u, 0u);
     if (dwl < per_wave) v = cnt4[(dw0 + dwl) >> 2];
     const uint32_t words[4] = {v.x, v.y, v.z, v.w};
     const int idbase = (dw0 + dwl) * 4;            // tile-local id of the first counter
-    int c = 0;
+    uint32_t sel = 0;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      int sc = (words[e >> 2] >> (8 * (e & 3))) & 255;
-      bool sel = (dwl < per_wave) && (idbase + e < tlen) && sc >= thr;
-      c += sel ? 1 : 0;
-      if (sel && pass != 2 && sc >= 1) atomicAdd(&S.hist[sc], 1);
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t ge = ((words[j] & 0x00FF00FFu) + add) & 0x01000100u;
+      const uint32_t go = (((words[j] >> 8) & 0x00FF00FFu) + add) & 0x01000100u;
+      const uint32_t b = ((ge >> 8) & 1u) | ((go >> 7) & 2u) | ((ge >> 22) & 4u) | ((go >> 21) & 8u);
+      sel |= b << (4 * j);
     }
+    const int nvalid = (dwl < per_wave) ? min(max(tlen - idbase, 0), 16) : 0;
+    sel &= (nvalid >= 16) ? 0xFFFFu : ((1u << nvalid) - 1u);
+    const int c = __popc(sel);
+    int pos = run;
     if (pass != 1) {
       unsigned long long b0m = __ballot(c & 1), b1m = __ballot(c & 2), b2m = __ballot(c & 4),
                          b3m = __ballot(c & 8), b4m = __ballot(c & 16);
-      int pre = __popcll(b0m & below) + 2 * __popcll(b1m & below) + 4 * __popcll(b2m & below) +
-                8 * __popcll(b3m & below) + 16 * __popcll(b4m & below);
-      int wt = __popcll(b0m) + 2 * __popcll(b1m) + 4 * __popcll(b2m) + 8 * __popcll(b3m) + 16 * __popcll(b4m);
-      int pos = run + pre;
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        int sc = (words[e >> 2] >> (8 * (e & 3))) & 255;
-        if ((dwl < per_wave) && (idbase + e < tlen) && sc >= thr) {
-          dst[pos] = static_cast<int32_t>(t0) + idbase + e;
-          dsc[pos] = static_cast<uint8_t>(sc);
-          ++pos;
-        }
+      pos += __popcll(b0m & below) + 2 * __popcll(b1m & below) + 4 * __popcll(b2m & below) +
+             8 * __popcll(b3m & below) + 16 * __popcll(b4m & below);
+      run += __popcll(b0m) + 2 * __popcll(b1m) + 4 * __popcll(b2m) + 8 * __popcll(b3m) + 16 * __popcll(b4m);
+    }
+    while (sel) {
+      const int e = __ffs(sel) - 1;
+      sel &= sel - 1u;
+      const int sc = (words[e >> 2] >> (8 * (e & 3))) & 255;
+      if (pass != 2 && sc >= 1) atomicAdd(&S.hist[sc], 1);
+      if (pass != 1) {
+        dst[pos] = static_cast<int32_t>(t0) + idbase + e;
+        dsc[pos] = static_cast<uint8_t>(sc);
+        ++pos;
       }
-      run += wt;
     }
   }
   if (pass != 1 && lane == 0) seg_cnt[(static_cast<long long>(q) * ntiles + tile) * kCountWaves + wv] = run;
@@ -611,23 +713,49 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(
 
 // ---------------------------------------------------------------------------
 // A5: Hamming order.  One block per query.  The query's sign code is built by
-// ballots over q' (bit i%64 of word i/64 = [q'_i > 0]).  Candidate code rows
-// are read by 8 lanes each (64 contiguous bytes per step) and popcount(xor)
-// reduced over those lanes; a stable counting sort by distance (ballot
-// matching inside a wavefront) then gives the (hamming, id) order.
+// ballots over q' (bit i%64 of word i/64 = [q'_i > 0]).
+//
+// Distances: each wavefront owns 64 consecutive candidates at a time (one
+// coalesced id load, ids passed between lanes by shuffles, so no block
+// barrier per group).  A code row is read by L lanes (L = the largest power
+// of two with kVec * L <= min(16, words)), each reading kVec consecutive
+// 64-bit words per load (kVec = 2, 16-byte loads, when rows have an even
+// number of words); four rows times four loads per lane are in flight per
+// batch, and the partial popcounts are reduced over the row's L lanes.
+// Order: a stable counting sort by distance, placed by one wavefront (ballot
+// matching gives each lane its rank among equal distances), with the next
+// group's loads issued before the current group is placed.
 // ---------------------------------------------------------------------------
 constexpr int kOrderThreads = 256;
 constexpr int kOrderWaves = kOrderThreads / kWave;
 
+template <int kVec>
+struct CodeVec;
+template <>
+struct CodeVec<1> {
+  using T = unsigned long long;
+  static __device__ __forceinline__ int pop(const uint64_t *qc, int w, T v) { return __popcll(qc[w] ^ v); }
+};
+template <>
+struct CodeVec<2> {
+  using T = ulonglong2;
+  static __device__ __forceinline__ int pop(const uint64_t *qc, int w, T v) {
+    return __popcll(qc[w] ^ v.x) + __popcll(qc[w + 1] ^ v.y);
+  }
+};
+
+__host__ __device__ inline int hamming_vec(int words) { return (words % 2 == 0) ? 2 : 1; }
+
+template <int kVec>
 __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
     const float *__restrict__ qrot, int d, const uint64_t *__restrict__ codes, const int32_t *__restrict__ ncand,
     const int32_t *__restrict__ cand, long long n, int32_t *__restrict__ hm_tmp, int32_t *__restrict__ order,
     int32_t *__restrict__ ham_sorted) {
+  using V = typename CodeVec<kVec>::T;
   extern __shared__ int bins[];          // d + 1
   __shared__ uint64_t qc[128];
-  __shared__ int chunk[kOrderThreads];
   __shared__ int tmp[kOrderWaves + 1];
-  const int q = blockIdx.x, tid = threadIdx.x, lane = lane_id(), wv = wave_id();
+  const int q = blockIdx.x, lane = lane_id(), wv = wave_id();
   const int words = d / 64;
   const int nc = ncand[q];
   const long long qo = static_cast<long long>(q) * n;
@@ -635,63 +763,56 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
     unsigned long long b = __ballot(qrot[static_cast<long long>(q) * d + w * 64 + lane] > 0.0f);
     if (lane == 0) qc[w] = b;
   }
-  for (int i = tid; i <= d; i += kOrderThreads) bins[i] = 0;
+  for (int i = threadIdx.x; i <= d; i += kOrderThreads) bins[i] = 0;
   __syncthreads();
-  // L = the largest power of two <= min(8, words) lanes per code row; lane
-  // `sub` of a row reads words sub, sub + L, ... so the L lanes of a row read
-  // L consecutive words per step.  Candidate ids are staged in LDS 256 at a
-  // time; a wave covers 64 / L rows per step, two steps per round.
-  const int L = words >= 8 ? 8 : words >= 4 ? 4 : words >= 2 ? 2 : 1;
+  const int span = words / kVec;                      // loads that cover a row
+  const int L = span >= 8 ? 8 : span >= 4 ? 4 : span >= 2 ? 2 : 1;
   const int rows_per = kWave / L;
   const int sub = lane % L, rsel = lane / L;
-  const int steps = (words + L - 1) / L;
-  for (int b0 = 0; b0 < nc; b0 += kOrderThreads) {
-    const int nb = min(kOrderThreads, nc - b0);
-    chunk[tid] = cand[qo + b0 + (tid < nb ? tid : 0)];
-    __syncthreads();
-    for (int r = 0; r < kWave; r += 2 * rows_per) {
-      int v[2];
+  const int J = (span + L - 1) / L;                   // loads per row per lane
+  for (int base = wv * kWave; base < nc; base += kOrderWaves * kWave) {
+    const int my_id = cand[qo + min(base + lane, nc - 1)];
+    for (int s0 = 0; s0 < L; s0 += 4) {
+      int hs[4], idr[4];
+      bool rok[4];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int loc = r + u * rows_per + rsel;
-        const int il = wv * kWave + loc;
-        const bool ok = loc < kWave && il < nb;
-        const uint64_t *row = codes + static_cast<long long>(chunk[ok ? il : 0]) * words;
-        int hs = 0;
-        int j = 0;
-        for (; j + 8 <= steps; j += 8) {
-          uint64_t cw[8];
+      for (int u = 0; u < 4; ++u) {
+        const int st = s0 + u;
+        const int r = st * rows_per + rsel;
+        rok[u] = st < L && base + r < nc;
+        idr[u] = __shfl(my_id, rok[u] ? r : 0, kWave);
+        hs[u] = 0;
+      }
+      for (int j0 = 0; j0 < J; j0 += 4) {
+        V cw[4][4];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int w = sub + (j + e) * L;
-            cw[e] = row[w < words ? w : 0];
-          }
+        for (int u = 0; u < 4; ++u) {
+          const V *row = reinterpret_cast<const V *>(codes + static_cast<long long>(idr[u]) * words);
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const int w = sub + (j + e) * L;
-            hs += (w < words) ? __popcll(qc[w] ^ cw[e]) : 0;
+          for (int e = 0; e < 4; ++e) {
+            const int v = sub + (j0 + e) * L;
+            cw[u][e] = row[(rok[u] && v < span) ? v : 0];   // clamped: every load is issued
           }
         }
-        for (; j < steps; ++j) {
-          const int w = sub + j * L;
-          const uint64_t c = row[w < words ? w : 0];
-          hs += (w < words) ? __popcll(qc[w] ^ c) : 0;
-        }
-        v[u] = hs;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int v = sub + (j0 + e) * L;
+            if (rok[u] && v < span) hs[u] += CodeVec<kVec>::pop(qc, v * kVec, cw[u][e]);
+          }
       }
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        int vv = v[u];
-        for (int s2 = L >> 1; s2 >= 1; s2 >>= 1) vv += __shfl_xor(vv, s2, kWave);
-        const int loc = r + u * rows_per + rsel;
-        const int il = wv * kWave + loc;
-        if (sub == 0 && loc < kWave && il < nb) {
-          hm_tmp[qo + b0 + il] = vv;
-          atomicAdd(&bins[vv], 1);
+      for (int u = 0; u < 4; ++u) {
+        int h = hs[u];
+        for (int s2 = L >> 1; s2 >= 1; s2 >>= 1) h += __shfl_xor(h, s2, kWave);
+        if (sub == 0 && rok[u]) {
+          const int r = (s0 + u) * rows_per + rsel;
+          hm_tmp[qo + base + r] = h;
+          atomicAdd(&bins[h], 1);
         }
       }
     }
-    __syncthreads();
   }
   __syncthreads();
   block_exclusive_scan(bins, d + 1, tmp);
@@ -701,14 +822,20 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
   // h, the lowest such lane advances bins[h]; this is a stable counting sort.
   if (wv == 0 && nc > 0) {
     const unsigned long long below = lanes_below_mask();
+    int hv[4], idv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int ic = min(u * kWave + lane, nc - 1);   // clamped: every load is issued
+      hv[u] = hm_tmp[qo + ic];
+      idv[u] = cand[qo + ic];
+    }
     for (int b0 = 0; b0 < nc; b0 += 4 * kWave) {
-      int hv[4], idv[4];
+      int hn[4], in[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int i = b0 + u * kWave + lane;
-        const int ic = i < nc ? i : nc - 1;       // clamped: every load is issued
-        hv[u] = hm_tmp[qo + ic];
-        idv[u] = cand[qo + ic];
+        const int ic = min(b0 + 4 * kWave + u * kWave + lane, nc - 1);
+        hn[u] = hm_tmp[qo + ic];
+        in[u] = cand[qo + ic];
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -729,6 +856,11 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
         __builtin_amdgcn_wave_barrier();
         if (valid && (same & below) == 0) bins[h] += __popcll(same);
         __builtin_amdgcn_wave_barrier();
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        hv[u] = hn[u];
+        idv[u] = in[u];
       }
     }
   }
@@ -1365,7 +1497,7 @@ __global__ void k_tile_offsets(const int32_t *__restrict__ offsets, const int32_
       int mid = (lo + hi) >> 1;
       if (row[mid] < bound) lo = mid + 1; else hi = mid;
     }
-    dst[tt] = lo;
+    dst[tt] = off[c] + lo;  // position in the subspace's id array
   }
 }
 
