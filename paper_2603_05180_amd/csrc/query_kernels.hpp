@@ -1,6 +1,7 @@
 // Query-path kernels of the CRISP engine (Algorithm 1, Sections 4.3.1-4.3.2).
 //
 //   k_rotate_rows   (A0) x' = x R, float64 ascending-i accumulation per output
+//                   on float64 matrix cores
 //   k_select_cells  (A1/A2) Dist_1 / Dist_2 of every half-centroid, then the
 //                   Multi-Sequence cell set + rank weights per (query, subspace)
 //   k_count         (A3/A4) LDS collision counters per (query, id tile),
@@ -17,30 +18,34 @@
 namespace crisp {
 
 // ---------------------------------------------------------------------------
-// A0: rotation.  128x64 output tile per 256-thread block, 8x4 outputs per
-// thread; the k dimension is staged through LDS 16 at a time, converted to
-// float64 once on the way in, with the next slab prefetched into registers.
-// Every output accumulates its D products in ascending k in float64
-// (products of two float32 are exact in float64, so the fused form equals
-// the unfused definition).
+// A0: rotation on float64 matrix cores.  v_mfma_f64_16x16x4_f64 adds its four
+// products to the accumulator one after another in k order, rounding after
+// each addition (checked bit for bit on gfx950), and products of two float32
+// values are exact in float64; so chaining the instructions in ascending k
+// gives every output exactly the ascending-k float64 sum of its definition.
+// 128x64 output tile per 256-thread block, 64x32 per wavefront (4x2 tiles of
+// 16x16); the k dimension is staged through LDS 16 at a time, converted to
+// float64 on the way in, with the next slab prefetched into registers.
 // ---------------------------------------------------------------------------
 constexpr int kRotBM = 128, kRotBN = 64, kRotBK = 16;
+typedef double rot_acc_t __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256) k_rotate_rows(const float *__restrict__ x, long long rows, int d,
                                                      const float *__restrict__ r, float *__restrict__ out) {
-  // Rows padded by two doubles: the transposing stores of a wave then fall in
-  // distinct banks, and 16-byte reads stay aligned.
+  // [k][row] / [k][col]: the 16 lanes of one k read 16 consecutive doubles;
+  // rows padded by two doubles so the four k of a fragment use other banks.
   __shared__ __align__(16) double sa[kRotBK][kRotBM + 2];
   __shared__ __align__(16) double sb[kRotBK][kRotBN + 2];
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int fi = lane & 15, fk = lane >> 4;          // fragment row / k of this lane
+  const int wr = (wv >> 1) * 64, wc = (wv & 1) * 32; // the wavefront's 64x32 sub-tile
   const long long row0 = static_cast<long long>(blockIdx.y) * kRotBM;
   const int col0 = blockIdx.x * kRotBN;
-  double acc[8][4];
+  rot_acc_t acc[4][2];
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int j = 0; j < 2; ++j) acc[i][j] = rot_acc_t{0.0, 0.0, 0.0, 0.0};
   float ra[8], rb[4];
   auto gload = [&](int k0) {
 #pragma unroll
@@ -73,34 +78,29 @@ __global__ void __launch_bounds__(256) k_rotate_rows(const float *__restrict__ x
     __syncthreads();
     if (k0 + kRotBK < d) gload(k0 + kRotBK);
 #pragma unroll
-    for (int kk = 0; kk < kRotBK; ++kk) {
-      double a[8], b[4];
+    for (int kk = 0; kk < kRotBK; kk += 4) {
+      double a[4], b[2];
 #pragma unroll
-      for (int i = 0; i < 8; i += 2) {
-        const double2 v = *reinterpret_cast<const double2 *>(&sa[kk][ty * 8 + i]);
-        a[i] = v.x; a[i + 1] = v.y;
-      }
+      for (int i = 0; i < 4; ++i) a[i] = sa[kk + fk][wr + i * 16 + fi];
 #pragma unroll
-      for (int j = 0; j < 4; j += 2) {
-        const double2 v = *reinterpret_cast<const double2 *>(&sb[kk][tx * 4 + j]);
-        b[j] = v.x; b[j + 1] = v.y;
-      }
+      for (int j = 0; j < 2; ++j) b[j] = sb[kk + fk][wc + j * 16 + fi];
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
+  // Accumulator element v of lane l holds row fk + 4v, column fi of its tile.
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const long long gr = row0 + ty * 8 + i;
-    if (gr < rows) {
-      float4 o = make_float4(static_cast<float>(acc[i][0]), static_cast<float>(acc[i][1]),
-                             static_cast<float>(acc[i][2]), static_cast<float>(acc[i][3]));
-      *reinterpret_cast<float4 *>(&out[gr * d + col0 + tx * 4]) = o;
-    }
-  }
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const long long gr = row0 + wr + i * 16 + fk + 4 * v;
+        if (gr < rows) out[gr * d + col0 + wc + j * 16 + fi] = static_cast<float>(acc[i][j][v]);
+      }
 }
 
 __global__ void k_copy_f32(const float *__restrict__ src, float *__restrict__ dst, long long n) {
