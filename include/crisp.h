@@ -232,6 +232,40 @@ crisp_status crisp_search(crisp_index *index, const float *queries, int64_t nq, 
                           void *hip_stream);
 
 /*
+ * Batch executor for uneven batch sizes (serving; each query still runs
+ * Algorithm 1 exactly as crisp_search does, with identical results).
+ * A plan serves batches of 1..max_batch queries with fixed k and parameters
+ * (params->limits must be NULL; the learned budget uses budget_source 1).
+ * Batch sizes are grouped in power-of-two buckets; the first batch of a
+ * bucket captures the whole search pipeline for the bucket's largest size
+ * into a HIP graph (on a private stream), and every later batch of that
+ * bucket replays it: the queries are copied into the plan's staging buffer,
+ * a device-side count of live queries makes the kernels skip the padding,
+ * and the results are copied out.
+ *   crisp_plan_bytes  -- device bytes the plan's buffer needs (workspace for
+ *                        max_batch queries, staging for queries and results).
+ *   crisp_plan_create -- `buffer` (device, caller-owned, kept alive until
+ *                        crisp_plan_free) is carved into those parts.  The
+ *                        index must outlive the plan.
+ *   crisp_plan_search -- enqueues one batch on hip_stream (device pointers:
+ *                        queries nq*D float32, ids nq*k int64, dists nq*k
+ *                        float32); 0 <= nq <= max_batch.  Batches of one
+ *                        plan must be stream-ordered: they share the staging
+ *                        buffers.  Capturing a new bucket synchronises the
+ *                        private stream only.
+ *   crisp_plan_free   -- releases the graphs and the private stream.
+ */
+typedef struct crisp_plan crisp_plan;
+crisp_status crisp_plan_bytes(const crisp_index *index, int32_t max_batch, int32_t k,
+                              const crisp_search_params *params, size_t *bytes);
+crisp_status crisp_plan_create(crisp_index *index, int32_t max_batch, int32_t k,
+                               const crisp_search_params *params, void *buffer, size_t bytes,
+                               crisp_plan **out);
+crisp_status crisp_plan_search(crisp_plan *plan, const float *queries, int64_t nq, int64_t *ids,
+                               float *dists, void *hip_stream);
+crisp_status crisp_plan_free(crisp_plan *plan);
+
+/*
  * Row rotation x' = x R with the float64 ascending-order definition above
  * (Section 3; used for queries, and for the data set when building).
  *   x -- device float32 [rows][d]; r -- device float32 [d][d]; out -- device

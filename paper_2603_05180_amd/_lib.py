@@ -71,6 +71,12 @@ _SIGS = {
                                                ctypes.POINTER(c_size_t)]),
     "crisp_search": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, ctypes.POINTER(SearchParams), c_void_p,
                                c_void_p, c_void_p, c_size_t, ctypes.POINTER(Taps), c_void_p]),
+    "crisp_plan_bytes": (c_int32, [c_void_p, c_int32, c_int32, ctypes.POINTER(SearchParams),
+                                   ctypes.POINTER(c_size_t)]),
+    "crisp_plan_create": (c_int32, [c_void_p, c_int32, c_int32, ctypes.POINTER(SearchParams), c_void_p, c_size_t,
+                                    ctypes.POINTER(c_void_p)]),
+    "crisp_plan_search": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]),
+    "crisp_plan_free": (c_int32, [c_void_p]),
     "crisp_rotate_rows": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p]),
     "crisp_build_covariance": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_int64, c_void_p, c_void_p]),
     "crisp_build_assign": (c_int32, [c_void_p, c_int64, c_int32, c_int32, c_int32, c_void_p, c_int64, c_void_p,

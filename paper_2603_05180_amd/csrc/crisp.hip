@@ -304,17 +304,19 @@ static crisp_status tap_copy(void *dst, const void *src, size_t bytes, hipStream
   return CRISP_OK;
 }
 
-crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int32_t k,
-                          const crisp_search_params *p, int64_t *ids, float *dists, void *workspace,
-                          size_t ws_bytes, const crisp_taps *taps, void *hip_stream) {
-  crisp_status s = check_params(ix, nq, k, p);
-  if (s != CRISP_OK) return s;
-  if (nq == 0) return CRISP_OK;
-  if (!queries || !ids || !dists || !workspace) return fail(CRISP_E_INVALID, "null argument");
+}  // extern "C"
+
+// The search pipeline.  live: NULL, or a device array with one count per
+// chunk of qc queries; kernels then skip the queries of chunk c at or beyond
+// live[c] (a captured graph sized for a batch-size bucket runs any smaller
+// batch this way).
+static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t nq, int32_t k,
+                                const crisp_search_params *p, int64_t *ids, float *dists, void *workspace,
+                                size_t ws_bytes, const crisp_taps *taps, hipStream_t st, const int32_t *live_base) {
+  crisp_status s = CRISP_OK;
   const long long qc = chunk_of(p, nq);
   const Layout L = make_layout(ix, qc);
   if (ws_bytes < L.total) return fail(CRISP_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
   char *ws = static_cast<char *>(workspace);
   float *qrot = reinterpret_cast<float *>(ws + L.qrot);
   double *hdist = reinterpret_cast<double *>(ws + L.hdist);
@@ -361,14 +363,16 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
   for (long long q0 = 0; q0 < nq; q0 += qc) {
     const int cq = static_cast<int>(std::min<long long>(qc, nq - q0));
     const float *qin = queries + q0 * d;
+    const int32_t *lv = live_base ? live_base + q0 / qc : nullptr;
     // A0
     StageTimer t0(ix, 0, st);
     if (ix->rot) {
       dim3 g(d / kRotBN, (cq + kRotBM - 1) / kRotBM);
-      k_rotate_rows<<<g, 256, 0, st>>>(qin, cq, d, ix->rot, qrot);
+      k_rotate_rows<<<g, 256, 0, st>>>(qin, cq, d, ix->rot, qrot, lv);
       LAUNCH_TRY("k_rotate_rows");
     } else {
-      k_copy_f32<<<grid1(static_cast<long long>(cq) * d, 256), 256, 0, st>>>(qin, qrot, static_cast<long long>(cq) * d);
+      k_copy_f32<<<grid1(static_cast<long long>(cq) * d, 256), 256, 0, st>>>(qin, qrot, static_cast<long long>(cq) * d,
+                                                                             lv, d);
       LAUNCH_TRY("k_copy_f32");
     }
     t0.stop();
@@ -378,7 +382,7 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
       dim3 g(m, cq);
       k_select_cells<<<g, 64, select_lds_bytes(kh, ix->h), st>>>(qrot, d, ix->cent_t, m, kh, ix->h, ix->off,
                                                                   budget, k, p->mode, hdist, ptab, ncell, cells,
-                                                                  retr, sstat);
+                                                                  retr, sstat, lv);
       LAUNCH_TRY("k_select_cells");
       t2.stop();
     }
@@ -390,22 +394,22 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
       dim3 g(ix->ntiles, cq);
       k_count<<<g, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
                                                    ix->ntiles, ix->tile, 0, p->tau, flag, taueff, segids, segscore,
-                                                   tilecnt, hist);
+                                                   tilecnt, hist, lv);
       LAUNCH_TRY("k_count pass 0");
-      k_flag<<<grid1(cq, 4), 256, 0, st>>>(tilecnt, nseg, cq, k, p->tau, flag, taueff, hist, nb);
+      k_flag<<<grid1(cq, 4), 256, 0, st>>>(tilecnt, nseg, cq, k, p->tau, flag, taueff, hist, nb, lv);
       LAUNCH_TRY("k_flag");
       k_count<<<g, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
                                                    ix->ntiles, ix->tile, 1, p->tau, flag, taueff, segids, segscore,
-                                                   tilecnt, hist);
+                                                   tilecnt, hist, lv);
       LAUNCH_TRY("k_count pass 1");
-      k_tau_eff<<<grid1(cq, 256), 256, 0, st>>>(flag, cq, k, p->tau, nb, hist, taueff, tilecnt, nseg);
+      k_tau_eff<<<grid1(cq, 256), 256, 0, st>>>(flag, cq, k, p->tau, nb, hist, taueff, tilecnt, nseg, lv);
       LAUNCH_TRY("k_tau_eff");
       k_count<<<g, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
                                                    ix->ntiles, ix->tile, 2, p->tau, flag, taueff, segids, segscore,
-                                                   tilecnt, hist);
+                                                   tilecnt, hist, lv);
       LAUNCH_TRY("k_count pass 2");
       k_compact<<<cq, kCompactThreads, 0, st>>>(segids, segscore, tilecnt, nseg, ix->tile / kCountWaves, n, cand,
-                                                 score, ncand);
+                                                 score, ncand, lv);
       LAUNCH_TRY("k_compact");
     }
     t3.stop();
@@ -415,20 +419,20 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
       StageTimer t4(ix, 4, st);
       if (hamming_vec(d / 64) == 2)
         k_hamming_order<2><<<cq, kOrderThreads, order_lds, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, segids,
-                                                                 regB);
+                                                                 regB, lv);
       else
         k_hamming_order<1><<<cq, kOrderThreads, order_lds, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, segids,
-                                                                 regB);
+                                                                 regB, lv);
       LAUNCH_TRY("k_hamming_order");
       t4.stop();
       // learned budget: features, then bfloat16 MFMA inference -> limits
       if (p->budget_source == 1 || (taps && taps->features)) {
         StageTimer t6(ix, 6, st);
-        k_features<<<grid1(cq, 256), 256, 0, st>>>(cq, m, d, k, 1, ncand, hist, taueff, sstat, regB, n, feat);
+        k_features<<<grid1(cq, 256), 256, 0, st>>>(cq, m, d, k, 1, ncand, hist, taueff, sstat, regB, n, feat, lv);
         LAUNCH_TRY("k_features");
         if (p->budget_source == 1) {
           k_mlp_limits<<<(cq + 15) / 16, 64, 0, st>>>(cq, nf, feat, ix->mlp_mean, ix->mlp_std, ix->mlp_params,
-                                                      ix->mlp_delta, k, ncand, llim, nullptr);
+                                                      ix->mlp_delta, k, ncand, llim, nullptr, lv);
           LAUNCH_TRY("k_mlp_limits");
           if (!lim) lim = llim;
         }
@@ -439,7 +443,7 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
       rerank1<<<cq, kRerankThreads, rr_lds, st>>>(qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
                                                         segids, n, k, patience, lim, regC, nullptr, nullptr,
                                                         ids + q0 * k,
-                                                        dists + q0 * k, exam, lastu, stopd, refd);
+                                                        dists + q0 * k, exam, lastu, stopd, refd, lv);
       LAUNCH_TRY("k_rerank");
       t5.stop();
     } else {
@@ -447,7 +451,7 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
       rerank0<<<cq, kRerankThreads, rr_lds, st>>>(qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
                                                         cand, n, k, patience, lim, regC,
                                                         reinterpret_cast<float *>(regA), regB, ids + q0 * k,
-                                                        dists + q0 * k, exam, lastu, stopd, refd);
+                                                        dists + q0 * k, exam, lastu, stopd, refd, lv);
       LAUNCH_TRY("k_rerank");
       t5.stop();
     }
@@ -477,6 +481,160 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
                                                  size_t(cq) * 4, st))) return s;
     }
   }
+  return CRISP_OK;
+}
+
+__global__ void k_set_live(int32_t *__restrict__ live, int nq, int qc, int nch) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < nch) live[c] = max(0, min(qc, nq - c * qc));
+}
+
+// A batch executor: one captured graph per batch-size bucket.
+struct crisp_plan {
+  crisp_index *ix = nullptr;
+  int max_batch = 0, k = 0, nbuckets = 0;
+  crisp_search_params p{};
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  float *q_stage = nullptr;
+  int64_t *id_stage = nullptr;
+  float *d_stage = nullptr;
+  int32_t *live = nullptr;
+  hipStream_t cap = nullptr;  // private stream the graphs are captured on
+  std::vector<hipGraphExec_t> exec;
+};
+
+namespace {
+struct PlanLayout {
+  size_t ws, q, ids, dists, live, total;
+};
+PlanLayout plan_layout(const crisp_index *ix, int max_batch, int k, const crisp_search_params *p) {
+  PlanLayout L{};
+  const long long qc = chunk_of(p, max_batch);
+  const long long nch = (max_batch + qc - 1) / qc;
+  L.ws = 0;
+  L.q = align_up(make_layout(ix, qc).total);
+  L.ids = L.q + align_up(static_cast<size_t>(max_batch) * ix->d * 4);
+  L.dists = L.ids + align_up(static_cast<size_t>(max_batch) * k * 8);
+  L.live = L.dists + align_up(static_cast<size_t>(max_batch) * k * 4);
+  L.total = L.live + align_up(static_cast<size_t>(nch) * 4);
+  return L;
+}
+int bucket_of(const crisp_plan *pl, int64_t nq) {
+  int b = 0;
+  while ((1ll << b) < nq) ++b;
+  return std::min(b, pl->nbuckets - 1);
+}
+long long bucket_size(const crisp_plan *pl, int b) { return std::min<long long>(1ll << b, pl->max_batch); }
+}  // namespace
+
+extern "C" {
+
+crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int32_t k,
+                          const crisp_search_params *p, int64_t *ids, float *dists, void *workspace,
+                          size_t ws_bytes, const crisp_taps *taps, void *hip_stream) {
+  crisp_status s = check_params(ix, nq, k, p);
+  if (s != CRISP_OK) return s;
+  if (nq == 0) return CRISP_OK;
+  if (!queries || !ids || !dists || !workspace) return fail(CRISP_E_INVALID, "null argument");
+  return search_impl(ix, queries, nq, k, p, ids, dists, workspace, ws_bytes, taps,
+                     static_cast<hipStream_t>(hip_stream), nullptr);
+}
+
+crisp_status crisp_plan_bytes(const crisp_index *ix, int32_t max_batch, int32_t k, const crisp_search_params *p,
+                              size_t *bytes) {
+  if (!bytes) return fail(CRISP_E_INVALID, "null argument");
+  if (max_batch < 1) return fail(CRISP_E_INVALID, "max_batch must be >= 1");
+  crisp_status s = check_params(ix, max_batch, k, p);
+  if (s != CRISP_OK) return s;
+  if (p->limits) return fail(CRISP_E_INVALID, "plans take no per-query limits (use budget_source 1)");
+  *bytes = plan_layout(ix, max_batch, k, p).total;
+  return CRISP_OK;
+}
+
+crisp_status crisp_plan_create(crisp_index *ix, int32_t max_batch, int32_t k, const crisp_search_params *p,
+                               void *buffer, size_t bytes, crisp_plan **out) {
+  if (!out || !buffer) return fail(CRISP_E_INVALID, "null argument");
+  size_t need = 0;
+  crisp_status s = crisp_plan_bytes(ix, max_batch, k, p, &need);
+  if (s != CRISP_OK) return s;
+  if (bytes < need) return fail(CRISP_E_WORKSPACE, "plan buffer %zu < %zu bytes", bytes, need);
+  const PlanLayout L = plan_layout(ix, max_batch, k, p);
+  crisp_plan *pl = new (std::nothrow) crisp_plan{};
+  if (!pl) return fail(CRISP_E_INVALID, "out of host memory");
+  char *b = static_cast<char *>(buffer);
+  pl->ix = ix; pl->max_batch = max_batch; pl->k = k; pl->p = *p;
+  pl->ws = b + L.ws; pl->ws_bytes = L.q - L.ws;
+  pl->q_stage = reinterpret_cast<float *>(b + L.q);
+  pl->id_stage = reinterpret_cast<int64_t *>(b + L.ids);
+  pl->d_stage = reinterpret_cast<float *>(b + L.dists);
+  pl->live = reinterpret_cast<int32_t *>(b + L.live);
+  while ((1ll << pl->nbuckets) < max_batch) ++pl->nbuckets;
+  ++pl->nbuckets;
+  pl->exec.assign(pl->nbuckets, nullptr);
+  hipError_t e = hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete pl;
+    return fail(CRISP_E_HIP, "hipStreamCreateWithFlags: %s", hipGetErrorString(e));
+  }
+  *out = pl;
+  return CRISP_OK;
+}
+
+static crisp_status plan_capture(crisp_plan *pl, int b) {
+  const long long nb = bucket_size(pl, b);
+  crisp_index *ix = pl->ix;
+  const bool prof = ix->prof_on;
+  ix->prof_on = false;
+  HIP_TRY(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
+  crisp_status s = search_impl(ix, pl->q_stage, nb, pl->k, &pl->p, pl->id_stage, pl->d_stage, pl->ws, pl->ws_bytes,
+                               nullptr, pl->cap, pl->live);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(pl->cap, &g);
+  ix->prof_on = prof;
+  if (s != CRISP_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return fail(CRISP_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(CRISP_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  pl->exec[b] = x;
+  return CRISP_OK;
+}
+
+crisp_status crisp_plan_search(crisp_plan *pl, const float *queries, int64_t nq, int64_t *ids, float *dists,
+                               void *hip_stream) {
+  if (!pl) return fail(CRISP_E_INVALID, "null plan");
+  if (nq < 0 || nq > pl->max_batch) return fail(CRISP_E_INVALID, "nq must be in [0, max_batch]");
+  if (nq == 0) return CRISP_OK;
+  if (!queries || !ids || !dists) return fail(CRISP_E_INVALID, "null argument");
+  const int b = bucket_of(pl, nq);
+  if (!pl->exec[b]) {
+    crisp_status s = plan_capture(pl, b);
+    if (s != CRISP_OK) return s;
+  }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const long long qc = chunk_of(&pl->p, bucket_size(pl, b));
+  const int nch = static_cast<int>((bucket_size(pl, b) + qc - 1) / qc);
+  const int d = pl->ix->d, k = pl->k;
+  HIP_TRY(hipMemcpyAsync(pl->q_stage, queries, static_cast<size_t>(nq) * d * 4, hipMemcpyDeviceToDevice, st));
+  k_set_live<<<grid1(nch, 64), 64, 0, st>>>(pl->live, static_cast<int>(nq), static_cast<int>(qc), nch);
+  LAUNCH_TRY("k_set_live");
+  HIP_TRY(hipGraphLaunch(pl->exec[b], st));
+  HIP_TRY(hipMemcpyAsync(ids, pl->id_stage, static_cast<size_t>(nq) * k * 8, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemcpyAsync(dists, pl->d_stage, static_cast<size_t>(nq) * k * 4, hipMemcpyDeviceToDevice, st));
+  return CRISP_OK;
+}
+
+crisp_status crisp_plan_free(crisp_plan *pl) {
+  if (!pl) return CRISP_OK;
+  for (auto &x : pl->exec)
+    if (x) (void)hipGraphExecDestroy(x);
+  if (pl->cap) (void)hipStreamDestroy(pl->cap);
+  delete pl;
   return CRISP_OK;
 }
 
@@ -577,7 +735,7 @@ crisp_status crisp_rotate_rows(const float *x, int64_t rows, int32_t d, const fl
   if ((rows + kRotBM - 1) / kRotBM > 65535) return fail(CRISP_E_UNSUPPORTED, "too many rows for one call");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   dim3 g(d / kRotBN, static_cast<unsigned>((rows + kRotBM - 1) / kRotBM));
-  k_rotate_rows<<<g, 256, 0, st>>>(x, rows, d, r, out);
+  k_rotate_rows<<<g, 256, 0, st>>>(x, rows, d, r, out, nullptr);
   LAUNCH_TRY("k_rotate_rows");
   return CRISP_OK;
 }

@@ -22,9 +22,9 @@ __host__ __device__ inline int n_features(int m) { return 1 + 16 + 3 * m + kHamP
 __global__ void k_features(int nq, int m, int d, int k, int have_ham, const int32_t *__restrict__ ncand,
                            const int32_t *__restrict__ hist, const int32_t *__restrict__ tau_eff,
                            const double *__restrict__ sstat, const int32_t *__restrict__ ham_sorted, long long n,
-                           float *__restrict__ feat) {
+                           float *__restrict__ feat, const int32_t *__restrict__ live) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nq) return;
+  if (q >= nq || (live && q >= *live)) return;
   const int nf = n_features(m);
   float *f = feat + static_cast<long long>(q) * nf;
   const int nc = ncand[q];
@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(64) k_mlp_limits(int nq, int nf, const float *
                                                    const float *__restrict__ mean, const float *__restrict__ sdev,
                                                    const float *__restrict__ params, double delta, int k,
                                                    const int32_t *__restrict__ ncand, int32_t *__restrict__ limits,
-                                                   float *__restrict__ yout) {
+                                                   float *__restrict__ yout, const int32_t *__restrict__ live) {
   const int lane = threadIdx.x;
   const int q0 = blockIdx.x * 16;
   const int row = lane & 15, kq = lane >> 4;          // A: row of the tile, k quad
@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(64) k_mlp_limits(int nq, int nf, const float *
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int q = q0 + 4 * kq + i;
-      if (q < nq) {
+      if (q < nq && (!live || q < *live)) {
         const float y = part[i] + b2;
         if (yout) yout[q] = y;
         const int nc = ncand[q];

@@ -30,8 +30,10 @@ namespace crisp {
 constexpr int kRotBM = 128, kRotBN = 64, kRotBK = 16;
 typedef double rot_acc_t __attribute__((ext_vector_type(4)));
 
+// live: NULL, or a device count of the rows to produce (rows beyond it are skipped).
 __global__ void __launch_bounds__(256) k_rotate_rows(const float *__restrict__ x, long long rows, int d,
-                                                     const float *__restrict__ r, float *__restrict__ out) {
+                                                     const float *__restrict__ r, float *__restrict__ out,
+                                                     const int32_t *__restrict__ live) {
   // [k][row] / [k][col]: the 16 lanes of one k read 16 consecutive doubles;
   // rows padded by two doubles so the four k of a fragment use other banks.
   __shared__ __align__(16) double sa[kRotBK][kRotBM + 2];
@@ -41,6 +43,8 @@ __global__ void __launch_bounds__(256) k_rotate_rows(const float *__restrict__ x
   const int wr = (wv >> 1) * 64, wc = (wv & 1) * 32; // the wavefront's 64x32 sub-tile
   const long long row0 = static_cast<long long>(blockIdx.y) * kRotBM;
   const int col0 = blockIdx.x * kRotBN;
+  if (live) rows = min(rows, static_cast<long long>(*live));
+  if (row0 >= rows) return;
   rot_acc_t acc[4][2];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -103,7 +107,9 @@ __global__ void __launch_bounds__(256) k_rotate_rows(const float *__restrict__ x
       }
 }
 
-__global__ void k_copy_f32(const float *__restrict__ src, float *__restrict__ dst, long long n) {
+__global__ void k_copy_f32(const float *__restrict__ src, float *__restrict__ dst, long long n,
+                           const int32_t *__restrict__ live, long long row_len) {
+  if (live) n = min(n, static_cast<long long>(*live) * row_len);
   long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   long long stride = static_cast<long long>(gridDim.x) * blockDim.x;
   for (; i < n; i += stride) dst[i] = src[i];
@@ -173,7 +179,7 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
                                                      int32_t *__restrict__ ptab_g, int32_t *__restrict__ ncell,
                                                      int32_t *__restrict__ cells_out,
                                                      int32_t *__restrict__ retrieved,
-                                                     double *__restrict__ sstat) {
+                                                     double *__restrict__ sstat, const int32_t *__restrict__ live) {
   extern __shared__ __align__(16) unsigned char dyn[];
   SelectLds S;
   {
@@ -190,6 +196,7 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
     S.qs = reinterpret_cast<float *>(p);
   }
   const int sub = blockIdx.x, q = blockIdx.y, lane = threadIdx.x;
+  if (live && q >= *live) return;
   const int ncells = k * k;
   const float *qa = qrot + static_cast<long long>(q) * d + sub * 2 * h;
   for (int t = lane; t < 2 * h; t += kWave) S.qs[t] = qa[t];
@@ -480,10 +487,11 @@ __global__ void __launch_bounds__(kCountThreads) k_count(
     const int32_t *__restrict__ tile_off, int ntiles, int tile_ids, int pass, int tau,
     const int32_t *__restrict__ flag, const int32_t *__restrict__ tau_eff,
     int32_t *__restrict__ seg_ids, uint8_t *__restrict__ seg_score, int32_t *__restrict__ seg_cnt,
-    int32_t *__restrict__ hist) {
+    int32_t *__restrict__ hist, const int32_t *__restrict__ live) {
   extern __shared__ __align__(16) uint32_t cnt[];
   __shared__ CountShared S;
   const int tile = blockIdx.x, q = blockIdx.y, tid = threadIdx.x;
+  if (live && q >= *live) return;
   if (pass != 0 && flag[q] == 0) return;
   const long long t0 = static_cast<long long>(tile) * tile_ids;
   const int tlen = static_cast<int>(min(static_cast<long long>(tile_ids), n - t0));
@@ -638,9 +646,9 @@ __global__ void __launch_bounds__(kCountThreads) k_count(
 // points reach it.
 __global__ void k_flag(const int32_t *__restrict__ seg_cnt, int nseg, int nq, int k, int tau,
                        int32_t *__restrict__ flag, int32_t *__restrict__ tau_eff, int32_t *__restrict__ hist,
-                       int nbins) {
+                       int nbins, const int32_t *__restrict__ live) {
   const int q = blockIdx.x * (blockDim.x / kWave) + wave_id();
-  if (q >= nq) return;
+  if (q >= nq || (live && q >= *live)) return;
   const int lane = lane_id();
   int tot = 0;
   for (int t = lane; t < nseg; t += kWave) tot += seg_cnt[static_cast<long long>(q) * nseg + t];
@@ -658,9 +666,9 @@ __global__ void k_flag(const int32_t *__restrict__ seg_cnt, int nseg, int nq, in
 // >= s, else 1; keep the histogram only from tau_eff up.
 __global__ void k_tau_eff(const int32_t *__restrict__ flag, int nq, int k, int tau, int nbins,
                           int32_t *__restrict__ hist, int32_t *__restrict__ tau_eff,
-                          int32_t *__restrict__ seg_cnt, int nseg) {
+                          int32_t *__restrict__ seg_cnt, int nseg, const int32_t *__restrict__ live) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nq || flag[q] == 0) return;
+  if (q >= nq || (live && q >= *live) || flag[q] == 0) return;
   int32_t *hq = hist + static_cast<long long>(q) * nbins;
   int ge = 0;
   for (int s = nbins - 1; s > tau; --s) ge += hq[s];
@@ -680,11 +688,12 @@ constexpr int kCompactThreads = 256;
 __global__ void __launch_bounds__(kCompactThreads) k_compact(
     const int32_t *__restrict__ seg_ids, const uint8_t *__restrict__ seg_score, const int32_t *__restrict__ seg_cnt,
     int nseg, int seg_len, long long n, int32_t *__restrict__ cand, uint8_t *__restrict__ score,
-    int32_t *__restrict__ ncand) {
+    int32_t *__restrict__ ncand, const int32_t *__restrict__ live) {
   __shared__ int base[kCompactThreads + 1];
   __shared__ int tmp[kCompactThreads / kWave + 1];
   __shared__ int carry;
   const int q = blockIdx.x, tid = threadIdx.x;
+  if (live && q >= *live) return;
   const long long qo = static_cast<long long>(q) * n;
   const int32_t *sc = seg_cnt + static_cast<long long>(q) * nseg;
   if (tid == 0) carry = 0;
@@ -750,12 +759,13 @@ template <int kVec>
 __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
     const float *__restrict__ qrot, int d, const uint64_t *__restrict__ codes, const int32_t *__restrict__ ncand,
     const int32_t *__restrict__ cand, long long n, int32_t *__restrict__ hm_tmp, int32_t *__restrict__ order,
-    int32_t *__restrict__ ham_sorted) {
+    int32_t *__restrict__ ham_sorted, const int32_t *__restrict__ live) {
   using V = typename CodeVec<kVec>::T;
   extern __shared__ int bins[];          // d + 1
   __shared__ uint64_t qc[128];
   __shared__ int tmp[kOrderWaves + 1];
   const int q = blockIdx.x, lane = lane_id(), wv = wave_id();
+  if (live && q >= *live) return;
   const int words = d / 64;
   const int nc = ncand[q];
   const long long qo = static_cast<long long>(q) * n;
@@ -1191,7 +1201,7 @@ __global__ void __launch_bounds__(kRerankThreads) k_rerank(
     const int32_t *__restrict__ limits, double *__restrict__ dkey, float *__restrict__ lbuf,
     int32_t *__restrict__ rbuf, int64_t *__restrict__ out_ids, float *__restrict__ out_d,
     int32_t *__restrict__ examined, int32_t *__restrict__ last_upd, int32_t *__restrict__ stopped,
-    int32_t *__restrict__ refined) {
+    int32_t *__restrict__ refined, const int32_t *__restrict__ live) {
   extern __shared__ __align__(16) unsigned char dyn[];
   const RerankLds LL = rerank_lds(d, k, kBf16);
   float *sq = reinterpret_cast<float *>(dyn);
@@ -1203,6 +1213,7 @@ __global__ void __launch_bounds__(kRerankThreads) k_rerank(
   int *xpc = reinterpret_cast<int *>(dyn + LL.pc);
   __shared__ RerankShared S;
   const int q = blockIdx.x, tid = threadIdx.x, lane = lane_id(), wv = wave_id();
+  if (live && q >= *live) return;
   const long long qo = static_cast<long long>(q) * n;
   for (int i = tid; i < d; i += kRerankThreads) sq[i] = qrot[static_cast<long long>(q) * d + i];
   const int nc = ncand[q];

@@ -108,12 +108,15 @@ class Index:
         return SearchParams(int(mode), float(alpha), int(tau), int(patience_factor), _ptr(limits), int(max_chunk),
                             int(budget_source), int(precision))
 
-    def enable_bf16(self, stream=None) -> torch.Tensor:
+    def enable_bf16(self, stream=None, buffer: torch.Tensor | None = None) -> torch.Tensor:
         """bfloat16 copy of the rows + per-row error bounds for precision=1
-        (the buffer is kept alive by the index)."""
+        (the buffer is kept alive by the index; another index over the same
+        rows may pass its buffer to share it)."""
         b = ctypes.c_size_t(0)
         check(lib.crisp_index_bf16_bytes(self._h, ctypes.byref(b)))
-        buf = torch.empty(b.value, dtype=torch.uint8, device=self.device)
+        buf = buffer if buffer is not None else torch.empty(b.value, dtype=torch.uint8, device=self.device)
+        if buf.numel() < b.value:
+            raise ValueError("bfloat16 buffer too small")
         check(lib.crisp_index_enable_bf16(self._h, _ptr(buf), b.value, _stream(stream)))
         self._bf16 = buf
         return buf
@@ -203,6 +206,48 @@ class Index:
                                _ptr(ws), ws.numel(), ctypes.byref(tp) if tp is not None else None,
                                _stream(stream)))
         return ids, dists
+
+
+class Plan:
+    """Batch executor for uneven batches (crisp_plan_*): one captured HIP
+    graph per power-of-two batch-size bucket, replayed for every batch of
+    that bucket.  Results equal Index.search with the same parameters."""
+
+    def __init__(self, index: Index, max_batch: int, k: int, **params):
+        if params.get("limits") is not None:
+            raise ValueError("plans take no per-query limits")
+        self._p = index.params(**params)
+        b = ctypes.c_size_t(0)
+        check(lib.crisp_plan_bytes(index._h, int(max_batch), int(k), ctypes.byref(self._p), ctypes.byref(b)))
+        self._buf = torch.empty(b.value, dtype=torch.uint8, device=index.device)
+        h = ctypes.c_void_p(0)
+        check(lib.crisp_plan_create(index._h, int(max_batch), int(k), ctypes.byref(self._p), _ptr(self._buf),
+                                    b.value, ctypes.byref(h)))
+        self._h = h
+        self.index, self.max_batch, self.k = index, int(max_batch), int(k)
+
+    def search(self, queries: torch.Tensor, out: tuple | None = None, stream=None):
+        if queries.device != self.index.device or queries.dtype != torch.float32 or not queries.is_contiguous():
+            raise ValueError("queries must be a contiguous float32 tensor on the index device")
+        nq = int(queries.shape[0])
+        if out is None:
+            ids = torch.empty(nq, self.k, dtype=torch.int64, device=self.index.device)
+            dists = torch.empty(nq, self.k, dtype=torch.float32, device=self.index.device)
+        else:
+            ids, dists = out
+        check(lib.crisp_plan_search(self._h, _ptr(queries), nq, _ptr(ids), _ptr(dists), _stream(stream)))
+        return ids, dists
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            lib.crisp_plan_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 # ----------------------------------------------------------------------------

@@ -1,0 +1,92 @@
+"""Uneven batches on the GPU (needs an MI355X): the batch executor's captured
+graphs must return exactly what a direct search returns, for every batch
+size of a bucket, replay after replay with other GPU work in between; and
+results must not depend on the id tile or the query chunk."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as omlp
+from parity_util import gpu_index, make_workload, oracle_index
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [1, 2, 3, 7, 16, 33, 64, 65, 100, 5, 1, 100, 47]
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    w, x, q = make_workload("cfg1", n_query=300)
+    idx = oracle_index(w, x)
+    g = gpu_index(idx)
+    g.enable_bf16()
+    return w, x, torch.from_numpy(q).cuda(), idx, g
+
+
+def _same(a, b):
+    ia, da = a
+    ib, db = b
+    torch.cuda.synchronize()
+    assert torch.equal(ia, ib)
+    assert torch.equal(da.view(torch.int32), db.view(torch.int32))
+
+
+@pytest.mark.parametrize("mode,precision,k", [(0, 0, 10), (0, 1, 1), (1, 0, 10), (1, 1, 100)])
+def test_plan_replays_match_direct_search(cfg1, mode, precision, k):
+    from paper_2603_05180_amd import engine
+    w, x, q, idx, g = cfg1
+    kw = dict(mode=mode, alpha=0.05, tau=4, precision=precision)
+    plan = engine.Plan(g, 100, k, **kw)
+    o = 0
+    for rep in range(2):
+        for nb in SIZES:
+            print(f"plan mode={mode} precision={precision} k={k} batch={nb} rep={rep}", flush=True)
+            qb = q[o:o + nb].contiguous()
+            o = (o + nb) % 200
+            got = plan.search(qb)
+            ref = g.search(qb, k, **kw)           # eager work between replays
+            _same(got, ref)
+    plan.free()
+
+
+def test_plan_several_chunks_per_bucket(cfg1):
+    from paper_2603_05180_amd import engine
+    w, x, q, idx, g = cfg1
+    kw = dict(mode=1, alpha=0.05, tau=4, max_chunk=16)
+    plan = engine.Plan(g, 100, 10, **kw)
+    for nb in (100, 17, 64, 99, 33):
+        print(f"chunked plan batch={nb}", flush=True)
+        qb = q[:nb].contiguous()
+        _same(plan.search(qb), g.search(qb, 10, **kw))
+
+
+def test_plan_with_learned_budget(cfg1):
+    from paper_2603_05180_amd import engine
+    w, x, q, idx, g = cfg1
+    f = g.n_features
+    p = omlp.init_params(f, 3)
+    p["b2"] = np.array([3.5], np.float32)
+    flat = np.concatenate([p["w1"].reshape(-1), p["b1"], p["w2"], p["b2"]]).astype(np.float32)
+    g.set_budget_model(torch.from_numpy(flat).cuda(), torch.zeros(f, device="cuda"), torch.ones(f, device="cuda"),
+                       0.5)
+    kw = dict(mode=1, alpha=0.05, tau=4, budget_source=1, precision=1)
+    plan = engine.Plan(g, 64, 10, **kw)
+    for nb in (64, 3, 40, 1):
+        print(f"learned plan batch={nb}", flush=True)
+        qb = q[100:100 + nb].contiguous()
+        _same(plan.search(qb), g.search(qb, 10, **kw))
+    g.set_budget_model(None)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_results_do_not_depend_on_tiles_or_chunks(cfg1, mode):
+    from paper_2603_05180_amd import engine
+    w, x, q, idx, g = cfg1
+    kw = dict(mode=mode, alpha=0.05, tau=4)
+    ref = g.search(q, 10, **kw)
+    for tile in (4096, 8192, 131072):
+        print(f"tile={tile} mode={mode}", flush=True)
+        gt = engine.Index(g.arrays | {"n": g.n, "d": g.d, "m": g.m, "k_half": g.k_half}, tile_ids=tile)
+        for chunk in (0, 7, 64):
+            _same(gt.search(q, 10, max_chunk=chunk, **kw), ref)
+        gt.free()
