@@ -237,7 +237,7 @@ def main():
     per_step = {
         "rotate": ("alu", 2.0 * d * d * w.n_query / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"),
         "count": ("hbm", (4.0 * c["retrieved"] + 5.0 * c["n_cand"] * 2) / 1e9, HBM_PEAK_GBS, "GB/s"),
-        "hamming_order": ("hbm", (d / 8.0 * c["n_cand"] + 12.0 * c["n_cand"]) / 1e9, HBM_PEAK_GBS, "GB/s"),
+        "hamming_dist": ("hbm", (d / 8.0 + 8.0) * c["n_cand"] / 1e9, HBM_PEAK_GBS, "GB/s"),
         "rerank": ("hbm", rerank_bytes / 1e9, HBM_PEAK_GBS, "GB/s"),
     }
     stage_out = {}
@@ -254,7 +254,7 @@ def main():
     dom = max((s for s in stage_out if s in per_step), key=lambda s: stage_out[s]["ms_per_step"])
     launches = stage_out[dom]["launches_per_step"]
     roof = {"kernel": {"rerank": "k_rerank", "count": "k_count", "rotate": "k_rotate_rows",
-                       "hamming_order": "k_hamming_order"}[dom],
+                       "hamming_dist": "k_hamming_dist"}[dom],
             "bound": per_step[dom][0], "achieved": stage_out[dom]["achieved"], "peak": per_step[dom][2],
             "unit": per_step[dom][3], "frac": stage_out[dom]["frac"], "traffic": None,
             "avg_launch_ms": round(stage_out[dom]["ms_per_step"] / launches, 4),

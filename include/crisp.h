@@ -156,6 +156,10 @@ crisp_status crisp_index_enable_bf16(crisp_index *index, void *buffer, size_t by
  *                      from the result.  Both give identical ids and
  *                      distances (every deciding comparison uses the exact
  *                      float64 key); 1 reads fewer bytes.
+ *   persistent      -- 0: the re-rank launches one block per query.  1: it
+ *                      launches about as many blocks as fit on the chip,
+ *                      each pulling queries from a device-side counter (same
+ *                      results; the batch executor's tuner picks per bucket).
  */
 typedef struct {
   int32_t mode;
@@ -166,6 +170,7 @@ typedef struct {
   int32_t max_chunk;
   int32_t budget_source;
   int32_t precision;
+  int32_t persistent;
 } crisp_search_params;
 
 /*
@@ -372,10 +377,10 @@ crisp_status crisp_mlp_adam(float *params, const float *grad, float *m1, float *
 
 /*
  * GPU time per query stage, measured with HIP events recorded on the search
- * stream around each stage's launches.  Stages: 0 rotation (A0), 1 unused,
- * 2 half distances + cell selection (A1/A2), 3 collision counting, fallback
- * and candidate lists (A3/A4), 4 Hamming order (A5), 5 re-rank (A6/A7),
- * 6 learned-budget features and inference.
+ * stream around each stage's launches.  Stages: 0 rotation, 1 Hamming
+ * order placement, 2 half distances + cell selection, 3 collision counting,
+ * fallback and candidate lists, 4 Hamming distances, 5 re-rank (exact keys,
+ * top-k or patience walk), 6 learned-budget features and inference.
  */
 typedef struct {
   double ms[8];

@@ -34,14 +34,14 @@ class IndexDesc(ctypes.Structure):
 class SearchParams(ctypes.Structure):
     _fields_ = [("mode", c_int32), ("alpha", c_double), ("tau", c_int32),
                 ("patience_factor", c_int32), ("limits", c_void_p), ("max_chunk", c_int32),
-                ("budget_source", c_int32), ("precision", c_int32)]
+                ("budget_source", c_int32), ("precision", c_int32), ("persistent", c_int32)]
 
 
 class Profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 8), ("intervals", c_int64 * 8), ("dropped", c_int64)]
 
 
-STAGES = ["rotate", "unused", "select", "count", "hamming_order", "rerank", "budget"]
+STAGES = ["rotate", "hamming_place", "select", "count", "hamming_dist", "rerank", "budget"]
 
 TAP_FIELDS = ["q_rot", "half_dist", "n_cells", "cells", "retrieved", "hist", "tau_eff", "n_cand",
               "cand", "cand_score", "order", "hamming", "examined", "last_update", "stopped", "features",

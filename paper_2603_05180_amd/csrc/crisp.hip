@@ -79,6 +79,7 @@ struct crisp_index {
   const float *rerr = nullptr;       // per-row bound of the bfloat16 rounding error
   int32_t *tile_off;
   float *cent_t;  // [M][2][h][K]
+  int ncu = 256;  // compute units of the device the index was loaded on
   // learned budget model (borrowed device pointers; null when unset)
   const float *mlp_params = nullptr, *mlp_mean = nullptr, *mlp_std = nullptr;
   int mlp_nf = 0;
@@ -116,7 +117,7 @@ struct StageTimer {
 // Workspace layout for one chunk of qc queries.
 struct Layout {
   size_t qrot, hdist, ptab, ncell, cells, retr, tilecnt, hist, flag, taueff, ncand, segids, segscore, cand,
-      score, regA, regB, regC, examined, lastupd, stopped, refined, sstat, feat, lim, total;
+      score, regA, regB, regC, examined, lastupd, stopped, refined, sstat, feat, lim, queue, total;
 };
 
 static Layout make_layout(const crisp_index *ix, long long qc) {
@@ -149,6 +150,7 @@ static Layout make_layout(const crisp_index *ix, long long qc) {
   L.sstat = take(qc * ix->m * 4 * 8);
   L.feat = take(qc * n_features(ix->m) * 4);
   L.lim = take(qc * 4);
+  L.queue = take(4);
   L.total = o;
   return L;
 }
@@ -231,6 +233,12 @@ crisp_status crisp_index_load(const crisp_index_desc *desc, int32_t tile_ids, vo
   ix->rot = desc->rotation; ix->cent = desc->centroids; ix->base = desc->base;
   ix->off = desc->offsets; ix->ids = desc->ids; ix->codes = desc->codes; ix->tile_off = tile_off;
   ix->cent_t = cent_t;
+  {
+    int dev = 0, cu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+      ix->ncu = cu;
+  }
   *out = ix;
   return CRISP_OK;
 }
@@ -286,6 +294,7 @@ static crisp_status check_params(const crisp_index *ix, int64_t nq, int32_t k, c
   if (p->budget_source == 1 && !ix->mlp_params) return fail(CRISP_E_INVALID, "no budget model set");
   if (p->precision != 0 && p->precision != 1) return fail(CRISP_E_INVALID, "precision must be 0 or 1");
   if (p->precision == 1 && !ix->base16) return fail(CRISP_E_INVALID, "precision 1 needs crisp_index_enable_bf16");
+  if (p->persistent != 0 && p->persistent != 1) return fail(CRISP_E_INVALID, "persistent must be 0 or 1");
   return CRISP_OK;
 }
 
@@ -340,6 +349,7 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
   int32_t *lastu = reinterpret_cast<int32_t *>(ws + L.lastupd);
   int32_t *stopd = reinterpret_cast<int32_t *>(ws + L.stopped);
   int32_t *refd = reinterpret_cast<int32_t *>(ws + L.refined);
+  int32_t *queue = reinterpret_cast<int32_t *>(ws + L.queue);
   double *sstat = reinterpret_cast<double *>(ws + L.sstat);
   float *feat = reinterpret_cast<float *>(ws + L.feat);
   int32_t *llim = reinterpret_cast<int32_t *>(ws + L.lim);
@@ -359,6 +369,14 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
   const double gam = lterms / (1.0 - lterms);
   auto rerank0 = bf16 ? k_rerank<0, true> : k_rerank<0, false>;
   auto rerank1 = bf16 ? k_rerank<1, true> : k_rerank<1, false>;
+  // Persistent re-rank: as many blocks as fit on the chip at once.
+  int rr_resident = 0;
+  if (p->persistent) {
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(p->mode == 0 ? rerank0 : rerank1), kRerankThreads, rr_lds));
+    rr_resident = std::max(1, per_cu) * ix->ncu;
+  }
 
   for (long long q0 = 0; q0 < nq; q0 += qc) {
     const int cq = static_cast<int>(std::min<long long>(qc, nq - q0));
@@ -416,15 +434,21 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
     const int32_t *lim = p->limits ? p->limits + q0 : nullptr;
     if (p->mode == 1) {
       // A5
-      StageTimer t4(ix, 4, st);
-      if (hamming_vec(d / 64) == 2)
-        k_hamming_order<2><<<cq, kOrderThreads, order_lds, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, segids,
-                                                                 regB, lv);
-      else
-        k_hamming_order<1><<<cq, kOrderThreads, order_lds, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, segids,
-                                                                 regB, lv);
-      LAUNCH_TRY("k_hamming_order");
+      StageTimer t4(ix, 4, st);  // distances
+      {
+        const int gx = static_cast<int>(std::max(1, std::min(64, (4096 + cq - 1) / cq)));
+        dim3 g(gx, cq);
+        if (hamming_vec(d / 64) == 2)
+          k_hamming_dist<2><<<g, kOrderThreads, 0, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, lv);
+        else
+          k_hamming_dist<1><<<g, kOrderThreads, 0, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, lv);
+        LAUNCH_TRY("k_hamming_dist");
+      }
       t4.stop();
+      StageTimer t1(ix, 1, st);  // order
+      k_hamming_place<<<cq, kOrderThreads, order_lds, st>>>(d, ncand, cand, n, regA, segids, regB, lv);
+      LAUNCH_TRY("k_hamming_place");
+      t1.stop();
       // learned budget: features, then bfloat16 MFMA inference -> limits
       if (p->budget_source == 1 || (taps && taps->features)) {
         StageTimer t6(ix, 6, st);
@@ -440,18 +464,28 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       }
       // A6 / A7
       StageTimer t5(ix, 5, st);
-      rerank1<<<cq, kRerankThreads, rr_lds, st>>>(qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
+      if (p->persistent) {
+        k_fill<int32_t><<<1, 64, 0, st>>>(queue, 1, 0);
+        LAUNCH_TRY("k_fill");
+      }
+      rerank1<<<p->persistent ? std::min(cq, rr_resident) : cq, kRerankThreads, rr_lds, st>>>(qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
                                                         segids, n, k, patience, lim, regC, nullptr, nullptr,
                                                         ids + q0 * k,
-                                                        dists + q0 * k, exam, lastu, stopd, refd, lv);
+                                                        dists + q0 * k, exam, lastu, stopd, refd, lv, cq,
+                                                        p->persistent ? queue : nullptr);
       LAUNCH_TRY("k_rerank");
       t5.stop();
     } else {
       StageTimer t5(ix, 5, st);
-      rerank0<<<cq, kRerankThreads, rr_lds, st>>>(qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
+      if (p->persistent) {
+        k_fill<int32_t><<<1, 64, 0, st>>>(queue, 1, 0);
+        LAUNCH_TRY("k_fill");
+      }
+      rerank0<<<p->persistent ? std::min(cq, rr_resident) : cq, kRerankThreads, rr_lds, st>>>(qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
                                                         cand, n, k, patience, lim, regC,
                                                         reinterpret_cast<float *>(regA), regB, ids + q0 * k,
-                                                        dists + q0 * k, exam, lastu, stopd, refd, lv);
+                                                        dists + q0 * k, exam, lastu, stopd, refd, lv, cq,
+                                                        p->persistent ? queue : nullptr);
       LAUNCH_TRY("k_rerank");
       t5.stop();
     }

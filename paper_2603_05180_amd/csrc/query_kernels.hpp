@@ -7,7 +7,8 @@
 //   k_count         (A3/A4) LDS collision counters per (query, id tile),
 //                   threshold, ordered compaction, score histogram
 //   k_flag / k_tau_eff / k_compact (A4) fallback rule and candidate lists
-//   k_hamming_order (A5) Hamming distance + stable counting sort
+//   k_hamming_dist / k_hamming_place (A5) Hamming distances, then a stable
+//                   counting sort per query
 //   k_rerank        (A6/A7) exact float64 keys, top-k / patience walk; the
 //                   bfloat16 variant first bounds every row from a bfloat16
 //                   copy and reads float32 rows only where the bound matters
@@ -721,19 +722,24 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(
 }
 
 // ---------------------------------------------------------------------------
-// A5: Hamming order.  One block per query.  The query's sign code is built by
-// ballots over q' (bit i%64 of word i/64 = [q'_i > 0]).
+// A5: Hamming order, in two kernels.
 //
-// Distances: each wavefront owns 64 consecutive candidates at a time (one
-// coalesced id load, ids passed between lanes by shuffles, so no block
-// barrier per group).  A code row is read by L lanes (L = the largest power
-// of two with kVec * L <= min(16, words)), each reading kVec consecutive
-// 64-bit words per load (kVec = 2, 16-byte loads, when rows have an even
-// number of words); four rows times four loads per lane are in flight per
-// batch, and the partial popcounts are reduced over the row's L lanes.
-// Order: a stable counting sort by distance, placed by one wavefront (ballot
-// matching gives each lane its rank among equal distances), with the next
-// group's loads issued before the current group is placed.
+// k_hamming_dist: grid (gx, queries), gx chosen from the batch size so that a
+// small batch still spreads over the chip.  Each wavefront takes 64
+// consecutive candidates at a time (one coalesced id load, ids passed
+// between lanes by shuffles), striding over the query's list with the
+// other gx * 4 - 1 wavefronts of its query.  The query's sign code is built
+// by ballots over q' (bit i%64 of word i/64 = [q'_i > 0]).  A code row is
+// read by L lanes (L = the largest power of two with kVec * L <= min(16,
+// words)), each reading kVec consecutive 64-bit words per load (kVec = 2,
+// 16-byte loads, when rows have an even number of words); four rows times
+// four loads per lane are in flight per batch, and the partial popcounts are
+// reduced over the row's L lanes.
+//
+// k_hamming_place: one block per query builds the distance histogram in
+// LDS, scans it, and one wavefront places the candidates (a stable counting
+// sort: ballot matching gives each lane its rank among equal distances),
+// with the next group's loads issued before the current group is placed.
 // ---------------------------------------------------------------------------
 constexpr int kOrderThreads = 256;
 constexpr int kOrderWaves = kOrderThreads / kWave;
@@ -756,15 +762,12 @@ struct CodeVec<2> {
 __host__ __device__ inline int hamming_vec(int words) { return (words % 2 == 0) ? 2 : 1; }
 
 template <int kVec>
-__global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
+__global__ void __launch_bounds__(kOrderThreads) k_hamming_dist(
     const float *__restrict__ qrot, int d, const uint64_t *__restrict__ codes, const int32_t *__restrict__ ncand,
-    const int32_t *__restrict__ cand, long long n, int32_t *__restrict__ hm_tmp, int32_t *__restrict__ order,
-    int32_t *__restrict__ ham_sorted, const int32_t *__restrict__ live) {
+    const int32_t *__restrict__ cand, long long n, int32_t *__restrict__ hm_tmp, const int32_t *__restrict__ live) {
   using V = typename CodeVec<kVec>::T;
-  extern __shared__ int bins[];          // d + 1
   __shared__ uint64_t qc[128];
-  __shared__ int tmp[kOrderWaves + 1];
-  const int q = blockIdx.x, lane = lane_id(), wv = wave_id();
+  const int q = blockIdx.y, lane = lane_id(), wv = wave_id();
   if (live && q >= *live) return;
   const int words = d / 64;
   const int nc = ncand[q];
@@ -773,14 +776,14 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
     unsigned long long b = __ballot(qrot[static_cast<long long>(q) * d + w * 64 + lane] > 0.0f);
     if (lane == 0) qc[w] = b;
   }
-  for (int i = threadIdx.x; i <= d; i += kOrderThreads) bins[i] = 0;
   __syncthreads();
   const int span = words / kVec;                      // loads that cover a row
   const int L = span >= 8 ? 8 : span >= 4 ? 4 : span >= 2 ? 2 : 1;
   const int rows_per = kWave / L;
   const int sub = lane % L, rsel = lane / L;
   const int J = (span + L - 1) / L;                   // loads per row per lane
-  for (int base = wv * kWave; base < nc; base += kOrderWaves * kWave) {
+  const int stride = gridDim.x * kOrderWaves * kWave;
+  for (int base = (blockIdx.x * kOrderWaves + wv) * kWave; base < nc; base += stride) {
     const int my_id = cand[qo + min(base + lane, nc - 1)];
     for (int s0 = 0; s0 < L; s0 += 4) {
       int hs[4], idr[4];
@@ -816,14 +819,25 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
       for (int u = 0; u < 4; ++u) {
         int h = hs[u];
         for (int s2 = L >> 1; s2 >= 1; s2 >>= 1) h += __shfl_xor(h, s2, kWave);
-        if (sub == 0 && rok[u]) {
-          const int r = (s0 + u) * rows_per + rsel;
-          hm_tmp[qo + base + r] = h;
-          atomicAdd(&bins[h], 1);
-        }
+        if (sub == 0 && rok[u]) hm_tmp[qo + base + (s0 + u) * rows_per + rsel] = h;
       }
     }
   }
+}
+
+__global__ void __launch_bounds__(kOrderThreads) k_hamming_place(
+    int d, const int32_t *__restrict__ ncand, const int32_t *__restrict__ cand, long long n,
+    const int32_t *__restrict__ hm_tmp, int32_t *__restrict__ order, int32_t *__restrict__ ham_sorted,
+    const int32_t *__restrict__ live) {
+  extern __shared__ int bins[];          // d + 1
+  __shared__ int tmp[kOrderWaves + 1];
+  const int q = blockIdx.x, lane = lane_id(), wv = wave_id();
+  if (live && q >= *live) return;
+  const int nc = ncand[q];
+  const long long qo = static_cast<long long>(q) * n;
+  for (int i = threadIdx.x; i <= d; i += kOrderThreads) bins[i] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < nc; i += kOrderThreads) atomicAdd(&bins[hm_tmp[qo + i]], 1);
   __syncthreads();
   block_exclusive_scan(bins, d + 1, tmp);
   // bins[h] = first position of distance h.  One wavefront places the
@@ -1193,15 +1207,20 @@ __device__ inline void select_topk(const double *__restrict__ keys, const int32_
 // kMode: 0 Guaranteed, 1 Optimized.  kBf16 = false: every verified row read
 // in float32.  kBf16 = true: every row first in bfloat16; float32 only where
 // the bounds cannot exclude it.
+#define CRISP_RERANK_PARAMS                                                                              \
+  const float *__restrict__ qrot, int d, const float *__restrict__ base, const uint16_t *__restrict__ base16, \
+      const float *__restrict__ rerr, double gam, const int32_t *__restrict__ ncand,                          \
+      const int32_t *__restrict__ list, long long n, int k, int patience, const int32_t *__restrict__ limits,  \
+      double *__restrict__ dkey, float *__restrict__ lbuf, int32_t *__restrict__ rbuf,                        \
+      int64_t *__restrict__ out_ids, float *__restrict__ out_d, int32_t *__restrict__ examined,              \
+      int32_t *__restrict__ last_upd, int32_t *__restrict__ stopped, int32_t *__restrict__ refined
+#define CRISP_RERANK_ARGS                                                                                 \
+  qrot, d, base, base16, rerr, gam, ncand, list, n, k, patience, limits, dkey, lbuf, rbuf, out_ids, out_d, \
+      examined, last_upd, stopped, refined
+
+// One query, whole block.
 template <int kMode, bool kBf16>
-__global__ void __launch_bounds__(kRerankThreads) k_rerank(
-    const float *__restrict__ qrot, int d, const float *__restrict__ base,
-    const uint16_t *__restrict__ base16, const float *__restrict__ rerr, double gam,
-    const int32_t *__restrict__ ncand, const int32_t *__restrict__ list, long long n, int k, int patience,
-    const int32_t *__restrict__ limits, double *__restrict__ dkey, float *__restrict__ lbuf,
-    int32_t *__restrict__ rbuf, int64_t *__restrict__ out_ids, float *__restrict__ out_d,
-    int32_t *__restrict__ examined, int32_t *__restrict__ last_upd, int32_t *__restrict__ stopped,
-    int32_t *__restrict__ refined, const int32_t *__restrict__ live) {
+__device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
   extern __shared__ __align__(16) unsigned char dyn[];
   const RerankLds LL = rerank_lds(d, k, kBf16);
   float *sq = reinterpret_cast<float *>(dyn);
@@ -1212,8 +1231,7 @@ __global__ void __launch_bounds__(kRerankThreads) k_rerank(
   double *xub = reinterpret_cast<double *>(dyn + LL.ub);
   int *xpc = reinterpret_cast<int *>(dyn + LL.pc);
   __shared__ RerankShared S;
-  const int q = blockIdx.x, tid = threadIdx.x, lane = lane_id(), wv = wave_id();
-  if (live && q >= *live) return;
+  const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   const long long qo = static_cast<long long>(q) * n;
   for (int i = tid; i < d; i += kRerankThreads) sq[i] = qrot[static_cast<long long>(q) * d + i];
   const int nc = ncand[q];
@@ -1451,6 +1469,32 @@ __global__ void __launch_bounds__(kRerankThreads) k_rerank(
       stopped[q] = S.misc[5];
       if (refined) refined[q] = kBf16 ? S.misc[8] : S.misc[6];
     }
+  }
+}
+
+// queue == NULL: block b re-ranks query b.  Otherwise the grid is persistent
+// (about as many blocks as fit on the chip at once) and every block pulls
+// the next query from the device counter *queue (zero at launch) until the
+// live queries are exhausted; every block then exits.
+template <int kMode, bool kBf16>
+__global__ void __launch_bounds__(kRerankThreads) k_rerank(CRISP_RERANK_PARAMS, const int32_t *__restrict__ live, int nq,
+                                                           int32_t *__restrict__ queue) {
+  if (queue == nullptr) {
+    const int q = blockIdx.x;
+    if (live && q >= *live) return;
+    rerank_query<kMode, kBf16>(q, CRISP_RERANK_ARGS);
+    return;
+  }
+  const int nl = live ? min(nq, *live) : nq;
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+    __syncthreads();
+    const int q = next;
+    __syncthreads();
+    if (q >= nl) return;
+    rerank_query<kMode, kBf16>(q, CRISP_RERANK_ARGS);
+    __syncthreads();
   }
 }
 

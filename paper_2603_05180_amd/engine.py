@@ -104,9 +104,9 @@ class Index:
             {"dropped": pr.dropped}
 
     def params(self, *, mode=0, alpha=0.01, tau=1, patience_factor=40, limits=None, max_chunk=0, budget_source=0,
-               precision=0):
+               precision=0, persistent=0):
         return SearchParams(int(mode), float(alpha), int(tau), int(patience_factor), _ptr(limits), int(max_chunk),
-                            int(budget_source), int(precision))
+                            int(budget_source), int(precision), int(persistent))
 
     def enable_bf16(self, stream=None, buffer: torch.Tensor | None = None) -> torch.Tensor:
         """bfloat16 copy of the rows + per-row error bounds for precision=1
@@ -137,6 +137,7 @@ class Index:
                          std: torch.Tensor | None = None, delta: float = 0.0):
         """Learned verification budget for budget_source=1 (tensors are kept alive here)."""
         self._model = (params, mean, std)
+        self._delta = float(delta)
         check(lib.crisp_set_budget_model(self._h, _ptr(params), self.n_features, _ptr(mean), _ptr(std),
                                          float(delta)))
 
@@ -180,8 +181,8 @@ class Index:
 
     def search(self, queries: torch.Tensor, k: int, *, mode: int = 0, alpha: float = 0.01, tau: int = 1,
                patience_factor: int = 40, limits: torch.Tensor | None = None, max_chunk: int = 0,
-               budget_source: int = 0, precision: int = 0, taps: dict | None = None, out: tuple | None = None,
-               stream=None):
+               budget_source: int = 0, precision: int = 0, persistent: int = 0, taps: dict | None = None,
+               out: tuple | None = None, stream=None):
         """Algorithm 1 for a batch; returns (ids int64 [nq, k], dists f32 [nq, k])."""
         if queries.device != self.device or queries.dtype != torch.float32 or not queries.is_contiguous():
             raise ValueError("queries must be a contiguous float32 tensor on the index device")
@@ -192,7 +193,8 @@ class Index:
             raise ValueError("limits must be an int32 device tensor with one entry per query")
         nq = int(queries.shape[0])
         p = self.params(mode=mode, alpha=alpha, tau=tau, patience_factor=patience_factor,
-                        limits=limits, max_chunk=max_chunk, budget_source=budget_source, precision=precision)
+                        limits=limits, max_chunk=max_chunk, budget_source=budget_source, precision=precision,
+                        persistent=persistent)
         ws = self.workspace(nq, k, p)
         if out is None:
             ids = torch.empty(nq, k, dtype=torch.int64, device=self.device)

@@ -63,7 +63,7 @@ _S32 = np.uint64(32)
 TAG = {
     "noise": 1, "latent": 2, "label": 3, "mean": 4, "factor": 5, "center": 6,
     "rotation": 7, "cev_sample": 8, "kmeans_sample": 9, "kmeans_init": 10,
-    "mlp_init": 11, "mlp_shuffle": 12, "batch": 13,
+    "mlp_init": 11, "mlp_shuffle": 12, "batch": 13, "batch_k": 14,
 }
 
 
@@ -228,6 +228,12 @@ def permutation_prefix(seed: int, tag: int, pool: np.ndarray, s: int) -> np.ndar
     key = (u << _S32) | np.arange(pool.size, dtype=np.uint64)
     order = np.argsort(key, kind="stable")
     return pool[order[:s]]
+
+
+def batch_ks(seed: int, count: int, choices=(1, 10, 100)) -> list[int]:
+    """k of each batch, uniform over ``choices`` (uneven-batching workload)."""
+    u = uniform_u32(seed, TAG["batch_k"], np.arange(count, dtype=np.uint64))
+    return [int(choices[int(v) % len(choices)]) for v in u]
 
 
 def batch_sizes(seed: int, total: int, max_batch: int = 4096) -> list[int]:

@@ -90,3 +90,40 @@ def test_results_do_not_depend_on_tiles_or_chunks(cfg1, mode):
         for chunk in (0, 7, 64):
             _same(gt.search(q, 10, max_chunk=chunk, **kw), ref)
         gt.free()
+
+
+@pytest.mark.parametrize("mode,precision", [(0, 1), (1, 0), (1, 1)])
+def test_persistent_rerank_matches(cfg1, mode, precision):
+    w, x, q, idx, g = cfg1
+    kw = dict(mode=mode, alpha=0.05, tau=4, precision=precision)
+    print(f"persistent mode={mode} precision={precision}", flush=True)
+    for k in (1, 10):
+        _same(g.search(q, k, persistent=1, **kw), g.search(q, k, **kw))
+        _same(g.search(q[:5].contiguous(), k, persistent=1, max_chunk=2, **kw), g.search(q[:5].contiguous(), k, **kw))
+
+
+def test_tuned_runner_serves_uneven_batches(cfg1, tmp_path):
+    """The tuner picks a setting per (k, bucket); every batch served through
+    it equals the direct search."""
+    import synth
+    from paper_2603_05180_amd import autotune
+    w, x, q, idx, g = cfg1
+    params = dict(mode=1, alpha=0.05, tau=4, precision=1)
+    srv = autotune.Server(None, g, params, max_batch=64, ks=(1, 10), tiles=(4096, 16384), chunks=(16, 64))
+    cache = str(tmp_path / "tune.json")
+    choice = srv.tune(q, [1, 2, 4, 8, 16, 32, 64], reps=1, cache=cache)
+    assert len(choice) == 14
+    sizes = synth.batch_sizes(5, 250, max_batch=64)
+    ks = synth.batch_ks(5, len(sizes), choices=(1, 10))
+    lat, outs = srv.run(q, sizes, ks)
+    assert len(lat) == len(sizes) and all(v > 0 for v in lat)
+    o = 0
+    for (ids, d), nq, k in zip(outs, sizes, ks):
+        print(f"runner batch={nq} k={k}", flush=True)
+        _same((ids, d), g.search(q[o:o + nq].contiguous(), k, **params))
+        o += nq
+    # the cache is reused
+    srv2 = autotune.Server(None, g, params, max_batch=64, ks=(1, 10), tiles=(4096, 16384), chunks=(16, 64))
+    assert srv2.tune(q, [1, 2, 4, 8, 16, 32, 64], cache=cache) == choice
+    srv.free()
+    srv2.free()
