@@ -56,6 +56,9 @@ def parse():
                     help="queries the learned budget is trained on (0 = no learned form)")
     ap.add_argument("--train-seed", type=int, default=3004)
     ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--uneven-workload", default="cfg5",
+                    help="workload of the uneven-batch section ('' = skip)")
+    ap.add_argument("--uneven-queries", type=int, default=50_000)
     ap.add_argument("--floor", type=float, default=0.998,
                     help="fraction of the plain top-k the learned budget must keep on held-out queries")
     return ap.parse_args()
@@ -153,25 +156,14 @@ def main():
     if args.nq:
         w = w.scaled(n_query=args.nq)
     dev = torch.device("cuda:0")
-    t_setup = time.time()
-    params = sg.mixture_params(w)
-    x = sg.rows(w, w.seed_data, 0, w.n, params)
+    t = time.time()
+    arrays, params = build_gpu_index(w)
     queries = sg.rows(w, w.seed_query, 0, w.n_query, params)
     torch.cuda.synchronize()
-    log(f"data {w.n}x{w.d} + {w.n_query} queries generated in {time.time() - t_setup:.1f}s")
-    t = time.time()
-    n = w.n
-    cev_rows = synth.sample_indices(w.seed_index, synth.TAG["cev_sample"], n, max(2, min(n // 10, 100_000)))
-    km_rows = synth.sample_indices(w.seed_index, synth.TAG["kmeans_sample"], n, min(n, 100_000))
-    km_init = synth.permutation_prefix(w.seed_index, synth.TAG["kmeans_init"], np.arange(km_rows.size), w.k_half)
-    arrays = engine.build_index(x, w.m, w.k_half, g=lambda: sg.gaussian_matrix(w.seed_index, w.d),
-                                cev_rows=cev_rows, km_rows=km_rows, km_init=km_init, keep_input=False)
-    torch.cuda.synchronize()
-    log(f"index built on the GPU in {time.time() - t:.1f}s (CEV {arrays['cev']:.3f}, "
+    log(f"data {w.n}x{w.d} generated and indexed on the GPU in {time.time() - t:.1f}s (CEV {arrays['cev']:.3f}, "
         f"rotated={arrays['rotation'] is not None})")
     index = engine.Index(arrays, tile_ids=args.tile)
     index.enable_bf16()
-    del x
     k = w.k
     base_kw = dict(mode=args.mode, alpha=args.alpha, tau=args.tau, patience_factor=args.patience,
                    max_chunk=args.max_chunk)
@@ -269,6 +261,7 @@ def main():
 
     for f in results.values():
         f.pop("_kw"); f.pop("_counts")
+    rotated = arrays["rotation"] is not None
     line = {
         "metric": METRIC, "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
@@ -277,7 +270,7 @@ def main():
                                f"{w.n_comp} comps), M={w.m} K={w.k_half}, {w.n_query} queries/batch, k={k}",
                    "mode": "optimized" if args.mode == 1 else "guaranteed", "alpha": args.alpha, "tau": args.tau,
                    "patience_factor": args.patience, "recall_at_10": results[head]["recall_at_10"],
-                   "rotated": arrays["rotation"] is not None,
+                   "rotated": rotated,
                    "mean_candidates": round(c["n_cand"] / w.n_query, 1),
                    "mean_verified": round(c["examined"] / w.n_query, 1), "form": head,
                    "learned_delta": None if model is None else round(model.delta, 4),
@@ -287,7 +280,106 @@ def main():
         "stages": stage_out,
         "cpu_baseline": cpu,
     }
+
+    # ---- uneven batches (served through the tuned batch executor) ------------
+    if args.uneven_workload:
+        del index, arrays, queries, qrot, truth, ids, dists, plain_ids, model
+        torch.cuda.empty_cache()
+        line["uneven_batching"] = uneven_batches(args)
     print(json.dumps(line), flush=True)
+
+
+def build_gpu_index(w):
+    """Seeded data of workload w generated and indexed on the GPU."""
+    import numpy as np
+    import synth
+    import synth.gpu as sg
+    from paper_2603_05180_amd import engine
+    params = sg.mixture_params(w)
+    x = sg.rows(w, w.seed_data, 0, w.n, params)
+    n = w.n
+    cev_rows = synth.sample_indices(w.seed_index, synth.TAG["cev_sample"], n, max(2, min(n // 10, 100_000)))
+    km_rows = synth.sample_indices(w.seed_index, synth.TAG["kmeans_sample"], n, min(n, 100_000))
+    km_init = synth.permutation_prefix(w.seed_index, synth.TAG["kmeans_init"], np.arange(km_rows.size), w.k_half)
+    arrays = engine.build_index(x, w.m, w.k_half, g=lambda: sg.gaussian_matrix(w.seed_index, w.d),
+                                cev_rows=cev_rows, km_rows=km_rows, km_init=km_init, keep_input=False)
+    return arrays, params
+
+
+def uneven_batches(args):
+    """Seeded batches of 1..4096 queries (log-uniform), k in {1, 10, 100},
+    served by the batch executor with the learned budget and the bfloat16
+    pass; the tuner picks tile, chunk and re-rank grid per (k, bucket)
+    first.  Reports per-batch GPU latency percentiles and throughput."""
+    import numpy as np
+    import torch
+    import synth
+    import synth.gpu as sg
+    from paper_2603_05180_amd import autotune, engine, learned
+
+    w = synth.WORKLOADS[args.uneven_workload]
+    t = time.time()
+    arrays, params = build_gpu_index(w)
+    torch.cuda.synchronize()
+    log(f"uneven: {w.name} index N={w.n} D={w.d} built in {time.time() - t:.1f}s")
+    index = engine.Index(arrays)
+    index.enable_bf16()
+    kw = dict(alpha=args.alpha, tau=args.tau, patience_factor=args.patience)
+    model = None
+    if args.train_queries > 0:
+        trainq = sg.rows(w, args.train_seed, 0, args.train_queries, params)
+        model = learned.train_budget(index, trainq, 10, epochs=args.epochs, floor=args.floor, **kw)
+        del trainq
+        torch.cuda.empty_cache()
+    queries = sg.rows(w, w.seed_query, 0, args.uneven_queries, params)
+    sizes = synth.batch_sizes(w.seed_query, args.uneven_queries, max_batch=4096)
+    ks = synth.batch_ks(w.seed_query, len(sizes))
+    sp = dict(kw, mode=1, precision=1, budget_source=1 if model is not None else 0)
+    t = time.time()
+    srv = autotune.Server(None, index, sp, max_batch=4096, ks=(1, 10, 100), tiles=(16384, 65536),
+                          chunks=(512, 1024))
+    choice = srv.tune(queries, [1 << i for i in range(13)], reps=2,
+                      cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
+                      if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
+    torch.cuda.synchronize()
+    log(f"uneven: tuned {len(choice)} (k, bucket) pairs in {time.time() - t:.1f}s")
+    srv.run(queries, sizes[:8], ks[:8])                   # first replays of the common buckets
+    torch.cuda.synchronize()
+    t0 = time.time()
+    lat, outs = srv.run(queries, sizes, ks)
+    wall = time.time() - t0
+    lat = np.asarray(lat)
+    # recall@10 on the batches with k >= 10, a sample of them
+    qrot = engine.rotate_rows(queries[:5000], arrays["rotation"]) if arrays["rotation"] is not None \
+        else queries[:5000]
+    truth = ground_truth(arrays["base"], qrot, 10)
+    hit = tot = 0
+    o = 0
+    for (ids, _), nq, k in zip(outs, sizes, ks):
+        if k >= 10 and o < 5000:
+            m = min(nq, 5000 - o)
+            found = ids[:m, :10]
+            hit += int((found[:, :, None] == truth[o:o + m, None, :]).any(-1).sum())
+            tot += m * 10
+        o += nq
+    tuned = {}
+    for (k, b), (tile, chunk, pers) in sorted(choice.items()):
+        tuned[f"k{k}_b{b}"] = [tile, chunk, pers]
+    out = {"workload": f"{w.name}: N={w.n} D={w.d} correlated Gaussian mixture ({w.kind} rank {w.rank}, "
+                       f"{w.n_comp} comps), M={w.m} K={w.k_half}",
+           "queries": int(sum(sizes)), "batches": len(sizes), "batch_sizes": "log-uniform in [1, 4096]",
+           "k": "uniform over {1, 10, 100}", "form": "learned_bf16" if model is not None else "bf16",
+           "queries_per_s": round(sum(sizes) / (lat.sum() / 1e3), 1),
+           "queries_per_s_wall": round(sum(sizes) / wall, 1),
+           "p50_batch_ms": round(float(np.percentile(lat, 50)), 4),
+           "p99_batch_ms": round(float(np.percentile(lat, 99)), 4),
+           "max_batch_ms": round(float(lat.max()), 4),
+           "recall_at_10_sample": round(hit / max(1, tot), 4),
+           "tuned_tile_chunk_persistent": tuned}
+    log(f"uneven: {out['queries_per_s']} q/s, p50 {out['p50_batch_ms']} ms, p99 {out['p99_batch_ms']} ms")
+    srv.free()
+    index.free()
+    return out
 
 
 def cpu_baseline(arrays, queries, k, kw, budget_s):

@@ -178,15 +178,18 @@ __global__ void k_csr_place(const int32_t *__restrict__ cell_of, long long n, in
   }
 }
 
-// Sign codes: one wave per (row, 64-dim word) via ballot.
+// Sign codes: one wave per (row, 64-dim word) via ballot, striding over all
+// n * D / 64 words (the grid is capped: a dispatch holds < 2^32 threads).
 __global__ void k_codes(const float *__restrict__ x, long long n, int d, uint64_t *__restrict__ codes) {
   const int words = d / 64;
-  long long w = static_cast<long long>(blockIdx.x) * (blockDim.x / kWave) + wave_id();
-  if (w >= n * words) return;
-  long long r = w / words;
-  int c = static_cast<int>(w % words);
-  unsigned long long b = __ballot(x[r * d + c * 64 + lane_id()] > 0.0f);
-  if (lane_id() == 0) codes[w] = b;
+  const long long total = n * words;
+  const long long step = static_cast<long long>(gridDim.x) * (blockDim.x / kWave);
+  for (long long w = static_cast<long long>(blockIdx.x) * (blockDim.x / kWave) + wave_id(); w < total; w += step) {
+    const long long r = w / words;
+    const int c = static_cast<int>(w % words);
+    const unsigned long long b = __ballot(x[r * d + c * 64 + lane_id()] > 0.0f);
+    if (lane_id() == 0) codes[w] = b;
+  }
 }
 
 }  // namespace crisp

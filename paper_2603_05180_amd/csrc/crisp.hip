@@ -54,6 +54,12 @@ inline unsigned grid1(long long n, int block) {
   return static_cast<unsigned>(std::max<long long>(1, std::min<long long>(g, 0x7fffffffll)));
 }
 
+// Blocks for a grid-stride kernel of 256-thread blocks: a dispatch must hold
+// fewer than 2^32 threads, and 65536 blocks keep every CU busy.
+inline unsigned grid_stride(long long n, int per_block) {
+  return static_cast<unsigned>(std::max<long long>(1, std::min<long long>((n + per_block - 1) / per_block, 65536)));
+}
+
 crisp_status check_shape(int64_t n, int32_t d, int32_t m, int32_t k) {
   if (n < 1 || d < 1 || m < 1 || k < 1) return fail(CRISP_E_INVALID, "n, d, m, k must be positive");
   if (n >= (int64_t(1) << 31)) return fail(CRISP_E_UNSUPPORTED, "N must be < 2^31");
@@ -265,7 +271,7 @@ crisp_status crisp_index_enable_bf16(crisp_index *ix, void *buffer, size_t bytes
   uint16_t *b16 = static_cast<uint16_t *>(buffer);
   float *err = reinterpret_cast<float *>(static_cast<char *>(buffer) +
                                          align_up(static_cast<size_t>(ix->n) * ix->d * 2));
-  k_base_bf16<<<grid1(ix->n, 256 / kWave), 256, 0, st>>>(ix->base, ix->n, ix->d, b16, err);
+  k_base_bf16<<<grid_stride(ix->n, 256 / kWave), 256, 0, st>>>(ix->base, ix->n, ix->d, b16, err);
   LAUNCH_TRY("k_base_bf16");
   ix->base16 = b16;
   ix->rerr = err;
@@ -861,7 +867,7 @@ crisp_status crisp_build_codes(const float *x, int64_t n, int32_t d, uint64_t *c
   if (n == 0) return CRISP_OK;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   long long waves = n * (d / 64);
-  k_codes<<<grid1(waves, 4), 256, 0, st>>>(x, n, d, codes);
+  k_codes<<<grid_stride(waves, 4), 256, 0, st>>>(x, n, d, codes);
   LAUNCH_TRY("k_codes");
   return CRISP_OK;
 }

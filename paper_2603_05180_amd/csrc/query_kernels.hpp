@@ -1071,12 +1071,8 @@ __device__ inline void heap_replace_top(double *h, int n, double v) {
   h[i] = v;
 }
 
-// One wavefront per row: bfloat16 copy and an upper bound of ||x - x~||
-// (float64 sum of exact squared differences, widened, rounded up to float).
-__global__ void __launch_bounds__(256) k_base_bf16(const float *__restrict__ base, long long n, int d,
-                                                    uint16_t *__restrict__ b16, float *__restrict__ err) {
-  const long long row = static_cast<long long>(blockIdx.x) * (256 / kWave) + wave_id();
-  if (row >= n) return;
+__device__ __forceinline__ void base_bf16_row(const float *__restrict__ base, long long row, int d,
+                                              uint16_t *__restrict__ b16, float *__restrict__ err) {
   const int lane = lane_id();
   const float *x = base + row * d;
   uint16_t *y = b16 + row * d;
@@ -1096,6 +1092,16 @@ __global__ void __launch_bounds__(256) k_base_bf16(const float *__restrict__ bas
     if (static_cast<double>(f) < e) f = nextafterf(f, __int_as_float(0x7f800000));
     err[row] = f;
   }
+}
+
+// One wavefront per row, striding over the rows (capped grid): bfloat16
+// copy and an upper bound of ||x - x~|| (float64 sum of exact squared
+// differences, widened, rounded up to float).
+__global__ void __launch_bounds__(256) k_base_bf16(const float *__restrict__ base, long long n, int d,
+                                                    uint16_t *__restrict__ b16, float *__restrict__ err) {
+  const long long step = static_cast<long long>(gridDim.x) * (256 / kWave);
+  for (long long row = static_cast<long long>(blockIdx.x) * (256 / kWave) + wave_id(); row < n; row += step)
+    base_bf16_row(base, row, d, b16, err);
 }
 
 // Dynamic LDS of k_rerank: q' (D floats) | top-k keys (k doubles) | top-k ids

@@ -96,3 +96,24 @@ def test_search_on_gpu_built_index_matches_oracle():
     gidx = engine.Index(got)
     for mode in (0, 1):
         compare(ref, q, 10, mode=mode, alpha=0.03, tau=3, gpu=gidx)
+
+
+def test_sign_codes_of_every_row_at_full_size():
+    """N = 2M, D = 3072: 96M code words, more wave-threads than one dispatch
+    holds, so the kernel strides; sampled rows across the whole range
+    (including the last) equal the signs of the rows."""
+    import ctypes
+    import synth.gpu as sg
+    from paper_2603_05180_amd._lib import check, lib
+    w = synth.WORKLOADS["cfg5"]
+    x = sg.rows(w, w.seed_data, 0, w.n, sg.mixture_params(w))
+    words = w.d // 64
+    codes = torch.empty(w.n, words, dtype=torch.int64, device="cuda")
+    check(lib.crisp_build_codes(ctypes.c_void_p(x.data_ptr()), w.n, w.d, ctypes.c_void_p(codes.data_ptr()), None))
+    torch.cuda.synchronize()
+    sh = torch.arange(64, device="cuda", dtype=torch.int64)
+    for r in (0, 1, 1_398_101, 1_398_102, 1_500_000, w.n - 2, w.n - 1):
+        bits = ((codes[r].view(words, 1) >> sh) & 1).bool().view(-1)
+        assert torch.equal(bits, x[r] > 0), r
+    del x, codes
+    torch.cuda.empty_cache()
