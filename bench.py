@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg3")
+    ap.add_argument("--workload", default="d4096")
     ap.add_argument("--n", type=int, default=0, help="override N (smaller dry runs)")
     ap.add_argument("--nq", type=int, default=0, help="override the batch size")
     ap.add_argument("--mode", type=int, default=1, help="0 Guaranteed, 1 Optimized")
@@ -56,7 +56,7 @@ def parse():
                     help="queries the learned budget is trained on (0 = no learned form)")
     ap.add_argument("--train-seed", type=int, default=3004)
     ap.add_argument("--epochs", type=int, default=20)
-    ap.add_argument("--uneven-workload", default="cfg5",
+    ap.add_argument("--uneven-workload", default="d3072",
                     help="workload of the uneven-batch section ('' = skip)")
     ap.add_argument("--uneven-queries", type=int, default=50_000)
     ap.add_argument("--floor", type=float, default=0.998,
@@ -90,6 +90,38 @@ def recall(found, truth):
     k = truth.shape[1]
     hit = (found[:, :, None] == truth[:, None, :]).any(-1).sum().item()
     return hit / float(truth.shape[0] * k)
+
+
+COPY_PROBE_BYTES = 1 << 30
+
+
+def copy_probe():
+    """One plain device-to-device copy of 1 GiB (outside the timed region):
+    the reference a hardware-counter run scales FETCH_SIZE / WRITE_SIZE by."""
+    import ctypes
+    import torch
+    from paper_2603_05180_amd._lib import check, lib
+    src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    check(lib.crisp_copy_probe(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), COPY_PROBE_BYTES,
+                               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when it was taken on other kernel sources or another kernel."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    ent = t.get(kernel)
+    from paper_2603_05180_amd.provenance import source_hash
+    if not ent or ent.get("source_hash") != source_hash() or ent.get("workload") != workload:
+        return None
+    return round(ent["fetch_bytes_per_launch"] + ent["write_bytes_per_launch"], 1)
 
 
 def timed(index, queries, k, kw, steps, ids, dists, profile=False):
@@ -219,6 +251,7 @@ def main():
     ok = [f for f in results if results[f]["recall_at_10"] >= 0.90] or list(results)
     head = max(ok, key=lambda f: results[f]["queries_per_s"])
     kw, c = results[head]["_kw"], results[head]["_counts"]
+    copy_probe()
     ms_step, stages = timed(index, queries, k, kw, args.steps, ids, dists, profile=True)
     qps = w.n_query / (ms_step / 1e3)
 
@@ -248,7 +281,9 @@ def main():
     roof = {"kernel": {"rerank": "k_rerank", "count": "k_count", "rotate": "k_rotate_rows",
                        "hamming_dist": "k_hamming_dist"}[dom],
             "bound": per_step[dom][0], "achieved": stage_out[dom]["achieved"], "peak": per_step[dom][2],
-            "unit": per_step[dom][3], "frac": stage_out[dom]["frac"], "traffic": None,
+            "unit": per_step[dom][3], "frac": stage_out[dom]["frac"],
+            "traffic": measured_traffic({"rerank": "k_rerank", "count": "k_count", "rotate": "k_rotate_rows",
+                                         "hamming_dist": "k_hamming_dist"}[dom], w.name),
             "avg_launch_ms": round(stage_out[dom]["ms_per_step"] / launches, 4),
             "algorithmic_per_launch": round(per_step[dom][1] / launches, 4)}
     if "rerank" in stage_out:

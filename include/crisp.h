@@ -373,6 +373,17 @@ crisp_status crisp_mlp_backward(const float *x, const float *t, int64_t b, int32
 crisp_status crisp_mlp_adam(float *params, const float *grad, float *m1, float *m2, int32_t f, int32_t step,
                             float lr, void *hip_stream);
 
+/* ---- Measurement --------------------------------------------------------- */
+
+/*
+ * Plain device-to-device copy of `bytes` (a multiple of 16; both pointers
+ * 16-byte aligned; the ranges must not overlap) by the kernel k_copy_probe,
+ * which reads and writes exactly `bytes`.  Hardware byte counters
+ * (FETCH_SIZE, WRITE_SIZE) read for it give the factor that turns the
+ * counters read for another kernel in the same run into bytes.
+ */
+crisp_status crisp_copy_probe(void *dst, const void *src, size_t bytes, void *hip_stream);
+
 /* ---- Stage timing ------------------------------------------------------ */
 
 /*

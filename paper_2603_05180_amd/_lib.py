@@ -88,6 +88,7 @@ _SIGS = {
     "crisp_build_combine": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
     "crisp_build_codes": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p]),
     "crisp_profile_begin": (c_int32, [c_void_p, c_int32]),
+    "crisp_copy_probe": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
     "crisp_feature_count": (c_int32, [c_int32]),
     "crisp_mlp_param_count": (c_int32, [c_int32]),
     "crisp_set_budget_model": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_double]),

@@ -678,6 +678,18 @@ crisp_status crisp_plan_free(crisp_plan *pl) {
   return CRISP_OK;
 }
 
+crisp_status crisp_copy_probe(void *dst, const void *src, size_t bytes, void *hip_stream) {
+  if (!dst || !src) return fail(CRISP_E_INVALID, "null argument");
+  if (bytes % 16 || reinterpret_cast<uintptr_t>(dst) % 16 || reinterpret_cast<uintptr_t>(src) % 16)
+    return fail(CRISP_E_INVALID, "bytes and both pointers must be multiples of 16");
+  const long long n = static_cast<long long>(bytes / 16);
+  if (n == 0) return CRISP_OK;
+  k_copy_probe<<<grid_stride(n, 256), 256, 0, static_cast<hipStream_t>(hip_stream)>>>(
+      static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n);
+  LAUNCH_TRY("k_copy_probe");
+  return CRISP_OK;
+}
+
 int32_t crisp_mlp_param_count(int32_t f) { return f > 0 ? mlp_param_count(f) : -1; }
 
 int32_t crisp_feature_count(int32_t m) { return m > 0 ? n_features(m) : -1; }

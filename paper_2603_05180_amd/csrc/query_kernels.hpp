@@ -108,6 +108,14 @@ __global__ void __launch_bounds__(256) k_rotate_rows(const float *__restrict__ x
       }
 }
 
+// Plain 16-byte copy: the reference kernel hardware byte counters are
+// calibrated against (it reads and writes exactly its size).
+__global__ void __launch_bounds__(256) k_copy_probe(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                     long long n) {
+  const long long step = static_cast<long long>(gridDim.x) * blockDim.x;
+  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += step) dst[i] = src[i];
+}
+
 __global__ void k_copy_f32(const float *__restrict__ src, float *__restrict__ dst, long long n,
                            const int32_t *__restrict__ live, long long row_len) {
   if (live) n = min(n, static_cast<long long>(*live) * row_len);

@@ -145,16 +145,16 @@ class Workload:
 
 WORKLOADS = {
     # Plain Guaranteed Mode, CPU-fast size (local rank-8 factors, 20 comps).
-    "cfg1": Workload("cfg1", 10_000, 128, 20, 8, 0.1, "local",
+    "d128": Workload("d128", 10_000, 128, 20, 8, 0.1, "local",
                      1001, 2001, 4001, 8, 8, 100, 10),
     # Plain engine at scale (local rank-32 factors, 100 comps), D=960.
-    "cfg2": Workload("cfg2", 1_000_000, 960, 100, 32, 0.1, "local",
+    "d960": Workload("d960", 1_000_000, 960, 100, 32, 0.1, "local",
                      1002, 2002, 4002, 16, 16, 10_000, 10),
     # Strongly correlated global rank-64 data, D=4096: the rotation fires.
-    "cfg3": Workload("cfg3", 1_000_000, 4096, 100, 64, 0.05, "global",
+    "d4096": Workload("d4096", 1_000_000, 4096, 100, 64, 0.05, "global",
                      1003, 2003, 4003, 32, 50, 10_000, 10),
     # Uneven batching workload, D=3072.
-    "cfg5": Workload("cfg5", 2_000_000, 3072, 200, 64, 0.05, "global",
+    "d3072": Workload("d3072", 2_000_000, 3072, 200, 64, 0.05, "global",
                      1005, 2005, 4005, 32, 50, 50_000, 10),
 }
 

@@ -15,8 +15,8 @@ SIZES = [1, 2, 3, 7, 16, 33, 64, 65, 100, 5, 1, 100, 47]
 
 
 @pytest.fixture(scope="module")
-def cfg1():
-    w, x, q = make_workload("cfg1", n_query=300)
+def d128():
+    w, x, q = make_workload("d128", n_query=300)
     idx = oracle_index(w, x)
     g = gpu_index(idx)
     g.enable_bf16()
@@ -32,9 +32,9 @@ def _same(a, b):
 
 
 @pytest.mark.parametrize("mode,precision,k", [(0, 0, 10), (0, 1, 1), (1, 0, 10), (1, 1, 100)])
-def test_plan_replays_match_direct_search(cfg1, mode, precision, k):
+def test_plan_replays_match_direct_search(d128, mode, precision, k):
     from paper_2603_05180_amd import engine
-    w, x, q, idx, g = cfg1
+    w, x, q, idx, g = d128
     kw = dict(mode=mode, alpha=0.05, tau=4, precision=precision)
     plan = engine.Plan(g, 100, k, **kw)
     o = 0
@@ -49,9 +49,9 @@ def test_plan_replays_match_direct_search(cfg1, mode, precision, k):
     plan.free()
 
 
-def test_plan_several_chunks_per_bucket(cfg1):
+def test_plan_several_chunks_per_bucket(d128):
     from paper_2603_05180_amd import engine
-    w, x, q, idx, g = cfg1
+    w, x, q, idx, g = d128
     kw = dict(mode=1, alpha=0.05, tau=4, max_chunk=16)
     plan = engine.Plan(g, 100, 10, **kw)
     for nb in (100, 17, 64, 99, 33):
@@ -60,9 +60,9 @@ def test_plan_several_chunks_per_bucket(cfg1):
         _same(plan.search(qb), g.search(qb, 10, **kw))
 
 
-def test_plan_with_learned_budget(cfg1):
+def test_plan_with_learned_budget(d128):
     from paper_2603_05180_amd import engine
-    w, x, q, idx, g = cfg1
+    w, x, q, idx, g = d128
     f = g.n_features
     p = omlp.init_params(f, 3)
     p["b2"] = np.array([3.5], np.float32)
@@ -79,9 +79,9 @@ def test_plan_with_learned_budget(cfg1):
 
 
 @pytest.mark.parametrize("mode", [0, 1])
-def test_results_do_not_depend_on_tiles_or_chunks(cfg1, mode):
+def test_results_do_not_depend_on_tiles_or_chunks(d128, mode):
     from paper_2603_05180_amd import engine
-    w, x, q, idx, g = cfg1
+    w, x, q, idx, g = d128
     kw = dict(mode=mode, alpha=0.05, tau=4)
     ref = g.search(q, 10, **kw)
     for tile in (4096, 8192, 131072):
@@ -93,8 +93,8 @@ def test_results_do_not_depend_on_tiles_or_chunks(cfg1, mode):
 
 
 @pytest.mark.parametrize("mode,precision", [(0, 1), (1, 0), (1, 1)])
-def test_persistent_rerank_matches(cfg1, mode, precision):
-    w, x, q, idx, g = cfg1
+def test_persistent_rerank_matches(d128, mode, precision):
+    w, x, q, idx, g = d128
     kw = dict(mode=mode, alpha=0.05, tau=4, precision=precision)
     print(f"persistent mode={mode} precision={precision}", flush=True)
     for k in (1, 10):
@@ -102,12 +102,12 @@ def test_persistent_rerank_matches(cfg1, mode, precision):
         _same(g.search(q[:5].contiguous(), k, persistent=1, max_chunk=2, **kw), g.search(q[:5].contiguous(), k, **kw))
 
 
-def test_tuned_runner_serves_uneven_batches(cfg1, tmp_path):
+def test_tuned_runner_serves_uneven_batches(d128, tmp_path):
     """The tuner picks a setting per (k, bucket); every batch served through
     it equals the direct search."""
     import synth
     from paper_2603_05180_amd import autotune
-    w, x, q, idx, g = cfg1
+    w, x, q, idx, g = d128
     params = dict(mode=1, alpha=0.05, tau=4, precision=1)
     srv = autotune.Server(None, g, params, max_batch=64, ks=(1, 10), tiles=(4096, 16384), chunks=(16, 64))
     cache = str(tmp_path / "tune.json")

@@ -19,16 +19,16 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
-def cfg1():
-    w, x, q = make_workload("cfg1")
+def d128():
+    w, x, q = make_workload("d128")
     idx = oracle_index(w, x)
     g = gpu_index(idx)
     g.enable_bf16()
     return w, x, q, idx, g
 
 
-def test_bf16_copy_and_row_error_bounds(cfg1):
-    w, x, q, idx, g = cfg1
+def test_bf16_copy_and_row_error_bounds(d128):
+    w, x, q, idx, g = d128
     rows, err = g.bf16_rows()
     torch.cuda.synchronize()
     got = rows.cpu().view(torch.int16).numpy().view(np.uint16)
@@ -58,9 +58,9 @@ def _both(idx, g, q, k, **kw):
 
 @pytest.mark.parametrize("mode,alpha,tau,k", [(0, 0.05, 4, 10), (0, 0.02, 6, 1), (0, 0.05, 2, 100),
                                               (1, 0.05, 4, 10), (1, 0.1, 6, 1), (1, 0.05, 2, 100)])
-def test_cfg1_bf16_equals_oracle(cfg1, mode, alpha, tau, k):
-    w, x, q, idx, g = cfg1
-    print(f"cfg1 bf16 mode={mode} alpha={alpha} tau={tau} k={k}", flush=True)
+def test_d128_bf16_equals_oracle(d128, mode, alpha, tau, k):
+    w, x, q, idx, g = d128
+    print(f"d128 bf16 mode={mode} alpha={alpha} tau={tau} k={k}", flush=True)
     t0, t1 = _both(idx, g, q, k, mode=mode, alpha=alpha, tau=tau)
     frac = t1["refined"].sum() / max(1, t1["examined"].sum())
     print(f"  float32 rows read: {frac:.3f} of the verified rows", flush=True)
@@ -70,7 +70,7 @@ def test_cfg1_bf16_equals_oracle(cfg1, mode, alpha, tau, k):
 
 def test_ragged_width_and_rotation():
     """D = 192 (bfloat16 row groups do not fill the wave) on a rotated index."""
-    w, x, q = make_workload("cfg3", n=3000, d=192, m=4, k_half=6, rank=8, n_query=24)
+    w, x, q = make_workload("d4096", n=3000, d=192, m=4, k_half=6, rank=8, n_query=24)
     idx = oracle_index(w, x)
     assert idx["rotation"] is not None
     g = gpu_index(idx)
@@ -81,7 +81,7 @@ def test_ragged_width_and_rotation():
 
 
 def test_ties_near_duplicates_and_exact_hits():
-    w, x, q = make_workload("cfg1", n=4000, d=128, m=8, k_half=8, n_query=40)
+    w, x, q = make_workload("d128", n=4000, d=128, m=8, k_half=8, n_query=40)
     x = x.copy()
     x[1::4] = x[0::4]                                     # exact duplicates (ties broken by id)
     x[2::4] = x[0::4] + np.float32(1e-5) * np.sign(x[0::4])  # closer than bfloat16 resolves
@@ -98,7 +98,7 @@ def test_ties_near_duplicates_and_exact_hits():
 
 def test_precision_needs_the_bf16_copy():
     from paper_2603_05180_amd._lib import CrispError
-    w, x, q = make_workload("cfg1", n=800, d=64, m=2, k_half=4, n_query=3)
+    w, x, q = make_workload("d128", n=800, d=64, m=2, k_half=4, n_query=3)
     idx = oracle_index(w, x)
     g = gpu_index(idx)
     with pytest.raises(CrispError):

@@ -12,8 +12,8 @@ pytestmark = pytest.mark.gpu
 
 def test_synth_gpu_twin_matches_numpy():
     import synth.gpu as sg
-    for name, kw in (("cfg1", dict(n=3000)), ("cfg3", dict(n=500, d=512, rank=64)),
-                     ("cfg2", dict(n=200, d=192, rank=32))):
+    for name, kw in (("d128", dict(n=3000)), ("d4096", dict(n=500, d=512, rank=64)),
+                     ("d960", dict(n=200, d=192, rank=32))):
         w = synth.WORKLOADS[name].scaled(**kw)
         p = synth.mixture_params(w)
         pg = sg.mixture_params(w)
@@ -31,7 +31,7 @@ def test_synth_gpu_twin_matches_numpy():
 def test_synth_full_size_rows_sampled():
     """The N = 1M, D = 4096 data set on the device: sampled rows equal the CPU twin."""
     import synth.gpu as sg
-    w = synth.WORKLOADS["cfg3"]
+    w = synth.WORKLOADS["d4096"]
     pg = sg.mixture_params(w)
     p = synth.mixture_params(w)
     x = sg.rows(w, w.seed_data, 0, w.n, pg)
@@ -70,7 +70,7 @@ def _assert_same_index(ref, got):
 
 
 def test_gpu_build_equals_oracle_build_unrotated():
-    w = synth.WORKLOADS["cfg1"]
+    w = synth.WORKLOADS["d128"]
     x = synth.rows(w, w.seed_data, 0, w.n)
     ref, got = _build_both(w, x)
     assert ref["rotation"] is None
@@ -78,7 +78,7 @@ def test_gpu_build_equals_oracle_build_unrotated():
 
 
 def test_gpu_build_equals_oracle_build_rotated():
-    w = synth.WORKLOADS["cfg3"].scaled(n=4000, d=256, m=8, k_half=6, rank=16)
+    w = synth.WORKLOADS["d4096"].scaled(n=4000, d=256, m=8, k_half=6, rank=16)
     x = synth.rows(w, w.seed_data, 0, w.n)
     ref, got = _build_both(w, x)
     assert ref["rotation"] is not None
@@ -88,7 +88,7 @@ def test_gpu_build_equals_oracle_build_rotated():
 def test_search_on_gpu_built_index_matches_oracle():
     """End to end: the GPU-built index, searched on the GPU, equals the oracle
     searching its own build (the two builds are identical)."""
-    w = synth.WORKLOADS["cfg3"].scaled(n=5000, d=256, m=8, k_half=8, rank=16, n_query=20)
+    w = synth.WORKLOADS["d4096"].scaled(n=5000, d=256, m=8, k_half=8, rank=16, n_query=20)
     x = synth.rows(w, w.seed_data, 0, w.n)
     q = synth.rows(w, w.seed_query, 0, w.n_query)
     ref, got = _build_both(w, x)
@@ -105,7 +105,7 @@ def test_sign_codes_of_every_row_at_full_size():
     import ctypes
     import synth.gpu as sg
     from paper_2603_05180_amd._lib import check, lib
-    w = synth.WORKLOADS["cfg5"]
+    w = synth.WORKLOADS["d3072"]
     x = sg.rows(w, w.seed_data, 0, w.n, sg.mixture_params(w))
     words = w.d // 64
     codes = torch.empty(w.n, words, dtype=torch.int64, device="cuda")

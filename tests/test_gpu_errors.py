@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 @pytest.fixture(scope="module")
 def small():
-    w, x, q = make_workload("cfg1", n=2000, d=64, m=4, k_half=4, n_query=4)
+    w, x, q = make_workload("d128", n=2000, d=64, m=4, k_half=4, n_query=4)
     return w, x, q, oracle_index(w, x)
 
 

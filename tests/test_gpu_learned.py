@@ -62,7 +62,7 @@ def test_training_kernels_match_reference():
 
 @pytest.fixture(scope="module")
 def small():
-    w, x, q = make_workload("cfg3", n=6000, d=256, m=8, k_half=8, rank=16, n_query=48)
+    w, x, q = make_workload("d4096", n=6000, d=256, m=8, k_half=8, rank=16, n_query=48)
     idx = oracle_index(w, x)
     return w, x, q, idx
 
@@ -122,7 +122,7 @@ def test_learned_budget_verifies_fewer_candidates():
     candidates than the patience rule alone, at recall within 0.005 of it."""
     import synth.gpu as sg
     from paper_2603_05180_amd import engine, learned
-    w = synth.WORKLOADS["cfg3"].scaled(n=200_000, d=1024, m=16, k_half=32, rank=64)
+    w = synth.WORKLOADS["d4096"].scaled(n=200_000, d=1024, m=16, k_half=32, rank=64)
     params = sg.mixture_params(w)
     x = sg.rows(w, w.seed_data, 0, w.n, params)
     n = w.n

@@ -15,30 +15,30 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
-def cfg1():
-    w, x, q = make_workload("cfg1")
+def d128():
+    w, x, q = make_workload("d128")
     idx = oracle_index(w, x)
     return w, x, q, idx
 
 
 @pytest.mark.parametrize("mode,alpha,tau", [(0, 0.05, 4), (0, 0.02, 6), (1, 0.05, 4), (1, 0.1, 6)])
-def test_cfg1_full(cfg1, mode, alpha, tau):
+def test_d128_full(d128, mode, alpha, tau):
     """Plain Guaranteed / Optimized Mode at the CPU-fast size (N=10k, D=128, 100 queries)."""
-    w, x, q, idx = cfg1
-    print(f"cfg1 mode={mode} alpha={alpha} tau={tau}", flush=True)
+    w, x, q, idx = d128
+    print(f"d128 mode={mode} alpha={alpha} tau={tau}", flush=True)
     compare(idx, q, w.k, mode=mode, alpha=alpha, tau=tau)
 
 
-def test_cfg1_ragged_tiles_and_chunks(cfg1):
+def test_d128_ragged_tiles_and_chunks(d128):
     """4096-id tiles (N=10k: 3 tiles, ragged tail) and 7-query chunks."""
-    w, x, q, idx = cfg1
-    print("cfg1 tiles=4096 chunk=7", flush=True)
+    w, x, q, idx = d128
+    print("d128 tiles=4096 chunk=7", flush=True)
     compare(idx, q[:30], w.k, mode=1, alpha=0.05, tau=4, tile_ids=4096, max_chunk=7)
     compare(idx, q[:30], w.k, mode=0, alpha=0.05, tau=4, tile_ids=4096, max_chunk=7)
 
 
-def test_fallback_and_degenerate_thresholds(cfg1):
-    w, x, q, idx = cfg1
+def test_fallback_and_degenerate_thresholds(d128):
+    w, x, q, idx = d128
     g = gpu_index(idx)
     print("fallback tau=16", flush=True)
     s = compare(idx, q[:20], w.k, mode=0, alpha=0.002, tau=16, gpu=g)          # forces the fallback
@@ -56,14 +56,14 @@ def test_fallback_and_degenerate_thresholds(cfg1):
 
 
 def test_padding_when_too_few_points_collide():
-    w, x, q = make_workload("cfg1", n=600, d=64, m=2, k_half=4, n_query=6)
+    w, x, q = make_workload("d128", n=600, d=64, m=2, k_half=4, n_query=6)
     idx = oracle_index(w, x)
     print("padding", flush=True)
     compare(idx, q, 50, mode=0, alpha=0.001, tau=2)
 
 
-def test_learned_prefix_limits(cfg1):
-    w, x, q, idx = cfg1
+def test_learned_prefix_limits(d128):
+    w, x, q, idx = d128
     lim = np.array([1, 5, 17, 0, 200, 3] * 5, dtype=np.int32)
     print("limits", flush=True)
     compare(idx, q[:30], w.k, mode=1, alpha=0.05, tau=4, limits=lim)
@@ -72,7 +72,7 @@ def test_learned_prefix_limits(cfg1):
 @pytest.mark.parametrize("k_half", [1, 64, 80])
 def test_codebook_sizes(k_half):
     """K = 1 (one cell), K = 64 (4096 cells), K = 80 (prefix tables in device memory)."""
-    w, x, q = make_workload("cfg1", n=4000, d=128, m=4, k_half=k_half, n_query=12)
+    w, x, q = make_workload("d128", n=4000, d=128, m=4, k_half=k_half, n_query=12)
     idx = oracle_index(w, x)
     print(f"K={k_half}", flush=True)
     for mode in (0, 1):
@@ -81,7 +81,7 @@ def test_codebook_sizes(k_half):
 
 def test_rotated_index():
     """Correlated data: the rotation fires, queries are rotated on the GPU."""
-    w, x, q = make_workload("cfg3", n=3000, d=256, m=8, k_half=6, rank=16, n_query=16)
+    w, x, q = make_workload("d4096", n=3000, d=256, m=8, k_half=6, rank=16, n_query=16)
     idx = oracle_index(w, x)
     assert idx["rotation"] is not None
     print("rotated", flush=True)
@@ -91,7 +91,7 @@ def test_rotated_index():
 
 def test_wide_rows_several_tiles():
     """D = 1024 (float4 path), 5 tiles of 4096 with a ragged tail."""
-    w, x, q = make_workload("cfg3", n=18000, d=1024, m=16, k_half=8, rank=32, n_query=10)
+    w, x, q = make_workload("d4096", n=18000, d=1024, m=16, k_half=8, rank=32, n_query=10)
     idx = oracle_index(w, x)
     print("D=1024", flush=True)
     for mode in (0, 1):
@@ -102,7 +102,7 @@ def test_wide_rows_several_tiles():
 def test_code_widths_not_a_power_of_two(d, m):
     """3, 5 and 7 sign-code words per row: the Hamming kernel's lanes per row
     must still cover every word exactly once."""
-    w, x, q = make_workload("cfg3", n=2500, d=d, m=m, k_half=6, rank=8, n_query=12)
+    w, x, q = make_workload("d4096", n=2500, d=d, m=m, k_half=6, rank=8, n_query=12)
     idx = oracle_index(w, x)
     print(f"D={d} M={m}", flush=True)
     for mode in (0, 1):

@@ -153,8 +153,8 @@ def test_sign_codes_match_signs():
             assert bit == (1 if x[i, dim] > 0 else 0)
 
 
-def test_build_index_structure_cfg1_small():
-    w = synth.WORKLOADS["cfg1"].scaled(n=3000, d=64, m=4, k_half=6)
+def test_build_index_structure_d128_small():
+    w = synth.WORKLOADS["d128"].scaled(n=3000, d=64, m=4, k_half=6)
     x = synth.rows(w, w.seed_data, 0, w.n)
     idx = build.build_index_for(w, x)
     assert idx["rotation"] is None
@@ -173,7 +173,7 @@ def test_build_index_structure_cfg1_small():
 
 
 def test_build_index_rotation_fires_on_correlated_data():
-    w = synth.WORKLOADS["cfg3"].scaled(n=2000, d=128, m=4, k_half=5, rank=8)
+    w = synth.WORKLOADS["d4096"].scaled(n=2000, d=128, m=4, k_half=5, rank=8)
     x = synth.rows(w, w.seed_data, 0, w.n)
     idx = build.build_index_for(w, x)
     assert idx["cev"] > 0.85 and idx["rotation"] is not None

@@ -56,7 +56,7 @@ def test_bf16_rounding():
 
 
 def test_features_follow_their_definitions():
-    w = synth.WORKLOADS["cfg1"].scaled(n=2000, d=64, m=4, k_half=5)
+    w = synth.WORKLOADS["d128"].scaled(n=2000, d=64, m=4, k_half=5)
     x = synth.rows(w, w.seed_data, 0, w.n)
     idx = build.build_index_for(w, x)
     q = synth.rows(w, 55, 0, 3)

@@ -62,7 +62,7 @@ def test_figure3_structure():
 
 
 def _tiny_index(seed=0, n=600, d=64, m=4, kh=4, rotate=None):
-    w = synth.WORKLOADS["cfg1"].scaled(n=n, d=d, m=m, k_half=kh, seed_data=100 + seed)
+    w = synth.WORKLOADS["d128"].scaled(n=n, d=d, m=m, k_half=kh, seed_data=100 + seed)
     x = synth.rows(w, w.seed_data, 0, n)
     idx = build.build_index_for(w, x, force_rotation=rotate)
     qs = synth.rows(w, 900 + seed, 0, 12)

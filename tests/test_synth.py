@@ -30,12 +30,12 @@ def test_normals_moments_and_exactness():
 
 
 def test_rows_are_random_access():
-    w = synth.WORKLOADS["cfg1"].scaled(n=300, d=64)
+    w = synth.WORKLOADS["d128"].scaled(n=300, d=64)
     p = synth.mixture_params(w)
     full = synth.rows(w, w.seed_data, 0, 300, p)
     part = synth.rows(w, w.seed_data, 123, 177, p)
     assert np.array_equal(full[123:177], part)
-    wg = synth.WORKLOADS["cfg3"].scaled(n=100, d=128)
+    wg = synth.WORKLOADS["d4096"].scaled(n=100, d=128)
     pg = synth.mixture_params(wg)
     assert np.array_equal(synth.rows(wg, 5, 0, 50, pg)[10:20], synth.rows(wg, 5, 10, 20, pg))
 

@@ -30,7 +30,7 @@ def test_empirical_recall_bound_with_rotation():
     """Over rebuilds with independent rotations, the rate at which the true
     nearest neighbour reaches tau collisions is at least the bound evaluated
     at its measured per-subspace collision rate (minus sampling slack)."""
-    w = synth.WORKLOADS["cfg3"].scaled(n=1500, d=64, m=8, k_half=4, n_comp=10)
+    w = synth.WORKLOADS["d4096"].scaled(n=1500, d=64, m=8, k_half=4, n_comp=10)
     x = synth.rows(w, w.seed_data, 0, w.n)
     qs = synth.rows(w, 777, 0, 10)
     gt, _ = brute.knn(x, qs, 1)
