@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--patience", type=int, default=40)
     ap.add_argument("--max-chunk", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--overlap", type=int, default=1,
+                    help="two chunk pipelines on two streams (the per-kernel roofline pass always runs with one)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-oracle time budget (0 = skip)")
     ap.add_argument("--train-queries", type=int, default=200_000,
                     help="queries the learned budget is trained on (0 = no learned form)")
@@ -198,7 +200,7 @@ def main():
     index.enable_bf16()
     k = w.k
     base_kw = dict(mode=args.mode, alpha=args.alpha, tau=args.tau, patience_factor=args.patience,
-                   max_chunk=args.max_chunk)
+                   max_chunk=args.max_chunk, overlap=args.overlap)
 
     # Rotated queries (same kernel as the search) for the exact ground truth.
     qrot = engine.rotate_rows(queries, arrays["rotation"]) if arrays["rotation"] is not None else queries
@@ -237,7 +239,7 @@ def main():
             plain_ids = ids.clone()
         same = float((ids[:, :, None] == plain_ids[:, None, :]).any(-1).float().mean())
         ms, _ = timed(index, queries, k, kw, args.steps, ids, dists)
-        c = counts(index, queries, k, kw)
+        c = counts(index, queries, k, dict(kw, overlap=0))
         results[name] = {"queries_per_s": round(w.n_query / (ms / 1e3), 1), "ms_per_step": round(ms, 3),
                          "recall_at_10": round(rec, 4), "plain_ids_kept": round(same, 5),
                          "mean_verified": round(c["examined"] / w.n_query, 1),
@@ -251,9 +253,12 @@ def main():
     ok = [f for f in results if results[f]["recall_at_10"] >= 0.90] or list(results)
     head = max(ok, key=lambda f: results[f]["queries_per_s"])
     kw, c = results[head]["_kw"], results[head]["_counts"]
+    ms_step = results[head]["ms_per_step"]
+    qps = results[head]["queries_per_s"]
+    # Per-kernel roofline: the same form timed stage by stage with one chunk
+    # pipeline, so that no other kernel shares the GPU during a launch.
     copy_probe()
-    ms_step, stages = timed(index, queries, k, kw, args.steps, ids, dists, profile=True)
-    qps = w.n_query / (ms_step / 1e3)
+    _, stages = timed(index, queries, k, dict(kw, overlap=0), args.steps, ids, dists, profile=True)
 
     # ---- roofline of each stage (algorithmic bytes / flops per step) --------
     d = w.d
@@ -305,6 +310,7 @@ def main():
                                f"{w.n_comp} comps), M={w.m} K={w.k_half}, {w.n_query} queries/batch, k={k}",
                    "mode": "optimized" if args.mode == 1 else "guaranteed", "alpha": args.alpha, "tau": args.tau,
                    "patience_factor": args.patience, "recall_at_10": results[head]["recall_at_10"],
+                   "overlap": args.overlap,
                    "rotated": rotated,
                    "mean_candidates": round(c["n_cand"] / w.n_query, 1),
                    "mean_verified": round(c["examined"] / w.n_query, 1), "form": head,

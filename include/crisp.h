@@ -160,6 +160,13 @@ crisp_status crisp_index_enable_bf16(crisp_index *index, void *buffer, size_t by
  *                      launches about as many blocks as fit on the chip,
  *                      each pulling queries from a device-side counter (same
  *                      results; the batch executor's tuner picks per bucket).
+ *   overlap         -- 0: query chunks run one after another on hip_stream.
+ *                      1: odd chunks run on a second stream owned by the
+ *                      index, with their own half of a doubled workspace, so
+ *                      the kernels of two chunks overlap (same results).  The
+ *                      second stream joins hip_stream before the call's work
+ *                      completes; calls with overlap on one index must be
+ *                      ordered on one stream.
  */
 typedef struct {
   int32_t mode;
@@ -171,6 +178,7 @@ typedef struct {
   int32_t budget_source;
   int32_t precision;
   int32_t persistent;
+  int32_t overlap;
 } crisp_search_params;
 
 /*

@@ -86,6 +86,8 @@ struct crisp_index {
   int32_t *tile_off;
   float *cent_t;  // [M][2][h][K]
   int ncu = 256;  // compute units of the device the index was loaded on
+  hipStream_t aux = nullptr;  // second chunk pipeline (overlap = 1)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // learned budget model (borrowed device pointers; null when unset)
   const float *mlp_params = nullptr, *mlp_mean = nullptr, *mlp_std = nullptr;
   int mlp_nf = 0;
@@ -245,6 +247,12 @@ crisp_status crisp_index_load(const crisp_index_desc *desc, int32_t tile_ids, vo
         hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
       ix->ncu = cu;
   }
+  if (hipStreamCreateWithFlags(&ix->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ix->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ix->ev_join, hipEventDisableTiming) != hipSuccess) {
+    crisp_index_free(ix);
+    return fail(CRISP_E_HIP, "stream or event creation failed");
+  }
   *out = ix;
   return CRISP_OK;
 }
@@ -279,8 +287,12 @@ crisp_status crisp_index_enable_bf16(crisp_index *ix, void *buffer, size_t bytes
 }
 
 crisp_status crisp_index_free(crisp_index *index) {
-  if (index)
+  if (index) {
     for (auto &e : index->prof_ev) (void)hipEventDestroy(e);
+    if (index->ev_fork) (void)hipEventDestroy(index->ev_fork);
+    if (index->ev_join) (void)hipEventDestroy(index->ev_join);
+    if (index->aux) (void)hipStreamDestroy(index->aux);
+  }
   delete index;
   return CRISP_OK;
 }
@@ -301,6 +313,7 @@ static crisp_status check_params(const crisp_index *ix, int64_t nq, int32_t k, c
   if (p->precision != 0 && p->precision != 1) return fail(CRISP_E_INVALID, "precision must be 0 or 1");
   if (p->precision == 1 && !ix->base16) return fail(CRISP_E_INVALID, "precision 1 needs crisp_index_enable_bf16");
   if (p->persistent != 0 && p->persistent != 1) return fail(CRISP_E_INVALID, "persistent must be 0 or 1");
+  if (p->overlap != 0 && p->overlap != 1) return fail(CRISP_E_INVALID, "overlap must be 0 or 1");
   return CRISP_OK;
 }
 
@@ -309,7 +322,7 @@ crisp_status crisp_search_workspace_bytes(const crisp_index *index, int64_t nq, 
   if (!bytes) return fail(CRISP_E_INVALID, "null argument");
   crisp_status s = check_params(index, nq, k, params);
   if (s != CRISP_OK) return s;
-  *bytes = make_layout(index, chunk_of(params, nq)).total;
+  *bytes = make_layout(index, chunk_of(params, nq)).total * (params->overlap == 1 ? 2 : 1);
   return CRISP_OK;
 }
 
@@ -327,47 +340,26 @@ static crisp_status tap_copy(void *dst, const void *src, size_t bytes, hipStream
 // batch this way).
 static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t nq, int32_t k,
                                 const crisp_search_params *p, int64_t *ids, float *dists, void *workspace,
-                                size_t ws_bytes, const crisp_taps *taps, hipStream_t st, const int32_t *live_base) {
+                                size_t ws_bytes, const crisp_taps *taps, hipStream_t st0, const int32_t *live_base) {
   crisp_status s = CRISP_OK;
   const long long qc = chunk_of(p, nq);
   const Layout L = make_layout(ix, qc);
-  if (ws_bytes < L.total) return fail(CRISP_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
-  char *ws = static_cast<char *>(workspace);
-  float *qrot = reinterpret_cast<float *>(ws + L.qrot);
-  double *hdist = reinterpret_cast<double *>(ws + L.hdist);
-  int32_t *ptab = reinterpret_cast<int32_t *>(ws + L.ptab);
-  int32_t *ncell = reinterpret_cast<int32_t *>(ws + L.ncell);
-  int32_t *cells = reinterpret_cast<int32_t *>(ws + L.cells);
-  int32_t *retr = reinterpret_cast<int32_t *>(ws + L.retr);
-  int32_t *tilecnt = reinterpret_cast<int32_t *>(ws + L.tilecnt);
-  int32_t *hist = reinterpret_cast<int32_t *>(ws + L.hist);
-  int32_t *flag = reinterpret_cast<int32_t *>(ws + L.flag);
-  int32_t *taueff = reinterpret_cast<int32_t *>(ws + L.taueff);
-  int32_t *ncand = reinterpret_cast<int32_t *>(ws + L.ncand);
-  int32_t *segids = reinterpret_cast<int32_t *>(ws + L.segids);
-  uint8_t *segscore = reinterpret_cast<uint8_t *>(ws + L.segscore);
-  int32_t *cand = reinterpret_cast<int32_t *>(ws + L.cand);
-  uint8_t *score = reinterpret_cast<uint8_t *>(ws + L.score);
-  int32_t *regA = reinterpret_cast<int32_t *>(ws + L.regA);
-  int32_t *regB = reinterpret_cast<int32_t *>(ws + L.regB);
-  double *regC = reinterpret_cast<double *>(ws + L.regC);
-  int32_t *exam = reinterpret_cast<int32_t *>(ws + L.examined);
-  int32_t *lastu = reinterpret_cast<int32_t *>(ws + L.lastupd);
-  int32_t *stopd = reinterpret_cast<int32_t *>(ws + L.stopped);
-  int32_t *refd = reinterpret_cast<int32_t *>(ws + L.refined);
-  int32_t *queue = reinterpret_cast<int32_t *>(ws + L.queue);
-  double *sstat = reinterpret_cast<double *>(ws + L.sstat);
-  float *feat = reinterpret_cast<float *>(ws + L.feat);
-  int32_t *llim = reinterpret_cast<int32_t *>(ws + L.lim);
+  // Two chunk pipelines (this stream and the index's second stream, each
+  // with its own workspace) when the batch has more than one chunk.
+  const bool two = p->overlap == 1 && nq > qc;
+  if (ws_bytes < (p->overlap == 1 ? 2 : 1) * L.total)
+    return fail(CRISP_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, (p->overlap == 1 ? 2 : 1) * L.total);
+  if (two) {
+    HIP_TRY(hipEventRecord(ix->ev_fork, st0));
+    HIP_TRY(hipStreamWaitEvent(ix->aux, ix->ev_fork, 0));
+  }
   const int nf = n_features(ix->m);
-
   const int d = ix->d, m = ix->m, kh = ix->k, nb = 2 * m + 1;
   const long long n = ix->n;
   const int budget = static_cast<int>(std::max<double>(1.0, std::ceil(p->alpha * static_cast<double>(n))));
   const int patience = p->mode == 1 ? p->patience_factor * k : 0;
   const size_t count_lds = static_cast<size_t>(ix->tile);
   const int nseg = ix->ntiles * kCountWaves;
-  const size_t order_lds = static_cast<size_t>(d + 1) * 4;
   const bool bf16 = p->precision == 1;
   const size_t rr_lds = rerank_lds(d, k, bf16).total;
   // float32 error factor of the bfloat16 row distance: gamma_{L+10}, L = terms per lane
@@ -385,6 +377,35 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
   }
 
   for (long long q0 = 0; q0 < nq; q0 += qc) {
+    const bool odd = two && ((q0 / qc) & 1);
+    hipStream_t st = odd ? ix->aux : st0;
+    char *ws = static_cast<char *>(workspace) + (odd ? L.total : 0);
+    float *qrot = reinterpret_cast<float *>(ws + L.qrot);
+    double *hdist = reinterpret_cast<double *>(ws + L.hdist);
+    int32_t *ptab = reinterpret_cast<int32_t *>(ws + L.ptab);
+    int32_t *ncell = reinterpret_cast<int32_t *>(ws + L.ncell);
+    int32_t *cells = reinterpret_cast<int32_t *>(ws + L.cells);
+    int32_t *retr = reinterpret_cast<int32_t *>(ws + L.retr);
+    int32_t *tilecnt = reinterpret_cast<int32_t *>(ws + L.tilecnt);
+    int32_t *hist = reinterpret_cast<int32_t *>(ws + L.hist);
+    int32_t *flag = reinterpret_cast<int32_t *>(ws + L.flag);
+    int32_t *taueff = reinterpret_cast<int32_t *>(ws + L.taueff);
+    int32_t *ncand = reinterpret_cast<int32_t *>(ws + L.ncand);
+    int32_t *segids = reinterpret_cast<int32_t *>(ws + L.segids);
+    uint8_t *segscore = reinterpret_cast<uint8_t *>(ws + L.segscore);
+    int32_t *cand = reinterpret_cast<int32_t *>(ws + L.cand);
+    uint8_t *score = reinterpret_cast<uint8_t *>(ws + L.score);
+    int32_t *regA = reinterpret_cast<int32_t *>(ws + L.regA);
+    int32_t *regB = reinterpret_cast<int32_t *>(ws + L.regB);
+    double *regC = reinterpret_cast<double *>(ws + L.regC);
+    int32_t *exam = reinterpret_cast<int32_t *>(ws + L.examined);
+    int32_t *lastu = reinterpret_cast<int32_t *>(ws + L.lastupd);
+    int32_t *stopd = reinterpret_cast<int32_t *>(ws + L.stopped);
+    int32_t *refd = reinterpret_cast<int32_t *>(ws + L.refined);
+    int32_t *queue = reinterpret_cast<int32_t *>(ws + L.queue);
+    double *sstat = reinterpret_cast<double *>(ws + L.sstat);
+    float *feat = reinterpret_cast<float *>(ws + L.feat);
+    int32_t *llim = reinterpret_cast<int32_t *>(ws + L.lim);
     const int cq = static_cast<int>(std::min<long long>(qc, nq - q0));
     const float *qin = queries + q0 * d;
     const int32_t *lv = live_base ? live_base + q0 / qc : nullptr;
@@ -452,7 +473,8 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       }
       t4.stop();
       StageTimer t1(ix, 1, st);  // order
-      k_hamming_place<<<cq, kOrderThreads, order_lds, st>>>(d, ncand, cand, n, regA, segids, regB, lv);
+      k_hamming_place<<<cq, kOrderThreads, 0, st>>>(d, ncand, cand, n, regA, reinterpret_cast<long long *>(regC),
+                                                     segids, regB, lv);
       LAUNCH_TRY("k_hamming_place");
       t1.stop();
       // learned budget: features, then bfloat16 MFMA inference -> limits
@@ -521,6 +543,10 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
                                                  size_t(cq) * 4, st))) return s;
     }
   }
+  if (two) {
+    HIP_TRY(hipEventRecord(ix->ev_join, ix->aux));
+    HIP_TRY(hipStreamWaitEvent(st0, ix->ev_join, 0));
+  }
   return CRISP_OK;
 }
 
@@ -553,7 +579,7 @@ PlanLayout plan_layout(const crisp_index *ix, int max_batch, int k, const crisp_
   const long long qc = chunk_of(p, max_batch);
   const long long nch = (max_batch + qc - 1) / qc;
   L.ws = 0;
-  L.q = align_up(make_layout(ix, qc).total);
+  L.q = align_up(make_layout(ix, qc).total * (p->overlap == 1 ? 2 : 1));
   L.ids = L.q + align_up(static_cast<size_t>(max_batch) * ix->d * 4);
   L.dists = L.ids + align_up(static_cast<size_t>(max_batch) * k * 8);
   L.live = L.dists + align_up(static_cast<size_t>(max_batch) * k * 4);

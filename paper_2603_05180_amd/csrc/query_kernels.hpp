@@ -744,10 +744,9 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(
 // four loads per lane are in flight per batch, and the partial popcounts are
 // reduced over the row's L lanes.
 //
-// k_hamming_place: one block per query builds the distance histogram in
-// LDS, scans it, and one wavefront places the candidates (a stable counting
-// sort: ballot matching gives each lane its rank among equal distances),
-// with the next group's loads issued before the current group is placed.
+// k_hamming_place: one block per query sorts the candidates by distance with
+// a two-pass stable LSD radix sort (7-bit digits) spread over its four
+// wavefronts.
 // ---------------------------------------------------------------------------
 constexpr int kOrderThreads = 256;
 constexpr int kOrderWaves = kOrderThreads / kWave;
@@ -833,69 +832,103 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_dist(
   }
 }
 
+// One pass of a stable LSD radix sort by 7-bit digits: the four wavefronts
+// take contiguous quarters of the input in order; per-wave digit counts give
+// each (wave, digit) its start, and inside a 64-lane step a lane's rank among
+// lower lanes with the same digit comes from 7 ballots.  Input element i is
+// (key[i], val[i]) or, when packed, the int64 (key << 32 | val).
+template <bool kPackedIn, bool kPackedOut>
+__device__ __forceinline__ void radix_pass(int nc, int shift, const int32_t *__restrict__ key_in,
+                                           const int32_t *__restrict__ val_in, const long long *__restrict__ pk_in,
+                                           int32_t *__restrict__ key_out, int32_t *__restrict__ val_out,
+                                           long long *__restrict__ pk_out, int (*cnt)[128]) {
+  const int lane = lane_id(), wv = wave_id();
+  const int per = ((nc + kOrderWaves - 1) / kOrderWaves + kWave - 1) / kWave * kWave;
+  const int b0 = min(nc, wv * per), b1 = min(nc, b0 + per);
+  auto load = [&](int i, int &k, int &v) {
+    if constexpr (kPackedIn) {
+      const long long e = pk_in[i];
+      k = static_cast<int>(e >> 32);
+      v = static_cast<int>(e & 0xffffffffll);
+    } else {
+      k = key_in[i];
+      v = val_in[i];
+    }
+  };
+  for (int t = threadIdx.x; t < kOrderWaves * 128; t += kOrderThreads) cnt[t >> 7][t & 127] = 0;
+  __syncthreads();
+  for (int i0 = b0; i0 < b1; i0 += 4 * kWave) {
+    int k[4], v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) load(min(i0 + u * kWave + lane, b1 - 1), k[u], v[u]);  // clamped
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + u * kWave + lane < b1) atomicAdd(&cnt[wv][(k[u] >> shift) & 127], 1);
+  }
+  __syncthreads();
+  // start of (wave w, digit g) = (elements of smaller digits) + (digit g in waves < w)
+  if (wv == 0) {
+    int t0 = 0, t1 = 0;
+    for (int w = 0; w < kOrderWaves; ++w) { t0 += cnt[w][2 * lane]; t1 += cnt[w][2 * lane + 1]; }
+    const int incl = wave_incl_scan_i32(t0 + t1);
+    int run0 = incl - t0 - t1, run1 = incl - t1;
+    for (int w = 0; w < kOrderWaves; ++w) {
+      const int c0 = cnt[w][2 * lane], c1 = cnt[w][2 * lane + 1];
+      cnt[w][2 * lane] = run0;
+      cnt[w][2 * lane + 1] = run1;
+      run0 += c0;
+      run1 += c1;
+    }
+  }
+  __syncthreads();
+  const unsigned long long below = lanes_below_mask();
+  for (int s0 = b0; s0 < b1; s0 += 4 * kWave) {
+    int kk[4], vv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) load(min(s0 + u * kWave + lane, b1 - 1), kk[u], vv[u]);  // clamped
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool valid = s0 + u * kWave + lane < b1;
+      const int k = kk[u], v = vv[u];
+      const int g = (k >> shift) & 127;
+      unsigned long long same = __ballot(valid);
+#pragma unroll
+      for (int bit = 0; bit < 7; ++bit) {
+        const bool on = (g >> bit) & 1;
+        const unsigned long long bb = __ballot(on);
+        same &= on ? bb : ~bb;
+      }
+      if (valid) {
+        const int pos = cnt[wv][g] + __popcll(same & below);
+        if constexpr (kPackedOut) {
+          pk_out[pos] = (static_cast<long long>(k) << 32) | static_cast<unsigned int>(v);
+        } else {
+          key_out[pos] = k;
+          val_out[pos] = v;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (valid && (same & below) == 0) cnt[wv][g] += __popcll(same);
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+}
+
+// Candidates in ascending (Hamming distance, id) order: the candidate list
+// is in ascending id order, so two stable 7-bit passes (low digit, then high
+// digit; distances <= 8192 < 2^14) give the order.  tmp: int64 per candidate.
 __global__ void __launch_bounds__(kOrderThreads) k_hamming_place(
     int d, const int32_t *__restrict__ ncand, const int32_t *__restrict__ cand, long long n,
-    const int32_t *__restrict__ hm_tmp, int32_t *__restrict__ order, int32_t *__restrict__ ham_sorted,
-    const int32_t *__restrict__ live) {
-  extern __shared__ int bins[];          // d + 1
-  __shared__ int tmp[kOrderWaves + 1];
-  const int q = blockIdx.x, lane = lane_id(), wv = wave_id();
+    const int32_t *__restrict__ hm_tmp, long long *__restrict__ tmp, int32_t *__restrict__ order,
+    int32_t *__restrict__ ham_sorted, const int32_t *__restrict__ live) {
+  __shared__ int cnt[kOrderWaves][128];
+  const int q = blockIdx.x;
   if (live && q >= *live) return;
   const int nc = ncand[q];
   const long long qo = static_cast<long long>(q) * n;
-  for (int i = threadIdx.x; i <= d; i += kOrderThreads) bins[i] = 0;
-  __syncthreads();
-  for (int i = threadIdx.x; i < nc; i += kOrderThreads) atomicAdd(&bins[hm_tmp[qo + i]], 1);
-  __syncthreads();
-  block_exclusive_scan(bins, d + 1, tmp);
-  // bins[h] = first position of distance h.  One wavefront places the
-  // candidates in ascending id order, 64 per step: a lane's rank among the
-  // step's lanes with the same distance comes from 14 ballots on the bits of
-  // h, the lowest such lane advances bins[h]; this is a stable counting sort.
-  if (wv == 0 && nc > 0) {
-    const unsigned long long below = lanes_below_mask();
-    int hv[4], idv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int ic = min(u * kWave + lane, nc - 1);   // clamped: every load is issued
-      hv[u] = hm_tmp[qo + ic];
-      idv[u] = cand[qo + ic];
-    }
-    for (int b0 = 0; b0 < nc; b0 += 4 * kWave) {
-      int hn[4], in[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int ic = min(b0 + 4 * kWave + u * kWave + lane, nc - 1);
-        hn[u] = hm_tmp[qo + ic];
-        in[u] = cand[qo + ic];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const bool valid = b0 + u * kWave + lane < nc;
-        const int h = hv[u];
-        unsigned long long same = __ballot(valid);
-#pragma unroll
-        for (int bit = 0; bit < 14; ++bit) {
-          const bool on = (h >> bit) & 1;
-          const unsigned long long bb = __ballot(on);
-          same &= on ? bb : ~bb;
-        }
-        if (valid) {
-          const int pos = bins[h] + __popcll(same & below);
-          order[qo + pos] = idv[u];
-          ham_sorted[qo + pos] = h;
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (valid && (same & below) == 0) bins[h] += __popcll(same);
-        __builtin_amdgcn_wave_barrier();
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        hv[u] = hn[u];
-        idv[u] = in[u];
-      }
-    }
-  }
+  radix_pass<false, true>(nc, 0, hm_tmp + qo, cand + qo, nullptr, nullptr, nullptr, tmp + qo, cnt);
+  radix_pass<true, false>(nc, 7, nullptr, nullptr, tmp + qo, ham_sorted + qo, order + qo, nullptr, cnt);
 }
 
 // ---------------------------------------------------------------------------

@@ -104,9 +104,9 @@ class Index:
             {"dropped": pr.dropped}
 
     def params(self, *, mode=0, alpha=0.01, tau=1, patience_factor=40, limits=None, max_chunk=0, budget_source=0,
-               precision=0, persistent=0):
+               precision=0, persistent=0, overlap=0):
         return SearchParams(int(mode), float(alpha), int(tau), int(patience_factor), _ptr(limits), int(max_chunk),
-                            int(budget_source), int(precision), int(persistent))
+                            int(budget_source), int(precision), int(persistent), int(overlap))
 
     def enable_bf16(self, stream=None, buffer: torch.Tensor | None = None) -> torch.Tensor:
         """bfloat16 copy of the rows + per-row error bounds for precision=1
@@ -181,8 +181,8 @@ class Index:
 
     def search(self, queries: torch.Tensor, k: int, *, mode: int = 0, alpha: float = 0.01, tau: int = 1,
                patience_factor: int = 40, limits: torch.Tensor | None = None, max_chunk: int = 0,
-               budget_source: int = 0, precision: int = 0, persistent: int = 0, taps: dict | None = None,
-               out: tuple | None = None, stream=None):
+               budget_source: int = 0, precision: int = 0, persistent: int = 0, overlap: int = 0,
+               taps: dict | None = None, out: tuple | None = None, stream=None):
         """Algorithm 1 for a batch; returns (ids int64 [nq, k], dists f32 [nq, k])."""
         if queries.device != self.device or queries.dtype != torch.float32 or not queries.is_contiguous():
             raise ValueError("queries must be a contiguous float32 tensor on the index device")
@@ -194,7 +194,7 @@ class Index:
         nq = int(queries.shape[0])
         p = self.params(mode=mode, alpha=alpha, tau=tau, patience_factor=patience_factor,
                         limits=limits, max_chunk=max_chunk, budget_source=budget_source, precision=precision,
-                        persistent=persistent)
+                        persistent=persistent, overlap=overlap)
         ws = self.workspace(nq, k, p)
         if out is None:
             ids = torch.empty(nq, k, dtype=torch.int64, device=self.device)

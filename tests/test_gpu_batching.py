@@ -127,3 +127,20 @@ def test_tuned_runner_serves_uneven_batches(d128, tmp_path):
     assert srv2.tune(q, [1, 2, 4, 8, 16, 32, 64], cache=cache) == choice
     srv.free()
     srv2.free()
+
+
+@pytest.mark.parametrize("mode,precision", [(0, 0), (1, 1)])
+def test_two_chunk_pipelines_match(d128, mode, precision):
+    """overlap = 1 runs odd chunks on the index's second stream with their own
+    workspace; results equal the single-stream search, also inside a plan."""
+    from paper_2603_05180_amd import engine
+    w, x, q, idx, g = d128
+    kw = dict(mode=mode, alpha=0.05, tau=4, precision=precision)
+    print(f"overlap mode={mode} precision={precision}", flush=True)
+    for chunk in (7, 64, 0):
+        _same(g.search(q, 10, overlap=1, max_chunk=chunk, **kw), g.search(q, 10, max_chunk=chunk, **kw))
+    plan = engine.Plan(g, 100, 10, overlap=1, max_chunk=16, **kw)
+    for nb in (100, 17, 3, 64):
+        qb = q[:nb].contiguous()
+        _same(plan.search(qb), g.search(qb, 10, **kw))
+    plan.free()
