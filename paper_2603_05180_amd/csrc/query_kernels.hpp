@@ -25,10 +25,11 @@ namespace crisp {
 // values are exact in float64; so chaining the instructions in ascending k
 // gives every output exactly the ascending-k float64 sum of its definition.
 // 128x64 output tile per 256-thread block, 64x32 per wavefront (4x2 tiles of
-// 16x16); the k dimension is staged through LDS 16 at a time, converted to
+// 16x16); the k dimension is staged through LDS 32 at a time, converted to
 // float64 on the way in, with the next slab prefetched into registers.
 // ---------------------------------------------------------------------------
-constexpr int kRotBM = 128, kRotBN = 64, kRotBK = 16;
+constexpr int kRotBM = 128, kRotBN = 64, kRotBK = 32;
+constexpr int kRotEA = kRotBM * kRotBK / 256, kRotEB = kRotBK * kRotBN / 256;  // staged floats per thread
 typedef double rot_acc_t __attribute__((ext_vector_type(4)));
 
 // live: NULL, or a device count of the rows to produce (rows beyond it are skipped).
@@ -51,34 +52,34 @@ __global__ void __launch_bounds__(256) k_rotate_rows(const float *__restrict__ x
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = rot_acc_t{0.0, 0.0, 0.0, 0.0};
-  float ra[8], rb[4];
+  float ra[kRotEA], rb[kRotEB];
   auto gload = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < kRotEA; ++e) {
       const int idx = tid + e * 256;
-      const int rr = idx >> 4, kk = idx & 15;
+      const int rr = idx / kRotBK, kk = idx % kRotBK;
       long long gr = row0 + rr;
       gr = gr < rows ? gr : rows - 1;            // clamped; such rows are never stored
       ra[e] = x[gr * d + k0 + kk];
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < kRotEB; ++e) {
       const int idx = tid + e * 256;
-      const int kk = idx >> 6, cc = idx & 63;
+      const int kk = idx / kRotBN, cc = idx % kRotBN;
       rb[e] = r[static_cast<long long>(k0 + kk) * d + col0 + cc];
     }
   };
   gload(0);
   for (int k0 = 0; k0 < d; k0 += kRotBK) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < kRotEA; ++e) {
       const int idx = tid + e * 256;
-      sa[idx & 15][idx >> 4] = static_cast<double>(ra[e]);
+      sa[idx % kRotBK][idx / kRotBK] = static_cast<double>(ra[e]);
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < kRotEB; ++e) {
       const int idx = tid + e * 256;
-      sb[idx >> 6][idx & 63] = static_cast<double>(rb[e]);
+      sb[idx / kRotBN][idx % kRotBN] = static_cast<double>(rb[e]);
     }
     __syncthreads();
     if (k0 + kRotBK < d) gload(k0 + kRotBK);
