@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--patience", type=int, default=40)
     ap.add_argument("--max-chunk", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--guaranteed", type=int, default=1, help="also time Guaranteed Mode (plain and bf16)")
     ap.add_argument("--overlap", type=int, default=1,
                     help="two chunk pipelines on two streams (the per-kernel roofline pass always runs with one)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-oracle time budget (0 = skip)")
@@ -225,6 +226,10 @@ def main():
     forms = {"plain": dict(precision=0), "bf16": dict(precision=1)}
     if model is not None:
         forms["learned_bf16"] = dict(precision=1, budget_source=1)
+    if args.mode == 1 and args.guaranteed:
+        # Guaranteed Mode (every candidate verified) at the same alpha and tau
+        forms["guaranteed"] = dict(mode=0, precision=0)
+        forms["guaranteed_bf16"] = dict(mode=0, precision=1)
     ids = torch.empty(w.n_query, k, dtype=torch.int64, device=dev)
     dists = torch.empty(w.n_query, k, dtype=torch.float32, device=dev)
     plain_ids = None
@@ -240,14 +245,20 @@ def main():
         same = float((ids[:, :, None] == plain_ids[:, None, :]).any(-1).float().mean())
         ms, _ = timed(index, queries, k, kw, args.steps, ids, dists)
         c = counts(index, queries, k, dict(kw, overlap=0))
+        # re-rank gather rate of this form: one single-pipeline step, stage-timed
+        _, st1 = timed(index, queries, k, dict(kw, overlap=0), 1, ids, dists, profile=True)
+        rr_bytes = (((2.0 * w.d + 4.0) * c["examined"] + 4.0 * w.d * c["refined"]) if kw.get("precision") == 1
+                    else 4.0 * w.d * c["examined"])
         results[name] = {"queries_per_s": round(w.n_query / (ms / 1e3), 1), "ms_per_step": round(ms, 3),
                          "recall_at_10": round(rec, 4), "plain_ids_kept": round(same, 5),
                          "mean_verified": round(c["examined"] / w.n_query, 1),
                          "mean_float32_rows": round(c["refined"] / w.n_query, 1),
+                         "rerank_gb_s": round(rr_bytes / 1e9 / (st1["rerank"]["ms"] / 1e3), 1),
                          "max_rel_err_vs_fp64": fp64_error(arrays["base"], qrot, ids, dists),
                          "_kw": kw, "_counts": c}
         log(f"form {name}: {results[name]['queries_per_s']} q/s, recall {rec:.4f}, "
-            f"verified {results[name]['mean_verified']}, float32 rows {results[name]['mean_float32_rows']}")
+            f"verified {results[name]['mean_verified']}, float32 rows {results[name]['mean_float32_rows']}, "
+            f"re-rank {results[name]['rerank_gb_s']} GB/s")
 
     # Headline: the fastest form at recall@10 >= 0.90.
     ok = [f for f in results if results[f]["recall_at_10"] >= 0.90] or list(results)

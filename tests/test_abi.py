@@ -44,3 +44,20 @@ def test_null_arguments_are_rejected_before_any_launch():
     assert _lib.lib.crisp_search(None, None, 1, 1, None, None, None, None, 0, None, None) == -1
     assert _lib.lib.crisp_rotate_rows(None, 1, 64, None, None, None) == -1
     assert _lib.lib.crisp_build_csr(None, 1, 1, None, None, None, None) == -1
+
+
+def test_new_entry_points_reject_bad_arguments_without_launching():
+    from paper_2603_05180_amd import _lib
+    lib = _lib.lib
+    # misaligned or null copy: rejected before any launch
+    assert lib.crisp_copy_probe(ctypes.c_void_p(16), ctypes.c_void_p(8), 32, None) == -1
+    assert lib.crisp_copy_probe(None, ctypes.c_void_p(16), 32, None) == -1
+    assert lib.crisp_copy_probe(ctypes.c_void_p(16), ctypes.c_void_p(32), 20, None) == -1
+    size = ctypes.c_size_t(0)
+    p = _lib.SearchParams(1, 0.01, 2, 40, None, 0, 0, 0, 0, 0)
+    assert lib.crisp_plan_bytes(None, 16, 10, ctypes.byref(p), ctypes.byref(size)) == -1
+    assert lib.crisp_plan_search(None, None, 0, None, None, None) == -1
+    assert lib.crisp_plan_free(None) == 0
+    assert lib.crisp_index_bf16_bytes(None, ctypes.byref(size)) == -1
+    assert lib.crisp_feature_count(32) == 1 + 16 + 3 * 32 + 13
+    assert lib.crisp_mlp_param_count(10) == 10 * 64 + 2 * 64 + 1

@@ -90,3 +90,37 @@ def test_empty_batch_is_a_noop(small):
     ids, d = g.search(torch.empty(0, w.d, dtype=torch.float32, device="cuda"), 5, mode=0, alpha=0.1, tau=2)
     torch.cuda.synchronize()
     assert ids.shape == (0, 5)
+
+
+def test_bad_options_and_plan_limits(small):
+    from paper_2603_05180_amd import engine
+    w, x, q, idx = small
+    g = engine.Index(idx)
+    qt = torch.from_numpy(q).cuda()
+    for kw in ({"persistent": 2}, {"overlap": 2}, {"precision": 1}, {"budget_source": 1}):
+        with pytest.raises(engine.CrispError) as e:
+            g.search(qt, 5, mode=1, alpha=0.1, tau=2, **kw)
+        assert e.value.status == -1
+    plan = engine.Plan(g, 4, 5, mode=1, alpha=0.1, tau=2)
+    with pytest.raises(engine.CrispError):
+        plan.search(torch.from_numpy(np.concatenate([q, q])).cuda())       # 8 > max_batch
+    plan.free()
+    with pytest.raises(ValueError):
+        engine.Plan(g, 4, 5, mode=1, alpha=0.1, tau=2, limits=torch.ones(4, dtype=torch.int32, device="cuda"))
+
+
+def test_overlap_needs_the_doubled_workspace(small):
+    from paper_2603_05180_amd import engine, _lib
+    w, x, q, idx = small
+    g = engine.Index(idx)
+    qt = torch.from_numpy(np.concatenate([q] * 4)).cuda()
+    p1 = g.params(mode=1, alpha=0.1, tau=2, max_chunk=4, overlap=0)
+    p2 = g.params(mode=1, alpha=0.1, tau=2, max_chunk=4, overlap=1)
+    b1, b2 = g.workspace_bytes(16, 5, p1), g.workspace_bytes(16, 5, p2)
+    assert b2 == 2 * b1
+    ws = torch.empty(b1, dtype=torch.uint8, device="cuda")
+    ids = torch.empty(16, 5, dtype=torch.int64, device="cuda")
+    d = torch.empty(16, 5, dtype=torch.float32, device="cuda")
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    st = _lib.lib.crisp_search(g._h, P(qt), 16, 5, ctypes.byref(p2), P(ids), P(d), P(ws), b1, None, None)
+    assert st == -2
