@@ -1005,6 +1005,7 @@ __device__ __forceinline__ bool key_less(double da, int ia, double db, int ib) {
 struct RerankShared {
   double dk[kChunk];
   int sid[kChunk];
+  float serr[kChunk];
   int plist[kChunk];
   int hist[256];
   int misc[16];
@@ -1371,20 +1372,26 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
       const int cnt = min(kChunk, lim - c0);
       const int tn0 = S.misc[2];
       const int free_slots = max(0, k - tn0);
+      // (a0) the chunk's ids (and row error bounds) staged in LDS by one
+      // coalesced load, so that no row load waits on an id load
+      if (tid < cnt) {
+        const int id = list[qo + c0 + tid];
+        S.sid[tid] = id;
+        if constexpr (kBf16) S.serr[tid] = rerr[id];
+      }
+      __syncthreads();
       if constexpr (kBf16) {
         // (a) bounds of the chunk from the bfloat16 rows
         for (int t = 2 * wv; t < cnt; t += 2 * kRerankWaves) {
-          const int ida = list[qo + c0 + t];
-          const int idb = list[qo + c0 + min(t + 1, cnt - 1)];
+          const int ida = S.sid[t];
+          const int idb = S.sid[min(t + 1, cnt - 1)];
           const float2 tt = row_dist_bf16_x2(sq, base16 + static_cast<long long>(ida) * d,
                                              base16 + static_cast<long long>(idb) * d, d);
           if (lane < 2 && t + lane < cnt) {
-            const int id = lane ? idb : ida;
             double lb, ub;
-            bf16_bounds(lane ? tt.y : tt.x, rerr[id], gam, lb, ub);
+            bf16_bounds(lane ? tt.y : tt.x, S.serr[t + lane], gam, lb, ub);
             xlb[t + lane] = lb;
             xub[t + lane] = ub;
-            S.sid[t + lane] = id;
           }
         }
         __syncthreads();
@@ -1416,9 +1423,8 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
       } else {
         // (a) exact keys of the chunk, in parallel
         for (int t = wv; t < cnt; t += kRerankWaves) {
-          const int id = list[qo + c0 + t];
-          const double dc = row_dist_canon(sq, base + static_cast<long long>(id) * d, d);
-          if (lane == 0) { S.dk[t] = dc; S.sid[t] = id; }
+          const double dc = row_dist_canon(sq, base + static_cast<long long>(S.sid[t]) * d, d);
+          if (lane == 0) S.dk[t] = dc;
         }
       }
       __syncthreads();
@@ -1525,23 +1531,26 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
 // the next query from the device counter *queue (zero at launch) until the
 // live queries are exhausted; every block then exits.
 template <int kMode, bool kBf16>
-__global__ void __launch_bounds__(kRerankThreads) k_rerank(CRISP_RERANK_PARAMS, const int32_t *__restrict__ live, int nq,
+__global__ void __launch_bounds__(kRerankThreads) __attribute__((amdgpu_waves_per_eu(kBf16 ? 4 : 1)))
+k_rerank(CRISP_RERANK_PARAMS, const int32_t *__restrict__ live, int nq,
                                                            int32_t *__restrict__ queue) {
-  if (queue == nullptr) {
-    const int q = blockIdx.x;
-    if (live && q >= *live) return;
-    rerank_query<kMode, kBf16>(q, CRISP_RERANK_ARGS);
-    return;
-  }
+  // One call site, so the per-query code is inlined once.
   const int nl = live ? min(nq, *live) : nq;
   __shared__ int next;
-  for (;;) {
+  int q = blockIdx.x;
+  if (queue != nullptr) {
     if (threadIdx.x == 0) next = atomicAdd(queue, 1);
     __syncthreads();
-    const int q = next;
+    q = next;
     __syncthreads();
-    if (q >= nl) return;
+  }
+  while (q < nl) {
     rerank_query<kMode, kBf16>(q, CRISP_RERANK_ARGS);
+    if (queue == nullptr) break;
+    __syncthreads();
+    if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+    __syncthreads();
+    q = next;
     __syncthreads();
   }
 }
