@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--max-chunk", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--guaranteed", type=int, default=1, help="also time Guaranteed Mode (plain and bf16)")
+    ap.add_argument("--tuned-patience", type=int, default=10,
+                    help="also time the bf16 form at this patience factor (0 = skip)")
     ap.add_argument("--overlap", type=int, default=1,
                     help="two chunk pipelines on two streams (the per-kernel roofline pass always runs with one)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-oracle time budget (0 = skip)")
@@ -226,6 +228,9 @@ def main():
     forms = {"plain": dict(precision=0), "bf16": dict(precision=1)}
     if model is not None:
         forms["learned_bf16"] = dict(precision=1, budget_source=1)
+    if args.mode == 1 and args.tuned_patience > 0:
+        # a tuned operating point: the same engine with a shorter patience
+        forms[f"bf16_pf{args.tuned_patience}"] = dict(precision=1, patience_factor=args.tuned_patience)
     if args.mode == 1 and args.guaranteed:
         # Guaranteed Mode (every candidate verified) at the same alpha and tau
         forms["guaranteed"] = dict(mode=0, precision=0)
@@ -319,8 +324,10 @@ def main():
         "vs_baseline": None, "dtype": "f32+bf16" if bf16 else "f32", "data": "synthetic",
         "config": {"workload": f"{w.name}: N={w.n} D={w.d} correlated Gaussian mixture ({w.kind} rank {w.rank}, "
                                f"{w.n_comp} comps), M={w.m} K={w.k_half}, {w.n_query} queries/batch, k={k}",
-                   "mode": "optimized" if args.mode == 1 else "guaranteed", "alpha": args.alpha, "tau": args.tau,
-                   "patience_factor": args.patience, "recall_at_10": results[head]["recall_at_10"],
+                   "mode": "optimized" if kw.get("mode", args.mode) == 1 else "guaranteed",
+                   "alpha": args.alpha, "tau": args.tau,
+                   "patience_factor": kw.get("patience_factor", args.patience),
+                   "recall_at_10": results[head]["recall_at_10"],
                    "overlap": args.overlap,
                    "rotated": rotated,
                    "mean_candidates": round(c["n_cand"] / w.n_query, 1),
