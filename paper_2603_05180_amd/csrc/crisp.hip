@@ -125,7 +125,7 @@ struct StageTimer {
 // Workspace layout for one chunk of qc queries.
 struct Layout {
   size_t qrot, hdist, ptab, ncell, cells, retr, tilecnt, hist, flag, taueff, ncand, segids, segscore, cand,
-      score, regA, regB, regC, examined, lastupd, stopped, refined, sstat, feat, lim, queue, total;
+      score, regA, regB, regC, examined, lastupd, stopped, refined, sstat, feat, lim, queue, order, total;
 };
 
 static Layout make_layout(const crisp_index *ix, long long qc) {
@@ -159,6 +159,7 @@ static Layout make_layout(const crisp_index *ix, long long qc) {
   L.feat = take(qc * n_features(ix->m) * 4);
   L.lim = take(qc * 4);
   L.queue = take(4);
+  L.order = take(qc * 4);
   L.total = o;
   return L;
 }
@@ -403,6 +404,7 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
     int32_t *stopd = reinterpret_cast<int32_t *>(ws + L.stopped);
     int32_t *refd = reinterpret_cast<int32_t *>(ws + L.refined);
     int32_t *queue = reinterpret_cast<int32_t *>(ws + L.queue);
+    int32_t *qord = reinterpret_cast<int32_t *>(ws + L.order);
     double *sstat = reinterpret_cast<double *>(ws + L.sstat);
     float *feat = reinterpret_cast<float *>(ws + L.feat);
     int32_t *llim = reinterpret_cast<int32_t *>(ws + L.lim);
@@ -456,6 +458,12 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       k_compact<<<cq, kCompactThreads, 0, st>>>(segids, segscore, tilecnt, nseg, ix->tile / kCountWaves, n, cand,
                                                  score, ncand, lv);
       LAUNCH_TRY("k_compact");
+      if (cq <= kQueryOrderMax) {
+        k_query_order<<<1, kQueryOrderThreads, 0, st>>>(cq, ncand, cand, n, qord, lv);
+        LAUNCH_TRY("k_query_order");
+      } else {
+        qord = nullptr;
+      }
     }
     t3.stop();
     const int32_t *lim = p->limits ? p->limits + q0 : nullptr;
@@ -466,9 +474,9 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
         const int gx = static_cast<int>(std::max(1, std::min(64, (4096 + cq - 1) / cq)));
         dim3 g(gx, cq);
         if (hamming_vec(d / 64) == 2)
-          k_hamming_dist<2><<<g, kOrderThreads, 0, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, lv);
+          k_hamming_dist<2><<<g, kOrderThreads, 0, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, lv, qord);
         else
-          k_hamming_dist<1><<<g, kOrderThreads, 0, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, lv);
+          k_hamming_dist<1><<<g, kOrderThreads, 0, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, lv, qord);
         LAUNCH_TRY("k_hamming_dist");
       }
       t4.stop();
@@ -500,7 +508,7 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
                                                         segids, n, k, patience, lim, regC, nullptr, nullptr,
                                                         ids + q0 * k,
                                                         dists + q0 * k, exam, lastu, stopd, refd, lv, cq,
-                                                        p->persistent ? queue : nullptr);
+                                                        p->persistent ? queue : nullptr, qord);
       LAUNCH_TRY("k_rerank");
       t5.stop();
     } else {
@@ -513,7 +521,7 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
                                                         cand, n, k, patience, lim, regC,
                                                         reinterpret_cast<float *>(regA), regB, ids + q0 * k,
                                                         dists + q0 * k, exam, lastu, stopd, refd, lv, cq,
-                                                        p->persistent ? queue : nullptr);
+                                                        p->persistent ? queue : nullptr, qord);
       LAUNCH_TRY("k_rerank");
       t5.stop();
     }

@@ -730,6 +730,54 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(
   if (tid == 0) ncand[q] = carry;
 }
 
+// Run order of a chunk's queries for the stages that read candidate rows
+// (Hamming distances, re-rank): ascending smallest candidate id, ties by query
+// index, queries past the live count and queries with no candidates last, so
+// live queries fill the first live-count positions.  Queries whose candidate
+// sets overlap then run side by side and find the shared code and base rows
+// in L2 / the last-level cache instead of HBM.  It only decides which query
+// a block takes: every per-query result is the same in any order.  One
+// block, bitonic sort of (key << 12 | q) in LDS.
+constexpr int kQueryOrderMax = 4096;
+constexpr int kQueryOrderThreads = 1024;
+constexpr int kQueryOrderBits = 12;
+static_assert(kQueryOrderMax <= (1 << kQueryOrderBits), "query index must fit its field");
+
+__global__ void __launch_bounds__(kQueryOrderThreads) k_query_order(int cq, const int32_t *__restrict__ ncand,
+                                                                    const int32_t *__restrict__ cand, long long n,
+                                                                    int32_t *__restrict__ order,
+                                                                    const int32_t *__restrict__ live) {
+  __shared__ long long key[kQueryOrderMax];
+  int n2 = 2;
+  while (n2 < cq) n2 <<= 1;
+  const int nl = live ? min(cq, *live) : cq;
+  for (int i = threadIdx.x; i < n2; i += kQueryOrderThreads) {
+    long long v = 0x7fffffffffffffffll;
+    if (i < cq) {
+      const long long first = (i < nl && ncand[i] > 0) ? cand[static_cast<long long>(i) * n] : n;
+      v = (first << kQueryOrderBits) | i;
+    }
+    key[i] = v;
+  }
+  __syncthreads();
+  for (int len = 2; len <= n2; len <<= 1)
+    for (int j = len >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n2; i += kQueryOrderThreads) {
+        const int p = i ^ j;
+        if (p > i) {
+          const long long a = key[i], b = key[p];
+          if ((a > b) == ((i & len) == 0)) {
+            key[i] = b;
+            key[p] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = threadIdx.x; i < cq; i += kQueryOrderThreads)
+    order[i] = static_cast<int32_t>(key[i] & ((1ll << kQueryOrderBits) - 1));
+}
+
 // ---------------------------------------------------------------------------
 // A5: Hamming order, in two kernels.
 //
@@ -772,10 +820,11 @@ __host__ __device__ inline int hamming_vec(int words) { return (words % 2 == 0) 
 template <int kVec>
 __global__ void __launch_bounds__(kOrderThreads) k_hamming_dist(
     const float *__restrict__ qrot, int d, const uint64_t *__restrict__ codes, const int32_t *__restrict__ ncand,
-    const int32_t *__restrict__ cand, long long n, int32_t *__restrict__ hm_tmp, const int32_t *__restrict__ live) {
+    const int32_t *__restrict__ cand, long long n, int32_t *__restrict__ hm_tmp, const int32_t *__restrict__ live,
+    const int32_t *__restrict__ order) {
   using V = typename CodeVec<kVec>::T;
   __shared__ uint64_t qc[128];
-  const int q = blockIdx.y, lane = lane_id(), wv = wave_id();
+  const int q = order ? order[blockIdx.y] : static_cast<int>(blockIdx.y), lane = lane_id(), wv = wave_id();
   if (live && q >= *live) return;
   const int words = d / 64;
   const int nc = ncand[q];
@@ -1526,14 +1575,16 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
   }
 }
 
-// queue == NULL: block b re-ranks query b.  Otherwise the grid is persistent
-// (about as many blocks as fit on the chip at once) and every block pulls
-// the next query from the device counter *queue (zero at launch) until the
-// live queries are exhausted; every block then exits.
+// Positions: queue == NULL, block b takes position b; otherwise the grid is
+// persistent (about as many blocks as fit on the chip at once) and every
+// block pulls the next position from the device counter *queue (zero at
+// launch) until the live positions are exhausted; every block then exits.
+// Position i re-ranks query order[i] (order from k_query_order, which keeps
+// live queries first), or query i when order is NULL.
 template <int kMode, bool kBf16>
 __global__ void __launch_bounds__(kRerankThreads) __attribute__((amdgpu_waves_per_eu(kBf16 ? 4 : 1)))
 k_rerank(CRISP_RERANK_PARAMS, const int32_t *__restrict__ live, int nq,
-                                                           int32_t *__restrict__ queue) {
+                                                           int32_t *__restrict__ queue, const int32_t *__restrict__ order) {
   // One call site, so the per-query code is inlined once.
   const int nl = live ? min(nq, *live) : nq;
   __shared__ int next;
@@ -1545,7 +1596,7 @@ k_rerank(CRISP_RERANK_PARAMS, const int32_t *__restrict__ live, int nq,
     __syncthreads();
   }
   while (q < nl) {
-    rerank_query<kMode, kBf16>(q, CRISP_RERANK_ARGS);
+    rerank_query<kMode, kBf16>(order ? order[q] : q, CRISP_RERANK_ARGS);
     if (queue == nullptr) break;
     __syncthreads();
     if (threadIdx.x == 0) next = atomicAdd(queue, 1);

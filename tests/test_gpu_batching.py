@@ -144,3 +144,18 @@ def test_two_chunk_pipelines_match(d128, mode, precision):
         qb = q[:nb].contiguous()
         _same(plan.search(qb), g.search(qb, 10, **kw))
     plan.free()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_query_run_order_does_not_change_results(d128, mode):
+    """Chunks of up to 4096 queries run their candidate-reading stages in a
+    sorted query order, larger chunks in index order: both, and chunks that
+    straddle the limit, give the same ids and distances."""
+    w, x, q, idx, g = d128
+    kw = dict(mode=mode, alpha=0.05, tau=4, precision=1)
+    qq = q.repeat(15, 1).contiguous()                     # 4,500 queries
+    ref = g.search(qq, 10, max_chunk=4500, **kw)          # one chunk, index order
+    _same(g.search(qq, 10, max_chunk=4096, **kw), ref)    # 4,096 sorted + 404 sorted
+    _same(g.search(qq, 10, max_chunk=1000, overlap=1, **kw), ref)
+    ids = ref[0].cpu().numpy()
+    assert np.array_equal(ids[:300], ids[4200:])          # repeated queries, repeated answers
