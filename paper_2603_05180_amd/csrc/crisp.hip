@@ -358,7 +358,8 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
   const int d = ix->d, m = ix->m, kh = ix->k, nb = 2 * m + 1;
   const long long n = ix->n;
   const int budget = static_cast<int>(std::max<double>(1.0, std::ceil(p->alpha * static_cast<double>(n))));
-  const int patience = p->mode == 1 ? p->patience_factor * k : 0;
+  const int patience =
+      p->mode == 1 ? static_cast<int>(std::min<long long>(static_cast<long long>(p->patience_factor) * k, INT32_MAX)) : 0;
   const size_t count_lds = static_cast<size_t>(ix->tile);
   const int nseg = ix->ntiles * kCountWaves;
   const bool bf16 = p->precision == 1;

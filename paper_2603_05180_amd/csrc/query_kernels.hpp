@@ -1417,8 +1417,12 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
     }
     if (tid == 0) { S.misc[2] = 0; S.misc[3] = 0; S.misc[4] = 0; S.misc[5] = 0; S.misc[6] = 0; S.misc[8] = 0; }
     __syncthreads();
-    for (int c0 = 0; c0 < lim; c0 += kChunk) {
-      const int cnt = min(kChunk, lim - c0);
+    for (int c0 = 0, cnt = 0; c0 < lim; c0 += cnt) {
+      // The walk cannot stop within the next patience - run candidates, so a
+      // chunk of that many (in whole wavefront widths, at most kChunk) is
+      // always walked in full; fewer rows are read past the stopping point.
+      const int need = max(patience - S.misc[3], 1);
+      cnt = min(min(kChunk, (need + kWave - 1) / kWave * kWave), lim - c0);
       const int tn0 = S.misc[2];
       const int free_slots = max(0, k - tn0);
       // (a0) the chunk's ids (and row error bounds) staged in LDS by one
