@@ -107,6 +107,18 @@ __device__ inline int block_exclusive_scan(int *a, int n, int *tmp /* >= blockDi
   return total;
 }
 
+// The dispatcher deals consecutive workgroups of a 1-D grid to the eight
+// XCDs in turn (workgroup b to XCD b % 8), and each XCD has its own L2.  For a
+// grid padded to a multiple of 8, xcd_major(b) gives XCD x the contiguous
+// range [x * nb / 8, (x + 1) * nb / 8) of logical blocks, so that neighbouring
+// logical blocks (which read overlapping rows) share one L2.  A bijection of
+// [0, nb); logical blocks past the real count simply exit.
+constexpr int kXcds = 8;
+__host__ __device__ inline int xcd_pad(int nb) { return (nb + kXcds - 1) / kXcds * kXcds; }
+__device__ __forceinline__ int xcd_major(int b, int nb_padded) {
+  return (b % kXcds) * (nb_padded / kXcds) + b / kXcds;
+}
+
 // Largest j in [0, n) with a[j] <= v, for non-decreasing a with a[0] <= v.
 __device__ __forceinline__ int upper_bound_minus1(const int *a, int n, int v) {
   int lo = 0, hi = n;  // first index with a[idx] > v

@@ -473,11 +473,11 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       StageTimer t4(ix, 4, st);  // distances
       {
         const int gx = static_cast<int>(std::max(1, std::min(64, (4096 + cq - 1) / cq)));
-        dim3 g(gx, cq);
+        const int g = xcd_pad(gx * cq);
         if (hamming_vec(d / 64) == 2)
-          k_hamming_dist<2><<<g, kOrderThreads, 0, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, lv, qord);
+          k_hamming_dist<2><<<g, kOrderThreads, 0, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, lv, qord, gx, cq);
         else
-          k_hamming_dist<1><<<g, kOrderThreads, 0, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, lv, qord);
+          k_hamming_dist<1><<<g, kOrderThreads, 0, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, lv, qord, gx, cq);
         LAUNCH_TRY("k_hamming_dist");
       }
       t4.stop();
@@ -505,7 +505,7 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
         k_fill<int32_t><<<1, 64, 0, st>>>(queue, 1, 0);
         LAUNCH_TRY("k_fill");
       }
-      rerank1<<<p->persistent ? std::min(cq, rr_resident) : cq, kRerankThreads, rr_lds, st>>>(qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
+      rerank1<<<p->persistent ? std::min(cq, rr_resident) : xcd_pad(cq), kRerankThreads, rr_lds, st>>>(qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
                                                         segids, n, k, patience, lim, regC, nullptr, nullptr,
                                                         ids + q0 * k,
                                                         dists + q0 * k, exam, lastu, stopd, refd, lv, cq,
@@ -518,7 +518,7 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
         k_fill<int32_t><<<1, 64, 0, st>>>(queue, 1, 0);
         LAUNCH_TRY("k_fill");
       }
-      rerank0<<<p->persistent ? std::min(cq, rr_resident) : cq, kRerankThreads, rr_lds, st>>>(qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
+      rerank0<<<p->persistent ? std::min(cq, rr_resident) : xcd_pad(cq), kRerankThreads, rr_lds, st>>>(qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
                                                         cand, n, k, patience, lim, regC,
                                                         reinterpret_cast<float *>(regA), regB, ids + q0 * k,
                                                         dists + q0 * k, exam, lastu, stopd, refd, lv, cq,

@@ -781,8 +781,9 @@ __global__ void __launch_bounds__(kQueryOrderThreads) k_query_order(int cq, cons
 // ---------------------------------------------------------------------------
 // A5: Hamming order, in two kernels.
 //
-// k_hamming_dist: grid (gx, queries), gx chosen from the batch size so that a
-// small batch still spreads over the chip.  Each wavefront takes 64
+// k_hamming_dist: gx blocks per query (gx chosen from the batch size so that a
+// small batch still spreads over the chip), in run order, dealt to the XCDs
+// in contiguous ranges.  Each wavefront takes 64
 // consecutive candidates at a time (one coalesced id load, ids passed
 // between lanes by shuffles), striding over the query's list with the
 // other gx * 4 - 1 wavefronts of its query.  The query's sign code is built
@@ -821,10 +822,13 @@ template <int kVec>
 __global__ void __launch_bounds__(kOrderThreads) k_hamming_dist(
     const float *__restrict__ qrot, int d, const uint64_t *__restrict__ codes, const int32_t *__restrict__ ncand,
     const int32_t *__restrict__ cand, long long n, int32_t *__restrict__ hm_tmp, const int32_t *__restrict__ live,
-    const int32_t *__restrict__ order) {
+    const int32_t *__restrict__ order, int gx, int cq) {
   using V = typename CodeVec<kVec>::T;
   __shared__ uint64_t qc[128];
-  const int q = order ? order[blockIdx.y] : static_cast<int>(blockIdx.y), lane = lane_id(), wv = wave_id();
+  const int lb = xcd_major(blockIdx.x, gridDim.x);
+  if (lb >= gx * cq) return;
+  const int bx = lb % gx, pos = lb / gx;
+  const int q = order ? order[pos] : pos, lane = lane_id(), wv = wave_id();
   if (live && q >= *live) return;
   const int words = d / 64;
   const int nc = ncand[q];
@@ -839,8 +843,8 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_dist(
   const int rows_per = kWave / L;
   const int sub = lane % L, rsel = lane / L;
   const int J = (span + L - 1) / L;                   // loads per row per lane
-  const int stride = gridDim.x * kOrderWaves * kWave;
-  for (int base = (blockIdx.x * kOrderWaves + wv) * kWave; base < nc; base += stride) {
+  const int stride = gx * kOrderWaves * kWave;
+  for (int base = (bx * kOrderWaves + wv) * kWave; base < nc; base += stride) {
     const int my_id = cand[qo + min(base + lane, nc - 1)];
     for (int s0 = 0; s0 < L; s0 += 4) {
       int hs[4], idr[4];
@@ -1579,7 +1583,8 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
   }
 }
 
-// Positions: queue == NULL, block b takes position b; otherwise the grid is
+// Positions: queue == NULL, the grid is padded to a multiple of 8 and each
+// XCD takes a contiguous range of positions; otherwise the grid is
 // persistent (about as many blocks as fit on the chip at once) and every
 // block pulls the next position from the device counter *queue (zero at
 // launch) until the live positions are exhausted; every block then exits.
@@ -1592,7 +1597,7 @@ k_rerank(CRISP_RERANK_PARAMS, const int32_t *__restrict__ live, int nq,
   // One call site, so the per-query code is inlined once.
   const int nl = live ? min(nq, *live) : nq;
   __shared__ int next;
-  int q = blockIdx.x;
+  int q = queue ? 0 : xcd_major(blockIdx.x, gridDim.x);
   if (queue != nullptr) {
     if (threadIdx.x == 0) next = atomicAdd(queue, 1);
     __syncthreads();
