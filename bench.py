@@ -49,7 +49,8 @@ def parse():
     ap.add_argument("--alpha", type=float, default=0.002)
     ap.add_argument("--tau", type=int, default=16)
     ap.add_argument("--patience", type=int, default=40)
-    ap.add_argument("--max-chunk", type=int, default=0)
+    ap.add_argument("--max-chunk", type=int, default=4096,
+                    help="queries per chunk (4096: two pipelines of N-sized per-query buffers fill most of HBM)")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--guaranteed", type=int, default=1, help="also time Guaranteed Mode (plain and bf16)")
     ap.add_argument("--tuned-patience", type=int, default=10,

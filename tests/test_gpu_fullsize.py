@@ -2,7 +2,7 @@
 
 The N = 1M, D = 4096 index and the N = 2M, D = 3072 index are generated and
 built on the GPU exactly as bench.py does; the whole batch is searched in
-the configuration bench.py times (10,000 queries, chunks of 2,048, two chunk
+the configuration bench.py times (10,000 queries, chunks of 4,096, two chunk
 pipelines, float32 and bfloat16 verification; the batch executor's graphs
 for the uneven workload), and sampled queries, spread over the chunks, are
 re-run one by one by the CPU oracle on a host copy of the same index arrays:
@@ -55,11 +55,12 @@ def test_d4096_bench_configuration_sampled():
     index = engine.Index(arrays)
     index.enable_bf16()
     kw = dict(mode=1, alpha=0.002, tau=16, patience_factor=40)
+    ck = dict(max_chunk=4096)
     res = {}
     for name, extra in (("float32", dict(overlap=1)), ("bf16", dict(overlap=1, precision=1)),
                         ("bf16 persistent", dict(precision=1, persistent=1))):
         print(f"d4096 full batch, {name}", flush=True)
-        ids, d = index.search(queries, w.k, **kw, **extra)
+        ids, d = index.search(queries, w.k, **kw, **ck, **extra)
         torch.cuda.synchronize()
         res[name] = (ids.cpu().numpy(), d.cpu().numpy())
     for name in res:
@@ -71,7 +72,7 @@ def test_d4096_bench_configuration_sampled():
     torch.cuda.synchronize()
     host = _host(arrays)
     q = queries.cpu().numpy()
-    sample = np.array([0, 1, 2047, 2048, 5000, 8191, 8192, 9999])
+    sample = np.array([0, 1, 2047, 4095, 4096, 5000, 8191, 8192, 9999])
     print("d4096 oracle on sampled queries", flush=True)
     _check(host, q, sample, *res["float32"], w.k, **kw)
     from oracle import query as oquery
@@ -84,7 +85,7 @@ def test_d4096_bench_configuration_sampled():
     trainq = sg.rows(w, 3004, 0, 20_000, params)
     learned.train_budget(index, trainq, w.k, epochs=5, alpha=0.002, tau=16, patience_factor=40)
     taps = {"limits": torch.empty(w.n_query, dtype=torch.int32, device="cuda")}
-    li, ld = index.search(queries, w.k, budget_source=1, precision=1, overlap=1, taps=taps, **kw)
+    li, ld = index.search(queries, w.k, budget_source=1, precision=1, overlap=1, taps=taps, **kw, **ck)
     torch.cuda.synchronize()
     lim = taps["limits"].cpu().numpy()
     oi, od, _ = oquery.search(host, q[sample], w.k, limits=lim[sample], **kw)
