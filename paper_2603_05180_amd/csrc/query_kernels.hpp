@@ -482,10 +482,13 @@ constexpr int kCountThreads = 1024;
 constexpr int kCountWaves = kCountThreads / kWave;
 constexpr int kItems = 1024;
 
+// A pointer into global memory (read back from LDS, the compiler would
+// otherwise treat it as generic and use flat loads).
+typedef const int32_t __attribute__((address_space(1))) *global_i32_ptr;
+
 struct CountShared {
-  long long start[kItems];
-  int pref[kItems + 1];
-  unsigned char w[kItems];
+  global_i32_ptr ptr[kItems];  // first id of the item's slice (ids itself for an empty slice)
+  int lw[kItems];              // slice length << 8 | rank weight
   int mbase[129];
   int hist[256];
   int tmp[kCountWaves + 1];
@@ -527,7 +530,7 @@ __global__ void __launch_bounds__(kCountThreads) k_count(
     const int nb = min(kItems, total_items - b0);
     for (int it = tid; it < kItems; it += kCountThreads) {
       int len = 0;
-      long long start = 0;
+      global_i32_ptr ptr = (global_i32_ptr)(ids);
       int w = 0;
       if (it < nb) {
         int g = b0 + it;
@@ -538,32 +541,34 @@ __global__ void __launch_bounds__(kCountThreads) k_count(
         const int32_t *to = tile_off + (static_cast<long long>(s) * ncells + cell) * (ntiles + 1);
         const int a = to[tile];
         len = to[tile + 1] - a;
-        start = static_cast<long long>(s) * n + a;
+        if (len > 0) ptr = (global_i32_ptr)(ids + static_cast<long long>(s) * n + a);
       }
-      S.pref[it] = len;
-      S.start[it] = start;
-      S.w[it] = static_cast<unsigned char>(w);
+      S.ptr[it] = ptr;
+      S.lw[it] = (len << 8) | w;
     }
     __syncthreads();
     // Waves take whole items (posting-list slices, a few dozen ids each on
     // average) round robin, kG at a time: the first 64 ids of kG slices are
     // loaded together, then any longer slice is strided with four coalesced
-    // loads in flight per lane.
+    // loads in flight per lane.  Item reads are unconditional (an item past
+    // the batch reads as an empty slice) so that no lane mask is set up per
+    // slice.
     constexpr int kG = 8;
-    for (int it0 = wave_id(); it0 < nb; it0 += kG * kCountWaves) {
+    const int wave0 = __builtin_amdgcn_readfirstlane(wave_id());
+    for (int it0 = wave0; it0 < nb; it0 += kG * kCountWaves) {
       int idv[kG], lenv[kG];
-      long long stv[kG];
+      global_i32_ptr ptrv[kG];
       uint32_t wgv[kG];
 #pragma unroll
       for (int u = 0; u < kG; ++u) {
         const int it = it0 + u * kCountWaves;
-        const bool ok = it < nb;
-        lenv[u] = ok ? S.pref[it] : 0;
-        stv[u] = ok ? S.start[it] : 0;
-        wgv[u] = ok ? S.w[it] : 0u;
-        // clamped: every load is issued, an empty slice reads element 0
-        const long long a = lenv[u] > 0 ? stv[u] + (lane < lenv[u] ? lane : lenv[u] - 1) : 0;
-        idv[u] = ids[a];
+        const int itc = min(it, kItems - 1);
+        const int lw = S.lw[itc];
+        lenv[u] = it < nb ? (lw >> 8) : 0;
+        wgv[u] = static_cast<uint32_t>(lw & 255);
+        ptrv[u] = S.ptr[itc];
+        // clamped: every load is issued, an empty slice reads its first element
+        idv[u] = ptrv[u][min(lane, max(lenv[u] - 1, 0))];
       }
 #pragma unroll
       for (int u = 0; u < kG; ++u) {
@@ -573,14 +578,14 @@ __global__ void __launch_bounds__(kCountThreads) k_count(
       }
 #pragma unroll 1
       for (int u = 0; u < kG; ++u) {
-        const long long st = stv[u];
+        const global_i32_ptr sp = ptrv[u];
         const int len = lenv[u];
         for (int p0 = kWave + lane; p0 < len; p0 += 4 * kWave) {
           int iv[4];
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int p = p0 + e * kWave;
-            iv[e] = ids[st + (p < len ? p : len - 1)];   // clamped: every load is issued
+            iv[e] = sp[p < len ? p : len - 1];   // clamped: every load is issued
           }
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
