@@ -282,8 +282,9 @@ def main():
     bf16 = kw.get("precision", 0) == 1
     rerank_bytes = ((2.0 * d + 4.0) * c["examined"] + 4.0 * d * c["refined"]) if bf16 else 4.0 * d * c["examined"]
     per_step = {
-        "rotate": ("alu", 2.0 * d * d * w.n_query / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"),
-        "count": ("hbm", (4.0 * c["retrieved"] + 5.0 * c["n_cand"] * 2) / 1e9, HBM_PEAK_GBS, "GB/s"),
+        "rotate": ("mfma", 2.0 * d * d * w.n_query / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"),
+        # first counting pass: every retrieved id read once, every candidate (id, score) written once
+        "count": ("hbm", (4.0 * c["retrieved"] + 5.0 * c["n_cand"]) / 1e9, HBM_PEAK_GBS, "GB/s"),
         "hamming_dist": ("hbm", (d / 8.0 + 8.0) * c["n_cand"] / 1e9, HBM_PEAK_GBS, "GB/s"),
         "rerank": ("hbm", rerank_bytes / 1e9, HBM_PEAK_GBS, "GB/s"),
     }
@@ -300,12 +301,12 @@ def main():
         stage_out[name] = ent
     dom = max((s for s in stage_out if s in per_step), key=lambda s: stage_out[s]["ms_per_step"])
     launches = stage_out[dom]["launches_per_step"]
-    roof = {"kernel": {"rerank": "k_rerank", "count": "k_count", "rotate": "k_rotate_rows",
-                       "hamming_dist": "k_hamming_dist"}[dom],
+    kernel_of = {"rerank": "k_rerank", "count": "k_count<0>", "rotate": "k_rotate_rows",
+                 "hamming_dist": "k_hamming_dist"}
+    roof = {"kernel": kernel_of[dom],
             "bound": per_step[dom][0], "achieved": stage_out[dom]["achieved"], "peak": per_step[dom][2],
             "unit": per_step[dom][3], "frac": stage_out[dom]["frac"],
-            "traffic": measured_traffic({"rerank": "k_rerank", "count": "k_count", "rotate": "k_rotate_rows",
-                                         "hamming_dist": "k_hamming_dist"}[dom], w.name),
+            "traffic": measured_traffic(kernel_of[dom], w.name),
             "avg_launch_ms": round(stage_out[dom]["ms_per_step"] / launches, 4),
             "algorithmic_per_launch": round(per_step[dom][1] / launches, 4)}
     if "rerank" in stage_out:
@@ -329,7 +330,7 @@ def main():
                    "alpha": args.alpha, "tau": args.tau,
                    "patience_factor": kw.get("patience_factor", args.patience),
                    "recall_at_10": results[head]["recall_at_10"],
-                   "overlap": args.overlap,
+                   "overlap": args.overlap, "queries_per_chunk": base_kw["max_chunk"],
                    "rotated": rotated,
                    "mean_candidates": round(c["n_cand"] / w.n_query, 1),
                    "mean_verified": round(c["examined"] / w.n_query, 1), "form": head,

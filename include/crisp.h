@@ -397,9 +397,11 @@ crisp_status crisp_copy_probe(void *dst, const void *src, size_t bytes, void *hi
 /*
  * GPU time per query stage, measured with HIP events recorded on the search
  * stream around each stage's launches.  Stages: 0 rotation, 1 Hamming
- * order placement, 2 half distances + cell selection, 3 collision counting,
- * fallback and candidate lists, 4 Hamming distances, 5 re-rank (exact keys,
- * top-k or patience walk), 6 learned-budget features and inference.
+ * order placement, 2 half distances + cell selection, 3 collision counting
+ * (the first counting pass alone), 4 Hamming distances, 5 re-rank (exact
+ * keys, top-k or patience walk), 6 learned-budget features and inference,
+ * 7 candidate lists (score histogram clear, fallback flag, the two fallback
+ * counting passes, effective threshold, compaction, query run order).
  */
 typedef struct {
   double ms[8];

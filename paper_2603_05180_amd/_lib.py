@@ -42,7 +42,7 @@ class Profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 8), ("intervals", c_int64 * 8), ("dropped", c_int64)]
 
 
-STAGES = ["rotate", "hamming_place", "select", "count", "hamming_dist", "rerank", "budget"]
+STAGES = ["rotate", "hamming_place", "select", "count", "hamming_dist", "rerank", "budget", "candidates"]
 
 TAP_FIELDS = ["q_rot", "half_dist", "n_cells", "cells", "retrieved", "hist", "tau_eff", "n_cand",
               "cand", "cand_score", "order", "hamming", "examined", "last_update", "stopped", "features",

@@ -224,7 +224,11 @@ crisp_status crisp_index_load(const crisp_index_desc *desc, int32_t tile_ids, vo
   const long long ncent = static_cast<long long>(desc->m) * 2 * desc->k_half * hh;
   k_transpose_centroids<<<grid1(ncent, 256), 256, 0, st>>>(desc->centroids, desc->m, desc->k_half, hh, cent_t);
   LAUNCH_TRY("k_transpose_centroids");
-  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_count), hipFuncAttributeMaxDynamicSharedMemorySize,
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_count<0>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              tile));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_count<1>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              tile));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_count<2>), hipFuncAttributeMaxDynamicSharedMemorySize,
                               tile));
   {
     const void *rr[4] = {reinterpret_cast<const void *>(&k_rerank<0, false>),
@@ -434,27 +438,34 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       LAUNCH_TRY("k_select_cells");
       t2.stop();
     }
-    // A3 / A4
-    StageTimer t3(ix, 3, st);
-    k_fill<int32_t><<<grid1(static_cast<long long>(cq) * nb, 256), 256, 0, st>>>(hist, static_cast<long long>(cq) * nb, 0);
-    LAUNCH_TRY("k_fill");
+    // A3 / A4: the first counting pass is stage 3; clearing, the fallback
+    // passes, compaction and the run order are stage 7
+    {
+      StageTimer t7(ix, 7, st);
+      k_fill<int32_t><<<grid1(static_cast<long long>(cq) * nb, 256), 256, 0, st>>>(hist, static_cast<long long>(cq) * nb, 0);
+      LAUNCH_TRY("k_fill");
+      t7.stop();
+    }
     {
       dim3 g(ix->ntiles, cq);
-      k_count<<<g, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
-                                                   ix->ntiles, ix->tile, 0, p->tau, flag, taueff, segids, segscore,
-                                                   tilecnt, hist, lv);
+      StageTimer t3(ix, 3, st);
+      k_count<0><<<g, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
+                                                      ix->ntiles, ix->tile, p->tau, flag, taueff, segids, segscore,
+                                                      tilecnt, hist, lv);
       LAUNCH_TRY("k_count pass 0");
+      t3.stop();
+      StageTimer t7(ix, 7, st);
       k_flag<<<grid1(cq, 4), 256, 0, st>>>(tilecnt, nseg, cq, k, p->tau, flag, taueff, hist, nb, lv);
       LAUNCH_TRY("k_flag");
-      k_count<<<g, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
-                                                   ix->ntiles, ix->tile, 1, p->tau, flag, taueff, segids, segscore,
-                                                   tilecnt, hist, lv);
+      k_count<1><<<g, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
+                                                      ix->ntiles, ix->tile, p->tau, flag, taueff, segids, segscore,
+                                                      tilecnt, hist, lv);
       LAUNCH_TRY("k_count pass 1");
       k_tau_eff<<<grid1(cq, 256), 256, 0, st>>>(flag, cq, k, p->tau, nb, hist, taueff, tilecnt, nseg, lv);
       LAUNCH_TRY("k_tau_eff");
-      k_count<<<g, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
-                                                   ix->ntiles, ix->tile, 2, p->tau, flag, taueff, segids, segscore,
-                                                   tilecnt, hist, lv);
+      k_count<2><<<g, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
+                                                      ix->ntiles, ix->tile, p->tau, flag, taueff, segids, segscore,
+                                                      tilecnt, hist, lv);
       LAUNCH_TRY("k_count pass 2");
       k_compact<<<cq, kCompactThreads, 0, st>>>(segids, segscore, tilecnt, nseg, ix->tile / kCountWaves, n, cand,
                                                  score, ncand, lv);
@@ -465,8 +476,8 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       } else {
         qord = nullptr;
       }
+      t7.stop();
     }
-    t3.stop();
     const int32_t *lim = p->limits ? p->limits + q0 : nullptr;
     if (p->mode == 1) {
       // A5

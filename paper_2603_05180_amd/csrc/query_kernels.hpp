@@ -494,13 +494,15 @@ struct CountShared {
   int tmp[kCountWaves + 1];
 };
 
+template <int kPass>
 __global__ void __launch_bounds__(kCountThreads) k_count(
     const int32_t *__restrict__ ncell, const int32_t *__restrict__ cells, int m, int ncells,
     const int32_t *__restrict__ offsets, const int32_t *__restrict__ ids, long long n,
-    const int32_t *__restrict__ tile_off, int ntiles, int tile_ids, int pass, int tau,
+    const int32_t *__restrict__ tile_off, int ntiles, int tile_ids, int tau,
     const int32_t *__restrict__ flag, const int32_t *__restrict__ tau_eff,
     int32_t *__restrict__ seg_ids, uint8_t *__restrict__ seg_score, int32_t *__restrict__ seg_cnt,
     int32_t *__restrict__ hist, const int32_t *__restrict__ live) {
+  constexpr int pass = kPass;
   extern __shared__ __align__(16) uint32_t cnt[];
   __shared__ CountShared S;
   const int tile = blockIdx.x, q = blockIdx.y, tid = threadIdx.x;

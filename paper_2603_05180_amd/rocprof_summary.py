@@ -2,6 +2,9 @@
 
   python -m paper_2603_05180_amd.rocprof_summary stats <kernel_stats.csv> <title> <command>
       per-kernel dispatch durations from `rocprofv3 --kernel-trace --stats`
+  python -m paper_2603_05180_amd.rocprof_summary dispatches <kernel_trace.csv> <kernel> [last]
+      one kernel's dispatch durations grouped by grid size (from --kernel-trace),
+      and the average of its last `last` dispatches
   python -m paper_2603_05180_amd.rocprof_summary traffic <fetch.csv> <write.csv> <kernel> <workload> <out.json>
       HBM bytes per launch of <kernel> from two `--pmc FETCH_SIZE` / `--pmc
       WRITE_SIZE` runs, each scaled by what the same counter reads for the
@@ -35,6 +38,33 @@ def stats(path: str, title: str, command: str) -> str:
     return "\n".join(out) + "\n"
 
 
+def _matches(name: str, kernel: str) -> bool:
+    """kernel 'k_count<0>' names one instantiation; 'k_rerank' every one."""
+    short = _short(name)
+    return short.endswith(kernel) if "<" in kernel else short.split("<")[0].endswith(kernel)
+
+
+def dispatches(path: str, kernel: str, last: int = 0) -> str:
+    groups = collections.defaultdict(list)
+    seq = []
+    for r in sorted(csv.DictReader(open(path)), key=lambda r: int(r["Start_Timestamp"])):
+        if _matches(r["Kernel_Name"], kernel):
+            grid = tuple(int(r[f"Grid_Size_{a}"]) // int(r[f"Workgroup_Size_{a}"]) for a in "XYZ")
+            us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            groups[grid].append(us)
+            seq.append(us)
+    out = [f"Dispatches of `{kernel}` by grid (workgroups x, y, z), from the kernel trace:", "",
+           "| grid | dispatches | avg us | min us | max us |", "|---|---:|---:|---:|---:|"]
+    for grid, v in sorted(groups.items(), key=lambda kv: -len(kv[1])):
+        out.append(f"| {grid[0]} x {grid[1]} x {grid[2]} | {len(v)} | {sum(v) / len(v):.1f} | {min(v):.1f} | "
+                   f"{max(v):.1f} |")
+    if last and len(seq) >= last:
+        v = seq[-last:]
+        out += ["", f"The last {last} dispatches (in time order): avg {sum(v) / len(v):.1f} us, "
+                    f"min {min(v):.1f} us, max {max(v):.1f} us."]
+    return "\n".join(out) + "\n"
+
+
 def _per_dispatch(path: str, counter: str):
     acc = collections.defaultdict(float)
     names = {}
@@ -56,7 +86,7 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, workload: str, out_json
             raise SystemExit(f"expected one k_copy_probe dispatch in {path}, found {len(copies)}")
         ref_kib = copies[0]
         factor = copy_bytes / (ref_kib * 1024.0)
-        ks = [v for d, v in acc.items() if _short(names[d]).split("<")[0].endswith(kernel)]
+        ks = [v for d, v in acc.items() if _matches(names[d], kernel)]
         if not ks:
             raise SystemExit(f"no {kernel} dispatch in {path}")
         res[counter] = {"kib_per_launch": sum(ks) / len(ks), "launches": len(ks), "copy_kib": ref_kib,
@@ -74,6 +104,8 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, workload: str, out_json
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         sys.stdout.write(stats(sys.argv[2], sys.argv[3], sys.argv[4]))
+    elif sys.argv[1] == "dispatches":
+        sys.stdout.write(dispatches(sys.argv[2], sys.argv[3], int(sys.argv[4]) if len(sys.argv) > 4 else 0))
     elif sys.argv[1] == "traffic":
         print(json.dumps(traffic(*sys.argv[2:7]), indent=1))
     else:

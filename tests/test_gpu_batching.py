@@ -159,3 +159,18 @@ def test_query_run_order_does_not_change_results(d128, mode):
     _same(g.search(qq, 10, max_chunk=1000, overlap=1, **kw), ref)
     ids = ref[0].cpu().numpy()
     assert np.array_equal(ids[:300], ids[4200:])          # repeated queries, repeated answers
+
+
+def test_stage_profile_intervals(d128):
+    """The per-stage timers: one counting interval (the first pass alone) per
+    chunk, two candidate-list intervals per chunk, positive times."""
+    w, x, q, idx, g = d128
+    g.profile_begin(1024)
+    g.search(q, 10, mode=1, alpha=0.05, tau=4, max_chunk=100)    # 300 queries: three chunks
+    torch.cuda.synchronize()
+    st = g.profile_end()
+    assert st["dropped"] == 0
+    for name in ("rotate", "select", "count", "hamming_dist", "hamming_place", "rerank"):
+        assert st[name]["intervals"] == 3 and st[name]["ms"] > 0, (name, st[name])
+    assert st["candidates"]["intervals"] == 6 and st["candidates"]["ms"] > 0
+    assert st["budget"]["intervals"] == 0
