@@ -5,10 +5,11 @@
   python -m paper_2603_05180_amd.rocprof_summary dispatches <kernel_trace.csv> <kernel> [last]
       one kernel's dispatch durations grouped by grid size (from --kernel-trace),
       and the average of its last `last` dispatches
-  python -m paper_2603_05180_amd.rocprof_summary traffic <fetch.csv> <write.csv> <kernel> <workload> <out.json>
+  python -m paper_2603_05180_amd.rocprof_summary traffic <fetch.csv> <write.csv> <kernel> <workload> <out.json> [last]
       HBM bytes per launch of <kernel> from two `--pmc FETCH_SIZE` / `--pmc
       WRITE_SIZE` runs, each scaled by what the same counter reads for the
-      run's k_copy_probe dispatch (a plain copy: 1 GiB read, 1 GiB written)
+      run's k_copy_probe dispatch (a plain copy: 1 GiB read, 1 GiB written);
+      with `last`, over the kernel's last `last` dispatches only
 """
 from __future__ import annotations
 
@@ -76,7 +77,10 @@ def _per_dispatch(path: str, counter: str):
     return acc, names
 
 
-def traffic(fetch_csv: str, write_csv: str, kernel: str, workload: str, out_json: str, copy_bytes=1 << 30):
+def traffic(fetch_csv: str, write_csv: str, kernel: str, workload: str, out_json: str, last: int = 0,
+            copy_bytes=1 << 30):
+    """HBM bytes per launch of `kernel`: over its last `last` dispatches (in
+    dispatch order; 0 = all of them)."""
     from .provenance import source_hash
     res = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
@@ -86,7 +90,9 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, workload: str, out_json
             raise SystemExit(f"expected one k_copy_probe dispatch in {path}, found {len(copies)}")
         ref_kib = copies[0]
         factor = copy_bytes / (ref_kib * 1024.0)
-        ks = [v for d, v in acc.items() if _matches(names[d], kernel)]
+        ks = [acc[d] for d in sorted(acc, key=int) if _matches(names[d], kernel)]
+        if last:
+            ks = ks[-last:]
         if not ks:
             raise SystemExit(f"no {kernel} dispatch in {path}")
         res[counter] = {"kib_per_launch": sum(ks) / len(ks), "launches": len(ks), "copy_kib": ref_kib,
@@ -107,6 +113,6 @@ if __name__ == "__main__":
     elif sys.argv[1] == "dispatches":
         sys.stdout.write(dispatches(sys.argv[2], sys.argv[3], int(sys.argv[4]) if len(sys.argv) > 4 else 0))
     elif sys.argv[1] == "traffic":
-        print(json.dumps(traffic(*sys.argv[2:7]), indent=1))
+        print(json.dumps(traffic(*sys.argv[2:7], last=int(sys.argv[7]) if len(sys.argv) > 7 else 0), indent=1))
     else:
         raise SystemExit(__doc__)
