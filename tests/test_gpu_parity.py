@@ -107,3 +107,20 @@ def test_code_widths_not_a_power_of_two(d, m):
     print(f"D={d} M={m}", flush=True)
     for mode in (0, 1):
         compare(idx, q, 10, mode=mode, alpha=0.05, tau=3)
+
+
+def test_hamming_order_wide_ranges():
+    """Every point a candidate (alpha = 1, tau = 1) at D = 1024: each query's
+    Hamming distances span several hundred values, so both digits of the
+    two-pass placement vary, and the (h, id) order must still equal the
+    oracle's."""
+    from oracle import query as oquery
+    w, x, q = make_workload("d4096", n=3000, d=1024, m=8, k_half=6, rank=16, n_query=6)
+    idx = oracle_index(w, x)
+    spans = []
+    for qi in range(q.shape[0]):
+        _, _, tr = oquery.search_one(idx, q[qi], 10, mode=1, alpha=1.0, tau=1, trace=True)
+        spans.append(int(tr["hamming"].max() - tr["hamming"].min()))
+    print("D=1024 alpha=1 spans", spans, flush=True)
+    assert min(spans) >= 256, spans
+    compare(idx, q, 10, mode=1, alpha=1.0, tau=1)
