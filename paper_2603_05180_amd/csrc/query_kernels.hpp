@@ -1150,30 +1150,6 @@ __device__ __forceinline__ void bf16_bounds(float t32, float ex, double g, doubl
   ub = shi * shi * (1.0 + kBoundRel) + kBoundAbs;
 }
 
-// Max-heap of doubles (the k smallest values seen; top = the k-th smallest).
-__device__ inline void heap_push(double *h, int &n, double v) {
-  int i = n++;
-  while (i > 0) {
-    const int p = (i - 1) >> 1;
-    if (h[p] >= v) break;
-    h[i] = h[p];
-    i = p;
-  }
-  h[i] = v;
-}
-__device__ inline void heap_replace_top(double *h, int n, double v) {
-  int i = 0;
-  for (;;) {
-    int c = 2 * i + 1;
-    if (c >= n) break;
-    if (c + 1 < n && h[c + 1] > h[c]) ++c;
-    if (h[c] <= v) break;
-    h[i] = h[c];
-    i = c;
-  }
-  h[i] = v;
-}
-
 __device__ __forceinline__ void base_bf16_row(const float *__restrict__ base, long long row, int d,
                                               uint16_t *__restrict__ b16, float *__restrict__ err) {
   const int lane = lane_id();
@@ -1208,10 +1184,10 @@ __global__ void __launch_bounds__(256) k_base_bf16(const float *__restrict__ bas
 }
 
 // Dynamic LDS of k_rerank: q' (D floats) | top-k keys (k doubles) | top-k ids
-// (k ints) | [bfloat16 pass] heap (k doubles), lower / upper bounds and
-// certification flags of a chunk.
+// (k ints) | [bfloat16 pass] lower / upper bounds and certification flags
+// of a chunk.
 struct RerankLds {
-  size_t top_d, top_i, heap, lb, ub, pc, total;
+  size_t top_d, top_i, lb, ub, pc, total;
 };
 __host__ __device__ inline RerankLds rerank_lds(int d, int k, bool bf16) {
   RerankLds L{};
@@ -1220,7 +1196,6 @@ __host__ __device__ inline RerankLds rerank_lds(int d, int k, bool bf16) {
   L.top_i = o; o += static_cast<size_t>(k) * 4;
   o = (o + 15) & ~static_cast<size_t>(15);
   if (bf16) {
-    L.heap = o; o += static_cast<size_t>(k) * 8;
     L.lb = o; o += kChunk * 8;
     L.ub = o; o += kChunk * 8;
     L.pc = o; o += kChunk * 4;
@@ -1335,7 +1310,6 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
   float *sq = reinterpret_cast<float *>(dyn);
   double *top_d = reinterpret_cast<double *>(dyn + LL.top_d);
   int *top_i = reinterpret_cast<int *>(dyn + LL.top_i);
-  double *heap = reinterpret_cast<double *>(dyn + LL.heap);
   double *xlb = reinterpret_cast<double *>(dyn + LL.lb);
   double *xub = reinterpret_cast<double *>(dyn + LL.ub);
   int *xpc = reinterpret_cast<int *>(dyn + LL.pc);
@@ -1461,21 +1435,33 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
         __syncthreads();
         // When candidate t is walked, the k-th key is at most the k-th smallest
         // of (the top-k keys at the chunk start, upper bounds of the chunk
-        // before t); a row whose lower bound exceeds that cannot update.
-        if (tid == 0) {
-          int hs = 0;
-          for (int e = tn0 - 1; e >= 0; --e) heap[hs++] = top_d[e];  // descending order is a max-heap
-          int np = 0;
-          for (int t = 0; t < cnt; ++t) {
-            const bool full = hs >= k;
-            const bool cert = !full || xlb[t] <= heap[0];
+        // before t); a row whose lower bound exceeds that cannot update.  The
+        // lower bound is at most that k-th smallest exactly when fewer than k
+        // of those values lie below it: each thread counts them for its own
+        // row, and the certified rows are then listed in order.
+        {
+          static_assert(kChunk <= kRerankThreads, "one row per thread");
+          const int t = tid;
+          bool cert = false;
+          if (t < cnt) {
+            const double lb = xlb[t];
+            int c = 0;
+            for (int e = 0; e < tn0 && c < k; ++e) c += top_d[e] < lb ? 1 : 0;
+            for (int j = 0; j < t && c < k; ++j) c += xub[j] < lb ? 1 : 0;
+            cert = c < k;
             xpc[t] = cert ? 1 : 0;
-            if (cert) S.plist[np++] = t;
-            const double u = xub[t];
-            if (!full) heap_push(heap, hs, u);
-            else if (u < heap[0]) heap_replace_top(heap, hs, u);
           }
-          S.misc[7] = np;
+          const unsigned long long bm = __ballot(cert);
+          if (lane == 0) S.hist[wv] = __popcll(bm);
+          __syncthreads();
+          int before = 0;
+          for (int w = 0; w < wv; ++w) before += S.hist[w];
+          if (cert) S.plist[before + __popcll(bm & lanes_below_mask())] = t;
+          if (tid == 0) {
+            int tot = 0;
+            for (int w = 0; w < kRerankWaves; ++w) tot += S.hist[w];
+            S.misc[7] = tot;
+          }
         }
         __syncthreads();
         const int np = S.misc[7];
