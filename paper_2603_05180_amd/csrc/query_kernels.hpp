@@ -158,7 +158,7 @@ constexpr int kPopCap = 256;  // cells the direct enumeration may pop before bis
 
 struct SelectLds {
   double *d1s, *d2s, *hd;
-  int *o1, *o2, *rowcnt, *roww, *ptab, *pops;
+  int *o1, *o2, *rowcnt, *roww, *pops;
   float *qs;
 };
 
@@ -166,7 +166,6 @@ __host__ __device__ inline size_t select_lds_bytes(int k, int h) {
   size_t b = 0;
   b += 8 * static_cast<size_t>(k) * 4;                      // d1s, d2s, hd (2k)
   b += 4 * static_cast<size_t>(k) * 4;                      // o1, o2, rowcnt, roww
-  b += (k <= 64) ? 4 * static_cast<size_t>(k) * (k + 1) : 0;  // ptab
   b += (k <= 64) ? 4 * static_cast<size_t>(kPopCap) : 0;      // pops
   b += 4 * 2 * static_cast<size_t>(h);                      // qs
   return (b + 15) / 16 * 16;
@@ -201,7 +200,6 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
     S.o2 = reinterpret_cast<int *>(p); p += 4 * k;
     S.rowcnt = reinterpret_cast<int *>(p); p += 4 * k;
     S.roww = reinterpret_cast<int *>(p); p += 4 * k;
-    S.ptab = reinterpret_cast<int *>(p); p += (k <= 64) ? 4 * k * (k + 1) : 0;
     S.pops = reinterpret_cast<int *>(p); p += (k <= 64) ? 4 * kPopCap : 0;
     S.qs = reinterpret_cast<float *>(p);
   }
@@ -310,22 +308,38 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
     }
   }
 
-  int *P = (k <= 64) ? S.ptab : (ptab_g + (static_cast<long long>(q) * m + sub) * k * (k + 1));
-  for (int i = lane; i < k; i += kWave) {
-    int base = S.o1[i] * k, acc = 0;
-    P[i * (k + 1)] = 0;
-    for (int j = 0; j < k; ++j) {
-      int c = base + S.o2[j];
-      acc += off[c + 1] - off[c];
-      P[i * (k + 1) + j + 1] = acc;
+  // Prefix sums of the cell sizes along each sorted row: a table in global
+  // memory for K > 64; for K <= 64 (where this bisection runs only when the
+  // direct enumeration ran out of pops) summed from the offsets on demand,
+  // which keeps the kernel's LDS small for the common path.
+  int *P = (k <= 64) ? nullptr : (ptab_g + (static_cast<long long>(q) * m + sub) * k * (k + 1));
+  if (P) {
+    for (int i = lane; i < k; i += kWave) {
+      int base = S.o1[i] * k, acc = 0;
+      P[i * (k + 1)] = 0;
+      for (int j = 0; j < k; ++j) {
+        int c = base + S.o2[j];
+        acc += off[c + 1] - off[c];
+        P[i * (k + 1) + j + 1] = acc;
+      }
     }
   }
   __syncthreads();
+  auto psum = [&](int i, int j) -> int {   // sizes of the first j cells of sorted row i
+    if (P) return P[i * (k + 1) + j];
+    const int base = S.o1[i] * k;
+    int acc = 0;
+    for (int jj = 0; jj < j; ++jj) {
+      const int c = base + S.o2[jj];
+      acc += off[c + 1] - off[c];
+    }
+    return acc;
+  };
 
   auto size_le = [&](unsigned long long bits) -> int {
     double th = from_dbits(bits);
     int tot = 0;
-    for (int i = lane; i < k; i += kWave) tot += P[i * (k + 1) + row_count_le(S.d1s, S.d2s, k, i, th)];
+    for (int i = lane; i < k; i += kWave) tot += psum(i, row_count_le(S.d1s, S.d2s, k, i, th));
     return wave_sum_i32(tot);
   };
   auto count_le = [&](unsigned long long bits) -> int {
@@ -354,7 +368,7 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
       if (i < k) {
         thi = row_count_le(S.d1s, S.d2s, k, i, from_dbits(cstar));
         tlo = (cstar > 0) ? row_count_le(S.d1s, S.d2s, k, i, from_dbits(cstar - 1)) : 0;
-        tsz = P[i * (k + 1) + thi] - P[i * (k + 1) + tlo];
+        tsz = psum(i, thi) - psum(i, tlo);
       }
       int incl = wave_incl_scan_i32(tsz) + carry;
       unsigned long long hit = __ballot(i < k && s_lt + incl >= budget);
@@ -365,7 +379,7 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
         int row = r0 + L;
         int acc = s_lt + excl_L, j = tlo_L;
         for (;; ++j) {
-          acc += P[row * (k + 1) + j + 1] - P[row * (k + 1) + j];
+          acc += psum(row, j + 1) - psum(row, j);
           if (acc >= budget) break;
         }
         istar = row;
@@ -385,7 +399,7 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
   int total = 0, retr = 0;
   for (int i = lane; i < k; i += kWave) {
     total += S.rowcnt[i];
-    retr += P[i * (k + 1) + S.rowcnt[i]];
+    retr += psum(i, S.rowcnt[i]);
   }
   total = wave_sum_i32(total);
   retr = wave_sum_i32(retr);
@@ -457,7 +471,7 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
     st[0] = c1;
     st[1] = c2;
     st[2] = from_dbits(cstar);
-    st[3] = static_cast<double>(P[1]);
+    st[3] = static_cast<double>(psum(0, 1));
   }
 }
 

@@ -79,6 +79,19 @@ def test_codebook_sizes(k_half):
         compare(idx, q, 10, mode=mode, alpha=0.03, tau=2)
 
 
+def test_cell_selection_beyond_direct_pops():
+    """K = 32 (1,024 cells of about three ids) with half the points as the
+    budget: several hundred cells per subspace, more than the direct
+    enumeration pops, so the selection takes its bisection path (prefix
+    sums of cell sizes summed from the offsets)."""
+    w, x, q = make_workload("d128", n=3000, d=128, m=4, k_half=32, n_query=8)
+    idx = oracle_index(w, x)
+    print("K=32 alpha=0.5", flush=True)
+    for mode in (0, 1):
+        s = compare(idx, q, 10, mode=mode, alpha=0.5, tau=3)
+        assert int(s["taps"]["n_cells"].min()) > 256
+
+
 def test_rotated_index():
     """Correlated data: the rotation fires, queries are rotated on the GPU."""
     w, x, q = make_workload("d4096", n=3000, d=256, m=8, k_half=6, rank=16, n_query=16)
