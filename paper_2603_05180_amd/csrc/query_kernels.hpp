@@ -839,6 +839,8 @@ struct CodeVec<2> {
 
 __host__ __device__ inline int hamming_vec(int words) { return (words % 2 == 0) ? 2 : 1; }
 
+constexpr int kHamRows = 4, kHamLoads = 4;  // code rows per lane step, loads per row in flight
+
 template <int kVec>
 __global__ void __launch_bounds__(kOrderThreads) k_hamming_dist(
     const float *__restrict__ qrot, int d, const uint64_t *__restrict__ codes, const int32_t *__restrict__ ncand,
@@ -867,38 +869,38 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_dist(
   const int stride = gx * kOrderWaves * kWave;
   for (int base = (bx * kOrderWaves + wv) * kWave; base < nc; base += stride) {
     const int my_id = cand[qo + min(base + lane, nc - 1)];
-    for (int s0 = 0; s0 < L; s0 += 4) {
-      int hs[4], idr[4];
-      bool rok[4];
+    for (int s0 = 0; s0 < L; s0 += kHamRows) {
+      int hs[kHamRows], idr[kHamRows];
+      bool rok[kHamRows];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kHamRows; ++u) {
         const int st = s0 + u;
         const int r = st * rows_per + rsel;
         rok[u] = st < L && base + r < nc;
         idr[u] = __shfl(my_id, rok[u] ? r : 0, kWave);
         hs[u] = 0;
       }
-      for (int j0 = 0; j0 < J; j0 += 4) {
-        V cw[4][4];
+      for (int j0 = 0; j0 < J; j0 += kHamLoads) {
+        V cw[kHamRows][kHamLoads];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kHamRows; ++u) {
           const V *row = reinterpret_cast<const V *>(codes + static_cast<long long>(idr[u]) * words);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
+          for (int e = 0; e < kHamLoads; ++e) {
             const int v = sub + (j0 + e) * L;
             cw[u][e] = row[(rok[u] && v < span) ? v : 0];   // clamped: every load is issued
           }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < kHamRows; ++u)
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
+          for (int e = 0; e < kHamLoads; ++e) {
             const int v = sub + (j0 + e) * L;
             if (rok[u] && v < span) hs[u] += CodeVec<kVec>::pop(qc, v * kVec, cw[u][e]);
           }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kHamRows; ++u) {
         int h = hs[u];
         for (int s2 = L >> 1; s2 >= 1; s2 >>= 1) h += __shfl_xor(h, s2, kWave);
         if (sub == 0 && rok[u]) hm_tmp[qo + base + (s0 + u) * rows_per + rsel] = h;
