@@ -159,7 +159,7 @@ constexpr int kPopCap = 256;  // cells the direct enumeration may pop before bis
 struct SelectLds {
   double *d1s, *d2s, *hd;
   int *o1, *o2, *rowcnt, *roww, *pops;
-  float *qs;
+  double *qs;  // the subspace's 2h coordinates of q', widened once
 };
 
 __host__ __device__ inline size_t select_lds_bytes(int k, int h) {
@@ -167,7 +167,7 @@ __host__ __device__ inline size_t select_lds_bytes(int k, int h) {
   b += 8 * static_cast<size_t>(k) * 4;                      // d1s, d2s, hd (2k)
   b += 4 * static_cast<size_t>(k) * 4;                      // o1, o2, rowcnt, roww
   b += (k <= 64) ? 4 * static_cast<size_t>(kPopCap) : 0;      // pops
-  b += 4 * 2 * static_cast<size_t>(h);                      // qs
+  b += 8 * 2 * static_cast<size_t>(h);                      // qs
   return (b + 15) / 16 * 16;
 }
 
@@ -201,13 +201,13 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
     S.rowcnt = reinterpret_cast<int *>(p); p += 4 * k;
     S.roww = reinterpret_cast<int *>(p); p += 4 * k;
     S.pops = reinterpret_cast<int *>(p); p += (k <= 64) ? 4 * kPopCap : 0;
-    S.qs = reinterpret_cast<float *>(p);
+    S.qs = reinterpret_cast<double *>(p);
   }
   const int sub = blockIdx.x, q = blockIdx.y, lane = threadIdx.x;
   if (live && q >= *live) return;
   const int ncells = k * k;
   const float *qa = qrot + static_cast<long long>(q) * d + sub * 2 * h;
-  for (int t = lane; t < 2 * h; t += kWave) S.qs[t] = qa[t];
+  for (int t = lane; t < 2 * h; t += kWave) S.qs[t] = static_cast<double>(qa[t]);
   __syncthreads();
   // ---- Dist_1 / Dist_2 -----------------------------------------------------
   double *hout = hdist_out + (static_cast<long long>(q) * m + sub) * 2 * k;
@@ -216,7 +216,7 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
     for (int c = lane; c < k; c += kWave) {
       double acc = 0.0;
       for (int t = 0; t < h; ++t) {
-        double delta = static_cast<double>(S.qs[s * h + t]) - static_cast<double>(ct[t * k + c]);
+        double delta = S.qs[s * h + t] - static_cast<double>(ct[t * k + c]);
         double sq = delta * delta;
         acc = acc + sq;
       }
