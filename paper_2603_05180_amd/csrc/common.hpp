@@ -62,6 +62,14 @@ __device__ __forceinline__ uint16_t bf16_bits(float x) {
   return static_cast<uint16_t>(u >> 16);
 }
 
+// Lane l's value of a double (l wave-uniform).
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffffll), l));
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | lo);
+}
+
 // Bits of a non-negative double: monotone as an unsigned integer.
 __device__ __forceinline__ unsigned long long dbits(double x) {
   return static_cast<unsigned long long>(__double_as_longlong(x));

@@ -261,21 +261,28 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
     int cell = row ? cbase + S.o2[0] : 0;
     int size = row ? off[cell + 1] - off[cell] : 0;
     double cost = row ? a + S.d2s[0] : __longlong_as_double(0x7ff0000000000000ll);
-    const int big = 1 << 30;
     int npop = 0, retr = 0;
     double ccut = 0.0;
     bool met = false;
+    // Rows start in order (an unstarted row's cost d1s[i] + d2s[0] is
+    // nondecreasing in i, so of the unstarted rows only the first can hold
+    // the smallest (cost, row)); each pop therefore takes the smallest
+    // (cost, row) over the started rows and the first unstarted one, read
+    // from their lanes in ascending row order (strict < keeps the lower row
+    // on equal costs).
+    int started = 0;
     while (npop < kPopCap) {
-      double bc = cost;
-      int bi = (row && j < k) ? lane : big;
-#pragma unroll
-      for (int sh = 32; sh >= 1; sh >>= 1) {
-        const double oc = __shfl_xor(bc, sh, kWave);
-        const int oi = __shfl_xor(bi, sh, kWave);
-        if (oc < bc || (oc == bc && oi < bi)) { bc = oc; bi = oi; }
+      double bc = __longlong_as_double(0x7ff0000000000000ll);
+      int bi = -1;
+      const int last = min(started, k - 1);
+      for (int i = 0; i <= last; ++i) {
+        const double ci = readlane_f64(cost, i);
+        if (ci < bc) { bc = ci; bi = i; }
       }
-      const int psz = __shfl(size, bi, kWave);
-      const int pcell = __shfl(cell, bi, kWave);
+      if (bi < 0) break;                    // every cell popped: cannot happen before the budget is met
+      if (bi == started) ++started;
+      const int psz = __builtin_amdgcn_readlane(size, bi);
+      const int pcell = __builtin_amdgcn_readlane(cell, bi);
       if (lane == 0) S.pops[npop] = pcell | ((phi == 1 && npop < ksize ? 2 : 1) << 24);
       ++npop;
       retr += psz;
