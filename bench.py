@@ -53,6 +53,8 @@ def parse():
                     help="queries per chunk (4096: two pipelines of N-sized per-query buffers fill most of HBM)")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--guaranteed", type=int, default=1, help="also time Guaranteed Mode (plain and bf16)")
+    ap.add_argument("--scoring", type=int, default=1,
+                    help="also time the tuned form with certified bfloat16 matrix-core pre-scoring (precision 2)")
     ap.add_argument("--tuned-patience", type=int, default=10,
                     help="also time the bf16 form at this patience factor (0 = skip)")
     ap.add_argument("--overlap", type=int, default=1,
@@ -232,6 +234,9 @@ def main():
     if args.mode == 1 and args.tuned_patience > 0:
         # a tuned operating point: the same engine with a shorter patience
         forms[f"bf16_pf{args.tuned_patience}"] = dict(precision=1, patience_factor=args.tuned_patience)
+        if args.scoring:
+            # and with the half distances pre-scored on bfloat16 matrix cores (same results)
+            forms[f"bf16_scored_pf{args.tuned_patience}"] = dict(precision=2, patience_factor=args.tuned_patience)
     if args.mode == 1 and args.guaranteed:
         # Guaranteed Mode (every candidate verified) at the same alpha and tau
         forms["guaranteed"] = dict(mode=0, precision=0)
@@ -253,7 +258,7 @@ def main():
         c = counts(index, queries, k, dict(kw, overlap=0))
         # re-rank gather rate of this form: one single-pipeline step, stage-timed
         _, st1 = timed(index, queries, k, dict(kw, overlap=0), 1, ids, dists, profile=True)
-        rr_bytes = (((2.0 * w.d + 4.0) * c["examined"] + 4.0 * w.d * c["refined"]) if kw.get("precision") == 1
+        rr_bytes = (((2.0 * w.d + 4.0) * c["examined"] + 4.0 * w.d * c["refined"]) if kw.get("precision", 0) >= 1
                     else 4.0 * w.d * c["examined"])
         results[name] = {"queries_per_s": round(w.n_query / (ms / 1e3), 1), "ms_per_step": round(ms, 3),
                          "recall_at_10": round(rec, 4), "plain_ids_kept": round(same, 5),
@@ -279,7 +284,7 @@ def main():
 
     # ---- roofline of each stage (algorithmic bytes / flops per step) --------
     d = w.d
-    bf16 = kw.get("precision", 0) == 1
+    bf16 = kw.get("precision", 0) >= 1
     rerank_bytes = ((2.0 * d + 4.0) * c["examined"] + 4.0 * d * c["refined"]) if bf16 else 4.0 * d * c["examined"]
     per_step = {
         "rotate": ("mfma", 2.0 * d * d * w.n_query / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"),

@@ -155,7 +155,18 @@ crisp_status crisp_index_enable_bf16(crisp_index *index, void *buffer, size_t by
  *                      in float32 only where the bound cannot exclude it
  *                      from the result.  Both give identical ids and
  *                      distances (every deciding comparison uses the exact
- *                      float64 key); 1 reads fewer bytes.
+ *                      float64 key); 1 reads fewer bytes.  2: as 1, and
+ *                      for K <= 64 the half-codebook distances (Algorithm 1,
+ *                      Dist_1 / Dist_2) are first scored on bfloat16 matrix
+ *                      cores (three-term split, float32 accumulation) with a
+ *                      certified error bound; the exact float64 distance is
+ *                      then computed only for centroids whose bound lets
+ *                      them be among the 4 nearest of their half, and the
+ *                      cell walk falls back to all exact distances whenever
+ *                      it needs a rank the bounds leave open.  Same ids,
+ *                      distances and stage outputs; half_dist is only filled
+ *                      for every centroid when that tap is requested (which
+ *                      then takes the exact path).
  *   persistent      -- 0: the re-rank launches one block per query.  1: it
  *                      launches about as many blocks as fit on the chip,
  *                      each pulling queries from a device-side counter (same
@@ -203,6 +214,9 @@ typedef struct {
  *   limits      int32  [nq]            predicted verification limits (budget_source 1)
  *   refined     int32  [nq]            verified rows read in float32 (precision 0:
  *                                      every one; 1: those the bfloat16 bound kept)
+ *   score_lb    float32 [nq][M][2][K]  precision 2, K <= 64: certified lower and
+ *   score_ub    float32 [nq][M][2][K]  upper bounds of Dist_1 / Dist_2 from the
+ *                                      bfloat16 matrix-core scoring
  */
 typedef struct {
   float *q_rot;
@@ -223,6 +237,8 @@ typedef struct {
   float *features;
   int32_t *limits;
   int32_t *refined;
+  float *score_lb;
+  float *score_ub;
 } crisp_taps;
 
 /* Bytes of workspace crisp_search needs for this index, batch and parameters. */

@@ -125,7 +125,8 @@ struct StageTimer {
 // Workspace layout for one chunk of qc queries.
 struct Layout {
   size_t qrot, hdist, ptab, ncell, cells, retr, tilecnt, hist, flag, taueff, ncand, segids, segscore, cand,
-      score, regA, regB, regC, examined, lastupd, stopped, refined, sstat, feat, lim, queue, order, total;
+      score, regA, regB, regC, examined, lastupd, stopped, refined, sstat, feat, lim, queue, order, sclb, scub,
+      total;
 };
 
 static Layout make_layout(const crisp_index *ix, long long qc) {
@@ -160,6 +161,8 @@ static Layout make_layout(const crisp_index *ix, long long qc) {
   L.lim = take(qc * 4);
   L.queue = take(4);
   L.order = take(qc * 4);
+  L.sclb = take(ix->k <= kWave ? qc * ix->m * 2 * ix->k * 4 : 0);
+  L.scub = take(ix->k <= kWave ? qc * ix->m * 2 * ix->k * 4 : 0);
   L.total = o;
   return L;
 }
@@ -315,8 +318,9 @@ static crisp_status check_params(const crisp_index *ix, int64_t nq, int32_t k, c
   if (p->budget_source != 0 && p->budget_source != 1) return fail(CRISP_E_INVALID, "budget_source must be 0 or 1");
   if (p->budget_source == 1 && p->mode != 1) return fail(CRISP_E_INVALID, "the learned budget applies to Optimized Mode");
   if (p->budget_source == 1 && !ix->mlp_params) return fail(CRISP_E_INVALID, "no budget model set");
-  if (p->precision != 0 && p->precision != 1) return fail(CRISP_E_INVALID, "precision must be 0 or 1");
-  if (p->precision == 1 && !ix->base16) return fail(CRISP_E_INVALID, "precision 1 needs crisp_index_enable_bf16");
+  if (p->precision < 0 || p->precision > 2) return fail(CRISP_E_INVALID, "precision must be 0, 1 or 2");
+  if (p->precision >= 1 && !ix->base16)
+    return fail(CRISP_E_INVALID, "precision 1 and 2 need crisp_index_enable_bf16");
   if (p->persistent != 0 && p->persistent != 1) return fail(CRISP_E_INVALID, "persistent must be 0 or 1");
   if (p->overlap != 0 && p->overlap != 1) return fail(CRISP_E_INVALID, "overlap must be 0 or 1");
   return CRISP_OK;
@@ -366,7 +370,12 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       p->mode == 1 ? static_cast<int>(std::min<long long>(static_cast<long long>(p->patience_factor) * k, INT32_MAX)) : 0;
   const size_t count_lds = static_cast<size_t>(ix->tile);
   const int nseg = ix->ntiles * kCountWaves;
-  const bool bf16 = p->precision == 1;
+  const bool bf16 = p->precision >= 1;
+  // precision 2: certified bfloat16 matrix-core pre-scoring of the half
+  // distances (K <= 64); the selection ignores it while the exact half
+  // distances are tapped
+  const bool score = p->precision == 2 && ix->k <= kWave;
+  const bool score_used = score && !(taps && taps->half_dist);
   const size_t rr_lds = rerank_lds(d, k, bf16).total;
   // float32 error factor of the bfloat16 row distance: gamma_{L+10}, L = terms per lane
   const double lterms = static_cast<double>((d / 8 + kWave - 1) / kWave * 8 + 10) * 5.9604644775390625e-08;
@@ -410,6 +419,8 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
     int32_t *refd = reinterpret_cast<int32_t *>(ws + L.refined);
     int32_t *queue = reinterpret_cast<int32_t *>(ws + L.queue);
     int32_t *qord = reinterpret_cast<int32_t *>(ws + L.order);
+    float *sclb = reinterpret_cast<float *>(ws + L.sclb);
+    float *scub = reinterpret_cast<float *>(ws + L.scub);
     double *sstat = reinterpret_cast<double *>(ws + L.sstat);
     float *feat = reinterpret_cast<float *>(ws + L.feat);
     int32_t *llim = reinterpret_cast<int32_t *>(ws + L.lim);
@@ -431,10 +442,15 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
     // A1 + A2
     {
       StageTimer t2(ix, 2, st);
+      if (score) {
+        k_score_bf16x3<<<dim3((cq + 15) / 16, m), 64, 0, st>>>(qrot, d, ix->cent_t, m, kh, ix->h, cq, sclb, scub, lv);
+        LAUNCH_TRY("k_score_bf16x3");
+      }
       dim3 g(m, cq);
       k_select_cells<<<g, 64, select_lds_bytes(kh, ix->h), st>>>(qrot, d, ix->cent_t, m, kh, ix->h, ix->off,
                                                                   budget, k, p->mode, hdist, ptab, ncell, cells,
-                                                                  retr, sstat, lv);
+                                                                  retr, sstat, lv, score_used ? sclb : nullptr,
+                                                                  score_used ? scub : nullptr);
       LAUNCH_TRY("k_select_cells");
       t2.stop();
     }
@@ -557,6 +573,11 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       if ((s = tap_copy(taps->last_update ? taps->last_update + q0 : nullptr, lastu, size_t(cq) * 4, st))) return s;
       if ((s = tap_copy(taps->stopped ? taps->stopped + q0 : nullptr, stopd, size_t(cq) * 4, st))) return s;
       if ((s = tap_copy(taps->refined ? taps->refined + q0 : nullptr, refd, size_t(cq) * 4, st))) return s;
+      if (score) {
+        const size_t sb = size_t(cq) * m * 2 * kh * 4;
+        if ((s = tap_copy(taps->score_lb ? taps->score_lb + q0 * m * 2 * kh : nullptr, sclb, sb, st))) return s;
+        if ((s = tap_copy(taps->score_ub ? taps->score_ub + q0 * m * 2 * kh : nullptr, scub, sb, st))) return s;
+      }
       if (p->mode == 1 && (s = tap_copy(taps->features ? taps->features + q0 * nf : nullptr, feat,
                                         size_t(cq) * nf * 4, st))) return s;
       if (p->budget_source == 1 && (s = tap_copy(taps->limits ? taps->limits + q0 : nullptr, llim,

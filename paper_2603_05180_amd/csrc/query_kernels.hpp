@@ -181,6 +181,130 @@ __device__ __forceinline__ int row_count_le(const double *d1s, const double *d2s
   return lo;
 }
 
+// ---------------------------------------------------------------------------
+// Certified pre-scoring of the half-codebook distances on bfloat16 matrix
+// cores (precision 2, K <= 64).  Each coordinate is split into two bfloat16
+// terms, x = x_hi + x_lo + r_x (x_hi = bf16(x), x_lo = bf16(x - x_hi)), and
+// q.c is approximated by q_hi.c_hi + q_lo.c_hi + q_hi.c_lo with three
+// v_mfma_f32_16x16x16_bf16 per 16-coordinate step (products of bfloat16 are
+// exact in float32).  With d~ = |q|^2 + |c|^2 - 2 q.c~ the distance
+// |q - c|^2 differs from d~ by at most
+//   2 (|q_lo||c_lo| + |q_hi + q_lo||r_c| + |r_q||c|)      omitted terms
+//   + 2 (3h + 16) 2^-22 |q~||c~|                             float32 sums
+//   + (4 nks + 4) 2^-23 (|q|^2 + |c|^2) + 2^-21 (|q|^2 + |c|^2 + 2|q.c~|)
+// (norms and the final expression in float32), and the canonical float64
+// half distance differs from |q - c|^2 by far less than 2^-40 of the same
+// scale.  The bound used is twice that sum plus that last term, and the
+// interval [d~ - E, d~ + E] is stored in float rounded outward.
+// One wavefront per (16 queries, subspace); lane l holds query row l & 15 of
+// the A operand and centroid column l & 15 of the B operand.
+// ---------------------------------------------------------------------------
+typedef short score_s4 __attribute__((ext_vector_type(4)));
+typedef float score_f4 __attribute__((ext_vector_type(4)));
+constexpr int kScoreRanks = 4;  // ranks per half certified before the exact pass
+
+__device__ __forceinline__ void split_bf16(float x, short &hi, short &lo, float &hf, float &lf) {
+  const uint16_t h = bf16_bits(x);
+  hf = __uint_as_float(static_cast<uint32_t>(h) << 16);
+  const uint16_t l = bf16_bits(x - hf);
+  lf = __uint_as_float(static_cast<uint32_t>(l) << 16);
+  hi = static_cast<short>(h);
+  lo = static_cast<short>(l);
+}
+
+__global__ void __launch_bounds__(64) k_score_bf16x3(const float *__restrict__ qrot, int d,
+                                                     const float *__restrict__ cent_t, int m, int k, int h, int cq,
+                                                     float *__restrict__ out_lb, float *__restrict__ out_ub,
+                                                     const int32_t *__restrict__ live) {
+  const int lane = threadIdx.x, r = lane & 15, kq = lane >> 4;
+  const int q0 = blockIdx.x * 16, sub = blockIdx.y;
+  const int nl = live ? min(cq, *live) : cq;
+  if (q0 >= nl) return;
+  const int nks = (h + 15) / 16;
+  const int qa = q0 + r;                        // this lane's query row of the A operand
+  const float *qrow = qrot + static_cast<long long>(min(qa, nl - 1)) * d + sub * 2 * h;
+  const float sacc = 3.f * static_cast<float>(3 * 16 * nks + 16) * 0x1p-22f;
+  const float snorm = static_cast<float>(4 * nks + 4) * 0x1p-23f;
+  for (int s = 0; s < 2; ++s) {
+    const float *ct = cent_t + static_cast<long long>(sub * 2 + s) * h * k;
+    for (int c0 = 0; c0 < k; c0 += 16) {
+      const int c = c0 + r;                     // this lane's centroid column of the B operand
+      score_f4 acc = score_f4{0.f, 0.f, 0.f, 0.f};
+      // partial norms over this lane's coordinates: |x|^2, |x_lo|^2, |r_x|^2, |x_hi + x_lo|^2
+      float nq = 0.f, nqlo = 0.f, nqr = 0.f, nqt = 0.f;
+      float nc = 0.f, nclo = 0.f, ncr = 0.f, nct = 0.f;
+      for (int ks = 0; ks < nks; ++ks) {
+        score_s4 qh, ql, ch, cl;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int dd = ks * 16 + 4 * kq + e;
+          const float xq = (dd < h && qa < nl) ? qrow[s * h + dd] : 0.f;
+          const float xc = (dd < h && c < k) ? ct[static_cast<long long>(dd) * k + c] : 0.f;
+          short hi, lo;
+          float hf, lf;
+          split_bf16(xq, hi, lo, hf, lf);
+          qh[e] = hi;
+          ql[e] = lo;
+          float rr = (xq - hf) - lf;
+          nq = fmaf(xq, xq, nq);
+          nqlo = fmaf(lf, lf, nqlo);
+          nqr = fmaf(rr, rr, nqr);
+          nqt = fmaf(hf + lf, hf + lf, nqt);
+          split_bf16(xc, hi, lo, hf, lf);
+          ch[e] = hi;
+          cl[e] = lo;
+          rr = (xc - hf) - lf;
+          nc = fmaf(xc, xc, nc);
+          nclo = fmaf(lf, lf, nclo);
+          ncr = fmaf(rr, rr, ncr);
+          nct = fmaf(hf + lf, hf + lf, nct);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qh, ch, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ql, ch, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(qh, cl, acc, 0, 0, 0);
+      }
+      // the four lanes of a row / column (kq = 0..3) hold its four partial sums
+#pragma unroll
+      for (int sh = 16; sh <= 32; sh <<= 1) {
+        nq += __shfl_xor(nq, sh, kWave);
+        nqlo += __shfl_xor(nqlo, sh, kWave);
+        nqr += __shfl_xor(nqr, sh, kWave);
+        nqt += __shfl_xor(nqt, sh, kWave);
+        nc += __shfl_xor(nc, sh, kWave);
+        nclo += __shfl_xor(nclo, sh, kWave);
+        ncr += __shfl_xor(ncr, sh, kWave);
+        nct += __shfl_xor(nct, sh, kWave);
+      }
+      // acc[i]: query q0 + 4 kq + i, centroid c
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 4 * kq + i;
+        const float vq = __shfl(nq, row, kWave), vqlo = __shfl(nqlo, row, kWave);
+        const float vqr = __shfl(nqr, row, kWave), vqt = __shfl(nqt, row, kWave);
+        const int qq = q0 + row;
+        if (qq < nl && c < k) {
+          const float dot = acc[i];
+          const float dt = vq + nc - 2.f * dot;
+          const float omit = sqrtf(vqlo * nclo) + sqrtf(vqt * ncr) + sqrtf(vqr * nc);
+          const float sums = sacc * (sqrtf(vqt) + sqrtf(vqlo)) * (sqrtf(nct) + sqrtf(nclo));
+          const float scale = vq + nc + 2.f * fabsf(dot);
+          const double e = 2.0 * (2.0 * (static_cast<double>(omit) + sums) + static_cast<double>(snorm) * (vq + nc) +
+                                  0x1p-21 * scale) +
+                           0x1p-40 * scale + 1e-300;
+          const double lo = fmax(0.0, static_cast<double>(dt) - e);
+          const double hi = static_cast<double>(dt) + e;
+          float lf = static_cast<float>(lo), hf = static_cast<float>(hi);
+          if (static_cast<double>(lf) > lo) lf = nextafterf(lf, 0.f);
+          if (static_cast<double>(hf) < hi) hf = nextafterf(hf, __int_as_float(0x7f800000));
+          const long long o = (static_cast<long long>(qq) * m + sub) * 2 * k + s * k + c;
+          out_lb[o] = lf;
+          out_ub[o] = hf;
+        }
+      }
+    }
+  }
+}
+
 __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ qrot, int d,
                                                      const float *__restrict__ cent_t, int m, int k, int h,
                                                      const int32_t *__restrict__ offsets, int budget, int ksize,
@@ -188,7 +312,9 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
                                                      int32_t *__restrict__ ptab_g, int32_t *__restrict__ ncell,
                                                      int32_t *__restrict__ cells_out,
                                                      int32_t *__restrict__ retrieved,
-                                                     double *__restrict__ sstat, const int32_t *__restrict__ live) {
+                                                     double *__restrict__ sstat, const int32_t *__restrict__ live,
+                                                     const float *__restrict__ sc_lb,
+                                                     const float *__restrict__ sc_ub) {
   extern __shared__ __align__(16) unsigned char dyn[];
   SelectLds S;
   {
@@ -209,6 +335,156 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
   const float *qa = qrot + static_cast<long long>(q) * d + sub * 2 * h;
   for (int t = lane; t < 2 * h; t += kWave) S.qs[t] = static_cast<double>(qa[t]);
   __syncthreads();
+  // ---- certified pre-scoring (precision 2, K <= 64) ------------------------
+  // From the bounds of k_score_bf16x3: T_s >= the R-th smallest upper bound of
+  // half s; every centroid whose lower bound is <= T_s gets its exact float64
+  // distance (X_s, all of X_0 and X_1 in one pass when they fit a wavefront).
+  // The R nearest of each half lie in X_s (the R smallest upper bounds
+  // belong to centroids whose distances are <= T_s, and every centroid
+  // outside X_s is farther), so ranks 0..R-1 are exact, and lb_s = min(exact
+  // values of X_s at ranks >= R, lower bounds outside X_s) bounds rank R from
+  // below.  The pops then run on the known ranks; whenever a cell with an
+  // unknown rank (row R, or column R of a started row) could come next, or
+  // the pops run out, the exact path below redoes the subspace.
+  if (sc_lb != nullptr && k <= kWave) {
+    const long long so = (static_cast<long long>(q) * m + sub) * 2 * k;
+    const bool inb = lane < k;
+    const float finf = __int_as_float(0x7f800000);
+    const double dinf = __longlong_as_double(0x7ff0000000000000ll);
+    const float lb0 = inb ? sc_lb[so + lane] : finf, ub0 = inb ? sc_ub[so + lane] : finf;
+    const float lb1 = inb ? sc_lb[so + k + lane] : finf, ub1 = inb ? sc_ub[so + k + lane] : finf;
+    const int R = min(k, kScoreRanks);
+    // T_s >= the R-th smallest upper bound: bisection over the top 12 bits
+    // of the (non-negative) float patterns, T_s = the top of the first
+    // bucket by which R upper bounds have appeared (at most 1/8 above it).
+    auto kth_ub = [&](float ub) -> float {
+      uint32_t lo = 0u, hi = 0x7f800000u >> 20;
+      const uint32_t bucket = __float_as_uint(ub) >> 20;
+      while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (__popcll(__ballot(inb && bucket <= mid)) >= R) hi = mid; else lo = mid + 1;
+      }
+      return lo >= (0x7f800000u >> 20) ? __int_as_float(0x7f800000) : __uint_as_float(((lo + 1u) << 20) - 1u);
+    };
+    const float t0 = kth_ub(ub0), t1 = kth_ub(ub1);
+    const unsigned long long x0 = __ballot(inb && lb0 <= t0), x1 = __ballot(inb && lb1 <= t1);
+    const int n0 = __popcll(x0), n1 = __popcll(x1), nx = n0 + n1;
+    if (nx <= kWave) {
+      int *xl = S.rowcnt;  // 2K ints: entry t = half << 6 | centroid, half 0 first
+      const unsigned long long below = lanes_below_mask();
+      if ((x0 >> lane) & 1ull) xl[__popcll(x0 & below)] = lane;
+      if ((x1 >> lane) & 1ull) xl[n0 + __popcll(x1 & below)] = 64 | lane;
+      __syncthreads();
+      int es = 0, ec = 0;
+      double ex = dinf;
+      if (lane < nx) {
+        const int e = xl[lane];
+        es = e >> 6;
+        ec = e & 63;
+        const float *ctp = cent_t + static_cast<long long>(sub * 2 + es) * h * k + ec;
+        double acc = 0.0;
+        for (int t = 0; t < h; ++t) {
+          double delta = S.qs[es * h + t] - static_cast<double>(ctp[t * k]);
+          double sq = delta * delta;
+          acc = acc + sq;
+        }
+        ex = acc;
+        S.hd[lane] = acc;
+      }
+      __syncthreads();
+      int rank = 0;
+      if (lane < nx) {
+        const int b0 = es ? n0 : 0, b1 = es ? nx : n0;
+        for (int t = b0; t < b1; ++t) {
+          const double v = S.hd[t];
+          const int c2 = xl[t] & 63;
+          rank += (v < ex) || (v == ex && c2 < ec);
+        }
+        if (rank < R) {
+          if (es == 0) { S.d1s[rank] = ex; S.o1[rank] = ec; }
+          else { S.d2s[rank] = ex; S.o2[rank] = ec; }
+        }
+      }
+      double l0 = (lane < nx && es == 0 && rank >= R) ? ex : dinf;
+      double l1 = (lane < nx && es == 1 && rank >= R) ? ex : dinf;
+      if (inb && !((x0 >> lane) & 1ull)) l0 = fmin(l0, static_cast<double>(lb0));
+      if (inb && !((x1 >> lane) & 1ull)) l1 = fmin(l1, static_cast<double>(lb1));
+#pragma unroll
+      for (int sh = 32; sh >= 1; sh >>= 1) {
+        l0 = fmin(l0, __shfl_xor(l0, sh, kWave));
+        l1 = fmin(l1, __shfl_xor(l1, sh, kWave));
+      }
+      __syncthreads();
+      const int32_t *off = offsets + static_cast<long long>(sub) * (ncells + 1);
+      const bool more = R < k;                          // ranks R.. exist and are not known exactly
+      const bool rowl = lane < R;
+      const double a = rowl ? S.d1s[lane] : 0.0;
+      const int cbase = rowl ? S.o1[lane] * k : 0;
+      int j = 0;
+      int cell = rowl ? cbase + S.o2[0] : 0;
+      int size = rowl ? off[cell + 1] - off[cell] : 0;
+      double cost = rowl ? a + S.d2s[0] : dinf;
+      double pend = dinf;                               // lower bound of the next cell once column R is reached
+      const double urow = more ? l0 + S.d2s[0] : dinf;  // lower bound of row R's first cell
+      int npop = 0, retr = 0, started = 0;
+      double ccut = 0.0;
+      bool met = false;
+      while (npop < kPopCap) {
+        double bc = dinf, bu = (started >= R) ? urow : dinf;
+        int bi = -1;
+        const int last = min(started, R - 1);
+        for (int i = 0; i <= last; ++i) {
+          const double ci = readlane_f64(cost, i);
+          if (ci < bc) { bc = ci; bi = i; }
+          bu = fmin(bu, readlane_f64(pend, i));
+        }
+        if (bi < 0 || bu <= bc) break;                 // an unknown rank could come next
+        if (bi == started) ++started;
+        const int psz = __builtin_amdgcn_readlane(size, bi);
+        const int pcell = __builtin_amdgcn_readlane(cell, bi);
+        if (lane == 0) S.pops[npop] = pcell | ((phi == 1 && npop < ksize ? 2 : 1) << 24);
+        ++npop;
+        retr += psz;
+        ccut = bc;
+        if (lane == bi) {
+          ++j;
+          if (j < R) {
+            cell = cbase + S.o2[j];
+            size = off[cell + 1] - off[cell];
+            cost = a + S.d2s[j];
+          } else {
+            cost = dinf;
+            if (more) pend = a + l1;
+          }
+        }
+        if (retr >= budget) { met = true; break; }
+      }
+      if (met) {
+        __syncthreads();
+        int32_t *dst = cells_out + (static_cast<long long>(q) * m + sub) * ncells;
+        double *st = sstat + (static_cast<long long>(q) * m + sub) * 4;
+        for (int t = lane; t < npop; t += kWave) dst[t] = S.pops[t];
+        if (lane == 0) {
+          const double c1 = S.d1s[0] + S.d2s[0];
+          double c2 = c1;
+          if (k > 1) {
+            const double u = S.d1s[0] + S.d2s[1], v = S.d1s[1] + S.d2s[0];
+            c2 = u < v ? u : v;
+          }
+          ncell[static_cast<long long>(q) * m + sub] = npop;
+          retrieved[static_cast<long long>(q) * m + sub] = retr;
+          st[0] = c1;
+          st[1] = c2;
+          st[2] = ccut;
+          const int cc = S.o1[0] * k + S.o2[0];
+          st[3] = static_cast<double>(off[cc + 1] - off[cc]);
+        }
+        return;
+      }
+      __syncthreads();
+    }
+  }
+
   // ---- Dist_1 / Dist_2 -----------------------------------------------------
   double *hout = hdist_out + (static_cast<long long>(q) * m + sub) * 2 * k;
   for (int s = 0; s < 2; ++s) {
