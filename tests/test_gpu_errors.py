@@ -97,7 +97,7 @@ def test_bad_options_and_plan_limits(small):
     w, x, q, idx = small
     g = engine.Index(idx)
     qt = torch.from_numpy(q).cuda()
-    for kw in ({"persistent": 2}, {"overlap": 2}, {"precision": 1}, {"budget_source": 1}):
+    for kw in ({"persistent": 2}, {"overlap": 2}, {"precision": 1}, {"precision": 3}, {"budget_source": 1}):
         with pytest.raises(engine.CrispError) as e:
             g.search(qt, 5, mode=1, alpha=0.1, tau=2, **kw)
         assert e.value.status == -1
