@@ -766,7 +766,7 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
 // contributes the slice of the cell's posting list inside the tile (from the
 // load-time cell x tile table); waves take whole slices round robin and
 // stride them with four coalesced id loads in flight per lane.
-// Each of the 16 waves then scans its sixteenth of the counters (16 per lane
+// Each of the 16 waves then scans its sixteenth of the counters (32 per lane
 // per step, compared four at a time in 16-bit fields) and writes the ids
 // reaching the threshold, in ascending order, to its own segment; segment
 // counts go to seg_cnt[q][tile][wave].
@@ -910,35 +910,42 @@ __global__ void __launch_bounds__(kCountThreads) k_count(
   // 16-bit fields, and adding 256 - thr to a field sets its bit 8 exactly
   // when the byte is >= thr (no carry leaves the field).
   const uint32_t add = static_cast<uint32_t>(0x100 - thr) * 0x00010001u;
-  for (int v0 = 0; v0 < per_wave; v0 += 4 * kWave) {
-    const int dwl = v0 + 4 * lane;                 // this lane's first dword within the wave range
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (dwl < per_wave) v = cnt4[(dw0 + dwl) >> 2];
-    const uint32_t words[4] = {v.x, v.y, v.z, v.w};
+  const uint8_t *cnt8 = reinterpret_cast<const uint8_t *>(cnt);
+  constexpr int kScanDw = 8;                       // dwords (32 counters) per lane per step
+  for (int v0 = 0; v0 < per_wave; v0 += kScanDw * kWave) {
+    const int dwl = v0 + kScanDw * lane;           // this lane's first dword within the wave range
+    uint4 va = make_uint4(0u, 0u, 0u, 0u), vb = make_uint4(0u, 0u, 0u, 0u);
+    if (dwl < per_wave) {
+      va = cnt4[(dw0 + dwl) >> 2];
+      vb = cnt4[((dw0 + dwl) >> 2) + 1];
+    }
+    const uint32_t words[kScanDw] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
     const int idbase = (dw0 + dwl) * 4;            // tile-local id of the first counter
     uint32_t sel = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kScanDw; ++j) {
       const uint32_t ge = ((words[j] & 0x00FF00FFu) + add) & 0x01000100u;
       const uint32_t go = (((words[j] >> 8) & 0x00FF00FFu) + add) & 0x01000100u;
       const uint32_t b = ((ge >> 8) & 1u) | ((go >> 7) & 2u) | ((ge >> 22) & 4u) | ((go >> 21) & 8u);
       sel |= b << (4 * j);
     }
-    const int nvalid = (dwl < per_wave) ? min(max(tlen - idbase, 0), 16) : 0;
-    sel &= (nvalid >= 16) ? 0xFFFFu : ((1u << nvalid) - 1u);
+    const int nvalid = (dwl < per_wave) ? min(max(tlen - idbase, 0), 32) : 0;
+    sel &= (nvalid >= 32) ? 0xFFFFFFFFu : ((1u << nvalid) - 1u);
     const int c = __popc(sel);
     int pos = run;
     if (pass != 1) {
-      unsigned long long b0m = __ballot(c & 1), b1m = __ballot(c & 2), b2m = __ballot(c & 4),
-                         b3m = __ballot(c & 8), b4m = __ballot(c & 16);
-      pos += __popcll(b0m & below) + 2 * __popcll(b1m & below) + 4 * __popcll(b2m & below) +
-             8 * __popcll(b3m & below) + 16 * __popcll(b4m & below);
-      run += __popcll(b0m) + 2 * __popcll(b1m) + 4 * __popcll(b2m) + 8 * __popcll(b3m) + 16 * __popcll(b4m);
+      // exclusive prefix of c over the lanes and the step's total, from its six bits
+#pragma unroll
+      for (int bit = 0; bit < 6; ++bit) {
+        const unsigned long long bm = __ballot((c >> bit) & 1);
+        pos += __popcll(bm & below) << bit;
+        run += __popcll(bm) << bit;
+      }
     }
     while (sel) {
       const int e = __ffs(sel) - 1;
       sel &= sel - 1u;
-      const int sc = (words[e >> 2] >> (8 * (e & 3))) & 255;
+      const int sc = cnt8[idbase + e];
       if (pass != 2 && sc >= 1) atomicAdd(&S.hist[sc], 1);
       if (pass != 1) {
         dst[pos] = static_cast<int32_t>(t0) + idbase + e;
