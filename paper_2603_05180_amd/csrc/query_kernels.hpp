@@ -766,7 +766,7 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
 // contributes the slice of the cell's posting list inside the tile (from the
 // load-time cell x tile table); waves take whole slices round robin and
 // stride them with four coalesced id loads in flight per lane.
-// Each of the 16 waves then scans its sixteenth of the counters (32 per lane
+// Each of the 16 waves then scans its sixteenth of the counters (64 per lane
 // per step, compared four at a time in 16-bit fields) and writes the ids
 // reaching the threshold, in ascending order, to its own segment; segment
 // counts go to seg_cnt[q][tile][wave].
@@ -911,40 +911,41 @@ __global__ void __launch_bounds__(kCountThreads) k_count(
   // when the byte is >= thr (no carry leaves the field).
   const uint32_t add = static_cast<uint32_t>(0x100 - thr) * 0x00010001u;
   const uint8_t *cnt8 = reinterpret_cast<const uint8_t *>(cnt);
-  constexpr int kScanDw = 8;                       // dwords (32 counters) per lane per step
+  constexpr int kScanDw = 16;                      // dwords (64 counters) per lane per step
   for (int v0 = 0; v0 < per_wave; v0 += kScanDw * kWave) {
     const int dwl = v0 + kScanDw * lane;           // this lane's first dword within the wave range
-    uint4 va = make_uint4(0u, 0u, 0u, 0u), vb = make_uint4(0u, 0u, 0u, 0u);
-    if (dwl < per_wave) {
-      va = cnt4[(dw0 + dwl) >> 2];
-      vb = cnt4[((dw0 + dwl) >> 2) + 1];
+    uint32_t words[kScanDw];
+#pragma unroll
+    for (int u = 0; u < kScanDw / 4; ++u) {
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (dwl < per_wave) v = cnt4[((dw0 + dwl) >> 2) + u];
+      words[4 * u] = v.x; words[4 * u + 1] = v.y; words[4 * u + 2] = v.z; words[4 * u + 3] = v.w;
     }
-    const uint32_t words[kScanDw] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
     const int idbase = (dw0 + dwl) * 4;            // tile-local id of the first counter
-    uint32_t sel = 0;
+    unsigned long long sel = 0;
 #pragma unroll
     for (int j = 0; j < kScanDw; ++j) {
       const uint32_t ge = ((words[j] & 0x00FF00FFu) + add) & 0x01000100u;
       const uint32_t go = (((words[j] >> 8) & 0x00FF00FFu) + add) & 0x01000100u;
       const uint32_t b = ((ge >> 8) & 1u) | ((go >> 7) & 2u) | ((ge >> 22) & 4u) | ((go >> 21) & 8u);
-      sel |= b << (4 * j);
+      sel |= static_cast<unsigned long long>(b) << (4 * j);
     }
-    const int nvalid = (dwl < per_wave) ? min(max(tlen - idbase, 0), 32) : 0;
-    sel &= (nvalid >= 32) ? 0xFFFFFFFFu : ((1u << nvalid) - 1u);
-    const int c = __popc(sel);
+    const int nvalid = (dwl < per_wave) ? min(max(tlen - idbase, 0), 64) : 0;
+    sel &= (nvalid >= 64) ? ~0ull : ((1ull << nvalid) - 1ull);
+    const int c = __popcll(sel);
     int pos = run;
     if (pass != 1) {
-      // exclusive prefix of c over the lanes and the step's total, from its six bits
+      // exclusive prefix of c over the lanes and the step's total, from its seven bits
 #pragma unroll
-      for (int bit = 0; bit < 6; ++bit) {
+      for (int bit = 0; bit < 7; ++bit) {
         const unsigned long long bm = __ballot((c >> bit) & 1);
         pos += __popcll(bm & below) << bit;
         run += __popcll(bm) << bit;
       }
     }
     while (sel) {
-      const int e = __ffs(sel) - 1;
-      sel &= sel - 1u;
+      const int e = __ffsll(static_cast<long long>(sel)) - 1;
+      sel &= sel - 1ull;
       const int sc = cnt8[idbase + e];
       if (pass != 2 && sc >= 1) atomicAdd(&S.hist[sc], 1);
       if (pass != 1) {
