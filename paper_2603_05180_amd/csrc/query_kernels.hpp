@@ -1205,6 +1205,8 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_dist(
 // each (wave, digit) its start, and inside a 64-lane step a lane's rank among
 // lower lanes with the same digit comes from 7 ballots.  Input element i is
 // (key[i], val[i]) or, when packed, the int64 (key << 32 | val).
+constexpr int kPlaceU = 8;  // elements per lane loaded together (loads in flight)
+
 template <bool kPackedIn, bool kPackedOut>
 __device__ __forceinline__ void radix_pass(int nc, int shift, const int32_t *__restrict__ key_in,
                                            const int32_t *__restrict__ val_in, const long long *__restrict__ pk_in,
@@ -1225,12 +1227,12 @@ __device__ __forceinline__ void radix_pass(int nc, int shift, const int32_t *__r
   };
   for (int t = threadIdx.x; t < kOrderWaves * 128; t += kOrderThreads) cnt[t >> 7][t & 127] = 0;
   __syncthreads();
-  for (int i0 = b0; i0 < b1; i0 += 4 * kWave) {
-    int k[4], v[4];
+  for (int i0 = b0; i0 < b1; i0 += kPlaceU * kWave) {
+    int k[kPlaceU], v[kPlaceU];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) load(min(i0 + u * kWave + lane, b1 - 1), k[u], v[u]);  // clamped
+    for (int u = 0; u < kPlaceU; ++u) load(min(i0 + u * kWave + lane, b1 - 1), k[u], v[u]);  // clamped
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < kPlaceU; ++u)
       if (i0 + u * kWave + lane < b1) atomicAdd(&cnt[wv][(k[u] >> shift) & 127], 1);
   }
   __syncthreads();
@@ -1250,12 +1252,12 @@ __device__ __forceinline__ void radix_pass(int nc, int shift, const int32_t *__r
   }
   __syncthreads();
   const unsigned long long below = lanes_below_mask();
-  for (int s0 = b0; s0 < b1; s0 += 4 * kWave) {
-    int kk[4], vv[4];
+  for (int s0 = b0; s0 < b1; s0 += kPlaceU * kWave) {
+    int kk[kPlaceU], vv[kPlaceU];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) load(min(s0 + u * kWave + lane, b1 - 1), kk[u], vv[u]);  // clamped
+    for (int u = 0; u < kPlaceU; ++u) load(min(s0 + u * kWave + lane, b1 - 1), kk[u], vv[u]);  // clamped
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kPlaceU; ++u) {
       const bool valid = s0 + u * kWave + lane < b1;
       const int k = kk[u], v = vv[u];
       const int g = (k >> shift) & 127;
