@@ -126,7 +126,7 @@ struct StageTimer {
 struct Layout {
   size_t qrot, hdist, ptab, ncell, cells, retr, tilecnt, hist, flag, taueff, ncand, segids, segscore, cand,
       score, regA, regB, regC, examined, lastupd, stopped, refined, sstat, feat, lim, queue, order, sclb, scub,
-      total;
+      flist, nflag, total;
 };
 
 static Layout make_layout(const crisp_index *ix, long long qc) {
@@ -163,6 +163,8 @@ static Layout make_layout(const crisp_index *ix, long long qc) {
   L.order = take(qc * 4);
   L.sclb = take(ix->k <= kWave ? qc * ix->m * 2 * ix->k * 4 : 0);
   L.scub = take(ix->k <= kWave ? qc * ix->m * 2 * ix->k * 4 : 0);
+  L.flist = take(qc * 4);
+  L.nflag = take(4);
   L.total = o;
   return L;
 }
@@ -421,6 +423,8 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
     int32_t *qord = reinterpret_cast<int32_t *>(ws + L.order);
     float *sclb = reinterpret_cast<float *>(ws + L.sclb);
     float *scub = reinterpret_cast<float *>(ws + L.scub);
+    int32_t *flist = reinterpret_cast<int32_t *>(ws + L.flist);
+    int32_t *nflag = reinterpret_cast<int32_t *>(ws + L.nflag);
     double *sstat = reinterpret_cast<double *>(ws + L.sstat);
     float *feat = reinterpret_cast<float *>(ws + L.feat);
     int32_t *llim = reinterpret_cast<int32_t *>(ws + L.lim);
@@ -460,6 +464,8 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       StageTimer t7(ix, 7, st);
       k_fill<int32_t><<<grid1(static_cast<long long>(cq) * nb, 256), 256, 0, st>>>(hist, static_cast<long long>(cq) * nb, 0);
       LAUNCH_TRY("k_fill");
+      k_fill<int32_t><<<1, 64, 0, st>>>(nflag, 1, 0);
+      LAUNCH_TRY("k_fill");
       t7.stop();
     }
     {
@@ -467,21 +473,23 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       StageTimer t3(ix, 3, st);
       k_count<0><<<g, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
                                                       ix->ntiles, ix->tile, p->tau, flag, taueff, segids, segscore,
-                                                      tilecnt, hist, lv);
+                                                      tilecnt, hist, lv, flist, nflag);
       LAUNCH_TRY("k_count pass 0");
       t3.stop();
       StageTimer t7(ix, 7, st);
-      k_flag<<<grid1(cq, 4), 256, 0, st>>>(tilecnt, nseg, cq, k, p->tau, flag, taueff, hist, nb, lv);
+      k_flag<<<grid1(cq, 4), 256, 0, st>>>(tilecnt, nseg, cq, k, p->tau, flag, taueff, hist, nb, lv, flist, nflag);
       LAUNCH_TRY("k_flag");
-      k_count<1><<<g, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
+      // the fallback passes walk the flagged queries' list
+      const dim3 gf(ix->ntiles, std::min(cq, 256));
+      k_count<1><<<gf, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
                                                       ix->ntiles, ix->tile, p->tau, flag, taueff, segids, segscore,
-                                                      tilecnt, hist, lv);
+                                                      tilecnt, hist, lv, flist, nflag);
       LAUNCH_TRY("k_count pass 1");
       k_tau_eff<<<grid1(cq, 256), 256, 0, st>>>(flag, cq, k, p->tau, nb, hist, taueff, tilecnt, nseg, lv);
       LAUNCH_TRY("k_tau_eff");
-      k_count<2><<<g, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
+      k_count<2><<<gf, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
                                                       ix->ntiles, ix->tile, p->tau, flag, taueff, segids, segscore,
-                                                      tilecnt, hist, lv);
+                                                      tilecnt, hist, lv, flist, nflag);
       LAUNCH_TRY("k_count pass 2");
       k_compact<<<cq, kCompactThreads, 0, st>>>(segids, segscore, tilecnt, nseg, ix->tile / kCountWaves, n, cand,
                                                  score, ncand, lv);

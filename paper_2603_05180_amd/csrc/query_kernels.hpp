@@ -791,18 +791,23 @@ struct CountShared {
   int tmp[kCountWaves + 1];
 };
 
+#define CRISP_COUNT_PARAMS                                                                                    \
+  const int32_t *__restrict__ ncell, const int32_t *__restrict__ cells, int m, int ncells,                    \
+      const int32_t *__restrict__ offsets, const int32_t *__restrict__ ids, long long n,                      \
+      const int32_t *__restrict__ tile_off, int ntiles, int tile_ids, int tau, const int32_t *__restrict__ flag, \
+      const int32_t *__restrict__ tau_eff, int32_t *__restrict__ seg_ids, uint8_t *__restrict__ seg_score,    \
+      int32_t *__restrict__ seg_cnt, int32_t *__restrict__ hist, const int32_t *__restrict__ live
+#define CRISP_COUNT_ARGS                                                                                  \
+  ncell, cells, m, ncells, offsets, ids, n, tile_off, ntiles, tile_ids, tau, flag, tau_eff, seg_ids, seg_score, \
+      seg_cnt, hist, live
+
+// One (id tile, query) block's work; every early return is uniform over the block.
 template <int kPass>
-__global__ void __launch_bounds__(kCountThreads) k_count(
-    const int32_t *__restrict__ ncell, const int32_t *__restrict__ cells, int m, int ncells,
-    const int32_t *__restrict__ offsets, const int32_t *__restrict__ ids, long long n,
-    const int32_t *__restrict__ tile_off, int ntiles, int tile_ids, int tau,
-    const int32_t *__restrict__ flag, const int32_t *__restrict__ tau_eff,
-    int32_t *__restrict__ seg_ids, uint8_t *__restrict__ seg_score, int32_t *__restrict__ seg_cnt,
-    int32_t *__restrict__ hist, const int32_t *__restrict__ live) {
+__device__ __forceinline__ void count_block(const int tile, const int q, CRISP_COUNT_PARAMS) {
   constexpr int pass = kPass;
   extern __shared__ __align__(16) uint32_t cnt[];
   __shared__ CountShared S;
-  const int tile = blockIdx.x, q = blockIdx.y, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   if (live && q >= *live) return;
   if (pass != 0 && flag[q] == 0) return;
   const long long t0 = static_cast<long long>(tile) * tile_ids;
@@ -964,11 +969,29 @@ __global__ void __launch_bounds__(kCountThreads) k_count(
   }
 }
 
+// pass 0: grid (tiles, queries).  Passes 1 and 2 concern the queries k_flag
+// listed (flist[0 .. *nflag)), usually none: a grid of (tiles, a few hundred)
+// blocks walks the list instead of launching a block for every query.
+template <int kPass>
+__global__ void __launch_bounds__(kCountThreads) k_count(CRISP_COUNT_PARAMS, const int32_t *__restrict__ flist,
+                                                          const int32_t *__restrict__ nflag) {
+  if constexpr (kPass == 0) {
+    count_block<0>(blockIdx.x, blockIdx.y, CRISP_COUNT_ARGS);
+  } else {
+    const int nf = *nflag;
+    for (int i = blockIdx.y; i < nf; i += gridDim.y) {
+      count_block<kPass>(blockIdx.x, flist[i], CRISP_COUNT_ARGS);
+      __syncthreads();
+    }
+  }
+}
+
 // Per query (one wavefront): |C| at tau; flag the fallback when fewer than k
-// points reach it.
+// points reach it, and list the flagged queries.
 __global__ void k_flag(const int32_t *__restrict__ seg_cnt, int nseg, int nq, int k, int tau,
                        int32_t *__restrict__ flag, int32_t *__restrict__ tau_eff, int32_t *__restrict__ hist,
-                       int nbins, const int32_t *__restrict__ live) {
+                       int nbins, const int32_t *__restrict__ live, int32_t *__restrict__ flist,
+                       int32_t *__restrict__ nflag) {
   const int q = blockIdx.x * (blockDim.x / kWave) + wave_id();
   if (q >= nq || (live && q >= *live)) return;
   const int lane = lane_id();
@@ -979,6 +1002,7 @@ __global__ void k_flag(const int32_t *__restrict__ seg_cnt, int nseg, int nq, in
   if (lane == 0) {
     flag[q] = f;
     tau_eff[q] = tau;
+    if (f) flist[atomicAdd(nflag, 1)] = q;   // nflag is zero at launch
   }
   if (f)
     for (int s = lane; s < nbins; s += kWave) hist[static_cast<long long>(q) * nbins + s] = 0;
