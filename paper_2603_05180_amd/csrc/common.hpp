@@ -50,6 +50,20 @@ __device__ __forceinline__ int wave_incl_scan_i32(int v) {
   return v;
 }
 
+// The same inclusive prefix sum on DPP lane moves (every lane active): four
+// in-row steps (row_shr 1, 2, 4, 8; lanes shifted in from outside the row
+// add 0), then lane 15 of rows 0 and 2 is added to rows 1 and 3 (row_bcast
+// 15) and lane 31 to rows 2 and 3 (row_bcast 31).
+__device__ __forceinline__ int wave_incl_scan_dpp(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
+  return v;
+}
+
 __device__ __forceinline__ unsigned long long lanes_below_mask() {
   const int lane = lane_id();
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));

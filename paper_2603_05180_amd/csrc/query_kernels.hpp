@@ -761,15 +761,19 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
 // ---------------------------------------------------------------------------
 // A3/A4: collision counting in LDS.  One 1024-thread block per (id tile,
 // query).  The tile's uint8 counters are packed four per dword and
-// incremented with ds_add_u32 of (w << 8 * (id & 3)); scores never exceed
-// 2M <= 254.  Work items are (subspace, activated cell) pairs; each
+// incremented with ds_add_u32 of w shifted to the id's byte; scores never
+// exceed 2M <= 254.  Within each group of 32 ids, id 8j + i (j < 4, i < 8)
+// is byte j of the group's dword i, so that the threshold test of a dword
+// lands, with one shift, on the bits that keep a lane's 64 counters in id
+// order.  Work items are (subspace, activated cell) pairs; each
 // contributes the slice of the cell's posting list inside the tile (from the
 // load-time cell x tile table); waves take whole slices round robin and
 // stride them with four coalesced id loads in flight per lane.
 // Each of the 16 waves then scans its sixteenth of the counters (64 per lane
-// per step, compared four at a time in 16-bit fields) and writes the ids
-// reaching the threshold, in ascending order, to its own segment; segment
-// counts go to seg_cnt[q][tile][wave].
+// per step, four bytes of a dword tested by one 32-bit add when 2M < 128,
+// else in two 16-bit fields) and writes the ids reaching the threshold, in
+// ascending order, to its own segment; segment counts go to
+// seg_cnt[q][tile][wave].
 //
 // pass 0: threshold tau, write candidates, histogram of scores >= max(tau, 1)
 // pass 1: queries flagged for the fallback only: histogram of scores >= 1
@@ -782,6 +786,10 @@ constexpr int kItems = 1024;
 // A pointer into global memory (read back from LDS, the compiler would
 // otherwise treat it as generic and use flat loads).
 typedef const int32_t __attribute__((address_space(1))) *global_i32_ptr;
+
+// LDS byte offset of the counter of tile-local id loc (the layout above).
+__device__ __forceinline__ int cnt_dword_bytes(int loc) { return (loc & ~31) | ((loc << 2) & 31); }
+__device__ __forceinline__ int cnt_byte(int loc) { return cnt_dword_bytes(loc) | ((loc >> 3) & 3); }
 
 struct CountShared {
   global_i32_ptr ptr[kItems];  // first id of the item's slice (ids itself for an empty slice)
@@ -878,7 +886,7 @@ __device__ __forceinline__ void count_block(const int tile, const int q, CRISP_C
       for (int u = 0; u < kG; ++u) {
         const int loc = idv[u] - static_cast<int>(t0);
         if (lane < lenv[u] && static_cast<unsigned>(loc) < static_cast<unsigned>(tlen))
-          atomicAdd(&cnt[loc >> 2], wgv[u] << ((loc & 3) * 8));
+          atomicAdd(&cnt[cnt_dword_bytes(loc) >> 2], wgv[u] << (loc & 0x18));
       }
 #pragma unroll 1
       for (int u = 0; u < kG; ++u) {
@@ -895,7 +903,7 @@ __device__ __forceinline__ void count_block(const int tile, const int q, CRISP_C
           for (int e = 0; e < 4; ++e) {
             const int loc = iv[e] - static_cast<int>(t0);
             if (p0 + e * kWave < len && static_cast<unsigned>(loc) < static_cast<unsigned>(tlen))
-              atomicAdd(&cnt[loc >> 2], wgv[u] << ((loc & 3) * 8));
+              atomicAdd(&cnt[cnt_dword_bytes(loc) >> 2], wgv[u] << (loc & 0x18));
           }
         }
       }
@@ -905,15 +913,18 @@ __device__ __forceinline__ void count_block(const int tile, const int q, CRISP_C
 
   // ---- scan: threshold, histogram, ordered per-wave compaction --------------
   const int wv = wave_id();
-  const int per_wave = ndw / kCountWaves;            // dwords per wave (multiple of 4)
+  const int per_wave = ndw / kCountWaves;            // dwords per wave (tiles of 2^12..2^17 ids: a multiple of 64)
   const int dw0 = wv * per_wave;
-  const unsigned long long below = lanes_below_mask();
   int32_t *dst = seg_ids + static_cast<long long>(q) * n + t0 + static_cast<long long>(dw0) * 4;
   uint8_t *dsc = seg_score + static_cast<long long>(q) * n + t0 + static_cast<long long>(dw0) * 4;
   int run = 0;
-  // Bytes >= thr, four at a time: the even and odd bytes of a dword sit in
+  // Bytes >= thr, four at a time.  When 2M < 128 adding 128 - thr to every
+  // byte of a dword sets each byte's bit 7 exactly when the byte is >= thr
+  // (no carry leaves a byte).  Otherwise the even and odd bytes sit in
   // 16-bit fields, and adding 256 - thr to a field sets its bit 8 exactly
-  // when the byte is >= thr (no carry leaves the field).
+  // when the byte is >= thr.
+  const bool narrow = 2 * m < 128;
+  const uint32_t add4 = static_cast<uint32_t>(0x80 - thr) * 0x01010101u;
   const uint32_t add = static_cast<uint32_t>(0x100 - thr) * 0x00010001u;
   const uint8_t *cnt8 = reinterpret_cast<const uint8_t *>(cnt);
   constexpr int kScanDw = 16;                      // dwords (64 counters) per lane per step
@@ -927,31 +938,39 @@ __device__ __forceinline__ void count_block(const int tile, const int q, CRISP_C
       words[4 * u] = v.x; words[4 * u + 1] = v.y; words[4 * u + 2] = v.z; words[4 * u + 3] = v.w;
     }
     const int idbase = (dw0 + dwl) * 4;            // tile-local id of the first counter
-    unsigned long long sel = 0;
+    // Bit 32g + 8j + i of sel (dword 8g + i of the lane's 16, byte j) is
+    // the counter of id idbase + 32g + 8j + i.
+    uint32_t half[2] = {0u, 0u};
+    if (narrow) {
 #pragma unroll
-    for (int j = 0; j < kScanDw; ++j) {
-      const uint32_t ge = ((words[j] & 0x00FF00FFu) + add) & 0x01000100u;
-      const uint32_t go = (((words[j] >> 8) & 0x00FF00FFu) + add) & 0x01000100u;
-      const uint32_t b = ((ge >> 8) & 1u) | ((go >> 7) & 2u) | ((ge >> 22) & 4u) | ((go >> 21) & 8u);
-      sel |= static_cast<unsigned long long>(b) << (4 * j);
+      for (int j = 0; j < kScanDw; ++j) {
+        const int i = j & 7;
+        half[j >> 3] |= ((words[j] + add4) >> (7 - i)) & (0x01010101u << i);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kScanDw; ++j) {
+        const int i = j & 7;
+        const uint32_t ge = (words[j] & 0x00FF00FFu) + add;           // bytes 0, 2 -> bits 8, 24
+        const uint32_t go = ((words[j] >> 8) & 0x00FF00FFu) + add;    // bytes 1, 3 -> bits 8, 24
+        half[j >> 3] |= ((ge >> (8 - i)) & (0x00010001u << i)) | ((go << i) & (0x01000100u << i));
+      }
     }
+    unsigned long long sel = (static_cast<unsigned long long>(half[1]) << 32) | half[0];
     const int nvalid = (dwl < per_wave) ? min(max(tlen - idbase, 0), 64) : 0;
     sel &= (nvalid >= 64) ? ~0ull : ((1ull << nvalid) - 1ull);
     const int c = __popcll(sel);
     int pos = run;
     if (pass != 1) {
-      // exclusive prefix of c over the lanes and the step's total, from its seven bits
-#pragma unroll
-      for (int bit = 0; bit < 7; ++bit) {
-        const unsigned long long bm = __ballot((c >> bit) & 1);
-        pos += __popcll(bm & below) << bit;
-        run += __popcll(bm) << bit;
-      }
+      // exclusive prefix of c over the lanes, and the step's total
+      const int incl = wave_incl_scan_dpp(c);
+      pos += incl - c;
+      run += __builtin_amdgcn_readlane(incl, kWave - 1);
     }
     while (sel) {
       const int e = __ffsll(static_cast<long long>(sel)) - 1;
       sel &= sel - 1ull;
-      const int sc = cnt8[idbase + e];
+      const int sc = cnt8[cnt_byte(idbase + e)];
       if (pass != 2 && sc >= 1) atomicAdd(&S.hist[sc], 1);
       if (pass != 1) {
         dst[pos] = static_cast<int32_t>(t0) + idbase + e;

@@ -111,6 +111,23 @@ def test_wide_rows_several_tiles():
         compare(idx, q, 10, mode=mode, alpha=0.02, tau=4, tile_ids=4096)
 
 
+@pytest.mark.parametrize("d,m,cases", [
+    (256, 64, [(1, 0.5, 128), (1, 0.5, 108), (0, 0.3, 32)]),
+    (192, 96, [(1, 0.5, 130), (1, 0.5, 172), (0, 0.3, 48)]),
+])
+def test_many_subspaces_scores_above_127(d, m, cases):
+    """M = 64 and 96: Optimized-Mode scores reach 2M = 128 and 192, so the
+    counting scan takes its 16-bit-field test; thresholds near the top force
+    the fallback passes (tau 128 = 2M at M = 64 drops to tau_eff of about 120)."""
+    w, x, q = make_workload("d128", n=3000, d=d, m=m, k_half=4, n_query=6)
+    idx = oracle_index(w, x)
+    for tile in (0, 4096):
+        g = gpu_index(idx, tile)
+        for mode, alpha, tau in cases:
+            print(f"M={m} tile={tile} mode={mode} alpha={alpha} tau={tau}", flush=True)
+            compare(idx, q, 10, mode=mode, alpha=alpha, tau=tau, gpu=g)
+
+
 @pytest.mark.parametrize("d,m", [(192, 4), (320, 5), (448, 7)])
 def test_code_widths_not_a_power_of_two(d, m):
     """3, 5 and 7 sign-code words per row: the Hamming kernel's lanes per row
