@@ -1,7 +1,7 @@
 """Full-size parity on sampled queries (needs an MI355X).
 
-The N = 1M, D = 4096 index and the N = 2M, D = 3072 index are generated and
-built on the GPU exactly as bench.py does; the whole batch is searched in
+The N = 1M, D = 4096 index, the N = 1M, D = 960 index and the N = 2M,
+D = 3072 index are generated and built on the GPU exactly as bench.py does; the whole batch is searched in
 the configuration bench.py times (10,000 queries, chunks of 4,096, two chunk
 pipelines, float32 and bfloat16 verification; the batch executor's graphs
 for the uneven workload), and sampled queries, spread over the chunks, are
@@ -91,6 +91,29 @@ def test_d4096_bench_configuration_sampled():
     oi, od, _ = oquery.search(host, q[sample], w.k, limits=lim[sample], **kw)
     assert np.array_equal(li.cpu().numpy()[sample], oi)
     assert np.array_equal(ld.cpu().numpy()[sample].view(np.uint32), od.view(np.uint32))
+    del host, index, arrays, queries
+    torch.cuda.empty_cache()
+
+
+def test_d960_both_modes_k10_k100_sampled():
+    """N = 1M, D = 960 (16 subspaces of 60 dims, 256 cells each, unrotated):
+    the whole batch of 10,000 queries in chunks of 4,096, both modes at
+    k = 10 and k = 100; sampled queries of every chunk re-run by the oracle."""
+    import synth.gpu as sg
+    from paper_2603_05180_amd import engine
+    w, arrays, params = _build("d960")
+    queries = sg.rows(w, w.seed_query, 0, w.n_query, params)
+    index = engine.Index(arrays)
+    host = _host(arrays)
+    q = queries.cpu().numpy()
+    sample = np.array([0, 4095, 4096, 9999])
+    for mode in (0, 1):
+        for k in (10, 100):
+            kw = dict(mode=mode, alpha=0.01, tau=4)
+            print(f"d960 full batch, mode={mode} k={k}", flush=True)
+            ids, d = index.search(queries, k, max_chunk=4096, **kw)
+            torch.cuda.synchronize()
+            _check(host, q, sample, ids.cpu().numpy(), d.cpu().numpy(), k, **kw)
     del host, index, arrays, queries
     torch.cuda.empty_cache()
 
