@@ -61,3 +61,19 @@ def test_new_entry_points_reject_bad_arguments_without_launching():
     assert lib.crisp_index_bf16_bytes(None, ctypes.byref(size)) == -1
     assert lib.crisp_feature_count(32) == 1 + 16 + 3 * 32 + 13
     assert lib.crisp_mlp_param_count(10) == 10 * 64 + 2 * 64 + 1
+
+
+def test_engine_without_the_library_fails_loudly(tmp_path):
+    """A copy of the package with no built library: importing the engine
+    raises ImportError naming the missing file (no CPU fallback exists)."""
+    import shutil
+    import subprocess
+    import sys
+    src = os.path.join(ROOT, "paper_2603_05180_amd")
+    shutil.copytree(src, tmp_path / "paper_2603_05180_amd",
+                    ignore=shutil.ignore_patterns("*.so", "__pycache__", "csrc"))
+    r = subprocess.run([sys.executable, "-c", "import paper_2603_05180_amd.engine"], cwd=tmp_path,
+                       capture_output=True, text=True, timeout=300,
+                       env=dict(os.environ, PYTHONPATH=str(tmp_path)))
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "libcrisp.so is missing" in r.stderr
