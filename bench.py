@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--uneven-workload", default="d3072",
                     help="workload of the uneven-batch section ('' = skip)")
     ap.add_argument("--uneven-queries", type=int, default=50_000)
+    ap.add_argument("--autotune-cache", default="",
+                    help="JSON file the uneven-batch tuner reuses and extends ('' = tune afresh, keep nothing)")
     ap.add_argument("--floor", type=float, default=0.998,
                     help="fraction of the plain top-k the learned budget must keep on held-out queries")
     return ap.parse_args()
@@ -404,9 +406,7 @@ def uneven_batches(args):
     t = time.time()
     srv = autotune.Server(None, index, sp, max_batch=4096, ks=(1, 10, 100), tiles=(16384, 65536),
                           chunks=(512, 1024))
-    choice = srv.tune(queries, [1 << i for i in range(13)], reps=2,
-                      cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
-                      if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
+    choice = srv.tune(queries, [1 << i for i in range(13)], reps=2, cache=args.autotune_cache or None)
     torch.cuda.synchronize()
     log(f"uneven: tuned {len(choice)} (k, bucket) pairs in {time.time() - t:.1f}s")
     srv.run(queries, sizes[:8], ks[:8])                   # first replays of the common buckets

@@ -7,7 +7,7 @@ network predicts log L* from the features the engine computes during the
 same search.  At search time the walk stops at the earlier of the patience
 stop and clamp(ceil(exp(y + delta)), k, |C|).  The margin delta is the
 smallest value (found by bisection) at which held-out queries keep a given
-fraction of their plain top-k: the plain result is the judge.  A prefix
+fraction of their plain top-k: the plain result is the reference.  A prefix
 never loses a plain result it contains, so that fraction is non-decreasing
 in delta and bisection finds the threshold.
 """
