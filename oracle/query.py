@@ -6,12 +6,11 @@ at a time, in the paper's order and notation:
   1. q' = q R when the index holds a rotation (Section 4.1: the rotation is
      kept in the index metadata so queries are mapped into the same space).
   2. For every subspace m: split q'^(m) into its left / right halves, compute
-     Dist_1 and Dist_2 against the two half-codebooks, sort them, and run the
-     Multi-Sequence traversal with a priority queue of (cost, i, j): pop the
-     cheapest cell, count it as one rank, give it weight 2 when the mode flag
-     phi = 1 and rank <= k_size (else 1), add the weight to the score of every
-     id in the cell's CSR posting list, and stop once ``retrieved`` reaches the
-     per-subspace budget.
+     Dist_1 and Dist_2 against the two half-codebooks, and take the cells the
+     Multi-Sequence traversal activates: in ascending cost until the ids
+     gathered reach the per-subspace budget, each cell one rank, weight 2 when
+     the mode flag phi = 1 and rank <= k_size (else 1); add the weight to the
+     score of every id in the cell's CSR posting list.
   3. Candidates C = {x : V[x] >= tau}, with the robustness fallback that keeps
      |C| >= k (Section 4.3.2, Stage 1).
   4. phi = 1: order C by Hamming distance of sign codes (Stage 2).
@@ -33,9 +32,9 @@ Readings where the paper is silent (each is also listed in the design notes):
 * Fallback: if fewer than k points reach tau, use the largest s <= tau with at
   least k points scoring >= s; if even s = 1 has fewer than k, C = {V >= 1}
   and the output is padded with id -1 / distance +inf.
-* Distance key: the float64 value d_canon defined by ``canonical_sqdist``; the
-  result order is ascending (d_canon, id).  Returned distances are
-  f32(d_canon).
+* Distance key: the squared L2 distance summed in float64 over the dimensions
+  in ascending order (``canonical_sqdist``); the result order is ascending
+  (key, id).  Returned distances are f32(key).
 * Patience: a candidate "updates" the top-k iff the top-k holds fewer than k
   items or its key is below the current k-th key; the counter of consecutive
   non-updates resets on an update and the walk stops when it reaches P.
@@ -43,15 +42,11 @@ Readings where the paper is silent (each is also listed in the design notes):
 """
 from __future__ import annotations
 
-import heapq
 import math
 
 import numpy as np
 
 from .build import half_distances, rotate_rows
-
-LANES = 64
-
 
 def budget_for(alpha: float, n: int) -> int:
     """Per-subspace retrieval budget: max(1, ceil(alpha * N)), in float64."""
@@ -80,34 +75,35 @@ def subspace_half_distances(index: dict, qp: np.ndarray) -> np.ndarray:
 
 def multi_sequence(d1: np.ndarray, d2: np.ndarray, sizes: np.ndarray, budget: int,
                    k_size: int, phi: int):
-    """Multi-Sequence cell traversal of one subspace (Algorithm 1).
+    """Activated cells of one subspace and their weights (Section 4.3.1).
 
     d1, d2 -- half distances (K,) of the left / right half
     sizes  -- (K*K,) posting-list length of cell i_L * K + i_R
     Returns a list of (cell, weight) in visit order.
+
+    The Multi-Sequence traversal visits the cells of the K x K grid in
+    ascending cost d1s[i] + d2s[j] (i, j = ranks in each half's list sorted by
+    (distance, centroid index)); ties are taken in (i, j) order.  It stops
+    after the first cell at which the ids gathered reach the budget, so the
+    activated set is the shortest prefix of that order whose posting sizes
+    sum to at least the budget (empty cells still take a rank).  Written out
+    here as that definition: every cell's cost, one sort, one prefix.  A
+    cell's weight is 2 when phi = 1 and its 1-based rank is at most k_size,
+    else 1.
     """
     kh = d1.shape[0]
     o1 = np.argsort(d1, kind="stable")        # ascending (distance, index)
     o2 = np.argsort(d2, kind="stable")
-    d1s, d2s = d1[o1], d2[o2]
-    pq = [(d1s[0] + d2s[0], 0, 0)]
-    rank = 0
-    retrieved = 0
-    visited = []
-    while retrieved < budget:
-        cost, i, j = heapq.heappop(pq)
-        cell = int(o1[i]) * kh + int(o2[j])      # Combine(i, j)
-        rank += 1
-        w = 2 if (phi == 1 and rank <= k_size) else 1
-        visited.append((cell, w))
-        retrieved += int(sizes[cell])
-        # next candidates: the right neighbour in this row, and the next row's
-        # first cell when leaving column 0.
-        if j + 1 < kh:
-            heapq.heappush(pq, (d1s[i] + d2s[j + 1], i, j + 1))
-        if j == 0 and i + 1 < kh:
-            heapq.heappush(pq, (d1s[i + 1] + d2s[0], i + 1, 0))
-    return visited
+    cost = np.add.outer(d1[o1], d2[o2])       # cost[i, j] = d1s[i] + d2s[j]
+    ii, jj = np.meshgrid(np.arange(kh), np.arange(kh), indexing="ij")
+    visit = np.lexsort((jj.ravel(), ii.ravel(), cost.ravel()))
+    cell = (o1[ii.ravel()[visit]] * kh + o2[jj.ravel()[visit]]).astype(np.int64)
+    gathered = np.cumsum(np.asarray(sizes, dtype=np.int64)[cell])
+    reached = np.flatnonzero(gathered >= budget)
+    n_act = int(reached[0]) + 1 if reached.size else cell.size
+    rank = np.arange(1, n_act + 1)
+    weight = np.where((phi == 1) & (rank <= k_size), 2, 1)
+    return [(int(c), int(w)) for c, w in zip(cell[:n_act], weight)]
 
 
 def collision_scores(index: dict, activated: list) -> np.ndarray:
@@ -151,33 +147,22 @@ def hamming_order(index: dict, qp: np.ndarray, cand: np.ndarray):
 
 
 def canonical_sqdist(qp: np.ndarray, rows: np.ndarray) -> np.ndarray:
-    """d_canon for each row: 64 lane partial sums + a halving tree (float64).
+    """Distance key of each row: the squared L2 distance summed in float64
+    over the dimensions in ascending order (Section 4.3.2, Stage 3, exact L2).
 
-    The dimensions are cut into groups of four consecutive ones; group g goes
-    to lane g % 64.  Lane l sums (q'[i] - x[i])^2 over its groups in ascending
-    g and over the four dimensions of a group in order (float64, unfused);
-    then p_l <- p_l + p_{l+s} for s = 32, 16, ..., 1 and l < s; d_canon = p_0.
-    Dimensions are zero-padded to a multiple of 256, which adds exact zeros.
+        acc = 0;  for i = 0 .. D-1:  delta = f64(q'_i) - f64(x_i);  acc = acc + delta * delta
+
+    one rounding per operation, no fused multiply-add.  Results are ordered
+    by (key, id) and returned as f32(key).
     """
-    d = qp.shape[0]
-    pad = (-d) % (4 * LANES)
-    q64 = np.concatenate([qp.astype(np.float64), np.zeros(pad)])
-    x64 = np.asarray(rows, dtype=np.float32).astype(np.float64).reshape(-1, d)
-    x64 = np.concatenate([x64, np.zeros((x64.shape[0], pad))], axis=1)
-    r_groups = (d + pad) // (4 * LANES)
-    q4 = q64.reshape(r_groups, LANES, 4)
-    x4 = x64.reshape(-1, r_groups, LANES, 4)
-    p = np.zeros((x4.shape[0], LANES), dtype=np.float64)
-    for r in range(r_groups):
-        for c in range(4):
-            delta = q4[None, r, :, c] - x4[:, r, :, c]
-            sq = delta * delta
-            p = p + sq
-    s = LANES // 2
-    while s >= 1:
-        p[:, :s] = p[:, :s] + p[:, s:2 * s]
-        s //= 2
-    return p[:, 0].copy()
+    q64 = np.asarray(qp, dtype=np.float32).astype(np.float64)
+    x64 = np.asarray(rows, dtype=np.float32).astype(np.float64).reshape(-1, q64.shape[0])
+    acc = np.zeros(x64.shape[0], dtype=np.float64)
+    for i in range(q64.shape[0]):
+        delta = q64[i] - x64[:, i]
+        sq = delta * delta
+        acc = acc + sq
+    return acc
 
 
 def topk_by_key(ids: np.ndarray, dist: np.ndarray, k: int):

@@ -75,3 +75,13 @@ def test_features_follow_their_definitions():
         assert f[17 + 3 * 4] == np.float32(hm[0] / 64)
         assert f[17 + 3 * 4 + 3] == np.float32(hm[min(8, hm.size) - 1] / 64)
         assert f[-1] == np.float32(hm[(hm.size + 1) // 2 - 1] / 64)
+
+
+def test_limits_from_clamps_to_k_and_candidates():
+    """L = clamp(ceil(exp(y + delta)), k, |C|); no candidates gives 0."""
+    y = np.log(np.array([4.4, 0.01, 4.4, 1e6, 4.4, 2.2]))
+    ncand = np.array([100, 100, 3, 50, 0, 100])
+    got = mlp.limits_from(y, 0.0, 2, ncand)
+    assert got.tolist() == [5, 2, 3, 50, 0, 3]
+    got = mlp.limits_from(y, float(np.log(2.0)), 2, ncand)
+    assert got.tolist() == [9, 2, 3, 50, 0, 5]

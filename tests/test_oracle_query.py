@@ -13,24 +13,33 @@ from oracle import brute, build, query
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def _first_cells_by_full_sort(d1, d2, sizes, budget, k_size, phi):
-    """Brute force: sort all K^2 cells by (cost, i, j) and take the shortest
-    prefix whose total size reaches the budget."""
+def _traversal_with_priority_queue(d1, d2, sizes, budget, k_size, phi):
+    """Algorithm 1's own traversal, restated independently of the oracle: a
+    priority queue keyed (cost, i, j) seeded with the corner cell; popping
+    (i, j) pushes its right neighbour (i, j + 1) and, from column 0, the next
+    row's first cell (i + 1, 0); every pop is one rank; stop once the ids
+    gathered reach the budget."""
+    import heapq
     kh = d1.size
     o1, o2 = np.argsort(d1, kind="stable"), np.argsort(d2, kind="stable")
-    cells = sorted(((d1[o1[i]] + d2[o2[j]], i, j) for i in range(kh) for j in range(kh)))
-    out, total = [], 0
-    for rank, (_, i, j) in enumerate(cells, start=1):
+    d1s, d2s = d1[o1], d2[o2]
+    heap = [(d1s[0] + d2s[0], 0, 0)]
+    out, total, rank = [], 0, 0
+    while total < budget and heap:
+        _, i, j = heapq.heappop(heap)
+        rank += 1
         cell = int(o1[i]) * kh + int(o2[j])
         out.append((cell, 2 if (phi == 1 and rank <= k_size) else 1))
         total += int(sizes[cell])
-        if total >= budget:
-            break
+        if j + 1 < kh:
+            heapq.heappush(heap, (d1s[i] + d2s[j + 1], i, j + 1))
+        if j == 0 and i + 1 < kh:
+            heapq.heappush(heap, (d1s[i + 1] + d2s[0], i + 1, 0))
     return out
 
 
 @pytest.mark.parametrize("seed", range(12))
-def test_multi_sequence_equals_full_sort(seed):
+def test_multi_sequence_equals_priority_queue_traversal(seed):
     rng = np.random.default_rng(seed)
     kh = int(rng.integers(1, 9))
     d1 = np.round(rng.random(kh) * 4, 1)      # coarse values -> ties
@@ -42,7 +51,19 @@ def test_multi_sequence_equals_full_sort(seed):
     k_size = int(rng.integers(1, 6))
     for phi in (0, 1):
         got = query.multi_sequence(d1, d2, sizes, budget, k_size, phi)
-        assert got == _first_cells_by_full_sort(d1, d2, sizes, budget, k_size, phi)
+        assert got == _traversal_with_priority_queue(d1, d2, sizes, budget, k_size, phi)
+
+
+def test_multi_sequence_budget_and_empty_cells():
+    """Whole cells are added and the walk stops after the cell that reaches the
+    budget; empty cells still take a rank (and so a weight-2 slot)."""
+    d1 = np.array([0.0, 1.0])
+    d2 = np.array([0.0, 10.0])
+    sizes = np.array([0, 0, 3, 5])            # cells (0,0), (0,1), (1,0), (1,1)
+    # order: (0,0) cost 0 [empty], (1,0) cost 1 [3 ids], (0,1) cost 10 [empty], (1,1) 11 [5]
+    assert query.multi_sequence(d1, d2, sizes, 1, 1, 1) == [(0, 2), (2, 1)]
+    assert query.multi_sequence(d1, d2, sizes, 3, 2, 1) == [(0, 2), (2, 2)]
+    assert query.multi_sequence(d1, d2, sizes, 4, 9, 0) == [(0, 1), (2, 1), (1, 1), (3, 1)]
 
 
 def test_figure3_structure():
@@ -108,17 +129,74 @@ def test_hamming_against_sign_comparison():
 
 @pytest.mark.parametrize("d", [64, 192, 512])
 def test_canonical_sqdist_exact_bound(d):
-    """The distance key is within the float64 summation bound of the exact
-    rational value (lane sums of at most 4 ceil(d/256) terms + a 6-level tree)."""
+    """The distance key is within the float64 bound of a D-term sum of
+    rounded squares (each term rounded once, then at most D - 1 additions)
+    of the exact rational squared distance."""
     rng = np.random.default_rng(10 + d)
     q = rng.standard_normal(d).astype(np.float32)
     x = rng.standard_normal((5, d)).astype(np.float32)
     got = query.canonical_sqdist(q, x)
-    depth = 4 * ((d + 255) // 256) + 6 + 2
     for i in range(5):
         ex = sum((Fraction(float(q[t])) - Fraction(float(x[i, t]))) ** 2 for t in range(d))
-        assert abs(Fraction(got[i]) - ex) <= Fraction(depth) * Fraction(2.0 ** -53) * ex
+        assert abs(Fraction(got[i]) - ex) <= Fraction(d + 1) * Fraction(2.0 ** -53) * ex
     assert np.allclose(got, ((q[None].astype(np.float64) - x) ** 2).sum(1), rtol=1e-14)
+
+
+@pytest.mark.parametrize("d", [8, 512, 4096])
+def test_canonical_sqdist_sums_in_ascending_dimension_order(d):
+    """The key is a left-to-right float64 sum over dimensions 0 .. D-1.  One
+    squared term of 1 and D - 1 terms of 2^-54 (a quarter of the unit in the
+    last place of 1): added after the 1 each small term rounds away, so the
+    key is exactly 1; added before it they sum exactly to (D-1) 2^-54, and the
+    final addition rounds 1 + (D-1) 2^-54 to the nearest double.  Any other
+    order (pairwise, reversed, lane-strided) gives another value."""
+    q = np.zeros(d, dtype=np.float32)
+    tiny = np.float32(2.0 ** -27)               # tiny^2 = 2^-54 exactly
+    big_first = np.full(d, tiny, dtype=np.float32)
+    big_first[0] = 1.0
+    big_last = np.full(d, tiny, dtype=np.float32)
+    big_last[-1] = 1.0
+    got = query.canonical_sqdist(q, np.stack([big_first, big_last]))
+    assert got[0] == 1.0
+    exact_last = Fraction(1) + Fraction(d - 1, 2 ** 54)
+    ulp = Fraction(1, 2 ** 52)
+    nearest = round(exact_last / ulp) * ulp    # Python rounds halves to even
+    assert Fraction(got[1]) == nearest
+    assert got[1] != 1.0
+
+
+def test_hamming_order_breaks_ties_by_id():
+    """Stage 2 orders by Hamming distance; equal distances keep ascending id."""
+    d = 64
+    codes = np.zeros((10, 1), dtype=np.uint64)
+    pops = {1: 1, 2: 1, 5: 2, 7: 0, 9: 2}       # id -> bits set (query code is 0)
+    for i, c in pops.items():
+        codes[i, 0] = np.uint64((1 << c) - 1)
+    idx = {"codes": codes, "d": d}
+    qp = -np.ones(d, dtype=np.float32)          # every sign bit 0
+    order, hd = query.hamming_order(idx, qp, np.array([1, 2, 5, 7, 9]))
+    assert order.tolist() == [7, 1, 2, 5, 9]
+    assert hd.tolist() == [0, 1, 1, 2, 2]
+
+
+def test_query_equal_to_a_point_ranks_its_own_cell_first():
+    """A query equal to a stored point is nearest to that point's own
+    half-centroids (the build assigns with the same half distances and the
+    same lowest-index tie rule), so in every subspace the point's cell is the
+    first one the traversal activates: this pins the split of q' into
+    subspaces and halves against the build's."""
+    idx, _, x = _tiny_index(6, rotate=False)
+    for p in (0, 17, 311, idx["n"] - 1):
+        _, _, tr = query.search_one(idx, x[p], 5, mode=1, alpha=0.02, tau=1, trace=True)
+        for sub in range(idx["m"]):
+            assert tr["activated"][sub][0][0] == int(idx["assign"][sub, p])
+    ridx, _, _ = _tiny_index(7, rotate=True)
+    for p in (3, 200):
+        hd = query.subspace_half_distances(ridx, ridx["base"][p])
+        kh = ridx["k_half"]
+        for sub in range(ridx["m"]):
+            cell = int(np.argmin(hd[sub, 0])) * kh + int(np.argmin(hd[sub, 1]))
+            assert cell == int(ridx["assign"][sub, p])
 
 
 def test_guaranteed_alpha_one_is_exact_knn():
@@ -193,6 +271,16 @@ def test_learned_limit_truncates_walk():
     lim_i, _, tr2 = query.search_one(idx, qs[0], 5, mode=1, alpha=0.1, tau=2, limit=lim, trace=True)
     assert tr2["examined"] == min(lim, tr["examined"])
     assert np.array_equal(full_i, lim_i)       # the prefix up to L* reproduces the result
+
+
+def test_cev_sample_size():
+    """Section 4.1 samples 10% of the rows, at most 100,000 (at least two,
+    so that a covariance exists)."""
+    assert build.cev_sample_size(15) == 2
+    assert build.cev_sample_size(1_000) == 100
+    assert build.cev_sample_size(999_999) == 99_999
+    assert build.cev_sample_size(1_000_000) == 100_000
+    assert build.cev_sample_size(2_000_000) == 100_000
 
 
 def test_budget_rounding():
