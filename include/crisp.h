@@ -42,13 +42,13 @@
  * * Cell order inside a subspace (Section 4.3.1, Multi-Sequence traversal):
  *   ascending (d1s[i] + d2s[j], i, j) with i, j the ranks of the left / right
  *   centroids in their half's (distance, index) order; cell id = iL * K + iR.
- * * Distance key (Section 4.3.2, Stage 3, exact L2): d_canon in float64.
- *   Dimensions are cut into groups of four; group g goes to lane g % 64;
- *   lane l sums (q'_i - x_i)^2 over its groups in ascending g, the four
- *   dimensions of a group in order (unfused); then p_l += p_{l+s} for
- *   s = 32, 16, ..., 1 and d_canon = p_0.  Results are ordered by
- *   (d_canon, id); returned distances are f32(d_canon).  Every verified
- *   candidate's key is computed exactly so.
+ * * Distance key (Section 4.3.2, Stage 3, exact L2): the squared L2
+ *   distance summed in float64 over the dimensions in ascending order,
+ *   acc = acc + (f64(q'_i) - f64(x_i))^2, unfused.  Results are ordered by
+ *   (key, id); returned distances are f32(key).  The kernels add the same
+ *   terms lane-parallel and use that value only where its rounding
+ *   interval decides a comparison or the float32 result; elsewhere they
+ *   compute the key by the definition.
  */
 #ifndef CRISP_H_
 #define CRISP_H_
@@ -248,8 +248,8 @@ crisp_status crisp_search_workspace_bytes(const crisp_index *index, int64_t nq, 
 /*
  * Algorithm 1 for a batch of queries.
  *   queries -- device float32 [nq][D] (original, unrotated space)
- *   ids     -- device int64 [nq][k], ascending (d_canon, id); -1 padding
- *   dists   -- device float32 [nq][k], f32(d_canon) squared L2; +inf padding
+ *   ids     -- device int64 [nq][k], ascending (key, id); -1 padding
+ *   dists   -- device float32 [nq][k], f32(key) squared L2; +inf padding
  *   workspace -- device, >= crisp_search_workspace_bytes(...)
  *   taps    -- NULL, or stage outputs to fill (see crisp_taps)
  * Padding occurs only when fewer than k points collide at all.

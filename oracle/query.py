@@ -166,7 +166,7 @@ def canonical_sqdist(qp: np.ndarray, rows: np.ndarray) -> np.ndarray:
 
 
 def topk_by_key(ids: np.ndarray, dist: np.ndarray, k: int):
-    """Top-k by ascending (d_canon, id), padded with (-1, +inf)."""
+    """Top-k by ascending (key, id), padded with (-1, +inf)."""
     order = np.lexsort((ids, dist))[:k]
     out_i = np.full(k, -1, dtype=np.int64)
     out_d = np.full(k, np.inf, dtype=np.float32)

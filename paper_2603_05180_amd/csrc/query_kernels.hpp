@@ -1347,15 +1347,26 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_place(
 // ---------------------------------------------------------------------------
 // A6/A7: re-rank.  One block (4 waves) per query; q' staged in LDS.
 //
-// Every verified row gets its exact float64 key d_canon, computed as defined
-// (4-element groups dealt round-robin to the 64 lanes, each lane summing its
-// groups in order, then a halving tree), one wavefront per row with up to 16
-// sixteen-byte loads in flight per lane.  The
-// extra float64 arithmetic is far below the row's HBM time on MI355X, and it
-// leaves no approximate comparison anywhere: Guaranteed Mode selects the
-// top-k of all candidate keys (radix select on the key bits, ties by id);
-// Optimized Mode walks the Hamming order chunk by chunk, computing a chunk's
-// keys in parallel and applying the patience rule to them in order.
+// The distance key of a row is the squared L2 distance summed in float64
+// over the dimensions in ascending order, one rounding per operation
+// (Section 4.3.2, Stage 3: exact L2).  A wavefront computes the same D terms
+// t_i = (q'_i - x_i)^2 but adds them lane-parallel (lane l sums the 4-element
+// groups l, l + 64, ... in order, then a halving tree), with up to 16
+// sixteen-byte loads in flight per lane.  Every t_i >= 0, so any summation
+// tree of depth h <= D is within gamma_D = D u / (1 - D u) (u = 2^-53) of the
+// exact sum T of the terms (the standard bound for recursive and pairwise
+// summation of non-negative terms), both the wave's value p and the defined
+// key s lie within gamma_D T of T, and |p - s| <= 2 gamma_D T / (1 - gamma_D)
+// p.  The key is therefore known to lie in the interval [p (1 - c), p (1 + c)]
+// with c = (2D + 16) u (which also covers the rounding of the two products).
+// Decisions are taken on the intervals: a comparison whose intervals overlap,
+// or a returned float32 value that the interval does not fix (f32 of its two
+// ends differ), is decided on s itself, computed by the definition
+// (row_dist_seq, one thread, ascending i).  Guaranteed Mode selects the
+// top-k of all candidate keys (radix select on the key bits, the band around
+// the k-th key made exact when it is ambiguous, ties by id); Optimized Mode
+// walks the Hamming order chunk by chunk, computing a chunk's keys in
+// parallel and applying the patience rule to them in order.
 // ---------------------------------------------------------------------------
 constexpr int kRerankThreads = 256;
 constexpr int kRerankWaves = kRerankThreads / kWave;
@@ -1390,8 +1401,8 @@ __device__ __forceinline__ double canon_partial(const float4 *__restrict__ qq, c
   return p;
 }
 
-// d_canon of one row, whole wave; result in every lane.  Lane l owns the
-// 4-element groups g = l, l + 64, ... (one 16-byte load each, all of a batch
+// Wave key p of one row (the key's terms added lane-parallel), whole wave;
+// result in every lane.  Lane l owns the 4-element groups g = l, l + 64, ... (one 16-byte load each, all of a batch
 // issued before use); groups past the end contribute exact zeros.
 // kWide = false keeps at most 4 loads in flight per lane (fewer registers,
 // for kernels that read few rows this way).
@@ -1414,8 +1425,45 @@ __device__ __forceinline__ bool key_less(double da, int ia, double db, int ib) {
   return da < db || (da == db && ia < ib);
 }
 
+// Relative half-width c of the interval around a wave key (see above).
+__host__ __device__ inline double key_band(int d) { return (2.0 * d + 16.0) * 0x1p-53; }
+__device__ __forceinline__ double key_lo(double p, double c) { return p * (1.0 - c); }
+__device__ __forceinline__ double key_hi(double p, double c) { return p * (1.0 + c); }
+
+// The defined key of one row: ascending i, acc = acc + (q'_i - x_i)^2 in
+// float64, one thread.  Used only where a wave key's interval cannot decide.
+__device__ inline double row_dist_seq(const float *__restrict__ sq, const float *__restrict__ x, int d) {
+  const float4 *qq = reinterpret_cast<const float4 *>(sq);
+  const float4 *xr = reinterpret_cast<const float4 *>(x);
+  double acc = 0.0;
+  for (int g = 0; g < (d >> 2); ++g) {
+    const float4 xv = xr[g];
+    const float4 qv = qq[g];
+    const double t0 = static_cast<double>(qv.x) - static_cast<double>(xv.x);
+    const double s0 = t0 * t0;
+    acc = acc + s0;
+    const double t1 = static_cast<double>(qv.y) - static_cast<double>(xv.y);
+    const double s1 = t1 * t1;
+    acc = acc + s1;
+    const double t2 = static_cast<double>(qv.z) - static_cast<double>(xv.z);
+    const double s2 = t2 * t2;
+    acc = acc + s2;
+    const double t3 = static_cast<double>(qv.w) - static_cast<double>(xv.w);
+    const double s3 = t3 * t3;
+    acc = acc + s3;
+  }
+  return acc;
+}
+
+// True when the float32 rounding of every value in the key's interval is
+// the same (then it is f32 of the defined key).
+__device__ __forceinline__ bool f32_fixed(double p, double c) {
+  return static_cast<float>(key_lo(p, c)) == static_cast<float>(key_hi(p, c));
+}
+
 struct RerankShared {
   double dk[kChunk];
+  int dx[kChunk];  // dk[t] is the defined key (1) or a wave key (0)
   int sid[kChunk];
   float serr[kChunk];
   int plist[kChunk];
@@ -1423,7 +1471,6 @@ struct RerankShared {
   int misc[16];
   unsigned long long umisc[2];
   double bd;
-  int bid;
 };
 
 // ---------------------------------------------------------------------------
@@ -1436,12 +1483,14 @@ struct RerankShared {
 // g = gamma_{L+10} = (L+10)u / (1 - (L+10)u), u = 2^-24.  The triangle
 // inequality then gives
 //     (sqrt(t (1 - g)) - e_x)_+^2  <=  ||q' - x||^2  <=  (sqrt(t (1 + 2g)) + e_x)^2.
-// d_canon is within a relative 2^-45 of ||q' - x||^2 for D <= 8192; both
-// bounds are widened by a relative 2^-36 (that, plus the float64 rounding of
-// the bound) and an absolute 2^-100 (float32 subnormals flushed to zero), so
-// lb <= d_canon <= ub holds for every row.  A row is read in float32 only if
-// its lower bound does not exclude it; all comparisons that decide a result
-// use d_canon, so the results equal the float32-only path bit for bit.
+// The defined key and the wave key are both within a relative (D + 4) 2^-53
+// (< 2^-39.9 for D <= 8192) of ||q' - x||^2; both bounds are widened by a
+// relative 2^-36 (that, plus the float64 rounding of the bound) and an
+// absolute 2^-100 (float32 subnormals flushed to zero), so lb <= key <= ub
+// holds for every row.  A row is read in float32 only if its lower bound
+// does not exclude it; every comparison that decides a result is taken on
+// the float32 row's key, so the results equal the float32-only path bit for
+// bit.
 // ---------------------------------------------------------------------------
 constexpr double kBoundRel = 1.0 / 68719476736.0;          // 2^-36
 constexpr double kBoundAbs = 7.888609052210118e-31;         // 2^-100
@@ -1536,16 +1585,17 @@ __global__ void __launch_bounds__(256) k_base_bf16(const float *__restrict__ bas
 }
 
 // Dynamic LDS of k_rerank: q' (D floats) | top-k keys (k doubles) | top-k ids
-// (k ints) | [bfloat16 pass] lower / upper bounds and certification flags
-// of a chunk.
+// (k ints) | top-k exactness flags (k ints) | [bfloat16 pass] lower / upper
+// bounds and certification flags of a chunk.
 struct RerankLds {
-  size_t top_d, top_i, lb, ub, pc, total;
+  size_t top_d, top_i, top_x, lb, ub, pc, total;
 };
 __host__ __device__ inline RerankLds rerank_lds(int d, int k, bool bf16) {
   RerankLds L{};
   size_t o = static_cast<size_t>(d) * 4;
   L.top_d = o; o += static_cast<size_t>(k) * 8;
   L.top_i = o; o += static_cast<size_t>(k) * 4;
+  L.top_x = o; o += static_cast<size_t>(k) * 4;
   o = (o + 15) & ~static_cast<size_t>(15);
   if (bf16) {
     L.lb = o; o += kChunk * 8;
@@ -1556,12 +1606,16 @@ __host__ __device__ inline RerankLds rerank_lds(int d, int k, bool bf16) {
   return L;
 }
 
-// kk-th smallest (1-based, kk <= n) of n non-negative doubles: radix select
-// over the bit pattern, 8 bits per round.  Whole block.  Returns the value
-// and, in *need_eq, how many entries equal to it are among the kk smallest.
-__device__ inline double radix_kth(const double *__restrict__ keys, int n, int kk, RerankShared &S, int *need_eq) {
+// kk-th smallest (1-based, kk <= n) by bit pattern of the n doubles whose
+// bits under `mask0` equal `prefix0` (all of them when both are 0; the
+// candidates must be non-negative, or all carry the sign bit, which then
+// orders them by magnitude): radix select, 8 bits per round.  Whole block.
+// Returns the value and, in *need_eq, how many entries equal to it are among
+// the kk smallest.
+__device__ inline double radix_kth(const double *__restrict__ keys, int n, int kk, RerankShared &S, int *need_eq,
+                                   unsigned long long prefix0 = 0ull, unsigned long long mask0 = 0ull) {
   const int tid = threadIdx.x;
-  unsigned long long prefix = 0ull, mask = 0ull;
+  unsigned long long prefix = prefix0, mask = mask0;
   for (int shift = 56; shift >= 0; shift -= 8) {
     for (int b = tid; b < 256; b += kRerankThreads) S.hist[b] = 0;
     __syncthreads();
@@ -1576,7 +1630,7 @@ __device__ inline double radix_kth(const double *__restrict__ keys, int n, int k
         if (cum + S.hist[b] >= kk) break;
         cum += S.hist[b];
       }
-      S.umisc[0] = prefix | (static_cast<unsigned long long>(b) << shift);
+      S.umisc[0] = (prefix & ~(255ull << shift)) | (static_cast<unsigned long long>(b) << shift);
       S.misc[0] = kk - cum;
     }
     __syncthreads();
@@ -1589,43 +1643,56 @@ __device__ inline double radix_kth(const double *__restrict__ keys, int n, int k
   return from_dbits(prefix);
 }
 
-// Top-k by (key, id) of n keys whose ids are ascending in list order; writes
-// the k results (padded with id -1 / +inf).  Whole block.
-__device__ inline void select_topk(const double *__restrict__ keys, const int32_t *__restrict__ kid, int n, int k,
-                                   RerankShared &S, double *top_d, int *top_i, int64_t *__restrict__ oi,
-                                   float *__restrict__ od) {
-  const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
-  double vk = 0.0;
-  int need_eq = 0;
-  if (n > k) vk = radix_kth(keys, n, k, S, &need_eq);
-  // Keys below the k-th value, then the first need_eq ids equal to it.
-  if (tid == 0) { S.misc[1] = 0; S.misc[2] = 0; }
+// Block-wide sum of one int per thread (every thread gets the total).
+__device__ inline int block_sum_i32(int v, RerankShared &S) {
+  v = wave_sum_i32(v);
   __syncthreads();
-  for (int i0 = 0; i0 < n; i0 += kRerankThreads) {
-    const int i = i0 + tid;
-    const double di = (i < n) ? keys[i] : 0.0;
-    const bool lt = (i < n) && (n <= k || di < vk);
-    const bool eq = (i < n) && (n > k) && (di == vk);
-    const unsigned long long bm = __ballot(eq);
-    const int eq_before = __popcll(bm & lanes_below_mask());
-    if (lane == kWave - 1) S.hist[wv] = __popcll(bm);
-    __syncthreads();
-    int wbase = 0;
-    for (int w = 0; w < wv; ++w) wbase += S.hist[w];
-    int eq_total_block = 0;
-    for (int w = 0; w < kRerankWaves; ++w) eq_total_block += S.hist[w];
-    const int eq_seen = S.misc[2];
-    __syncthreads();
-    if (lt || (eq && eq_seen + wbase + eq_before < need_eq)) {
-      const int p = atomicAdd(&S.misc[1], 1);
-      top_d[p] = di;
-      top_i[p] = kid[i];
+  if (lane_id() == 0) S.hist[wave_id()] = v;
+  __syncthreads();
+  int t = 0;
+  for (int w = 0; w < kRerankWaves; ++w) t += S.hist[w];
+  __syncthreads();
+  return t;
+}
+
+constexpr unsigned long long kSignBit = 0x8000000000000000ull;
+
+// Sorts the ns (<= k) rows held in top_d / top_i / top_x by (key, id) and
+// writes them (padded with id -1 / +inf to k).  A wave key (top_x = 0) is
+// made exact when its interval overlaps another row's or does not fix its
+// float32 value; one round suffices, since making a key exact only shrinks
+// its interval.  Whole block.
+__device__ inline void write_topk(int ns, int k, double c, const float *sq, const float *__restrict__ base, int d,
+                                  double *top_d, int *top_i, int *top_x, int64_t *__restrict__ oi,
+                                  float *__restrict__ od) {
+  const int tid = threadIdx.x;
+  bool amb[(1024 + kRerankThreads - 1) / kRerankThreads];
+#pragma unroll
+  for (int u = 0; u < (1024 + kRerankThreads - 1) / kRerankThreads; ++u) {
+    const int j = tid + u * kRerankThreads;
+    amb[u] = false;
+    if (j < ns && !top_x[j]) {
+      const double p = top_d[j], lo = key_lo(p, c), hi = key_hi(p, c);
+      bool a = !f32_fixed(p, c);
+      for (int t = 0; t < ns && !a; ++t) {
+        if (t == j) continue;
+        const double pt = top_d[t];
+        const double lt = top_x[t] ? pt : key_lo(pt, c), ht = top_x[t] ? pt : key_hi(pt, c);
+        a = lt <= hi && lo <= ht;
+      }
+      amb[u] = a;
     }
-    __syncthreads();
-    if (tid == 0) S.misc[2] = eq_seen + eq_total_block;
-    __syncthreads();
   }
-  const int ns = S.misc[1];
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < (1024 + kRerankThreads - 1) / kRerankThreads; ++u) {
+    const int j = tid + u * kRerankThreads;
+    if (amb[u]) {
+      top_d[j] = row_dist_seq(sq, base + static_cast<long long>(top_i[j]) * d, d);
+      top_x[j] = 1;
+    }
+  }
+  __syncthreads();
   for (int j = tid; j < ns; j += kRerankThreads) {
     const double dj = top_d[j];
     const int ij = top_i[j];
@@ -1638,6 +1705,89 @@ __device__ inline void select_topk(const double *__restrict__ keys, const int32_
     oi[r] = -1;
     od[r] = __int_as_float(0x7f800000);
   }
+}
+
+// Top-k by (key, id) of n rows with wave keys, whose ids are ascending in
+// list order; writes the k results (padded with id -1 / +inf).  Whole block.
+// With v the k-th smallest wave key, a row whose interval lies wholly below
+// v's interval is below the k-th defined key (set A, all taken), a row whose
+// interval lies wholly above it is not in the top-k, and the band between
+// holds every other row of the top-k.  When the band holds exactly the
+// k - |A| rows still needed, all of them are taken; otherwise the band's
+// keys are made exact (stored negated in `keys`, so the sign marks the band:
+// a band key is 0 only when no row is in A) and its k - |A| smallest by
+// (key, id) are taken.
+__device__ inline void select_topk(double *__restrict__ keys, const int32_t *__restrict__ kid, int n, int k,
+                                   double c, const float *sq, const float *__restrict__ base, int d,
+                                   RerankShared &S, double *top_d, int *top_i, int *top_x,
+                                   int64_t *__restrict__ oi, float *__restrict__ od) {
+  const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
+  double vlo = 0.0, vhi = 0.0;
+  bool exact_band = false;
+  int need = 0, need_eq = 0;
+  unsigned long long vb = 0ull;
+  if (n > k) {
+    int unused;
+    const double vk = radix_kth(keys, n, k, S, &unused);
+    vlo = key_lo(vk, c);
+    vhi = key_hi(vk, c);
+    int na = 0, nb = 0;
+    for (int i = tid; i < n; i += kRerankThreads) {
+      const double p = keys[i];
+      if (key_hi(p, c) < vlo) ++na;
+      else if (key_lo(p, c) <= vhi) ++nb;
+    }
+    na = block_sum_i32(na, S);
+    nb = block_sum_i32(nb, S);
+    if (na + nb > k) {
+      exact_band = true;
+      need = k - na;
+      for (int i = tid; i < n; i += kRerankThreads) {
+        const double p = keys[i];
+        if (!(key_hi(p, c) < vlo) && key_lo(p, c) <= vhi)
+          keys[i] = -row_dist_seq(sq, base + static_cast<long long>(kid[i]) * d, d);
+      }
+      __syncthreads();
+      vb = dbits(radix_kth(keys, n, need, S, &need_eq, kSignBit, kSignBit));
+    }
+  }
+  // Rows taken: all (n <= k); A and the band; or A, band keys below vb and
+  // the first need_eq band keys equal to it in list order.
+  if (tid == 0) { S.misc[1] = 0; S.misc[2] = 0; }
+  __syncthreads();
+  for (int i0 = 0; i0 < n; i0 += kRerankThreads) {
+    const int i = i0 + tid;
+    const double di = (i < n) ? keys[i] : 0.0;
+    const unsigned long long bi = dbits(di);
+    const bool band_x = exact_band && (bi & kSignBit) != 0;
+    bool take = false, eq = false;
+    if (i < n) {
+      if (n <= k) take = true;
+      else if (!band_x) take = key_hi(di, c) < vlo || (!exact_band && key_lo(di, c) <= vhi);
+      else if (bi < vb) take = true;
+      else eq = bi == vb;
+    }
+    const unsigned long long bm = __ballot(eq);
+    const int eq_before = __popcll(bm & lanes_below_mask());
+    if (lane == kWave - 1) S.hist[wv] = __popcll(bm);
+    __syncthreads();
+    int wbase = 0;
+    for (int w = 0; w < wv; ++w) wbase += S.hist[w];
+    int eq_total_block = 0;
+    for (int w = 0; w < kRerankWaves; ++w) eq_total_block += S.hist[w];
+    const int eq_seen = S.misc[2];
+    __syncthreads();
+    if (take || (eq && eq_seen + wbase + eq_before < need_eq)) {
+      const int p = atomicAdd(&S.misc[1], 1);
+      top_d[p] = band_x ? -di : di;
+      top_i[p] = kid[i];
+      top_x[p] = band_x ? 1 : 0;
+    }
+    __syncthreads();
+    if (tid == 0) S.misc[2] = eq_seen + eq_total_block;
+    __syncthreads();
+  }
+  write_topk(S.misc[1], k, c, sq, base, d, top_d, top_i, top_x, oi, od);
 }
 
 // kMode: 0 Guaranteed, 1 Optimized.  kBf16 = false: every verified row read
@@ -1662,12 +1812,14 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
   float *sq = reinterpret_cast<float *>(dyn);
   double *top_d = reinterpret_cast<double *>(dyn + LL.top_d);
   int *top_i = reinterpret_cast<int *>(dyn + LL.top_i);
+  int *top_x = reinterpret_cast<int *>(dyn + LL.top_x);
   double *xlb = reinterpret_cast<double *>(dyn + LL.lb);
   double *xub = reinterpret_cast<double *>(dyn + LL.ub);
   int *xpc = reinterpret_cast<int *>(dyn + LL.pc);
   __shared__ RerankShared S;
   const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   const long long qo = static_cast<long long>(q) * n;
+  const double cb = key_band(d);
   for (int i = tid; i < d; i += kRerankThreads) sq[i] = qrot[static_cast<long long>(q) * d + i];
   const int nc = ncand[q];
   __syncthreads();
@@ -1735,7 +1887,7 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
       }
     }
     __syncthreads();
-    select_topk(dkey + qo, kid, nk, k, S, top_d, top_i, oi, od);
+    select_topk(dkey + qo, kid, nk, k, cb, sq, base, d, S, top_d, top_i, top_x, oi, od);
     if (tid == 0) {
       examined[q] = nc;
       last_upd[q] = 0;
@@ -1798,7 +1950,7 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
           if (t < cnt) {
             const double lb = xlb[t];
             int c = 0;
-            for (int e = 0; e < tn0 && c < k; ++e) c += top_d[e] < lb ? 1 : 0;
+            for (int e = 0; e < tn0 && c < k; ++e) c += key_hi(top_d[e], cb) < lb ? 1 : 0;
             for (int j = 0; j < t && c < k; ++j) c += xub[j] < lb ? 1 : 0;
             cert = c < k;
             xpc[t] = cert ? 1 : 0;
@@ -1820,13 +1972,13 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
         for (int e = wv; e < np; e += kRerankWaves) {
           const int t = S.plist[e];
           const double dc = row_dist_canon<false>(sq, base + static_cast<long long>(S.sid[t]) * d, d);
-          if (lane == 0) S.dk[t] = dc;
+          if (lane == 0) { S.dk[t] = dc; S.dx[t] = 0; }
         }
       } else {
         // (a) exact keys of the chunk, in parallel
         for (int t = wv; t < cnt; t += kRerankWaves) {
           const double dc = row_dist_canon(sq, base + static_cast<long long>(S.sid[t]) * d, d);
-          if (lane == 0) S.dk[t] = dc;
+          if (lane == 0) { S.dk[t] = dc; S.dx[t] = 0; }
         }
       }
       __syncthreads();
@@ -1834,16 +1986,16 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
       // below its k-th key at the chunk start; while it fills, the first `free`
       // candidates always update and later ones only below the k-th key of
       // (top-k so far + those `free`), which bounds the k-th key from then on.
+      // Taken on the intervals: a row whose lower end exceeds the upper end of
+      // that bound cannot update; the rest are decided in (c).
       if (tid == 0) {
         if (tn0 >= k) {
-          S.bd = top_d[k - 1]; S.bid = top_i[k - 1];
+          S.bd = key_hi(top_d[k - 1], cb);
         } else if (cnt > free_slots) {
-          double bd = -1.0; int bid = -1;
-          for (int e = 0; e < tn0; ++e)
-            if (!key_less(top_d[e], top_i[e], bd, bid)) { bd = top_d[e]; bid = top_i[e]; }
-          for (int e = 0; e < free_slots; ++e)
-            if (!key_less(S.dk[e], S.sid[e], bd, bid)) { bd = S.dk[e]; bid = S.sid[e]; }
-          S.bd = bd; S.bid = bid;
+          double bd = 0.0;
+          for (int e = 0; e < tn0; ++e) bd = fmax(bd, key_hi(top_d[e], cb));
+          for (int e = 0; e < free_slots; ++e) bd = fmax(bd, key_hi(S.dk[e], cb));
+          S.bd = bd;
         }
       }
       __syncthreads();
@@ -1851,7 +2003,7 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
         const int t = tid;
         bool pot = t < cnt;
         if constexpr (kBf16) pot = pot && xpc[t] != 0;
-        pot = pot && (t < free_slots || key_less(S.dk[t], S.sid[t], S.bd, S.bid));
+        pot = pot && (t < free_slots || key_lo(S.dk[t], cb) <= S.bd);
         const unsigned long long bm = __ballot(pot);
         if (lane == 0) S.hist[wv] = __popcll(bm);
         __syncthreads();
@@ -1866,8 +2018,28 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
       }
       __syncthreads();
       // (c) the patience rule in order over those candidates; every candidate
-      // between two of them is a non-update and only advances the run.
+      // between two of them is a non-update and only advances the run.  A
+      // comparison whose intervals overlap is taken on the defined keys.
       if (tid == 0) {
+        // (key, id) of chunk row t before top-k entry e
+        auto before_top = [&](int t, int e) -> bool {
+          if (!(S.dx[t] && top_x[e])) {
+            const double a = S.dk[t], b = top_d[e];
+            const double alo = S.dx[t] ? a : key_lo(a, cb), ahi = S.dx[t] ? a : key_hi(a, cb);
+            const double blo = top_x[e] ? b : key_lo(b, cb), bhi = top_x[e] ? b : key_hi(b, cb);
+            if (ahi < blo) return true;
+            if (bhi < alo) return false;
+            if (!S.dx[t]) {
+              S.dk[t] = row_dist_seq(sq, base + static_cast<long long>(S.sid[t]) * d, d);
+              S.dx[t] = 1;
+            }
+            if (!top_x[e]) {
+              top_d[e] = row_dist_seq(sq, base + static_cast<long long>(top_i[e]) * d, d);
+              top_x[e] = 1;
+            }
+          }
+          return key_less(S.dk[t], S.sid[t], top_d[e], top_i[e]);
+        };
         int tn = S.misc[2], run = S.misc[3], last = S.misc[4], stop = 0, pos = c0 + cnt, prev = -1;
         const int np = S.misc[7];
         for (int e = 0; e <= np; ++e) {
@@ -1880,17 +2052,17 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
           }
           run += gap;
           if (e == np) break;
-          const int id = S.sid[t];
-          const double dc = S.dk[t];
-          if (tn < k || key_less(dc, id, top_d[k - 1], top_i[k - 1])) {
+          if (tn < k || before_top(t, k - 1)) {
             int p = (tn < k) ? tn : k - 1;
-            while (p > 0 && key_less(dc, id, top_d[p - 1], top_i[p - 1])) {
+            while (p > 0 && before_top(t, p - 1)) {
               top_d[p] = top_d[p - 1];
               top_i[p] = top_i[p - 1];
+              top_x[p] = top_x[p - 1];
               --p;
             }
-            top_d[p] = dc;
-            top_i[p] = id;
+            top_d[p] = S.dk[t];
+            top_i[p] = S.sid[t];
+            top_x[p] = S.dx[t];
             if (tn < k) ++tn;
             run = 0;
             last = c0 + t + 1;
@@ -1914,11 +2086,8 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
       if (S.misc[5]) break;
     }
     __syncthreads();
-    const int tn = S.misc[2];
-    for (int r = tid; r < k; r += kRerankThreads) {
-      if (r < tn) { oi[r] = top_i[r]; od[r] = static_cast<float>(top_d[r]); }
-      else { oi[r] = -1; od[r] = __int_as_float(0x7f800000); }
-    }
+    // The top-k is in (key, id) order; write_topk fixes the float32 values.
+    write_topk(S.misc[2], k, cb, sq, base, d, top_d, top_i, top_x, oi, od);
     if (tid == 0) {
       examined[q] = S.misc[6];
       last_upd[q] = S.misc[4];

@@ -79,3 +79,27 @@ def compare(idx, q, k, *, mode, alpha, tau, patience_factor=40, limits=None, gpu
     assert np.array_equal(gi, oi), "ids"
     assert np.array_equal(gd.view(np.uint32), od.view(np.uint32)), "dists"
     return {"n_cand": [t["candidates"].size for t in tr], "gpu": g, "taps": tp, "ids": gi, "dists": gd}
+
+
+def key_stress_rows(d: int = 128):
+    """Rows whose distance from the zero query separates the defined key (sum
+    over the dimensions in ascending order) from other summation orders.
+
+    Returns {name: row}: with q = 0 the terms are (x_i)^2.
+      A  -- 1, then d-1 terms of 2^-54: every term after the first is a
+            quarter of an ulp of 1 and is absorbed, so the key is exactly 1;
+            an order that first adds the small terms together gives more.
+      B  -- 1 + 2^-52 exactly (two terms): above A's key, below A's other sums.
+      C  -- 1, 2^-24, then d-2 terms of 2^-54: the key is exactly 1 + 2^-24,
+            the float32 midpoint between 1 and 1 + 2^-23, so its float32 value
+            is 1 (ties to even); the small terms added first round it up.
+    """
+    a = np.full(d, -2.0 ** -27, dtype=np.float32)
+    a[0] = -1.0
+    b = np.zeros(d, dtype=np.float32)
+    b[0] = -1.0
+    b[1] = -2.0 ** -26
+    c = np.full(d, -2.0 ** -27, dtype=np.float32)
+    c[0] = -1.0
+    c[1] = -2.0 ** -12
+    return {"A": a, "B": b, "C": c}

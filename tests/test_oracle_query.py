@@ -288,3 +288,23 @@ def test_budget_rounding():
     assert query.budget_for(0.0101, 1000) == 11
     assert query.budget_for(1e-9, 1000) == 1
     assert query.budget_for(1.0, 77) == 77
+
+
+def test_key_on_rows_where_order_matters():
+    """Closed forms of the defined key on rows built so that summation order
+    changes the result (1 absorbs 2^-54; 1 + 2^-24 is a float32 midpoint)."""
+    from parity_util import key_stress_rows
+    rows = key_stress_rows(128)
+    got = query.canonical_sqdist(np.zeros(128, dtype=np.float32), np.stack([rows["A"], rows["B"], rows["C"]]))
+    assert got[0] == 1.0
+    assert got[1] == 1.0 + 2.0 ** -52
+    assert got[2] == 1.0 + 2.0 ** -24
+    assert np.float32(got[2]) == np.float32(1.0)
+    # The same terms added pairwise (any order that first combines the small
+    # terms) give different values: the rows do separate the orders.
+    terms = np.stack([rows["A"], rows["C"]]).astype(np.float64) ** 2
+    pair = terms.copy()
+    while pair.shape[1] > 1:
+        pair = pair[:, 0::2] + pair[:, 1::2]
+    assert pair[0, 0] > got[1] > got[0]
+    assert np.float32(pair[1, 0]) != np.float32(got[2])
