@@ -261,6 +261,28 @@ crisp_status crisp_search(crisp_index *index, const float *queries, int64_t nq, 
                           void *hip_stream);
 
 /*
+ * crisp_search without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP stream capture, tight serving
+ * loops, hosts that forbid allocation).  The pipeline's scratch is a static
+ * device array of CRISP_STATIC_SCRATCH_BYTES per GPU, which every GPU the
+ * library is loaded on holds until the process ends; its address is taken
+ * once per device when an index is loaded there.  Arguments as for
+ * crisp_search (device pointers, caller-owned); params->overlap is ignored
+ * (one pipeline) and there are no taps.  Queries run in chunks of at most
+ * params->max_chunk (0 = the default), fewer when a chunk's workspace would
+ * not fit the array; CRISP_E_WORKSPACE when even one query's workspace does
+ * not fit (it grows with N: crisp_search_workspace_bytes(index, 1, ...)).
+ * Results equal crisp_search's bit for bit.  Calls on one GPU share the
+ * array: calls that overlap in time on that GPU (other streams, other
+ * threads, other indexes) race and must be serialised by the caller.  Never
+ * calls hipMalloc or hipFree.
+ */
+#define CRISP_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+crisp_status crisp_search_static(crisp_index *index, const float *queries, int64_t nq, int32_t k,
+                                 const crisp_search_params *params, int64_t *ids, float *dists,
+                                 void *hip_stream);
+
+/*
  * Batch executor for uneven batch sizes (serving; each query still runs
  * Algorithm 1 exactly as crisp_search does, with identical results).
  * A plan serves batches of 1..max_batch queries with fixed k and parameters

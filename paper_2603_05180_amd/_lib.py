@@ -72,6 +72,8 @@ _SIGS = {
                                                ctypes.POINTER(c_size_t)]),
     "crisp_search": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, ctypes.POINTER(SearchParams), c_void_p,
                                c_void_p, c_void_p, c_size_t, ctypes.POINTER(Taps), c_void_p]),
+    "crisp_search_static": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, ctypes.POINTER(SearchParams),
+                                      c_void_p, c_void_p, c_void_p]),
     "crisp_plan_bytes": (c_int32, [c_void_p, c_int32, c_int32, ctypes.POINTER(SearchParams),
                                    ctypes.POINTER(c_size_t)]),
     "crisp_plan_create": (c_int32, [c_void_p, c_int32, c_int32, ctypes.POINTER(SearchParams), c_void_p, c_size_t,
@@ -107,6 +109,9 @@ for _name, (_res, _args) in _SIGS.items():
     _fn.argtypes = _args
 
 EXPORTED = sorted(_SIGS)
+
+# CRISP_STATIC_SCRATCH_BYTES of crisp.h: the static scratch of crisp_search_static
+STATIC_SCRATCH_BYTES = 256 << 20
 
 
 def check(status: int) -> None:

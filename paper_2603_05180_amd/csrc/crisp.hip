@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -75,6 +76,35 @@ int resolve_tile(int32_t tile_ids) { return tile_ids > 0 ? tile_ids : kDefaultTi
 
 }  // namespace
 
+// Scratch of crisp_search_static: one copy per GPU, held until the process
+// ends.  Host code never takes its name as an address; each device's
+// address comes from hipGetSymbolAddress (static_scratch_ptr).
+static __device__ __align__(256) unsigned char scratch[CRISP_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's copy of `scratch`, looked up once per
+// device.
+crisp_status static_scratch_ptr(void **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CRISP_E_UNSUPPORTED, "device ordinal %d >= %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(CRISP_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return CRISP_OK;
+}
+}  // namespace
+
 struct crisp_index {
   int64_t n;
   int d, m, k, h, ncells, tile, ntiles;
@@ -86,6 +116,8 @@ struct crisp_index {
   int32_t *tile_off;
   float *cent_t;  // [M][2][h][K]
   int ncu = 256;  // compute units of the device the index was loaded on
+  void *scratch = nullptr;  // that device's static scratch (crisp_search_static)
+  std::string scratch_err;  // why it is unavailable
   hipStream_t aux = nullptr;  // second chunk pipeline (overlap = 1)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // learned budget model (borrowed device pointers; null when unset)
@@ -256,6 +288,10 @@ crisp_status crisp_index_load(const crisp_index_desc *desc, int32_t tile_ids, vo
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
       ix->ncu = cu;
+  }
+  if (static_scratch_ptr(&ix->scratch) != CRISP_OK) {
+    ix->scratch = nullptr;
+    ix->scratch_err = g_err;
   }
   if (hipStreamCreateWithFlags(&ix->aux, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&ix->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -653,6 +689,30 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
   if (nq == 0) return CRISP_OK;
   if (!queries || !ids || !dists || !workspace) return fail(CRISP_E_INVALID, "null argument");
   return search_impl(ix, queries, nq, k, p, ids, dists, workspace, ws_bytes, taps,
+                     static_cast<hipStream_t>(hip_stream), nullptr);
+}
+
+crisp_status crisp_search_static(crisp_index *ix, const float *queries, int64_t nq, int32_t k,
+                                 const crisp_search_params *p, int64_t *ids, float *dists, void *hip_stream) {
+  crisp_status s = check_params(ix, nq, k, p);
+  if (s != CRISP_OK) return s;
+  if (!ix->scratch) return fail(CRISP_E_HIP, "static scratch unavailable: %s", ix->scratch_err.c_str());
+  const size_t cap = CRISP_STATIC_SCRATCH_BYTES;
+  const size_t one = make_layout(ix, 1).total;
+  if (one > cap)
+    return fail(CRISP_E_WORKSPACE, "one query needs %zu bytes of workspace; the static scratch holds %zu", one, cap);
+  if (nq == 0) return CRISP_OK;
+  if (!queries || !ids || !dists) return fail(CRISP_E_INVALID, "null argument");
+  // Largest chunk (up to the requested one) whose workspace fits.
+  long long lo = 1, hi = chunk_of(p, nq);
+  while (lo < hi) {
+    const long long mid = (lo + hi + 1) / 2;
+    if (make_layout(ix, mid).total <= cap) lo = mid; else hi = mid - 1;
+  }
+  crisp_search_params q = *p;
+  q.overlap = 0;
+  q.max_chunk = static_cast<int32_t>(lo);
+  return search_impl(ix, queries, nq, k, &q, ids, dists, ix->scratch, cap, nullptr,
                      static_cast<hipStream_t>(hip_stream), nullptr);
 }
 

@@ -209,6 +209,24 @@ class Index:
                                _stream(stream)))
         return ids, dists
 
+    def search_static(self, queries: torch.Tensor, k: int, *, out: tuple | None = None, stream=None, **params):
+        """crisp_search_static: as search() (no taps, one pipeline), with the
+        library's static per-GPU scratch instead of a workspace."""
+        if queries.device != self.device or queries.dtype != torch.float32 or not queries.is_contiguous():
+            raise ValueError("queries must be a contiguous float32 tensor on the index device")
+        if queries.dim() != 2 or queries.shape[1] != self.d:
+            raise ValueError(f"queries must have shape [nq, {self.d}]")
+        nq = int(queries.shape[0])
+        p = self.params(**params)
+        if out is None:
+            ids = torch.empty(nq, k, dtype=torch.int64, device=self.device)
+            dists = torch.empty(nq, k, dtype=torch.float32, device=self.device)
+        else:
+            ids, dists = out
+        check(lib.crisp_search_static(self._h, _ptr(queries), nq, int(k), ctypes.byref(p), _ptr(ids), _ptr(dists),
+                                      _stream(stream)))
+        return ids, dists
+
 
 class Plan:
     """Batch executor for uneven batches (crisp_plan_*): one captured HIP

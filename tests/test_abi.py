@@ -77,3 +77,13 @@ def test_engine_without_the_library_fails_loudly(tmp_path):
                        env=dict(os.environ, PYTHONPATH=str(tmp_path)))
     assert r.returncode != 0
     assert "ImportError" in r.stderr and "libcrisp.so is missing" in r.stderr
+
+
+def test_static_scratch_entry_point():
+    """crisp_search_static validates before touching the GPU, and the
+    binding's copy of the scratch size matches the header."""
+    from paper_2603_05180_amd import _lib
+    assert _lib.lib.crisp_search_static(None, None, 1, 1, None, None, None, None) == -1
+    with open(os.path.join(ROOT, "include", "crisp.h")) as f:
+        m = re.search(r"#define CRISP_STATIC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", f.read())
+    assert m and int(m.group(1)) << int(m.group(2)) == _lib.STATIC_SCRATCH_BYTES
