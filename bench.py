@@ -14,6 +14,16 @@ bfloat16 first pass; identical results) and, in Optimized Mode, learned_bf16
 (the learned verification budget trained beforehand on 200,000 separate
 queries, plus the bfloat16 pass).  The headline value is the fastest form
 whose recall@10 is at least 0.90; every form is listed under "forms".
+
+Also measured (each section can be switched off): a patience-factor sweep of
+the bf16 form, which places the learned form against the plain walk at
+matched recall; the ablations of Section 6.4 on this workload (Optimized
+Mode without the Hamming order; the correlation-check threshold, i.e. the
+index with and without its rotation); an alpha x tau operating-point grid;
+the N = 1M, D = 960 workload (K = 256 centroids per half) in both modes at
+k = 10 and 100; uneven batches on N = 2M, D = 3072; and the CPU oracle on
+the host cores, timed in worker processes forked before this process first
+touches the GPU.
 Prints one JSON line; see ``--help`` for the knobs.
 """
 from __future__ import annotations
@@ -71,6 +81,16 @@ def parse():
                     help="JSON file the uneven-batch tuner reuses and extends ('' = tune afresh, keep nothing)")
     ap.add_argument("--floor", type=float, default=0.998,
                     help="fraction of the plain top-k the learned budget must keep on held-out queries")
+    ap.add_argument("--patience-sweep", default="5,20,30,60",
+                    help="extra patience factors of the bf16 form ('' = none; 10 and 40 are always timed)")
+    ap.add_argument("--ablations", type=int, default=1,
+                    help="Section 6.4 ablations: Hamming order off, correlation-check threshold")
+    ap.add_argument("--grid", type=int, default=1, help="alpha x tau operating-point grid of the head form")
+    ap.add_argument("--d960", type=int, default=1, help="time the N=1M, D=960 (K=256) workload, both modes")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="CPU oracle worker processes (0 = the host cores, at most 16)")
+    ap.add_argument("--label-check", type=int, default=32,
+                    help="training queries whose learned-budget labels are checked against the oracle's trace")
     return ap.parse_args()
 
 
@@ -179,12 +199,120 @@ def fp64_error(base, qrot, ids, dists):
     return worst
 
 
+def stage_rates(stages, steps, per_step, workload):
+    """Per-stage time and rate.  A byte-bound stage whose algorithmic bytes
+    arrive faster than HBM can deliver them is served from L2 / the
+    last-level cache: it is labelled so, with no HBM fraction from the
+    algorithmic bytes; its HBM fraction then comes only from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE per launch), when that summary
+    was taken on the current kernel sources."""
+    kernel_of = {"rerank": "k_rerank", "count": "k_count<0>", "rotate": "k_rotate_rows",
+                 "hamming_dist": "k_hamming_dist"}
+    out = {}
+    for name, rec_s in stages.items():
+        if name == "dropped" or rec_s["intervals"] == 0:
+            continue
+        ms = rec_s["ms"] / steps
+        launches = rec_s["intervals"] / steps
+        ent = {"ms_per_step": round(ms, 4), "launches_per_step": launches}
+        if name in per_step:
+            bound, amount, peak, unit = per_step[name]
+            ach = amount / (ms / 1e3)
+            ent.update(bound=bound, achieved=round(ach, 2), peak=peak, unit=unit, frac=round(ach / peak, 4),
+                       algorithmic_per_launch=round(amount / launches, 4))
+            if bound == "hbm":
+                traffic = measured_traffic(kernel_of[name], workload)
+                if traffic is not None:
+                    ent["hbm_bytes_per_launch"] = traffic
+                    ent["hbm_frac_measured"] = round(traffic / ((ms / launches) / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                if ach > peak:
+                    ent["bound"] = "l2/mall"
+                    ent["frac"] = None
+                    ent["note"] = ("algorithmic bytes above what HBM delivers: served from cache; "
+                                   "HBM share only from counters")
+        out[name] = ent
+    return out, kernel_of
+
+
+def run_form(index, queries, truth, k, kw, args, ids, dists, plain_ids, base, qrot, d):
+    """Warm up, time, count and stage-profile one form; returns its record."""
+    import torch
+    for _ in range(args.warmup):
+        index.search(queries, k, out=(ids, dists), **kw)
+    torch.cuda.synchronize()
+    rec = recall(ids, truth)
+    same = None
+    if plain_ids is not None:
+        same = round(float((ids[:, :, None] == plain_ids[:, None, :]).any(-1).float().mean()), 5)
+    ms, _ = timed(index, queries, k, kw, args.steps, ids, dists)
+    c = counts(index, queries, k, dict(kw, overlap=0))
+    _, st1 = timed(index, queries, k, dict(kw, overlap=0), 1, ids, dists, profile=True)
+    rr_bytes = (((2.0 * d + 4.0) * c["examined"] + 4.0 * d * c["refined"]) if kw.get("precision", 0) >= 1
+                else 4.0 * d * c["examined"])
+    nq = queries.shape[0]
+    return {"queries_per_s": round(nq / (ms / 1e3), 1), "ms_per_step": round(ms, 3),
+            "recall_at_k": round(rec, 4), "plain_ids_kept": same,
+            "mean_verified": round(c["examined"] / nq, 1),
+            "mean_float32_rows": round(c["refined"] / nq, 1),
+            "mean_candidates": round(c["n_cand"] / nq, 1),
+            "rerank_algorithmic_gb_s": round(rr_bytes / 1e9 / (st1["rerank"]["ms"] / 1e3), 1),
+            "max_rel_err_vs_fp64": fp64_error(base, qrot, ids, dists),
+            "_kw": kw, "_counts": c}
+
+
+def matched_recall(results, learned="learned_bf16"):
+    """The learned form against the plain bf16 walk at the learned form's
+    recall: the plain patience sweep's queries/s interpolated (linearly in
+    recall) between the two sweep points around that recall."""
+    if learned not in results:
+        return None
+    sweep = sorted(((r["_kw"]["patience_factor"], r) for f, r in results.items()
+                    if f.startswith("bf16_pf") or f == "bf16"), key=lambda t: t[0])
+    pts = sorted({(r["recall_at_k"], r["queries_per_s"], pf) for pf, r in sweep})
+    lr, lq = results[learned]["recall_at_k"], results[learned]["queries_per_s"]
+    above = [p for p in pts if p[0] >= lr]
+    below = [p for p in pts if p[0] < lr]
+    out = {"learned": {"recall_at_10": lr, "queries_per_s": lq,
+                       "mean_verified": results[learned]["mean_verified"]},
+           "plain_sweep": [{"patience_factor": pf, "recall_at_10": r["recall_at_k"],
+                            "queries_per_s": r["queries_per_s"], "mean_verified": r["mean_verified"]}
+                           for pf, r in sweep]}
+    if not above:
+        out["outcome"] = "the plain sweep does not reach the learned form's recall"
+        return out
+    hi = min(above, key=lambda p: p[0])
+    if below:
+        lo = max(below, key=lambda p: p[0])
+        t = (lr - lo[0]) / (hi[0] - lo[0]) if hi[0] > lo[0] else 1.0
+        q_plain = lo[1] + t * (hi[1] - lo[1])
+    else:
+        q_plain = hi[1]
+    gain = lq / q_plain - 1.0
+    out["plain_queries_per_s_at_learned_recall"] = round(q_plain, 1)
+    out["learned_gain"] = round(gain, 4)
+    out["outcome"] = ("learned beats the plain walk at matched recall" if gain > 0.01 else
+                      "no gain: the plain walk with a tuned patience is as fast at this recall")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the engine shards by query batch; see the design notes)", file=sys.stderr)
         sys.exit(2)
+    # The CPU oracle's workers are forked now, before anything touches the GPU.
+    pool = start_cpu_pool(args.cpu_workers) if args.cpu_seconds > 0 else None
+    try:
+        line = measure(args, pool)
+    finally:
+        if pool is not None:
+            pool.terminate()
+            pool.join()
+    print(json.dumps(line), flush=True)
+
+
+def measure(args, pool):
     import numpy as np
     import torch
 
@@ -239,6 +367,9 @@ def main():
         if args.scoring:
             # and with the half distances pre-scored on bfloat16 matrix cores (same results)
             forms[f"bf16_scored_pf{args.tuned_patience}"] = dict(precision=2, patience_factor=args.tuned_patience)
+    if args.mode == 1:
+        for pf in [int(v) for v in args.patience_sweep.split(",") if v.strip()]:
+            forms.setdefault(f"bf16_pf{pf}", dict(precision=1, patience_factor=pf))
     if args.mode == 1 and args.guaranteed:
         # Guaranteed Mode (every candidate verified) at the same alpha and tau
         forms["guaranteed"] = dict(mode=0, precision=0)
@@ -249,32 +380,17 @@ def main():
     results = {}
     for name, extra in forms.items():
         kw = dict(base_kw, **extra)
-        for _ in range(args.warmup):
-            index.search(queries, k, out=(ids, dists), **kw)
-        torch.cuda.synchronize()
-        rec = recall(ids, truth)
+        results[name] = run_form(index, queries, truth, k, kw, args, ids, dists, plain_ids, arrays["base"], qrot,
+                                 w.d)
         if plain_ids is None:
             plain_ids = ids.clone()
-        same = float((ids[:, :, None] == plain_ids[:, None, :]).any(-1).float().mean())
-        ms, _ = timed(index, queries, k, kw, args.steps, ids, dists)
-        c = counts(index, queries, k, dict(kw, overlap=0))
-        # re-rank gather rate of this form: one single-pipeline step, stage-timed
-        _, st1 = timed(index, queries, k, dict(kw, overlap=0), 1, ids, dists, profile=True)
-        rr_bytes = (((2.0 * w.d + 4.0) * c["examined"] + 4.0 * w.d * c["refined"]) if kw.get("precision", 0) >= 1
-                    else 4.0 * w.d * c["examined"])
-        results[name] = {"queries_per_s": round(w.n_query / (ms / 1e3), 1), "ms_per_step": round(ms, 3),
-                         "recall_at_10": round(rec, 4), "plain_ids_kept": round(same, 5),
-                         "mean_verified": round(c["examined"] / w.n_query, 1),
-                         "mean_float32_rows": round(c["refined"] / w.n_query, 1),
-                         "rerank_gb_s": round(rr_bytes / 1e9 / (st1["rerank"]["ms"] / 1e3), 1),
-                         "max_rel_err_vs_fp64": fp64_error(arrays["base"], qrot, ids, dists),
-                         "_kw": kw, "_counts": c}
-        log(f"form {name}: {results[name]['queries_per_s']} q/s, recall {rec:.4f}, "
-            f"verified {results[name]['mean_verified']}, float32 rows {results[name]['mean_float32_rows']}, "
-            f"re-rank {results[name]['rerank_gb_s']} GB/s")
+            results[name]["plain_ids_kept"] = 1.0
+        r = results[name]
+        log(f"form {name}: {r['queries_per_s']} q/s, recall {r['recall_at_k']:.4f}, verified {r['mean_verified']}, "
+            f"float32 rows {r['mean_float32_rows']}, re-rank {r['rerank_algorithmic_gb_s']} GB/s algorithmic")
 
     # Headline: the fastest form at recall@10 >= 0.90.
-    ok = [f for f in results if results[f]["recall_at_10"] >= 0.90] or list(results)
+    ok = [f for f in results if results[f]["recall_at_k"] >= 0.90] or list(results)
     head = max(ok, key=lambda f: results[f]["queries_per_s"])
     kw, c = results[head]["_kw"], results[head]["_counts"]
     ms_step = results[head]["ms_per_step"]
@@ -295,21 +411,12 @@ def main():
         "hamming_dist": ("hbm", (d / 8.0 + 8.0) * c["n_cand"] / 1e9, HBM_PEAK_GBS, "GB/s"),
         "rerank": ("hbm", rerank_bytes / 1e9, HBM_PEAK_GBS, "GB/s"),
     }
-    stage_out = {}
-    for name, rec_s in stages.items():
-        if name == "dropped" or rec_s["intervals"] == 0:
-            continue
-        ms = rec_s["ms"] / args.steps
-        ent = {"ms_per_step": round(ms, 4), "launches_per_step": rec_s["intervals"] / args.steps}
-        if name in per_step:
-            bound, amount, peak, unit = per_step[name]
-            ach = amount / (ms / 1e3)
-            ent.update(bound=bound, achieved=round(ach, 2), peak=peak, unit=unit, frac=round(ach / peak, 4))
-        stage_out[name] = ent
-    dom = max((s for s in stage_out if s in per_step), key=lambda s: stage_out[s]["ms_per_step"])
+    if arrays["rotation"] is None:
+        per_step.pop("rotate")
+    stage_out, kernel_of = stage_rates(stages, args.steps, per_step, w.name)
+    cands = [s_ for s_ in stage_out if s_ in per_step and stage_out[s_].get("frac") is not None]
+    dom = max(cands, key=lambda s_: stage_out[s_]["ms_per_step"])
     launches = stage_out[dom]["launches_per_step"]
-    kernel_of = {"rerank": "k_rerank", "count": "k_count<0>", "rotate": "k_rotate_rows",
-                 "hamming_dist": "k_hamming_dist"}
     roof = {"kernel": kernel_of[dom],
             "bound": per_step[dom][0], "achieved": stage_out[dom]["achieved"], "peak": per_step[dom][2],
             "unit": per_step[dom][3], "frac": stage_out[dom]["frac"],
@@ -317,15 +424,14 @@ def main():
             "avg_launch_ms": round(stage_out[dom]["ms_per_step"] / launches, 4),
             "algorithmic_per_launch": round(per_step[dom][1] / launches, 4)}
     if "rerank" in stage_out:
-        roof["rerank_gather"] = {k_: stage_out["rerank"][k_] for k_ in ("achieved", "peak", "unit", "frac")}
+        rr = stage_out["rerank"]
+        roof["rerank_gather"] = {"achieved_algorithmic": rr["achieved"], "peak": rr["peak"], "unit": rr["unit"],
+                                 "frac_algorithmic": rr["frac"],
+                                 "hbm_frac_measured": rr.get("hbm_frac_measured")}
 
-    # ---- CPU oracle baseline on a bounded sample of the same workload --------
-    cpu = None
-    if args.cpu_seconds > 0:
-        cpu = cpu_baseline(arrays, queries, k, base_kw, args.cpu_seconds)
+    # ---- the learned form against the plain walk at matched recall --------
+    mr = matched_recall(results)
 
-    for f in results.values():
-        f.pop("_kw"); f.pop("_counts")
     rotated = arrays["rotation"] is not None
     line = {
         "metric": METRIC, "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
@@ -336,7 +442,7 @@ def main():
                    "mode": "optimized" if kw.get("mode", args.mode) == 1 else "guaranteed",
                    "alpha": args.alpha, "tau": args.tau,
                    "patience_factor": kw.get("patience_factor", args.patience),
-                   "recall_at_10": results[head]["recall_at_10"],
+                   "recall_at_10": results[head]["recall_at_k"],
                    "overlap": args.overlap, "queries_per_chunk": base_kw["max_chunk"],
                    "rotated": rotated,
                    "mean_candidates": round(c["n_cand"] / w.n_query, 1),
@@ -344,20 +450,176 @@ def main():
                    "learned_delta": None if model is None else round(model.delta, 4),
                    "learned_train_queries": args.train_queries if model is not None else 0},
         "forms": results,
+        "learned_vs_plain_at_matched_recall": mr,
         "roofline": roof,
         "stages": stage_out,
-        "cpu_baseline": cpu,
     }
+
+    # ---- Section 6.4 ablation: Optimized Mode without the Hamming order -----
+    if args.ablations and args.mode == 1:
+        abl = {}
+        for pf in sorted({args.tuned_patience or args.patience, args.patience}):
+            kwx = dict(base_kw, precision=1, patience_factor=pf)
+            r_on = next((results[f] for f in results if results[f]["_kw"] == kwx), None)
+            r_off = run_form(index, queries, truth, k, dict(kwx, walk_order=1), args, ids, dists, None,
+                             arrays["base"], qrot, d)
+            ent = {"patience_factor": pf,
+                   "hamming_order": None if r_on is None else {x_: r_on[x_] for x_ in
+                                                               ("queries_per_s", "recall_at_k", "mean_verified")},
+                   "id_order": {x_: r_off[x_] for x_ in ("queries_per_s", "recall_at_k", "mean_verified")}}
+            if r_on is not None:
+                ent["throughput_without_hamming_rel"] = round(r_off["queries_per_s"] / r_on["queries_per_s"], 4)
+            abl[f"pf{pf}"] = ent
+            log(f"ablation hamming off pf{pf}: {r_off['queries_per_s']} q/s, recall {r_off['recall_at_k']:.4f}")
+        line["ablation_hamming_order"] = abl
+
+    # ---- operating-point grid: alpha x tau (tau = ceil(beta M)) -------------
+    if args.grid:
+        grid = []
+        for alpha in (0.002, 0.005, 0.01, 0.02, 0.04, 0.06):
+            for beta in (0.1, 0.2, 0.3, 0.4, 0.5, 0.6):
+                tau = int(math.ceil(beta * w.m))
+                kwg = dict(kw, alpha=alpha, tau=tau)
+                for _ in range(1):
+                    index.search(queries, k, out=(ids, dists), **kwg)
+                torch.cuda.synchronize()
+                rec = recall(ids, truth)
+                ms, _ = timed(index, queries, k, kwg, 2, ids, dists)
+                grid.append({"alpha": alpha, "beta": beta, "tau": tau, "queries_per_s": round(w.n_query / ms * 1e3, 1),
+                             "recall_at_10": round(rec, 4)})
+        best = max((g_ for g_ in grid if g_["recall_at_10"] >= 0.90), key=lambda g_: g_["queries_per_s"],
+                   default=None)
+        line["operating_grid"] = {"form": head, "points": grid, "best_at_recall_0.90": best}
+        log(f"grid: best {best}")
+
+    # ---- CPU oracle: baseline on a bounded sample, learned-label check -------
+    cpu = None
+    if pool is not None:
+        import shutil
+        t = time.time()
+        tmp, paths, meta = export_index(arrays)
+        log(f"CPU oracle: index arrays written to {tmp} in {time.time() - t:.1f}s")
+        try:
+            okw = dict(mode=kw["mode"], alpha=kw["alpha"], tau=kw["tau"], patience_factor=kw["patience_factor"],
+                       hamming=kw.get("walk_order", 0) == 0)
+            cpu = cpu_baseline(pool, paths, meta, queries, k, okw, args.cpu_seconds)
+            if model is not None and args.label_check > 0:
+                sample = sg.rows(w, args.train_seed, 0, args.label_check, params)
+                eng = learned.collect(index, sample, k, alpha=args.alpha, tau=args.tau,
+                                      patience_factor=args.patience)
+                lk = dict(mode=1, alpha=args.alpha, tau=args.tau, patience_factor=args.patience)
+                line["learned_label_check"] = check_labels(pool, paths, meta, sample,
+                                                           {x_: eng[x_].cpu() for x_ in
+                                                            ("last_update", "examined", "n_cand")}, k, lk)
+                log(f"learned labels vs oracle: {line['learned_label_check']}")
+        finally:
+            shutil.rmtree(tmp, ignore_errors=True)
+    line["cpu_baseline"] = cpu
+
+    for f in results.values():
+        f.pop("_kw"); f.pop("_counts")
+    cev = float(arrays["cev"])
+    head_kw = dict(kw)
+    index.free()
+    del index, arrays, queries, qrot, truth, ids, dists, plain_ids, model
+    torch.cuda.empty_cache()
+
+    # ---- Section 6.4 ablation: the correlation-check threshold --------------
+    if args.ablations:
+        line["ablation_cev_threshold"] = cev_ablation(w, head_kw, cev, head, results[head], args)
+
+    # ---- the N = 1M, D = 960 workload, both modes, k = 10 and 100 -----------
+    if args.d960:
+        torch.cuda.empty_cache()
+        line["d960"] = d960_section(args)
 
     # ---- uneven batches (served through the tuned batch executor) ------------
     if args.uneven_workload:
-        del index, arrays, queries, qrot, truth, ids, dists, plain_ids, model
         torch.cuda.empty_cache()
         line["uneven_batching"] = uneven_batches(args)
-    print(json.dumps(line), flush=True)
+    return line
 
 
-def build_gpu_index(w):
+def cev_ablation(w, kw, cev, head, head_rec, args):
+    """The index built with the rotation decision reversed (Section 6.4:
+    the threshold tau_CEV on the correlation check decides whether the data
+    are rotated): the head form timed on it.  Every threshold below the
+    measured CEV rotates, every threshold at or above it does not."""
+    import torch
+    import synth.gpu as sg
+    from paper_2603_05180_amd import engine
+    t = time.time()
+    rotated = cev > engine.TAU_CEV
+    arrays, params = build_gpu_index(w, force_rotation=not rotated)
+    queries = sg.rows(w, w.seed_query, 0, w.n_query, params)
+    index = engine.Index(arrays, tile_ids=args.tile)
+    index.enable_bf16()
+    qrot = engine.rotate_rows(queries, arrays["rotation"]) if arrays["rotation"] is not None else queries
+    truth = ground_truth(arrays["base"], qrot, w.k)
+    log(f"ablation: index with rotated={arrays['rotation'] is not None} built in {time.time() - t:.1f}s")
+    ids = torch.empty(w.n_query, w.k, dtype=torch.int64, device="cuda")
+    dists = torch.empty_like(ids, dtype=torch.float32)
+    r = run_form(index, queries, truth, w.k, kw, args, ids, dists, None, arrays["base"], qrot, w.d)
+    other = {x_: r[x_] for x_ in ("queries_per_s", "recall_at_k", "mean_candidates", "mean_verified")}
+    mine = {x_: head_rec[x_] for x_ in ("queries_per_s", "recall_at_k", "mean_verified")}
+    variants = {"rotated" if rotated else "not_rotated": dict(mine, form=head),
+                "not_rotated" if rotated else "rotated": dict(other, form=head)}
+    sweep = [{"tau_cev": tc, "rotated": bool(cev > tc)} for tc in (0.5, 0.7, 0.8, 0.85, 0.9, 0.95, 0.99, 0.999)]
+    del index, arrays, queries, qrot, truth
+    torch.cuda.empty_cache()
+    return {"cev": round(cev, 4), "variants": variants, "threshold_sweep": sweep}
+
+
+def d960_section(args):
+    """The N = 1M, D = 960 workload (100 local rank-32 components, 16
+    subspaces of 60 dims, K = 256 centroids per half; the correlation check
+    does not fire): both modes at k = 10 and k = 100, 10,000 queries."""
+    import torch
+    import synth
+    import synth.gpu as sg
+    from paper_2603_05180_amd import engine
+    w = synth.WORKLOADS["d960k256"]
+    t = time.time()
+    arrays, params = build_gpu_index(w)
+    queries = sg.rows(w, w.seed_query, 0, w.n_query, params)
+    index = engine.Index(arrays, tile_ids=args.tile)
+    index.enable_bf16()
+    log(f"d960: index built in {time.time() - t:.1f}s (CEV {arrays['cev']:.3f})")
+    out = {"workload": f"{w.name}: N={w.n} D={w.d} local rank {w.rank}, {w.n_comp} comps, M={w.m} K={w.k_half}",
+           "rotated": arrays["rotation"] is not None}
+    truth100 = ground_truth(arrays["base"], queries, 100, pool=192)
+    for k in (10, 100):
+        truth = truth100[:, :k].contiguous()
+        ids = torch.empty(w.n_query, k, dtype=torch.int64, device="cuda")
+        dists = torch.empty(w.n_query, k, dtype=torch.float32, device="cuda")
+        for mode, name in ((0, "guaranteed"), (1, "optimized")):
+            # operating point: the fastest of a small alpha x tau grid (one
+            # timed search each) whose recall@k reaches 0.90
+            base = dict(mode=mode, patience_factor=10, precision=1, max_chunk=2048, overlap=1)
+            pick, pick_q = None, -1.0
+            for alpha in (0.005, 0.01, 0.02, 0.05):
+                for tau in ((4, 8, 12) if mode == 0 else (8, 16, 24)):
+                    kwg = dict(base, alpha=alpha, tau=tau)
+                    index.search(queries, k, out=(ids, dists), **kwg)
+                    torch.cuda.synchronize()
+                    rec = recall(ids, truth)
+                    ms, _ = timed(index, queries, k, kwg, 1, ids, dists)
+                    if rec >= 0.90 and w.n_query / ms > pick_q:
+                        pick, pick_q = kwg, w.n_query / ms
+            kw = pick or dict(base, alpha=0.05, tau=4 if mode == 0 else 8)
+            r = run_form(index, queries, truth, k, kw, args, ids, dists, None, arrays["base"], queries, w.d)
+            r.pop("_counts")
+            r["operating_point"] = {x_: kw[x_] for x_ in ("alpha", "tau", "patience_factor", "precision")}
+            r.pop("_kw")
+            out[f"{name}_k{k}"] = r
+            log(f"d960 {name} k={k}: {r['queries_per_s']} q/s, recall@{k} {r['recall_at_k']:.4f}")
+    index.free()
+    del index, arrays, queries, truth100
+    torch.cuda.empty_cache()
+    return out
+
+
+def build_gpu_index(w, force_rotation=None):
     """Seeded data of workload w generated and indexed on the GPU."""
     import numpy as np
     import synth
@@ -370,7 +632,8 @@ def build_gpu_index(w):
     km_rows = synth.sample_indices(w.seed_index, synth.TAG["kmeans_sample"], n, min(n, 100_000))
     km_init = synth.permutation_prefix(w.seed_index, synth.TAG["kmeans_init"], np.arange(km_rows.size), w.k_half)
     arrays = engine.build_index(x, w.m, w.k_half, g=lambda: sg.gaussian_matrix(w.seed_index, w.d),
-                                cev_rows=cev_rows, km_rows=km_rows, km_init=km_init, keep_input=False)
+                                cev_rows=cev_rows, km_rows=km_rows, km_init=km_init, keep_input=False,
+                                force_rotation=force_rotation)
     return arrays, params
 
 
@@ -448,33 +711,135 @@ def uneven_batches(args):
     return out
 
 
-def cpu_baseline(arrays, queries, k, kw, budget_s):
-    """The CPU oracle's query engine, timed on the host cores on the first S
-    queries of the batch against the same index arrays (timing only)."""
-    import numpy as np
-    import torch
-    from oracle import query as oquery
+def start_cpu_pool(n_workers=0):
+    """Worker processes for the CPU oracle, forked before the GPU is first
+    touched; they import numpy and the oracle only, one BLAS thread each."""
+    import multiprocessing as mp
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    n = n_workers or min(16, avail)
+    return mp.get_context("fork").Pool(n, initializer=_cpu_worker_init)
 
-    t = time.time()
-    host = {"n": arrays["n"], "d": arrays["d"], "m": arrays["m"], "k_half": arrays["k_half"],
-            "rotation": None if arrays["rotation"] is None else arrays["rotation"].cpu().numpy(),
-            "centroids": arrays["centroids"].cpu().numpy(), "offsets": arrays["offsets"].cpu().numpy(),
-            "ids": arrays["ids"].cpu().numpy(), "base": arrays["base"].cpu().numpy(),
-            "codes": arrays["codes"].cpu().numpy().view(np.uint64)}
-    qh = queries[:512].cpu().numpy()
-    log(f"host copy of the index for the CPU baseline in {time.time() - t:.1f}s")
-    okw = dict(mode=kw["mode"], alpha=kw["alpha"], tau=kw["tau"], patience_factor=kw["patience_factor"])
+
+def _cpu_worker_init():
+    os.environ["OMP_NUM_THREADS"] = "1"
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+
+
+def _cpu_worker(task):
+    """One worker's share: the oracle's query engine over its queries, on
+    the index arrays memory-mapped from files."""
+    import numpy as np
+    from oracle import query as oquery
+    paths, meta, q, k, okw = task
+    index = dict(meta)
+    for name, path in paths.items():
+        index[name] = None if path is None else np.load(path, mmap_mode="r")
+    t0 = time.perf_counter()
+    oquery.search(index, q, k, **okw)
+    return time.perf_counter() - t0, int(q.shape[0])
+
+
+def _cpu_info():
+    model, flags = "", ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name") and not model:
+                    model = ln.split(":", 1)[1].strip()
+                if ln.startswith("flags") and not flags:
+                    flags = ln.split(":", 1)[1]
+    except OSError:
+        pass
+    avx512 = sorted({t for t in flags.split() if t.startswith("avx512")})
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model,
+            "avx512": avx512[:8]}
+
+
+def export_index(arrays):
+    """The index arrays written once to .npy files (in /dev/shm when it has
+    room) that the CPU workers memory-map.  Returns (folder, paths, meta)."""
+    import shutil
+    import tempfile
+    import numpy as np
+    need = sum(v.numel() * v.element_size() for v in arrays.values() if hasattr(v, "numel"))
+    try:
+        root = "/dev/shm" if shutil.disk_usage("/dev/shm").free > 1.5 * need else tempfile.gettempdir()
+    except OSError:
+        root = tempfile.gettempdir()
+    tmp = tempfile.mkdtemp(prefix="crisp_cpu_", dir=root)
+    paths = {}
+    for name in ("rotation", "centroids", "offsets", "ids", "base", "codes"):
+        v = arrays[name]
+        if v is None:
+            paths[name] = None
+            continue
+        path = os.path.join(tmp, name + ".npy")
+        dt = np.uint64 if name == "codes" else v[:0].cpu().numpy().dtype
+        mm = np.lib.format.open_memmap(path, mode="w+", dtype=dt, shape=tuple(v.shape))
+        step = max(1, (1 << 28) // max(1, v[0].numel() * v.element_size())) if v.dim() > 1 else v.shape[0]
+        for r0 in range(0, v.shape[0], step):
+            chunk = v[r0:r0 + step].cpu().numpy()
+            mm[r0:r0 + step] = chunk.view(np.uint64) if name == "codes" else chunk
+        mm.flush()
+        del mm
+        paths[name] = path
+    meta = {"n": int(arrays["n"]), "d": int(arrays["d"]), "m": int(arrays["m"]), "k_half": int(arrays["k_half"])}
+    return tmp, paths, meta
+
+
+def _cpu_labels(task):
+    """Oracle trace of one query: the plain walk's last update and prefix."""
+    import numpy as np
+    from oracle import query as oquery
+    paths, meta, q, k, okw = task
+    index = dict(meta)
+    for name, path in paths.items():
+        index[name] = None if path is None else np.load(path, mmap_mode="r")
+    _, _, tr = oquery.search(index, q, k, trace=True, **okw)
+    return [(int(t["last_update"]), int(t["examined"]), int(t["candidates"].size)) for t in tr]
+
+
+def check_labels(pool, paths, meta, queries, engine_out, k, okw):
+    """The learned budget's training labels (the engine's plain walk: last
+    update L*, verified prefix, |C|) against the oracle's trace on a sample
+    of the training queries."""
+    qh = queries.cpu().numpy()
+    res = pool.map(_cpu_labels, [(paths, meta, qh[i:i + 1], k, okw) for i in range(qh.shape[0])], chunksize=1)
+    got = list(zip(engine_out["last_update"].tolist(), engine_out["examined"].tolist(),
+                   engine_out["n_cand"].tolist()))
+    ref = [r[0] for r in res]
+    return {"sample": len(ref), "equal": sum(1 for a_, b_ in zip(got, ref) if tuple(a_) == tuple(b_)),
+            "compared": "L* (last top-k update), verified prefix and |C| of the plain walk"}
+
+
+def cpu_baseline(pool, paths, meta, queries, k, okw, budget_s):
+    """The CPU oracle's query engine (the plain numpy one of the parity
+    tests, untuned), timed on the host cores at the headline form's operating
+    point: each worker process searches its own slice of the batch's first
+    queries against the memory-mapped index arrays."""
+    qh = queries[:4096].cpu().numpy()
+    nw = pool._processes
+    # one query on one worker sizes the shares
+    el, _ = pool.apply(_cpu_worker, ((paths, meta, qh[:1], k, okw),))
+    per = int(max(1, min(qh.shape[0] // nw, budget_s / max(el, 1e-3))))
+    tasks = [(paths, meta, qh[i * per:(i + 1) * per], k, okw) for i in range(nw)]
     t0 = time.time()
-    oquery.search(host, qh[:1], k, **okw)
-    per_q = max(1e-3, time.time() - t0)
-    s = int(max(2, min(qh.shape[0], budget_s / per_q)))
-    t0 = time.time()
-    oquery.search(host, qh[:s], k, **okw)
-    el = time.time() - t0
-    log(f"CPU oracle: {s} queries in {el:.1f}s")
-    return {"value": round(s / el, 3), "unit": "queries/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {s} queries of the batch through the oracle query engine (oracle/query.py, "
-                      f"one process, numpy) against the same index arrays"}
+    res = pool.map(_cpu_worker, tasks, chunksize=1)
+    wall = time.time() - t0
+    total = sum(n_ for _, n_ in res)
+    single = sum(n_ / e_ for e_, n_ in res) / len(res)
+    log(f"CPU oracle: {total} queries on {nw} processes in {wall:.1f}s")
+    return {"value": round(total / wall, 3), "unit": "queries/s", "cores": nw, "kind": "oracle",
+            "single_core_queries_per_s": round(single, 4),
+            "host": _cpu_info(),
+            "operating_point": {x_: okw[x_] for x_ in ("mode", "alpha", "tau", "patience_factor")},
+            "sample": f"the batch's first {total} queries, {per} per process, through the oracle query engine "
+                      f"(oracle/query.py, numpy, one BLAS thread per process) on {nw} worker processes against "
+                      f"the same index arrays (memory-mapped), at the headline form's operating point"}
 
 
 if __name__ == "__main__":

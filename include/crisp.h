@@ -178,6 +178,22 @@ crisp_status crisp_index_enable_bf16(crisp_index *index, void *buffer, size_t by
  *                      second stream joins hip_stream before the call's work
  *                      completes; calls with overlap on one index must be
  *                      ordered on one stream.
+ *   walk_order      -- Optimized Mode only.  0: candidates are verified in
+ *                      ascending (Hamming distance, id) order (Section
+ *                      4.3.2, Stage 2).  1: in ascending id order, the
+ *                      Hamming stage skipped (the ablation of Section 6.4
+ *                      without Hamming re-ranking); not with budget_source 1,
+ *                      whose features are Hamming distances.
+ *   verify          -- Optimized Mode only.  0: every walked candidate is
+ *                      verified by its exact L2 distance key.  1: ADSampling
+ *                      (Section 3, Eq. (2); Section 4.3.2, Stage 3): once the
+ *                      top-k holds k items, a walked candidate is pruned at
+ *                      the first t = 32, 64, ... below D where the key's
+ *                      running sum over its first t dimensions exceeds
+ *                      r_k^2 (t/D)(1 + eps_0/sqrt(t))^2, eps_0 = 2.1, r_k^2
+ *                      the k-th key at that moment (the product in float64);
+ *                      a pruned candidate counts as a non-update, the others
+ *                      are verified exactly.  Needs precision 0.
  */
 typedef struct {
   int32_t mode;
@@ -190,6 +206,8 @@ typedef struct {
   int32_t precision;
   int32_t persistent;
   int32_t overlap;
+  int32_t walk_order;
+  int32_t verify;
 } crisp_search_params;
 
 /*
@@ -213,7 +231,10 @@ typedef struct {
  *   features    float32 [nq][F]        learned-budget features (mode 1), F = 17 + 3M + 13
  *   limits      int32  [nq]            predicted verification limits (budget_source 1)
  *   refined     int32  [nq]            verified rows read in float32 (precision 0:
- *                                      every one; 1: those the bfloat16 bound kept)
+ *                                      every one; 1: those the bfloat16 bound kept;
+ *                                      verify 1: those ADSampling did not prune)
+ *   row_bytes   int64  [nq]            bytes of stored rows the verification read
+ *                                      (rows of a walk chunk past the stop included)
  *   score_lb    float32 [nq][M][2][K]  precision 2, K <= 64: certified lower and
  *   score_ub    float32 [nq][M][2][K]  upper bounds of Dist_1 / Dist_2 from the
  *                                      bfloat16 matrix-core scoring
@@ -239,6 +260,7 @@ typedef struct {
   int32_t *refined;
   float *score_lb;
   float *score_ub;
+  int64_t *row_bytes;
 } crisp_taps;
 
 /* Bytes of workspace crisp_search needs for this index, batch and parameters. */
@@ -303,7 +325,14 @@ crisp_status crisp_search_static(crisp_index *index, const float *queries, int64
  *                        float32); 0 <= nq <= max_batch.  Batches of one
  *                        plan must be stream-ordered: they share the staging
  *                        buffers.  Capturing a new bucket synchronises the
- *                        private stream only.
+ *                        private stream only.  The parameters are checked
+ *                        against the index again on every call (a budget
+ *                        model cleared since, a bfloat16 copy dropped:
+ *                        CRISP_E_INVALID).  A bucket captured before the
+ *                        index's budget model or bfloat16 copy last changed
+ *                        (crisp_set_budget_model, crisp_index_enable_bf16) is
+ *                        captured anew: that call first synchronises
+ *                        hip_stream, where the earlier batches ran.
  *   crisp_plan_free   -- releases the graphs and the private stream.
  */
 typedef struct crisp_plan crisp_plan;

@@ -16,10 +16,10 @@ at a time, in the paper's order and notation:
   4. phi = 1: order C by Hamming distance of sign codes (Stage 2).
   5. Verify: phi = 0 computes the exact L2 distance of every candidate;
      phi = 1 walks the Hamming order and stops after P = patience_factor * k
-     consecutive candidates that leave the top-k unchanged (Stage 3).  The
-     ADSampling estimator of Stage 3 is not part of this engine: distances
-     are exact (the paper's "Hamming re-ranking with exact L2" variant,
-     Section 6.4).
+     consecutive candidates that leave the top-k unchanged (Stage 3), each
+     candidate verified by exact L2 (the paper's "Hamming re-ranking with
+     exact L2" variant, Section 6.4) or, with ads=True, by ADSampling
+     (Eq. (2): prune once a partial distance exceeds the scaled k-th key).
   6. Return the top-k.
 
 Readings where the paper is silent (each is also listed in the design notes):
@@ -39,6 +39,13 @@ Readings where the paper is silent (each is also listed in the design notes):
   items or its key is below the current k-th key; the counter of consecutive
   non-updates resets on an update and the walk stops when it reaches P.
 * Learned budget: the walk additionally stops after ``limit`` candidates.
+* ADSampling: the test of Eq. (2) runs every 32 dimensions below D with
+  eps_0 = 2.1; r_k^2 is the k-th key of the top-k at the moment the
+  candidate is verified (none while the top-k holds fewer than k items, so
+  nothing is pruned then); d_t^2 is the key's own float64 running sum after
+  t dimensions, the threshold r_k^2 * (t/D)(1 + eps_0/sqrt(t))^2 a float64
+  product with the factor formed as in ``ads_factors``.  A pruned candidate
+  counts as a non-update; one that passes every test is verified exactly.
 """
 from __future__ import annotations
 
@@ -165,6 +172,91 @@ def canonical_sqdist(qp: np.ndarray, rows: np.ndarray) -> np.ndarray:
     return acc
 
 
+# ADSampling (Section 3, Eq. (2); Section 4.3.2, Stage 3): the test runs every
+# ADS_STEP dimensions with the safety margin eps_0 = ADS_EPS0 (both the paper's
+# settings).
+ADS_EPS0 = 2.1
+ADS_STEP = 32
+
+
+def ads_factors(d: int) -> np.ndarray:
+    """(t / D) (1 + eps_0 / sqrt(t))^2 of Eq. (2) for t = 32, 64, ... below D,
+    in float64: b = 1 + eps_0 / sqrt(t), factor = (t / D) * (b * b)."""
+    t = np.arange(ADS_STEP, d, ADS_STEP, dtype=np.float64)
+    b = 1.0 + ADS_EPS0 / np.sqrt(t)
+    return (t / float(d)) * (b * b)
+
+
+def sqdist_with_prefixes(qp: np.ndarray, rows: np.ndarray):
+    """The distance key of each row (as canonical_sqdist) together with the
+    running sum after every ADS_STEP dimensions below D: prefixes[:, j] is
+    the partial distance d_t^2 of Eq. (2) at t = ADS_STEP (j + 1), the same
+    float64 accumulation stopped early."""
+    q64 = np.asarray(qp, dtype=np.float32).astype(np.float64)
+    d = q64.shape[0]
+    x64 = np.asarray(rows, dtype=np.float32).astype(np.float64).reshape(-1, d)
+    acc = np.zeros(x64.shape[0], dtype=np.float64)
+    pre = np.zeros((x64.shape[0], max(0, (d - 1) // ADS_STEP)), dtype=np.float64)
+    for i in range(d):
+        delta = q64[i] - x64[:, i]
+        sq = delta * delta
+        acc = acc + sq
+        if (i + 1) % ADS_STEP == 0 and i + 1 < d:
+            pre[:, (i + 1) // ADS_STEP - 1] = acc
+    return acc, pre
+
+
+def ads_walk(ids: np.ndarray, keys: np.ndarray, prefixes: np.ndarray, factors: np.ndarray, k: int,
+             patience: int, limit: int | None = None):
+    """Optimized Mode verification with ADSampling and patience.
+
+    Candidates are verified in order.  Once the top-k holds k items, with
+    r_k^2 its current k-th key, a candidate is pruned at the first t with
+    d_t^2 > r_k^2 * factor_t (Eq. (2); the product rounded in float64): it is
+    not verified further and counts as a non-update.  A candidate that
+    passes every test is verified exactly and updates the top-k iff the
+    top-k holds fewer than k items or its (key, id) is below the k-th.  The
+    walk stops after `patience` consecutive non-updates.
+
+    Returns (top-k list of (key, id), examined prefix, last update L*, stop
+    position or None, candidates pruned, dimensions read).
+    """
+    top = []
+    run = 0
+    last_update = 0
+    stop = None
+    pruned = 0
+    dims = 0
+    d_full = (prefixes.shape[1] + 1) * ADS_STEP if prefixes.ndim == 2 else 0
+    n = ids.size if limit is None else min(ids.size, int(limit))
+    pos = 0
+    for pos in range(1, n + 1):
+        key = (float(keys[pos - 1]), int(ids[pos - 1]))
+        cut = None
+        if len(top) == k:
+            over = np.flatnonzero(prefixes[pos - 1] > top[-1][0] * factors)
+            if over.size:
+                cut = int(over[0])
+        if cut is not None:
+            pruned += 1
+            dims += (cut + 1) * ADS_STEP
+            run += 1
+        else:
+            dims += d_full
+            if len(top) < k or key < top[-1]:
+                top.append(key)
+                top.sort()
+                del top[k:]
+                run = 0
+                last_update = pos
+            else:
+                run += 1
+        if run >= patience:
+            stop = pos
+            break
+    return top, pos, last_update, stop, pruned, dims
+
+
 def topk_by_key(ids: np.ndarray, dist: np.ndarray, k: int):
     """Top-k by ascending (key, id), padded with (-1, +inf)."""
     order = np.lexsort((ids, dist))[:k]
@@ -206,8 +298,15 @@ def patience_walk(ids: np.ndarray, dist: np.ndarray, k: int, patience: int,
 
 def search_one(index: dict, q: np.ndarray, k: int, *, mode: int, alpha: float,
                tau: int, patience_factor: int = 40, limit: int | None = None,
-               trace: bool = False):
-    """One query through Algorithm 1.  Returns (ids[k], dists[k], trace)."""
+               trace: bool = False, hamming: bool = True, ads: bool = False):
+    """One query through Algorithm 1.  Returns (ids[k], dists[k], trace).
+
+    hamming=False is the ablation of Section 6.4 without Hamming re-ranking:
+    Optimized Mode verifies the candidates in the order C is produced in,
+    ascending id (the paper does not name the order; ids are the natural one).
+    ads=True verifies with ADSampling (Optimized Mode; Algorithm 1's Verify
+    with phi = 1) instead of exact L2 on every walked candidate.
+    """
     n, m = index["n"], index["m"]
     budget = budget_for(alpha, n)
     qp = rotate_query(index, q)[0]
@@ -225,17 +324,31 @@ def search_one(index: dict, q: np.ndarray, k: int, *, mode: int, alpha: float,
         out_i, out_d = topk_by_key(cand, dist, k)
         tr.update(order=cand, examined=cand.size)
     else:
-        order, hdist = hamming_order(index, qp, cand)
-        dist_all = canonical_sqdist(qp, index["base"][order])
-        examined, last_upd, stop = patience_walk(order, dist_all, k, patience_factor * k, limit)
-        out_i, out_d = topk_by_key(order[:examined], dist_all[:examined], k)
+        if hamming:
+            order, hdist = hamming_order(index, qp, cand)
+        else:
+            order, hdist = cand, None
+        if ads:
+            dist_all, pre = sqdist_with_prefixes(qp, index["base"][order])
+            top, examined, last_upd, stop, pruned, dims = ads_walk(
+                order, dist_all, pre, ads_factors(qp.shape[0]), k, patience_factor * k, limit)
+            out_i = np.full(k, -1, dtype=np.int64)
+            out_d = np.full(k, np.inf, dtype=np.float32)
+            for j, (dk, ik) in enumerate(top):
+                out_i[j], out_d[j] = ik, np.float32(dk)
+            tr.update(ads_pruned=pruned, ads_dims=dims)
+        else:
+            dist_all = canonical_sqdist(qp, index["base"][order])
+            examined, last_upd, stop = patience_walk(order, dist_all, k, patience_factor * k, limit)
+            out_i, out_d = topk_by_key(order[:examined], dist_all[:examined], k)
         tr.update(order=order, hamming=hdist, examined=examined, last_update=last_upd,
                   stop=stop, dist_order=dist_all)
     return out_i, out_d, (tr if trace else None)
 
 
 def search(index: dict, queries: np.ndarray, k: int, *, mode: int, alpha: float, tau: int,
-           patience_factor: int = 40, limits=None, trace: bool = False):
+           patience_factor: int = 40, limits=None, trace: bool = False, hamming: bool = True,
+           ads: bool = False):
     """All queries; returns ids (Q, k) int64, dists (Q, k) f32 and traces."""
     queries = np.asarray(queries, dtype=np.float32).reshape(-1, index["d"])
     nq = queries.shape[0]
@@ -248,7 +361,8 @@ def search(index: dict, queries: np.ndarray, k: int, *, mode: int, alpha: float,
         if limits is not None and int(limits[qi]) >= 1:
             lim = int(limits[qi])
         i, d, tr = search_one(index, queries[qi], k, mode=mode, alpha=alpha, tau=tau,
-                              patience_factor=patience_factor, limit=lim, trace=trace)
+                              patience_factor=patience_factor, limit=lim, trace=trace, hamming=hamming,
+                              ads=ads and mode == 1)
         ids[qi], dists[qi] = i, d
         traces.append(tr)
     return ids, dists, traces

@@ -74,6 +74,19 @@ crisp_status check_shape(int64_t n, int32_t d, int32_t m, int32_t k) {
 
 int resolve_tile(int32_t tile_ids) { return tile_ids > 0 ? tile_ids : kDefaultTile; }
 
+// ADSampling (Eq. (2)): eps_0 = 2.1, a test every 32 dimensions below D.
+// factor_t = (t / D) * (b * b) with b = 1 + eps_0 / sqrt(t), float64.
+constexpr double kAdsEps0 = 2.1;
+std::vector<double> ads_factors(int d) {
+  std::vector<double> f;
+  for (int t = kAdsStep; t < d; t += kAdsStep) {
+    const double b = 1.0 + kAdsEps0 / std::sqrt(static_cast<double>(t));
+    f.push_back((static_cast<double>(t) / static_cast<double>(d)) * (b * b));
+  }
+  return f;
+}
+size_t ads_table_bytes(int d) { return align_up(static_cast<size_t>(d / kAdsStep + 1) * sizeof(double)); }
+
 }  // namespace
 
 // Scratch of crisp_search_static: one copy per GPU, held until the process
@@ -115,8 +128,12 @@ struct crisp_index {
   const float *rerr = nullptr;       // per-row bound of the bfloat16 rounding error
   int32_t *tile_off;
   float *cent_t;  // [M][2][h][K]
+  double *ads_fac;  // ADSampling factors (t/D)(1 + eps_0/sqrt(t))^2, t = 32, 64, ... < D
   int ncu = 256;  // compute units of the device the index was loaded on
   void *scratch = nullptr;  // that device's static scratch (crisp_search_static)
+  // Bumped whenever state a captured plan bakes in changes (budget model,
+  // bfloat16 copy); plans re-capture buckets captured under an older value.
+  uint64_t gen = 0;
   std::string scratch_err;  // why it is unavailable
   hipStream_t aux = nullptr;  // second chunk pipeline (overlap = 1)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -158,7 +175,7 @@ struct StageTimer {
 struct Layout {
   size_t qrot, hdist, ptab, ncell, cells, retr, tilecnt, hist, flag, taueff, ncand, segids, segscore, cand,
       score, regA, regB, regC, examined, lastupd, stopped, refined, sstat, feat, lim, queue, order, sclb, scub,
-      flist, nflag, total;
+      flist, nflag, rbytes, total;
 };
 
 static Layout make_layout(const crisp_index *ix, long long qc) {
@@ -197,6 +214,7 @@ static Layout make_layout(const crisp_index *ix, long long qc) {
   L.scub = take(ix->k <= kWave ? qc * ix->m * 2 * ix->k * 4 : 0);
   L.flist = take(qc * 4);
   L.nflag = take(4);
+  L.rbytes = take(qc * 8);
   L.total = o;
   return L;
 }
@@ -223,7 +241,7 @@ crisp_status crisp_index_derived_bytes(const crisp_index_desc *desc, int32_t til
   long long ncells = static_cast<long long>(desc->k_half) * desc->k_half;
   const size_t h = static_cast<size_t>(desc->d) / (2 * desc->m);
   *bytes = align_up(static_cast<size_t>(desc->m) * ncells * (ntiles + 1) * 4) +
-           align_up(static_cast<size_t>(desc->m) * 2 * desc->k_half * h * 4) + 256;
+           align_up(static_cast<size_t>(desc->m) * 2 * desc->k_half * h * 4) + ads_table_bytes(desc->d) + 256;
   return CRISP_OK;
 }
 
@@ -261,6 +279,15 @@ crisp_status crisp_index_load(const crisp_index_desc *desc, int32_t tile_ids, vo
   const long long ncent = static_cast<long long>(desc->m) * 2 * desc->k_half * hh;
   k_transpose_centroids<<<grid1(ncent, 256), 256, 0, st>>>(desc->centroids, desc->m, desc->k_half, hh, cent_t);
   LAUNCH_TRY("k_transpose_centroids");
+  // ADSampling factors of Eq. (2), formed on the host in IEEE float64 (one
+  // correctly rounded square root each); the copy completes before returning.
+  double *ads_fac = reinterpret_cast<double *>(reinterpret_cast<char *>(cent_t) +
+                                               align_up(static_cast<size_t>(desc->m) * 2 * desc->k_half * hh * 4));
+  std::vector<double> fac = ads_factors(desc->d);
+  if (!fac.empty()) {
+    HIP_TRY(hipMemcpyAsync(ads_fac, fac.data(), fac.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_count<0>), hipFuncAttributeMaxDynamicSharedMemorySize,
                               tile));
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_count<1>), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -268,13 +295,14 @@ crisp_status crisp_index_load(const crisp_index_desc *desc, int32_t tile_ids, vo
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_count<2>), hipFuncAttributeMaxDynamicSharedMemorySize,
                               tile));
   {
-    const void *rr[4] = {reinterpret_cast<const void *>(&k_rerank<0, false>),
+    const void *rr[5] = {reinterpret_cast<const void *>(&k_rerank<0, false>),
                          reinterpret_cast<const void *>(&k_rerank<0, true>),
                          reinterpret_cast<const void *>(&k_rerank<1, false>),
-                         reinterpret_cast<const void *>(&k_rerank<1, true>)};
-    for (int i = 0; i < 4; ++i)
+                         reinterpret_cast<const void *>(&k_rerank<1, true>),
+                         reinterpret_cast<const void *>(&k_rerank<1, false, true>)};
+    for (int i = 0; i < 5; ++i)
       HIP_TRY(hipFuncSetAttribute(rr[i], hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  static_cast<int>(rerank_lds(desc->d, 1024, (i & 1) != 0).total)));
+                                  static_cast<int>(rerank_lds(desc->d, 1024, i < 4 && (i & 1) != 0).total)));
   }
   crisp_index *ix = new (std::nothrow) crisp_index{};
   if (!ix) return fail(CRISP_E_INVALID, "out of host memory");
@@ -283,6 +311,7 @@ crisp_status crisp_index_load(const crisp_index_desc *desc, int32_t tile_ids, vo
   ix->rot = desc->rotation; ix->cent = desc->centroids; ix->base = desc->base;
   ix->off = desc->offsets; ix->ids = desc->ids; ix->codes = desc->codes; ix->tile_off = tile_off;
   ix->cent_t = cent_t;
+  ix->ads_fac = ads_fac;
   {
     int dev = 0, cu = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
@@ -314,6 +343,7 @@ crisp_status crisp_index_enable_bf16(crisp_index *ix, void *buffer, size_t bytes
   if (!buffer) {
     ix->base16 = nullptr;
     ix->rerr = nullptr;
+    ++ix->gen;
     return CRISP_OK;
   }
   size_t need = 0;
@@ -329,6 +359,7 @@ crisp_status crisp_index_enable_bf16(crisp_index *ix, void *buffer, size_t bytes
   LAUNCH_TRY("k_base_bf16");
   ix->base16 = b16;
   ix->rerr = err;
+  ++ix->gen;
   return CRISP_OK;
 }
 
@@ -361,6 +392,12 @@ static crisp_status check_params(const crisp_index *ix, int64_t nq, int32_t k, c
     return fail(CRISP_E_INVALID, "precision 1 and 2 need crisp_index_enable_bf16");
   if (p->persistent != 0 && p->persistent != 1) return fail(CRISP_E_INVALID, "persistent must be 0 or 1");
   if (p->overlap != 0 && p->overlap != 1) return fail(CRISP_E_INVALID, "overlap must be 0 or 1");
+  if (p->walk_order != 0 && p->walk_order != 1) return fail(CRISP_E_INVALID, "walk_order must be 0 or 1");
+  if (p->walk_order == 1 && p->budget_source == 1)
+    return fail(CRISP_E_INVALID, "the learned budget's features need the Hamming order (walk_order 0)");
+  if (p->verify != 0 && p->verify != 1) return fail(CRISP_E_INVALID, "verify must be 0 or 1");
+  if (p->verify == 1 && p->mode != 1) return fail(CRISP_E_INVALID, "ADSampling (verify 1) is for Optimized Mode");
+  if (p->verify == 1 && p->precision != 0) return fail(CRISP_E_INVALID, "ADSampling (verify 1) needs precision 0");
   return CRISP_OK;
 }
 
@@ -419,7 +456,7 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
   const double lterms = static_cast<double>((d / 8 + kWave - 1) / kWave * 8 + 10) * 5.9604644775390625e-08;
   const double gam = lterms / (1.0 - lterms);
   auto rerank0 = bf16 ? k_rerank<0, true> : k_rerank<0, false>;
-  auto rerank1 = bf16 ? k_rerank<1, true> : k_rerank<1, false>;
+  auto rerank1 = bf16 ? k_rerank<1, true> : (p->verify == 1 ? k_rerank<1, false, true> : k_rerank<1, false>);
   // Persistent re-rank: as many blocks as fit on the chip at once.
   int rr_resident = 0;
   if (p->persistent) {
@@ -464,6 +501,7 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
     double *sstat = reinterpret_cast<double *>(ws + L.sstat);
     float *feat = reinterpret_cast<float *>(ws + L.feat);
     int32_t *llim = reinterpret_cast<int32_t *>(ws + L.lim);
+    long long *rbytes = reinterpret_cast<long long *>(ws + L.rbytes);
     const int cq = static_cast<int>(std::min<long long>(qc, nq - q0));
     const float *qin = queries + q0 * d;
     const int32_t *lv = live_base ? live_base + q0 / qc : nullptr;
@@ -539,7 +577,9 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       t7.stop();
     }
     const int32_t *lim = p->limits ? p->limits + q0 : nullptr;
-    if (p->mode == 1) {
+    // walk_order 1 (ablation): the walk takes the candidates in id order
+    const bool ham = p->walk_order == 0;
+    if (p->mode == 1 && ham) {
       // A5
       StageTimer t4(ix, 4, st);  // distances
       {
@@ -557,8 +597,10 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
                                                      segids, regB, lv);
       LAUNCH_TRY("k_hamming_place");
       t1.stop();
+    }
+    if (p->mode == 1) {
       // learned budget: features, then bfloat16 MFMA inference -> limits
-      if (p->budget_source == 1 || (taps && taps->features)) {
+      if (ham && (p->budget_source == 1 || (taps && taps->features))) {
         StageTimer t6(ix, 6, st);
         k_features<<<grid1(cq, 256), 256, 0, st>>>(cq, m, d, k, 1, ncand, hist, taueff, sstat, regB, n, feat, lv);
         LAUNCH_TRY("k_features");
@@ -577,10 +619,10 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
         LAUNCH_TRY("k_fill");
       }
       rerank1<<<p->persistent ? std::min(cq, rr_resident) : xcd_pad(cq), kRerankThreads, rr_lds, st>>>(qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
-                                                        segids, n, k, patience, lim, regC, nullptr, nullptr,
+                                                        ham ? segids : cand, n, k, patience, lim, regC, nullptr, nullptr,
                                                         ids + q0 * k,
-                                                        dists + q0 * k, exam, lastu, stopd, refd, lv, cq,
-                                                        p->persistent ? queue : nullptr, qord);
+                                                        dists + q0 * k, exam, lastu, stopd, refd, ix->ads_fac,
+                                                        rbytes, lv, cq, p->persistent ? queue : nullptr, qord);
       LAUNCH_TRY("k_rerank");
       t5.stop();
     } else {
@@ -592,8 +634,8 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       rerank0<<<p->persistent ? std::min(cq, rr_resident) : xcd_pad(cq), kRerankThreads, rr_lds, st>>>(qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
                                                         cand, n, k, patience, lim, regC,
                                                         reinterpret_cast<float *>(regA), regB, ids + q0 * k,
-                                                        dists + q0 * k, exam, lastu, stopd, refd, lv, cq,
-                                                        p->persistent ? queue : nullptr, qord);
+                                                        dists + q0 * k, exam, lastu, stopd, refd, ix->ads_fac,
+                                                        rbytes, lv, cq, p->persistent ? queue : nullptr, qord);
       LAUNCH_TRY("k_rerank");
       t5.stop();
     }
@@ -609,7 +651,7 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       if ((s = tap_copy(taps->n_cand ? taps->n_cand + q0 : nullptr, ncand, size_t(cq) * 4, st))) return s;
       if ((s = tap_copy(taps->cand ? taps->cand + q0 * n : nullptr, cand, qn * 4, st))) return s;
       if ((s = tap_copy(taps->cand_score ? taps->cand_score + q0 * n : nullptr, score, qn, st))) return s;
-      if (p->mode == 1) {
+      if (p->mode == 1 && ham) {
         if ((s = tap_copy(taps->order ? taps->order + q0 * n : nullptr, segids, qn * 4, st))) return s;
         if ((s = tap_copy(taps->hamming ? taps->hamming + q0 * n : nullptr, regB, qn * 4, st))) return s;
       }
@@ -617,12 +659,13 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       if ((s = tap_copy(taps->last_update ? taps->last_update + q0 : nullptr, lastu, size_t(cq) * 4, st))) return s;
       if ((s = tap_copy(taps->stopped ? taps->stopped + q0 : nullptr, stopd, size_t(cq) * 4, st))) return s;
       if ((s = tap_copy(taps->refined ? taps->refined + q0 : nullptr, refd, size_t(cq) * 4, st))) return s;
+      if ((s = tap_copy(taps->row_bytes ? taps->row_bytes + q0 : nullptr, rbytes, size_t(cq) * 8, st))) return s;
       if (score) {
         const size_t sb = size_t(cq) * m * 2 * kh * 4;
         if ((s = tap_copy(taps->score_lb ? taps->score_lb + q0 * m * 2 * kh : nullptr, sclb, sb, st))) return s;
         if ((s = tap_copy(taps->score_ub ? taps->score_ub + q0 * m * 2 * kh : nullptr, scub, sb, st))) return s;
       }
-      if (p->mode == 1 && (s = tap_copy(taps->features ? taps->features + q0 * nf : nullptr, feat,
+      if (p->mode == 1 && ham && (s = tap_copy(taps->features ? taps->features + q0 * nf : nullptr, feat,
                                         size_t(cq) * nf * 4, st))) return s;
       if (p->budget_source == 1 && (s = tap_copy(taps->limits ? taps->limits + q0 : nullptr, llim,
                                                  size_t(cq) * 4, st))) return s;
@@ -653,6 +696,7 @@ struct crisp_plan {
   int32_t *live = nullptr;
   hipStream_t cap = nullptr;  // private stream the graphs are captured on
   std::vector<hipGraphExec_t> exec;
+  std::vector<uint64_t> exec_gen;  // index generation each bucket was captured under
 };
 
 namespace {
@@ -747,6 +791,7 @@ crisp_status crisp_plan_create(crisp_index *ix, int32_t max_batch, int32_t k, co
   while ((1ll << pl->nbuckets) < max_batch) ++pl->nbuckets;
   ++pl->nbuckets;
   pl->exec.assign(pl->nbuckets, nullptr);
+  pl->exec_gen.assign(pl->nbuckets, 0);
   hipError_t e = hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete pl;
@@ -777,6 +822,7 @@ static crisp_status plan_capture(crisp_plan *pl, int b) {
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(CRISP_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
   pl->exec[b] = x;
+  pl->exec_gen[b] = ix->gen;
   return CRISP_OK;
 }
 
@@ -786,12 +832,23 @@ crisp_status crisp_plan_search(crisp_plan *pl, const float *queries, int64_t nq,
   if (nq < 0 || nq > pl->max_batch) return fail(CRISP_E_INVALID, "nq must be in [0, max_batch]");
   if (nq == 0) return CRISP_OK;
   if (!queries || !ids || !dists) return fail(CRISP_E_INVALID, "null argument");
+  // The index's state may have changed since the plan was made (a budget
+  // model cleared, the bfloat16 copy dropped): validate again.
+  crisp_status sv = check_params(pl->ix, nq, pl->k, &pl->p);
+  if (sv != CRISP_OK) return sv;
   const int b = bucket_of(pl, nq);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (pl->exec[b] && pl->exec_gen[b] != pl->ix->gen) {
+    // Captured before the budget model or bfloat16 copy changed: earlier
+    // replays are ordered on this stream, so wait for them and capture anew.
+    HIP_TRY(hipStreamSynchronize(st));
+    (void)hipGraphExecDestroy(pl->exec[b]);
+    pl->exec[b] = nullptr;
+  }
   if (!pl->exec[b]) {
     crisp_status s = plan_capture(pl, b);
     if (s != CRISP_OK) return s;
   }
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const long long qc = chunk_of(&pl->p, bucket_size(pl, b));
   const int nch = static_cast<int>((bucket_size(pl, b) + qc - 1) / qc);
   const int d = pl->ix->d, k = pl->k;
@@ -835,6 +892,7 @@ crisp_status crisp_set_budget_model(crisp_index *ix, const float *params, int32_
   if (!params) {
     ix->mlp_params = ix->mlp_mean = ix->mlp_std = nullptr;
     ix->mlp_nf = 0;
+    ++ix->gen;
     return CRISP_OK;
   }
   if (f != n_features(ix->m)) return fail(CRISP_E_INVALID, "model has %d features, the index needs %d", f,
@@ -842,6 +900,7 @@ crisp_status crisp_set_budget_model(crisp_index *ix, const float *params, int32_
   if (!feat_mean || !feat_std) return fail(CRISP_E_INVALID, "feature mean and std are required");
   if (!std::isfinite(delta)) return fail(CRISP_E_INVALID, "delta must be finite");
   ix->mlp_params = params; ix->mlp_mean = feat_mean; ix->mlp_std = feat_std; ix->mlp_nf = f; ix->mlp_delta = delta;
+  ++ix->gen;
   return CRISP_OK;
 }
 

@@ -1461,9 +1461,128 @@ __device__ __forceinline__ bool f32_fixed(double p, double c) {
   return static_cast<float>(key_lo(p, c)) == static_cast<float>(key_hi(p, c));
 }
 
+// ---------------------------------------------------------------------------
+// ADSampling (Eq. (2)): a walked candidate is pruned at the first t = 32, 64,
+// ... below D with d_t^2 > r_k^2 * factor_t, where d_t^2 is the distance
+// key's running sum after t dimensions, r_k^2 the k-th key of the top-k when
+// the candidate is walked and factor_t = (t/D)(1 + eps_0/sqrt(t))^2 (table
+// from the host, eps_0 = 2.1).  fl(r * factor_t) is monotone in r, so a row
+// pruned against a larger r is pruned against every smaller one.
+// ---------------------------------------------------------------------------
+constexpr int kAdsStep = 32;
+constexpr double kAdsMargin = 0x1p-50;  // covers the roundings of L / factor and r * factor
+
+// Inclusive prefix sum of a double across the 64 lanes.
+__device__ __forceinline__ double wave_incl_scan_f64(double v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int s = 1; s < kWave; s <<= 1) {
+    const double u = __shfl_up(v, s, kWave);
+    if (lane >= s) v = v + u;
+  }
+  return v;
+}
+
+__device__ __forceinline__ double wave_max_f64(double v) {
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) v = fmax(v, __shfl_xor(v, s, kWave));
+  return v;
+}
+
+struct AdsRow {
+  double key, mlo, mhi;
+  int dims;
+  bool pruned;
+};
+
+// One row, whole wave, read in 256-dimension blocks two at a time (lane l
+// holds dimensions 256b + 4l .. + 3 of block b).  After each block the lanes'
+// partial sums are scanned: lane 8j + 7 then holds the wave value p_t of
+// d_t^2 at t = 256b + 32(j + 1), whose defined value lies in [p_t(1 - c_t),
+// p_t(1 + c_t)], c_t = (2t + 16) u (the same argument as the key's, t
+// terms).  The row is pruned for certain when some t has p_t(1 - c_t) >
+// fl(rhi * factor_t) (rhi an upper end of r_k^2); otherwise it is read to the
+// end and gets its wave key and the bounds mlo <= max_t d_t^2 / factor_t <=
+// mhi (widened by kAdsMargin).  dims = dimensions loaded.
+__device__ inline AdsRow ads_row(const float *__restrict__ sq, const float *__restrict__ x, int d, double rhi,
+                                 const double *__restrict__ fac) {
+  const int lane = lane_id();
+  const int nv = d >> 2;
+  const int nblk = (d + 255) >> 8;
+  const float4 *qq = reinterpret_cast<const float4 *>(sq);
+  const float4 *xr = reinterpret_cast<const float4 *>(x);
+  double carry = 0.0, mlo = 0.0, mhi = 0.0;
+  AdsRow r{0.0, 0.0, 0.0, d, false};
+  for (int b0 = 0; b0 < nblk; b0 += 2) {
+    float4 xv[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int g = (b0 + u) * kWave + lane;
+      xv[u] = xr[g < nv ? g : 0];  // clamped: every load is issued
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int b = b0 + u;
+      if (b >= nblk) break;
+      const int g = b * kWave + lane;
+      const bool ok = g < nv;
+      const float4 qv = qq[ok ? g : 0];
+      double v = 0.0;
+      if (ok) {
+        const double t0 = static_cast<double>(qv.x) - static_cast<double>(xv[u].x);
+        const double t1 = static_cast<double>(qv.y) - static_cast<double>(xv[u].y);
+        const double t2 = static_cast<double>(qv.z) - static_cast<double>(xv[u].z);
+        const double t3 = static_cast<double>(qv.w) - static_cast<double>(xv[u].w);
+        const double s0 = t0 * t0, s1 = t1 * t1, s2 = t2 * t2, s3 = t3 * t3;
+        v = s0;
+        v = v + s1;
+        v = v + s2;
+        v = v + s3;
+      }
+      const double p = carry + wave_incl_scan_f64(v);
+      const int t = (g + 1) * 4;  // dimensions summed through this lane's group
+      bool cut = false;
+      if ((lane & 7) == 7 && t < d) {
+        const double ct = (2.0 * t + 16.0) * 0x1p-53;
+        const double f = fac[t / kAdsStep - 1];
+        const double lo = p * (1.0 - ct), hi = p * (1.0 + ct);
+        cut = lo > rhi * f;
+        mlo = fmax(mlo, lo / f);
+        mhi = fmax(mhi, hi / f);
+      }
+      if (__ballot(cut)) {
+        r.pruned = true;
+        r.dims = min(d, (b0 + 2) * 256);
+        return r;
+      }
+      carry = readlane_f64(p, kWave - 1);
+    }
+  }
+  r.key = carry;
+  r.mlo = wave_max_f64(mlo) * (1.0 - kAdsMargin);
+  r.mhi = wave_max_f64(mhi) * (1.0 + kAdsMargin);
+  return r;
+}
+
+// The ADSampling decision by the definition: the running float64 sum in
+// ascending dimension order against fl(r * factor_t) at every test point.
+__device__ inline bool ads_pruned_seq(const float *__restrict__ sq, const float *__restrict__ x, int d, double r,
+                                      const double *__restrict__ fac) {
+  double acc = 0.0;
+  for (int i = 0; i < d; ++i) {
+    const double t = static_cast<double>(sq[i]) - static_cast<double>(x[i]);
+    const double s = t * t;
+    acc = acc + s;
+    if ((i + 1) % kAdsStep == 0 && i + 1 < d && acc > r * fac[(i + 1) / kAdsStep - 1]) return true;
+  }
+  return false;
+}
+
 struct RerankShared {
   double dk[kChunk];
   int dx[kChunk];  // dk[t] is the defined key (1) or a wave key (0)
+  double amlo[kChunk], amhi[kChunk];  // ADSampling: bounds of max_t d_t^2 / factor_t of a surviving row
+  unsigned long long rbytes;          // bytes of stored rows read for this query
   int sid[kChunk];
   float serr[kChunk];
   int plist[kChunk];
@@ -1799,13 +1918,15 @@ __device__ inline void select_topk(double *__restrict__ keys, const int32_t *__r
       const int32_t *__restrict__ list, long long n, int k, int patience, const int32_t *__restrict__ limits,  \
       double *__restrict__ dkey, float *__restrict__ lbuf, int32_t *__restrict__ rbuf,                        \
       int64_t *__restrict__ out_ids, float *__restrict__ out_d, int32_t *__restrict__ examined,              \
-      int32_t *__restrict__ last_upd, int32_t *__restrict__ stopped, int32_t *__restrict__ refined
+      int32_t *__restrict__ last_upd, int32_t *__restrict__ stopped, int32_t *__restrict__ refined,           \
+      const double *__restrict__ ads_fac, long long *__restrict__ row_bytes
 #define CRISP_RERANK_ARGS                                                                                 \
   qrot, d, base, base16, rerr, gam, ncand, list, n, k, patience, limits, dkey, lbuf, rbuf, out_ids, out_d, \
-      examined, last_upd, stopped, refined
+      examined, last_upd, stopped, refined, ads_fac, row_bytes
 
-// One query, whole block.
-template <int kMode, bool kBf16>
+// One query, whole block.  kAds (Optimized Mode, float32 rows): walked
+// candidates are verified with ADSampling.
+template <int kMode, bool kBf16, bool kAds>
 __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
   extern __shared__ __align__(16) unsigned char dyn[];
   const RerankLds LL = rerank_lds(d, k, kBf16);
@@ -1893,6 +2014,7 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
       last_upd[q] = 0;
       stopped[q] = 0;
       if (refined) refined[q] = nk;
+      if (row_bytes) row_bytes[q] = static_cast<long long>(d) * (kBf16 ? 2ll * nc + 4ll * nk : 4ll * nc);
     }
     return;
   }
@@ -1904,7 +2026,10 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
       const int l = limits[q];
       if (l > 0 && l < lim) lim = l;
     }
-    if (tid == 0) { S.misc[2] = 0; S.misc[3] = 0; S.misc[4] = 0; S.misc[5] = 0; S.misc[6] = 0; S.misc[8] = 0; }
+    if (tid == 0) {
+      S.misc[2] = 0; S.misc[3] = 0; S.misc[4] = 0; S.misc[5] = 0; S.misc[6] = 0; S.misc[8] = 0;
+      S.rbytes = 0;
+    }
     __syncthreads();
     for (int c0 = 0, cnt = 0; c0 < lim; c0 += cnt) {
       // The walk cannot stop within the next patience - run candidates, so a
@@ -1969,12 +2094,30 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
         }
         __syncthreads();
         const int np = S.misc[7];
+        if (tid == 0) S.rbytes += static_cast<unsigned long long>(d) * (2ull * cnt + 4ull * np);
         for (int e = wv; e < np; e += kRerankWaves) {
           const int t = S.plist[e];
           const double dc = row_dist_canon<false>(sq, base + static_cast<long long>(S.sid[t]) * d, d);
           if (lane == 0) { S.dk[t] = dc; S.dx[t] = 0; }
         }
+      } else if constexpr (kAds) {
+        // (a) ADSampling against the k-th key at the chunk start: the walk's
+        // k-th key is never larger, so a row pruned here is pruned in the
+        // walk; the others are read in full and decided again in (c)
+        const double rhi = tn0 >= k ? key_hi(top_d[k - 1], cb) : __longlong_as_double(0x7ff0000000000000ll);
+        for (int t = wv; t < cnt; t += kRerankWaves) {
+          const AdsRow r = ads_row(sq, base + static_cast<long long>(S.sid[t]) * d, d, rhi, ads_fac);
+          if (lane == 0) {
+            S.dk[t] = r.pruned ? __longlong_as_double(0x7ff0000000000000ll) : r.key;
+            S.dx[t] = 0;
+            S.amlo[t] = r.mlo;
+            S.amhi[t] = r.mhi;
+            atomicAdd(&S.rbytes, static_cast<unsigned long long>(r.dims) * 4ull);
+            if (!r.pruned) atomicAdd(&S.misc[8], 1);
+          }
+        }
       } else {
+        if (tid == 0) S.rbytes += static_cast<unsigned long long>(d) * 4ull * cnt;
         // (a) exact keys of the chunk, in parallel
         for (int t = wv; t < cnt; t += kRerankWaves) {
           const double dc = row_dist_canon(sq, base + static_cast<long long>(S.sid[t]) * d, d);
@@ -2040,6 +2183,18 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
           }
           return key_less(S.dk[t], S.sid[t], top_d[e], top_i[e]);
         };
+        // ADSampling of chunk row t against the current k-th key (top-k full)
+        auto ads_cut = [&](int t) -> bool {
+          const double r = top_d[k - 1];
+          const double rl = top_x[k - 1] ? r : key_lo(r, cb), rh = top_x[k - 1] ? r : key_hi(r, cb);
+          if (S.amlo[t] > rh * (1.0 + kAdsMargin)) return true;
+          if (S.amhi[t] < rl * (1.0 - kAdsMargin)) return false;
+          if (!top_x[k - 1]) {
+            top_d[k - 1] = row_dist_seq(sq, base + static_cast<long long>(top_i[k - 1]) * d, d);
+            top_x[k - 1] = 1;
+          }
+          return ads_pruned_seq(sq, base + static_cast<long long>(S.sid[t]) * d, d, top_d[k - 1], ads_fac);
+        };
         int tn = S.misc[2], run = S.misc[3], last = S.misc[4], stop = 0, pos = c0 + cnt, prev = -1;
         const int np = S.misc[7];
         for (int e = 0; e <= np; ++e) {
@@ -2052,7 +2207,9 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
           }
           run += gap;
           if (e == np) break;
-          if (tn < k || before_top(t, k - 1)) {
+          bool cut = false;
+          if constexpr (kAds) cut = tn >= k && ads_cut(t);
+          if (!cut && (tn < k || before_top(t, k - 1))) {
             int p = (tn < k) ? tn : k - 1;
             while (p > 0 && before_top(t, p - 1)) {
               top_d[p] = top_d[p - 1];
@@ -2092,7 +2249,8 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
       examined[q] = S.misc[6];
       last_upd[q] = S.misc[4];
       stopped[q] = S.misc[5];
-      if (refined) refined[q] = kBf16 ? S.misc[8] : S.misc[6];
+      if (refined) refined[q] = (kBf16 || kAds) ? S.misc[8] : S.misc[6];
+      if (row_bytes) row_bytes[q] = static_cast<long long>(S.rbytes);
     }
   }
 }
@@ -2104,8 +2262,8 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
 // launch) until the live positions are exhausted; every block then exits.
 // Position i re-ranks query order[i] (order from k_query_order, which keeps
 // live queries first), or query i when order is NULL.
-template <int kMode, bool kBf16>
-__global__ void __launch_bounds__(kRerankThreads) __attribute__((amdgpu_waves_per_eu(kBf16 ? 4 : 1)))
+template <int kMode, bool kBf16, bool kAds = false>
+__global__ void __launch_bounds__(kRerankThreads) __attribute__((amdgpu_waves_per_eu((kBf16 || kAds) ? 4 : 1)))
 k_rerank(CRISP_RERANK_PARAMS, const int32_t *__restrict__ live, int nq,
                                                            int32_t *__restrict__ queue, const int32_t *__restrict__ order) {
   // One call site, so the per-query code is inlined once.
@@ -2119,7 +2277,7 @@ k_rerank(CRISP_RERANK_PARAMS, const int32_t *__restrict__ live, int nq,
     __syncthreads();
   }
   while (q < nl) {
-    rerank_query<kMode, kBf16>(order ? order[q] : q, CRISP_RERANK_ARGS);
+    rerank_query<kMode, kBf16, kAds>(order ? order[q] : q, CRISP_RERANK_ARGS);
     if (queue == nullptr) break;
     __syncthreads();
     if (threadIdx.x == 0) next = atomicAdd(queue, 1);

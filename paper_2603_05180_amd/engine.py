@@ -38,6 +38,54 @@ def _stream(stream=None) -> ctypes.c_void_p:
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _check_out(name: str, t, dtype, shape, device):
+    """A caller-provided output must be exactly what the C side writes."""
+    if (not isinstance(t, torch.Tensor) or t.dtype != dtype or t.device != device or not t.is_contiguous()
+            or tuple(t.shape) != tuple(shape)):
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape {list(shape)} on {device}")
+
+
+def _check_queries(queries, d: int, device):
+    if (not isinstance(queries, torch.Tensor) or queries.device != device or queries.dtype != torch.float32
+            or not queries.is_contiguous()):
+        raise ValueError("queries must be a contiguous float32 tensor on the index device")
+    if queries.dim() != 2 or queries.shape[1] != d:
+        raise ValueError(f"queries must have shape [nq, {d}]")
+
+
+def _outputs(out, nq: int, k: int, device):
+    if out is None:
+        return (torch.empty(nq, k, dtype=torch.int64, device=device),
+                torch.empty(nq, k, dtype=torch.float32, device=device))
+    if not isinstance(out, (tuple, list)) or len(out) != 2:
+        raise ValueError("out must be a tuple (ids, dists)")
+    ids, dists = out
+    _check_out("out ids", ids, torch.int64, (nq, k), device)
+    _check_out("out dists", dists, torch.float32, (nq, k), device)
+    return ids, dists
+
+
+# Device memory left free after any buffer the binding allocates: kernels'
+# private scratch, kernel arguments and library allocations come from it.
+DEVICE_MEMORY_RESERVE = 4 << 30
+
+
+def ensure_device_memory(nbytes: int, device) -> None:
+    """Refuse (MemoryError, nothing allocated) a buffer that would leave less
+    than DEVICE_MEMORY_RESERVE bytes of device memory free; the allocator's
+    cached blocks are released first."""
+    free, total = torch.cuda.mem_get_info(device)
+    cached = torch.cuda.memory_reserved(device) - torch.cuda.memory_allocated(device)
+    if nbytes + DEVICE_MEMORY_RESERVE <= free + cached:
+        return
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info(device)
+    if nbytes + DEVICE_MEMORY_RESERVE > free:
+        raise MemoryError(f"a buffer of {nbytes / 2**30:.1f} GiB would leave less than "
+                          f"{DEVICE_MEMORY_RESERVE / 2**30:.0f} GiB of the {free / 2**30:.1f} GiB free on {device}; "
+                          f"use a smaller max_chunk or overlap=0")
+
+
 def budget_for(alpha: float, n: int) -> int:
     return max(1, int(math.ceil(float(alpha) * float(n))))
 
@@ -79,7 +127,7 @@ class Index:
         check(lib.crisp_index_load(ctypes.byref(self._desc), int(tile_ids), _ptr(self._derived),
                                    nbytes.value, _stream(stream), ctypes.byref(h)))
         self._h = h
-        self._ws = None
+        self._ws = {}     # one workspace per stream (searches on two streams must not share one)
 
     # ------------------------------------------------------------------
     def free(self):
@@ -104,9 +152,10 @@ class Index:
             {"dropped": pr.dropped}
 
     def params(self, *, mode=0, alpha=0.01, tau=1, patience_factor=40, limits=None, max_chunk=0, budget_source=0,
-               precision=0, persistent=0, overlap=0):
+               precision=0, persistent=0, overlap=0, walk_order=0, verify=0):
         return SearchParams(int(mode), float(alpha), int(tau), int(patience_factor), _ptr(limits), int(max_chunk),
-                            int(budget_source), int(precision), int(persistent), int(overlap))
+                            int(budget_source), int(precision), int(persistent), int(overlap), int(walk_order),
+                            int(verify))
 
     def enable_bf16(self, stream=None, buffer: torch.Tensor | None = None) -> torch.Tensor:
         """bfloat16 copy of the rows + per-row error bounds for precision=1
@@ -146,64 +195,83 @@ class Index:
         check(lib.crisp_search_workspace_bytes(self._h, int(nq), int(k), ctypes.byref(params), ctypes.byref(b)))
         return b.value
 
-    def workspace(self, nq: int, k: int, params: SearchParams) -> torch.Tensor:
+    def workspace(self, nq: int, k: int, params: SearchParams, stream=None) -> torch.Tensor:
+        """The search workspace for `stream` (kept per stream and grown on
+        demand; allocated on that stream so the caching allocator never hands
+        it to another stream while a search may still run there)."""
         need = self.workspace_bytes(nq, k, params)
-        if self._ws is None or self._ws.numel() < need:
-            self._ws = None
-            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
-        return self._ws
+        key = _stream(stream).value
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < need:
+            self._ws.pop(key, None)
+            ws = None
+            ensure_device_memory(need, self.device)
+            if isinstance(stream, torch.cuda.Stream):
+                with torch.cuda.stream(stream):
+                    ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            else:
+                ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
+
+    def tap_specs(self, nq: int) -> dict:
+        """(dtype, shape) of every stage tap crisp_search can fill."""
+        n, m, kh, d = self.n, self.m, self.k_half, self.d
+        return {
+            "q_rot": (torch.float32, (nq, d)),
+            "half_dist": (torch.float64, (nq, m, 2, kh)),
+            "n_cells": (torch.int32, (nq, m)),
+            "cells": (torch.int32, (nq, m, kh * kh)),
+            "retrieved": (torch.int32, (nq, m)),
+            "hist": (torch.int32, (nq, 2 * m + 1)),
+            "tau_eff": (torch.int32, (nq,)),
+            "n_cand": (torch.int32, (nq,)),
+            "cand": (torch.int32, (nq, n)),
+            "cand_score": (torch.uint8, (nq, n)),
+            "examined": (torch.int32, (nq,)),
+            "last_update": (torch.int32, (nq,)),
+            "stopped": (torch.int32, (nq,)),
+            "refined": (torch.int32, (nq,)),
+            "order": (torch.int32, (nq, n)),
+            "hamming": (torch.int32, (nq, n)),
+            "features": (torch.float32, (nq, self.n_features)),
+            "limits": (torch.int32, (nq,)),
+            "score_lb": (torch.float32, (nq, m, 2, kh)),
+            "score_ub": (torch.float32, (nq, m, 2, kh)),
+            "row_bytes": (torch.int64, (nq,)),
+        }
 
     def alloc_taps(self, nq: int, mode: int) -> dict:
-        n, m, kh, d = self.n, self.m, self.k_half, self.d
-        z = dict(device=self.device)
-        t = {
-            "q_rot": torch.empty(nq, d, dtype=torch.float32, **z),
-            "half_dist": torch.empty(nq, m, 2, kh, dtype=torch.float64, **z),
-            "n_cells": torch.empty(nq, m, dtype=torch.int32, **z),
-            "cells": torch.empty(nq, m, kh * kh, dtype=torch.int32, **z),
-            "retrieved": torch.empty(nq, m, dtype=torch.int32, **z),
-            "hist": torch.empty(nq, 2 * m + 1, dtype=torch.int32, **z),
-            "tau_eff": torch.empty(nq, dtype=torch.int32, **z),
-            "n_cand": torch.empty(nq, dtype=torch.int32, **z),
-            "cand": torch.empty(nq, n, dtype=torch.int32, **z),
-            "cand_score": torch.empty(nq, n, dtype=torch.uint8, **z),
-            "examined": torch.empty(nq, dtype=torch.int32, **z),
-            "last_update": torch.empty(nq, dtype=torch.int32, **z),
-            "stopped": torch.empty(nq, dtype=torch.int32, **z),
-            "refined": torch.empty(nq, dtype=torch.int32, **z),
-        }
-        if mode == 1:
-            t["order"] = torch.empty(nq, n, dtype=torch.int32, **z)
-            t["hamming"] = torch.empty(nq, n, dtype=torch.int32, **z)
-            t["features"] = torch.empty(nq, self.n_features, dtype=torch.float32, **z)
-            t["limits"] = torch.empty(nq, dtype=torch.int32, **z)
-        return t
+        only1 = {"order", "hamming", "features", "limits"}
+        skip = {"score_lb", "score_ub"}
+        return {name: torch.empty(shape, dtype=dt, device=self.device)
+                for name, (dt, shape) in self.tap_specs(nq).items()
+                if name not in skip and (mode == 1 or name not in only1)}
 
     def search(self, queries: torch.Tensor, k: int, *, mode: int = 0, alpha: float = 0.01, tau: int = 1,
                patience_factor: int = 40, limits: torch.Tensor | None = None, max_chunk: int = 0,
                budget_source: int = 0, precision: int = 0, persistent: int = 0, overlap: int = 0,
-               taps: dict | None = None, out: tuple | None = None, stream=None):
+               walk_order: int = 0, verify: int = 0, taps: dict | None = None, out: tuple | None = None,
+               stream=None):
         """Algorithm 1 for a batch; returns (ids int64 [nq, k], dists f32 [nq, k])."""
-        if queries.device != self.device or queries.dtype != torch.float32 or not queries.is_contiguous():
-            raise ValueError("queries must be a contiguous float32 tensor on the index device")
-        if queries.dim() != 2 or queries.shape[1] != self.d:
-            raise ValueError(f"queries must have shape [nq, {self.d}]")
+        _check_queries(queries, self.d, self.device)
         if limits is not None and (limits.dtype != torch.int32 or limits.device != self.device
                                    or limits.numel() != queries.shape[0]):
             raise ValueError("limits must be an int32 device tensor with one entry per query")
         nq = int(queries.shape[0])
         p = self.params(mode=mode, alpha=alpha, tau=tau, patience_factor=patience_factor,
                         limits=limits, max_chunk=max_chunk, budget_source=budget_source, precision=precision,
-                        persistent=persistent, overlap=overlap)
-        ws = self.workspace(nq, k, p)
-        if out is None:
-            ids = torch.empty(nq, k, dtype=torch.int64, device=self.device)
-            dists = torch.empty(nq, k, dtype=torch.float32, device=self.device)
-        else:
-            ids, dists = out
+                        persistent=persistent, overlap=overlap, walk_order=walk_order, verify=verify)
+        ids, dists = _outputs(out, nq, int(k), self.device)
         tp = None
         if taps is not None:
+            specs = self.tap_specs(nq)
+            for name, t in taps.items():
+                if name not in specs:
+                    raise ValueError(f"unknown tap {name!r}")
+                _check_out(f"tap {name}", t, specs[name][0], specs[name][1], self.device)
             tp = Taps(*[_ptr(taps.get(f)) for f in _lib.TAP_FIELDS])
+        ws = self.workspace(nq, k, p, stream)
         check(lib.crisp_search(self._h, _ptr(queries), nq, int(k), ctypes.byref(p), _ptr(ids), _ptr(dists),
                                _ptr(ws), ws.numel(), ctypes.byref(tp) if tp is not None else None,
                                _stream(stream)))
@@ -212,17 +280,14 @@ class Index:
     def search_static(self, queries: torch.Tensor, k: int, *, out: tuple | None = None, stream=None, **params):
         """crisp_search_static: as search() (no taps, one pipeline), with the
         library's static per-GPU scratch instead of a workspace."""
-        if queries.device != self.device or queries.dtype != torch.float32 or not queries.is_contiguous():
-            raise ValueError("queries must be a contiguous float32 tensor on the index device")
-        if queries.dim() != 2 or queries.shape[1] != self.d:
-            raise ValueError(f"queries must have shape [nq, {self.d}]")
+        _check_queries(queries, self.d, self.device)
         nq = int(queries.shape[0])
+        if params.get("limits") is not None:
+            lim = params["limits"]
+            if lim.dtype != torch.int32 or lim.device != self.device or lim.numel() != nq:
+                raise ValueError("limits must be an int32 device tensor with one entry per query")
         p = self.params(**params)
-        if out is None:
-            ids = torch.empty(nq, k, dtype=torch.int64, device=self.device)
-            dists = torch.empty(nq, k, dtype=torch.float32, device=self.device)
-        else:
-            ids, dists = out
+        ids, dists = _outputs(out, nq, int(k), self.device)
         check(lib.crisp_search_static(self._h, _ptr(queries), nq, int(k), ctypes.byref(p), _ptr(ids), _ptr(dists),
                                       _stream(stream)))
         return ids, dists
@@ -239,6 +304,7 @@ class Plan:
         self._p = index.params(**params)
         b = ctypes.c_size_t(0)
         check(lib.crisp_plan_bytes(index._h, int(max_batch), int(k), ctypes.byref(self._p), ctypes.byref(b)))
+        ensure_device_memory(b.value, index.device)
         self._buf = torch.empty(b.value, dtype=torch.uint8, device=index.device)
         h = ctypes.c_void_p(0)
         check(lib.crisp_plan_create(index._h, int(max_batch), int(k), ctypes.byref(self._p), _ptr(self._buf),
@@ -247,14 +313,11 @@ class Plan:
         self.index, self.max_batch, self.k = index, int(max_batch), int(k)
 
     def search(self, queries: torch.Tensor, out: tuple | None = None, stream=None):
-        if queries.device != self.index.device or queries.dtype != torch.float32 or not queries.is_contiguous():
-            raise ValueError("queries must be a contiguous float32 tensor on the index device")
+        _check_queries(queries, self.index.d, self.index.device)
         nq = int(queries.shape[0])
-        if out is None:
-            ids = torch.empty(nq, self.k, dtype=torch.int64, device=self.index.device)
-            dists = torch.empty(nq, self.k, dtype=torch.float32, device=self.index.device)
-        else:
-            ids, dists = out
+        if nq > self.max_batch:
+            raise ValueError(f"a batch holds at most {self.max_batch} queries")
+        ids, dists = _outputs(out, nq, self.k, self.index.device)
         check(lib.crisp_plan_search(self._h, _ptr(queries), nq, _ptr(ids), _ptr(dists), _stream(stream)))
         return ids, dists
 

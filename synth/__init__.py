@@ -150,6 +150,9 @@ WORKLOADS = {
     # Plain engine at scale (local rank-32 factors, 100 comps), D=960.
     "d960": Workload("d960", 1_000_000, 960, 100, 32, 0.1, "local",
                      1002, 2002, 4002, 16, 16, 10_000, 10),
+    # The same data with K = 256 centroids per half (65,536 cells per subspace).
+    "d960k256": Workload("d960k256", 1_000_000, 960, 100, 32, 0.1, "local",
+                         1002, 2002, 4002, 16, 256, 10_000, 10),
     # Strongly correlated global rank-64 data, D=4096: the rotation fires.
     "d4096": Workload("d4096", 1_000_000, 4096, 100, 64, 0.05, "global",
                      1003, 2003, 4003, 32, 50, 10_000, 10),

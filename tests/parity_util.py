@@ -27,26 +27,28 @@ def gpu_index(idx, tile_ids=0):
 
 
 def run_gpu(gidx, q: np.ndarray, k: int, *, mode, alpha, tau, patience_factor=40, limits=None, max_chunk=0,
-            precision=0):
+            precision=0, walk_order=0, verify=0):
     qt = torch.from_numpy(np.ascontiguousarray(q, dtype=np.float32)).to(gidx.device)
-    taps = gidx.alloc_taps(q.shape[0], mode)
+    taps = gidx.alloc_taps(q.shape[0], mode if walk_order == 0 else 0)
     lim = None
     if limits is not None:
         lim = torch.from_numpy(np.asarray(limits, dtype=np.int32)).to(gidx.device)
     ids, d = gidx.search(qt, k, mode=mode, alpha=alpha, tau=tau, patience_factor=patience_factor,
-                         limits=lim, max_chunk=max_chunk, precision=precision, taps=taps)
+                         limits=lim, max_chunk=max_chunk, precision=precision, walk_order=walk_order,
+                         verify=verify, taps=taps)
     torch.cuda.synchronize()
     return ids.cpu().numpy(), d.cpu().numpy(), {kk: v.cpu().numpy() for kk, v in taps.items()}
 
 
 def compare(idx, q, k, *, mode, alpha, tau, patience_factor=40, limits=None, gpu=None, max_chunk=0,
-            tile_ids=0, check_stages=True, precision=0):
+            tile_ids=0, check_stages=True, precision=0, walk_order=0, verify=0):
     """Run both sides; assert bit-exact stages and results.  Returns a summary."""
     g = gpu if gpu is not None else gpu_index(idx, tile_ids)
     gi, gd, tp = run_gpu(g, q, k, mode=mode, alpha=alpha, tau=tau, patience_factor=patience_factor,
-                         limits=limits, max_chunk=max_chunk, precision=precision)
+                         limits=limits, max_chunk=max_chunk, precision=precision, walk_order=walk_order,
+                         verify=verify)
     oi, od, tr = oquery.search(idx, q, k, mode=mode, alpha=alpha, tau=tau, patience_factor=patience_factor,
-                               limits=limits, trace=True)
+                               limits=limits, trace=True, hamming=(walk_order == 0), ads=(verify == 1))
     m, kh, n = idx["m"], idx["k_half"], idx["n"]
     for qi in range(q.shape[0]):
         t = tr[qi]
@@ -71,8 +73,9 @@ def compare(idx, q, k, *, mode, alpha, tau, patience_factor=40, limits=None, gpu
             hist = np.bincount(v[v >= floor], minlength=2 * m + 1)
             assert np.array_equal(tp["hist"][qi], hist), f"hist q={qi}"
             if mode == 1:
-                assert np.array_equal(tp["order"][qi, :nc], t["order"]), f"order q={qi}"
-                assert np.array_equal(tp["hamming"][qi, :nc], t["hamming"]), f"hamming q={qi}"
+                if walk_order == 0:
+                    assert np.array_equal(tp["order"][qi, :nc], t["order"]), f"order q={qi}"
+                    assert np.array_equal(tp["hamming"][qi, :nc], t["hamming"]), f"hamming q={qi}"
                 assert int(tp["examined"][qi]) == t["examined"], f"examined q={qi}"
                 assert int(tp["last_update"][qi]) == t["last_update"], f"last_update q={qi}"
                 assert int(tp["stopped"][qi]) == (0 if t["stop"] is None else 1), f"stopped q={qi}"
@@ -103,3 +106,59 @@ def key_stress_rows(d: int = 128):
     c[0] = -1.0
     c[1] = -2.0 ** -12
     return {"A": a, "B": b, "C": c}
+
+
+# ---------------------------------------------------------------------------
+# The oracle on many queries at full size: worker processes (new interpreters,
+# numpy and the oracle only) over the index arrays memory-mapped from files.
+# ---------------------------------------------------------------------------
+def oracle_pool(n: int = 0):
+    import multiprocessing as mp
+    import os
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return mp.get_context("spawn").Pool(n or min(16, avail), initializer=_pool_init)
+
+
+def _pool_init():
+    import os
+    os.environ["OMP_NUM_THREADS"] = "1"
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+
+
+def _mapped(paths, meta):
+    index = dict(meta)
+    for name, path in paths.items():
+        index[name] = None if path is None else np.load(path, mmap_mode="r")
+    return index
+
+
+def _oracle_one(task):
+    from oracle import mlp as omlp
+    paths, meta, q, k, okw, feats = task
+    index = _mapped(paths, meta)
+    ids, dists, tr = oquery.search(index, q[None, :], k, trace=True, **okw)
+    t = tr[0]
+    rec = {"ids": ids[0], "dists": dists[0], "q_rot": t["q_rot"], "tau_eff": t["tau_eff"],
+           "candidates": np.asarray(t["candidates"]), "examined": t["examined"]}
+    if okw["mode"] == 1:
+        rec.update(order=np.asarray(t["order"]), last_update=t["last_update"], stopped=t["stop"] is not None)
+        if t.get("hamming") is not None:
+            rec["hamming"] = np.asarray(t["hamming"])
+        if feats:
+            rec["features"] = omlp.features(index, t, k)
+    return rec
+
+
+def oracle_many(pool, paths, meta, q: np.ndarray, k: int, feats=False, limits=None, **okw):
+    """oracle traces of every row of q (one task per query)."""
+    tasks = []
+    for i in range(q.shape[0]):
+        kw = dict(okw)
+        if limits is not None and int(limits[i]) >= 1:
+            kw["limits"] = np.array([int(limits[i])])
+        tasks.append((paths, meta, q[i], k, kw, feats))
+    return pool.map(_oracle_one, tasks, chunksize=1)

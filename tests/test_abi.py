@@ -87,3 +87,25 @@ def test_static_scratch_entry_point():
     with open(os.path.join(ROOT, "include", "crisp.h")) as f:
         m = re.search(r"#define CRISP_STATIC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", f.read())
     assert m and int(m.group(1)) << int(m.group(2)) == _lib.STATIC_SCRATCH_BYTES
+
+
+def test_binding_validates_outputs_on_the_host():
+    """The binding's checks of caller-provided outputs and queries (CPU
+    tensors stand in for device ones; nothing reaches the library)."""
+    import pytest
+    import torch
+    from paper_2603_05180_amd import engine
+    dev = torch.device("cpu")
+    ids, d = engine._outputs(None, 4, 3, dev)
+    assert ids.shape == (4, 3) and ids.dtype == torch.int64 and d.dtype == torch.float32
+    ok = (torch.empty(4, 3, dtype=torch.int64), torch.empty(4, 3, dtype=torch.float32))
+    assert engine._outputs(ok, 4, 3, dev)[0] is ok[0]
+    for bad in [(ok[0],), (torch.empty(4, 2, dtype=torch.int64), ok[1]), (ok[0], torch.empty(4, 3, dtype=torch.float64)),
+                (ok[0], torch.empty(3, 4, dtype=torch.float32).t()), (ok[0].int(), ok[1])]:
+        with pytest.raises(ValueError):
+            engine._outputs(bad, 4, 3, dev)
+    engine._check_queries(torch.zeros(5, 64), 64, dev)
+    for bad in [torch.zeros(5, 32), torch.zeros(320), torch.zeros(5, 64, dtype=torch.float64),
+                torch.zeros(64, 5).t(), "queries"]:
+        with pytest.raises(ValueError):
+            engine._check_queries(bad, 64, dev)

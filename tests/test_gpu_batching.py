@@ -78,6 +78,36 @@ def test_plan_with_learned_budget(d128):
     g.set_budget_model(None)
 
 
+def test_plan_follows_budget_model_and_bf16_changes(d128):
+    """A plan captured under one budget model (or bfloat16 copy) must not
+    replay stale state after it changes: the bucket is captured anew."""
+    from paper_2603_05180_amd import engine
+    w, x, q, idx, g = d128
+    f = g.n_features
+    p = omlp.init_params(f, 5)
+    p["b2"] = np.array([3.0], np.float32)
+    flat = np.concatenate([p["w1"].reshape(-1), p["b1"], p["w2"], p["b2"]]).astype(np.float32)
+    params = torch.from_numpy(flat).cuda()
+    mean, std = torch.zeros(f, device="cuda"), torch.ones(f, device="cuda")
+    kw = dict(mode=1, alpha=0.05, tau=4, budget_source=1, precision=1)
+    qb = q[:50].contiguous()
+    g.set_budget_model(params, mean, std, -2.0)
+    plan = engine.Plan(g, 64, 10, **kw)
+    first = plan.search(qb)
+    _same(first, g.search(qb, 10, **kw))
+    g.set_budget_model(params, mean, std, 1.5)        # another margin: other limits
+    second = plan.search(qb)
+    _same(second, g.search(qb, 10, **kw))
+    torch.cuda.synchronize()
+    assert not torch.equal(first[0], second[0])        # the change is visible
+    g.enable_bf16()                                     # new copy, new pointers
+    _same(plan.search(qb), g.search(qb, 10, **kw))
+    g.set_budget_model(None)
+    with pytest.raises(engine.CrispError):              # the model is gone
+        plan.search(qb)
+    plan.free()
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_results_do_not_depend_on_tiles_or_chunks(d128, mode):
     from paper_2603_05180_amd import engine

@@ -102,8 +102,15 @@ def test_bad_options_and_plan_limits(small):
             g.search(qt, 5, mode=1, alpha=0.1, tau=2, **kw)
         assert e.value.status == -1
     plan = engine.Plan(g, 4, 5, mode=1, alpha=0.1, tau=2)
-    with pytest.raises(engine.CrispError):
-        plan.search(torch.from_numpy(np.concatenate([q, q])).cuda())       # 8 > max_batch
+    q8 = torch.from_numpy(np.concatenate([q, q])).cuda()
+    with pytest.raises(ValueError):                                        # the binding: 8 > max_batch
+        plan.search(q8)
+    from paper_2603_05180_amd import _lib
+    o_i = torch.empty(8, 5, dtype=torch.int64, device="cuda")
+    o_d = torch.empty(8, 5, dtype=torch.float32, device="cuda")
+    st = _lib.lib.crisp_plan_search(plan._h, ctypes.c_void_p(q8.data_ptr()), 8, ctypes.c_void_p(o_i.data_ptr()),
+                                    ctypes.c_void_p(o_d.data_ptr()), None)
+    assert st == -1                                                        # and the library itself
     plan.free()
     with pytest.raises(ValueError):
         engine.Plan(g, 4, 5, mode=1, alpha=0.1, tau=2, limits=torch.ones(4, dtype=torch.int32, device="cuda"))
@@ -124,3 +131,59 @@ def test_overlap_needs_the_doubled_workspace(small):
     P = lambda t: ctypes.c_void_p(t.data_ptr())
     st = _lib.lib.crisp_search(g._h, P(qt), 16, 5, ctypes.byref(p2), P(ids), P(d), P(ws), b1, None, None)
     assert st == -2
+
+
+def test_mis_shaped_tensors_are_rejected_before_launch(small):
+    """Outputs, taps and queries that do not match what the C side writes or
+    reads raise ValueError in the binding (no launch)."""
+    from paper_2603_05180_amd import engine
+    w, x, q, idx = small
+    g = engine.Index(idx)
+    qt = torch.from_numpy(q).cuda()
+    nq, k = qt.shape[0], 3
+    good = (torch.empty(nq, k, dtype=torch.int64, device="cuda"), torch.empty(nq, k, dtype=torch.float32, device="cuda"))
+    bad_outs = [
+        (torch.empty(nq, k + 1, dtype=torch.int64, device="cuda"), good[1]),
+        (good[0], torch.empty(nq, k, dtype=torch.float64, device="cuda")),
+        (torch.empty(nq, k, dtype=torch.int32, device="cuda"), good[1]),
+        (good[0], torch.empty(k, nq, dtype=torch.float32, device="cuda").t()),
+        (torch.empty(nq, k, dtype=torch.int64), good[1]),
+    ]
+    for out in bad_outs:
+        with pytest.raises(ValueError):
+            g.search(qt, k, mode=0, alpha=0.1, tau=2, out=out)
+        with pytest.raises(ValueError):
+            g.search_static(qt, k, mode=0, alpha=0.1, tau=2, out=out)
+    taps = g.alloc_taps(nq, 1)
+    taps["cand"] = torch.empty(nq, g.n - 1, dtype=torch.int32, device="cuda")
+    with pytest.raises(ValueError):
+        g.search(qt, k, mode=1, alpha=0.1, tau=2, taps=taps)
+    with pytest.raises(ValueError):
+        g.search(qt, k, mode=0, alpha=0.1, tau=2, taps={"nonsense": good[0]})
+    plan = engine.Plan(g, 8, k, mode=0, alpha=0.1, tau=2)
+    with pytest.raises(ValueError):
+        plan.search(qt[:, : g.d // 2].contiguous())
+    with pytest.raises(ValueError):
+        plan.search(qt.reshape(-1))
+    with pytest.raises(ValueError):
+        plan.search(torch.zeros(9, g.d, device="cuda"))
+    with pytest.raises(ValueError):
+        plan.search(qt, out=bad_outs[0])
+    ids, d = g.search(qt, k, mode=0, alpha=0.1, tau=2, out=good)
+    torch.cuda.synchronize()
+    assert ids.data_ptr() == good[0].data_ptr()
+    plan.free()
+
+
+def test_searches_on_two_streams_use_two_workspaces(small):
+    from paper_2603_05180_amd import engine
+    w, x, q, idx = small
+    g = engine.Index(idx)
+    qt = torch.from_numpy(q).cuda()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    a = g.search(qt, 3, mode=0, alpha=0.1, tau=2, stream=s1)
+    b = g.search(qt, 3, mode=0, alpha=0.1, tau=2, stream=s2)
+    torch.cuda.synchronize()
+    assert len(g._ws) >= 2
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])

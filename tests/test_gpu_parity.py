@@ -154,3 +154,59 @@ def test_hamming_order_wide_ranges():
     print("D=1024 alpha=1 spans", spans, flush=True)
     assert min(spans) >= 256, spans
     compare(idx, q, 10, mode=1, alpha=1.0, tau=1)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_walk_in_id_order(d128, precision):
+    """Optimized Mode without the Hamming order (the Section 6.4 ablation):
+    candidates verified in ascending id order, patience as usual."""
+    w, x, q, idx = d128[:4]
+    g = gpu_index(idx)
+    if precision:
+        g.enable_bf16()
+    for pf in (2, 40):
+        print(f"id-order walk precision={precision} patience={pf}", flush=True)
+        compare(idx, q, w.k, mode=1, alpha=0.05, tau=4, patience_factor=pf, gpu=g, precision=precision,
+                walk_order=1)
+
+
+@pytest.fixture(scope="module")
+def d128_rotated():
+    w, x, q = make_workload("d128", n_query=60)
+    idx = oracle_index(w, x, force_rotation=True)
+    return w, x, q, idx
+
+
+@pytest.mark.parametrize("k,pf", [(1, 40), (10, 2), (10, 40), (100, 5)])
+def test_adsampling_walk(d128_rotated, k, pf):
+    """Optimized Mode with ADSampling (Eq. (2)) on a rotated index: the
+    verified prefix, last update, stop flag, ids and distances equal the
+    oracle's sequential walk."""
+    w, x, q, idx = d128_rotated
+    g = gpu_index(idx)
+    print(f"adsampling k={k} patience={pf}", flush=True)
+    r = compare(idx, q, k, mode=1, alpha=0.05, tau=4, patience_factor=pf, gpu=g, verify=1)
+    assert sum(r["n_cand"]) > 0
+
+
+def test_adsampling_unrotated_chunks_and_limits(d128):
+    """Unrotated data (the test still runs; only its statistics change),
+    7-query chunks, learned-style prefix limits."""
+    w, x, q, idx = d128[:4]
+    g = gpu_index(idx)
+    lim = np.array([0, 1, 5, 17, 40, 300] * 17)[: q.shape[0]]
+    compare(idx, q, 10, mode=1, alpha=0.05, tau=4, patience_factor=3, gpu=g, verify=1, max_chunk=7, limits=lim)
+
+
+def test_adsampling_rejects_guaranteed_and_bf16(d128):
+    import torch
+    from paper_2603_05180_amd import engine
+    w, x, q, idx = d128[:4]
+    g = gpu_index(idx)
+    g.enable_bf16()
+    qt = torch.from_numpy(q).cuda()
+    for kw in (dict(mode=0), dict(mode=1, precision=1), dict(mode=1, verify=2)):
+        args = dict(alpha=0.05, tau=4, verify=1)
+        args.update(kw)
+        with pytest.raises(engine.CrispError):
+            g.search(qt, 10, **args)

@@ -126,3 +126,27 @@ def test_bench_measures_one_gpu_only():
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
     assert r.stdout == ""
+
+
+def test_bench_matched_recall_and_cache_served_stages():
+    """bench.py's learned-vs-plain comparison interpolates the plain sweep at
+    the learned recall, and a byte-bound stage faster than HBM is labelled
+    cache-served with no HBM fraction from algorithmic bytes."""
+    import bench
+    def form(pf, rec, qps, **kw):
+        return {"_kw": dict(patience_factor=pf, **kw), "recall_at_k": rec, "queries_per_s": qps,
+                "mean_verified": pf * 10.0}
+    res = {"bf16": form(40, 0.999, 400.0), "bf16_pf10": form(10, 0.98, 500.0), "bf16_pf20": form(20, 0.995, 460.0),
+           "learned_bf16": form(40, 0.9975, 450.0, budget_source=1)}
+    mr = bench.matched_recall(res)
+    # between pf20 (0.995, 460) and pf40 (0.999, 400): 460 - 0.625 * 60 = 422.5
+    assert abs(mr["plain_queries_per_s_at_learned_recall"] - 422.5) < 1e-6
+    assert mr["learned_gain"] > 0 and mr["outcome"].startswith("learned beats")
+    res["learned_bf16"]["queries_per_s"] = 420.0
+    assert bench.matched_recall(res)["outcome"].startswith("no gain")
+    stages = {"rerank": {"ms": 10.0, "intervals": 5}, "hamming_dist": {"ms": 1.0, "intervals": 5},
+              "dropped": 0}
+    per_step = {"rerank": ("hbm", 10.0, 8000.0, "GB/s"), "hamming_dist": ("hbm", 50.0, 8000.0, "GB/s")}
+    out, _ = bench.stage_rates(stages, 5, per_step, "none")
+    assert out["rerank"]["bound"] == "hbm" and abs(out["rerank"]["frac"] - 5000.0 / 8000.0) < 1e-9
+    assert out["hamming_dist"]["bound"] == "l2/mall" and out["hamming_dist"]["frac"] is None

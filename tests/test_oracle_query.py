@@ -308,3 +308,125 @@ def test_key_on_rows_where_order_matters():
         pair = pair[:, 0::2] + pair[:, 1::2]
     assert pair[0, 0] > got[1] > got[0]
     assert np.float32(pair[1, 0]) != np.float32(got[2])
+
+
+def test_walk_without_hamming_order_is_the_id_order_walk():
+    """The Section 6.4 ablation without Hamming re-ranking walks C in ascending
+    id order: its trace equals the patience walk over C as produced."""
+    import synth
+    from oracle import build as obuild
+    w = synth.WORKLOADS["d128"].scaled(n=1500, n_query=3)
+    p = synth.mixture_params(w)
+    x = synth.rows(w, w.seed_data, 0, w.n, p)
+    q = synth.rows(w, w.seed_query, 0, w.n_query, p)
+    idx = obuild.build_index_for(w, x)
+    _, _, tr = query.search(idx, q, 5, mode=1, alpha=0.05, tau=3, patience_factor=2, trace=True, hamming=False)
+    for t in tr:
+        assert np.array_equal(t["order"], t["candidates"])
+        assert np.all(np.diff(t["order"]) > 0)
+        d = query.canonical_sqdist(t["q_rot"], idx["base"][t["candidates"]])
+        assert query.patience_walk(t["candidates"], d, 5, 10)[0] == t["examined"]
+
+
+# ---------------------------------------------------------------------------
+# ADSampling (Eq. (2), Section 4.3.2 Stage 3)
+# ---------------------------------------------------------------------------
+def test_ads_factors_match_eq2_in_high_precision():
+    """(t/D)(1 + eps0/sqrt(t))^2 against 50-digit decimal arithmetic on the
+    same float64 eps0: within a relative 8 u (u = 2^-53; five roundings and
+    a square root, each at most u/2, the square doubling b's error)."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 50
+    for d in (64, 128, 960, 4096):
+        f = query.ads_factors(d)
+        assert f.size == (d - 1) // 32
+        for j, v in enumerate(f):
+            t = 32 * (j + 1)
+            exact = (Decimal(t) / Decimal(d)) * (1 + Decimal(query.ADS_EPS0) / Decimal(t).sqrt()) ** 2
+            assert abs(Decimal(float(v)) - exact) <= exact * Decimal(8) * Decimal(2.0 ** -53)
+        # the margin shrinks with t: (1 + eps0/sqrt(t))^2 decreases towards 1
+        ratio = f * d / np.arange(32, d, 32)
+        assert np.all(np.diff(ratio) < 0) and np.all(ratio > 1)
+
+
+def test_prefixes_are_the_key_of_the_leading_dimensions():
+    """d_t^2 is the key's own running sum: the key of the first t dimensions."""
+    rng = np.random.default_rng(3)
+    q = rng.standard_normal(160).astype(np.float32)
+    x = rng.standard_normal((7, 160)).astype(np.float32)
+    key, pre = query.sqdist_with_prefixes(q, x)
+    assert np.array_equal(key, query.canonical_sqdist(q, x))
+    assert pre.shape == (7, 4)
+    for j in range(4):
+        t = 32 * (j + 1)
+        assert np.array_equal(pre[:, j], query.canonical_sqdist(q[:t], x[:, :t]))
+
+
+def test_ads_walk_without_pruning_is_the_exact_walk():
+    rng = np.random.default_rng(5)
+    n, d, k = 300, 96, 5
+    ids = rng.permutation(10_000)[:n]
+    keys = rng.random(n) * 100
+    pre = rng.random((n, 2)) * 100
+    for patience in (3, 20, 10_000):
+        top, ex, last, stop, pruned, dims = query.ads_walk(ids, keys, pre, np.full(2, np.inf), k, patience)
+        assert (ex, last, stop) == query.patience_walk(ids, keys, k, patience)
+        oi, od = query.topk_by_key(ids[:ex], keys[:ex], k)
+        assert [i for _, i in top] == list(oi) and pruned == 0 and dims == ex * d
+
+
+def test_ads_walk_prunes_by_eq2_on_constructed_rows():
+    """D = 64, k = 1, one test at t = 32 with factor (32/64)(1 + 2.1/sqrt 32)^2
+    ~ 0.94: after a first row at key 64 (r_k^2 = 64, threshold ~ 60.1), a row
+    with d_32^2 = 128 is pruned at t = 32, a row with d_32^2 = 8 and key 296
+    is verified and rejected, a row at key 51.84 updates."""
+    d = 64
+    q = np.zeros(d, dtype=np.float32)
+    rows = np.zeros((4, d), dtype=np.float32)
+    rows[0] = 1.0
+    rows[1, :32] = 2.0
+    rows[2, :32] = 0.5
+    rows[2, 32:] = 3.0
+    rows[3] = 0.9
+    key, pre = query.sqdist_with_prefixes(q, rows)
+    f = query.ads_factors(d)
+    assert f.size == 1 and 60.0 < 64 * f[0] < 60.2
+    ids = np.array([10, 11, 12, 13])
+    top, ex, last, stop, pruned, dims = query.ads_walk(ids, key, pre, f, 1, 100)
+    assert pruned == 1 and dims == 64 + 32 + 64 + 64
+    assert ex == 4 and last == 4 and stop is None
+    assert top == [(float(key[3]), 13)]
+    # the same rows with the top-k not yet full: nothing is pruned
+    top, ex, last, stop, pruned, dims = query.ads_walk(ids, key, pre, f, 2, 100)
+    assert pruned == 0
+
+
+def test_ads_pruning_is_monotone_in_the_kth_key():
+    """A candidate pruned under r_k^2 is pruned under any smaller r_k^2."""
+    rng = np.random.default_rng(8)
+    f = query.ads_factors(4096)
+    for _ in range(200):
+        p = np.cumsum(rng.random(f.size) * 3)
+        r = rng.random() * p[-1]
+        if np.any(p > r * f):
+            assert np.any(p > (r * rng.random()) * f)
+
+
+def test_ads_keeps_nearly_all_exact_results_on_rotated_data():
+    """The statistical guarantee of ADSampling after a random rotation: the
+    walk with Eq. (2) returns almost the same top-k as the exact walk."""
+    import synth
+    from oracle import build as obuild
+    w = synth.WORKLOADS["d128"].scaled(n=3000, n_query=20)
+    p = synth.mixture_params(w)
+    x = synth.rows(w, w.seed_data, 0, w.n, p)
+    q = synth.rows(w, w.seed_query, 0, w.n_query, p)
+    idx = obuild.build_index_for(w, x, force_rotation=True)
+    kw = dict(mode=1, alpha=0.05, tau=3, patience_factor=40)
+    ei, _, _ = query.search(idx, q, 10, **kw)
+    ai, _, tr = query.search(idx, q, 10, ads=True, trace=True, **kw)
+    same = np.mean([len(set(a) & set(e)) / 10.0 for a, e in zip(ai, ei)])
+    assert same >= 0.97
+    assert sum(t["ads_pruned"] for t in tr) > 0
+    read = sum(t["ads_dims"] for t in tr) / float(sum(t["examined"] for t in tr) * w.d)
+    assert read < 0.9
