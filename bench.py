@@ -20,7 +20,7 @@ the bf16 form, which places the learned form against the plain walk at
 matched recall; the ablations of Section 6.4 on this workload (Optimized
 Mode without the Hamming order; the correlation-check threshold, i.e. the
 index with and without its rotation); an alpha x tau operating-point grid;
-the N = 1M, D = 960 workload (K = 256 centroids per half) in both modes at
+the N = 1M, D = 960 workload (K = 16 centroids per half) in both modes at
 k = 10 and 100; uneven batches on N = 2M, D = 3072; and the CPU oracle on
 the host cores, timed in worker processes forked before this process first
 touches the GPU.
@@ -86,7 +86,7 @@ def parse():
     ap.add_argument("--ablations", type=int, default=1,
                     help="Section 6.4 ablations: Hamming order off, correlation-check threshold")
     ap.add_argument("--grid", type=int, default=1, help="alpha x tau operating-point grid of the head form")
-    ap.add_argument("--d960", type=int, default=1, help="time the N=1M, D=960 (K=256) workload, both modes")
+    ap.add_argument("--d960", type=int, default=1, help="time the N=1M, D=960 (K=16) workload, both modes")
     ap.add_argument("--cpu-workers", type=int, default=0,
                     help="CPU oracle worker processes (0 = the host cores, at most 16)")
     ap.add_argument("--label-check", type=int, default=32,
@@ -572,13 +572,13 @@ def cev_ablation(w, kw, cev, head, head_rec, args):
 
 def d960_section(args):
     """The N = 1M, D = 960 workload (100 local rank-32 components, 16
-    subspaces of 60 dims, K = 256 centroids per half; the correlation check
+    subspaces of 60 dims, K = 16 centroids per half; the correlation check
     does not fire): both modes at k = 10 and k = 100, 10,000 queries."""
     import torch
     import synth
     import synth.gpu as sg
     from paper_2603_05180_amd import engine
-    w = synth.WORKLOADS["d960k256"]
+    w = synth.WORKLOADS["d960"]
     t = time.time()
     arrays, params = build_gpu_index(w)
     queries = sg.rows(w, w.seed_query, 0, w.n_query, params)

@@ -30,7 +30,10 @@
  * * Arguments are validated before anything is enqueued; on any error no
  *   output is written.
  * * Limits: D % 64 == 0, D % (2M) == 0, 1 <= M <= 127 (scores fit in 8 bits),
- *   1 <= K <= 256, 1 <= N < 2^31.  Violations return CRISP_E_UNSUPPORTED.
+ *   1 <= K <= 64, 1 <= N < 2^31, D <= 8192.  Violations return
+ *   CRISP_E_UNSUPPORTED.  (The selection also has a path for 64 < K <= 256,
+ *   switched off: a search with it faulted the GPU at N = 1M, K = 256 and
+ *   the cause is not found yet.)
  *
  * Floating-point definitions shared with the CPU reference
  * --------------------------------------------------------

@@ -69,6 +69,10 @@ crisp_status check_shape(int64_t n, int32_t d, int32_t m, int32_t k) {
   if (m > 127) return fail(CRISP_E_UNSUPPORTED, "M must be <= 127");
   if (d % (2 * m) != 0) return fail(CRISP_E_UNSUPPORTED, "D must be a multiple of 2M");
   if (k > 256) return fail(CRISP_E_UNSUPPORTED, "K must be <= 256");
+  // The selection's path for K > 64 (prefix-size tables in device memory)
+  // faulted the GPU in a search at N = 1M, D = 960, K = 256; the cause is
+  // not found yet, so that path is switched off.
+  if (k > 64) return fail(CRISP_E_UNSUPPORTED, "K > 64 is switched off (an unexplained GPU fault at K = 256)");
   return CRISP_OK;
 }
 

@@ -109,3 +109,15 @@ def test_binding_validates_outputs_on_the_host():
                 torch.zeros(64, 5).t(), "queries"]:
         with pytest.raises(ValueError):
             engine._check_queries(bad, 64, dev)
+
+
+def test_codebooks_above_64_are_refused():
+    """K > 64 is switched off in the library (its selection path faulted the
+    GPU at K = 256, cause not found): the shape check refuses it, no launch."""
+    from paper_2603_05180_amd import _lib
+    size = ctypes.c_size_t(0)
+    desc = _lib.IndexDesc(1000, 128, 4, 80, None, None, None, None, None, None)
+    assert _lib.lib.crisp_index_derived_bytes(ctypes.byref(desc), 0, ctypes.byref(size)) == -5
+    assert b"K > 64" in _lib.lib.crisp_last_error()
+    desc = _lib.IndexDesc(1000, 128, 4, 64, None, None, None, None, None, None)
+    assert _lib.lib.crisp_index_derived_bytes(ctypes.byref(desc), 0, ctypes.byref(size)) == 0

@@ -69,7 +69,11 @@ def test_learned_prefix_limits(d128):
     compare(idx, q[:30], w.k, mode=1, alpha=0.05, tau=4, limits=lim)
 
 
-@pytest.mark.parametrize("k_half", [1, 64, 80])
+K_ABOVE_64_OFF = ("the library refuses K > 64: its selection path for K > 64 faulted the GPU in a search "
+                  "at N = 1M, D = 960, K = 256 and the cause is not found yet")
+
+
+@pytest.mark.parametrize("k_half", [1, 64, pytest.param(80, marks=pytest.mark.skip(reason=K_ABOVE_64_OFF))])
 def test_codebook_sizes(k_half):
     """K = 1 (one cell), K = 64 (4096 cells), K = 80 (prefix tables in device memory)."""
     w, x, q = make_workload("d128", n=4000, d=128, m=4, k_half=k_half, n_query=12)
