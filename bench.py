@@ -83,6 +83,7 @@ def parse():
                     help="fraction of the plain top-k the learned budget must keep on held-out queries")
     ap.add_argument("--patience-sweep", default="5,20,30,60",
                     help="extra patience factors of the bf16 form ('' = none; 10 and 40 are always timed)")
+    ap.add_argument("--ads", type=int, default=1, help="also time ADSampling verification (Optimized Mode)")
     ap.add_argument("--ablations", type=int, default=1,
                     help="Section 6.4 ablations: Hamming order off, correlation-check threshold")
     ap.add_argument("--grid", type=int, default=1, help="alpha x tau operating-point grid of the head form")
@@ -178,7 +179,8 @@ def counts(index, queries, k, kw):
     taps = {"examined": torch.empty(nq, dtype=torch.int32, device=dev),
             "refined": torch.empty(nq, dtype=torch.int32, device=dev),
             "n_cand": torch.empty(nq, dtype=torch.int32, device=dev),
-            "retrieved": torch.empty(nq, m, dtype=torch.int32, device=dev)}
+            "retrieved": torch.empty(nq, m, dtype=torch.int32, device=dev),
+            "row_bytes": torch.empty(nq, dtype=torch.int64, device=dev)}
     index.search(queries, k, taps=taps, **kw)
     torch.cuda.synchronize()
     return {key: int(v.long().sum()) for key, v in taps.items()}
@@ -234,6 +236,19 @@ def stage_rates(stages, steps, per_step, workload):
     return out, kernel_of
 
 
+def rerank_bytes_of(kw, c, d):
+    """Algorithmic bytes of stored rows the verification needs per step:
+    the verified prefix in float32, or in bfloat16 (+ a 4-byte bound) plus
+    the float32 rows the bounds kept; with ADSampling the rows as far as the
+    kernel read them (its row-byte count: each pruned row to the end of the
+    256-dimension block pair where the test fired)."""
+    if kw.get("verify", 0) == 1:
+        return float(c["row_bytes"])
+    if kw.get("precision", 0) >= 1:
+        return (2.0 * d + 4.0) * c["examined"] + 4.0 * d * c["refined"]
+    return 4.0 * d * c["examined"]
+
+
 def run_form(index, queries, truth, k, kw, args, ids, dists, plain_ids, base, qrot, d):
     """Warm up, time, count and stage-profile one form; returns its record."""
     import torch
@@ -247,14 +262,14 @@ def run_form(index, queries, truth, k, kw, args, ids, dists, plain_ids, base, qr
     ms, _ = timed(index, queries, k, kw, args.steps, ids, dists)
     c = counts(index, queries, k, dict(kw, overlap=0))
     _, st1 = timed(index, queries, k, dict(kw, overlap=0), 1, ids, dists, profile=True)
-    rr_bytes = (((2.0 * d + 4.0) * c["examined"] + 4.0 * d * c["refined"]) if kw.get("precision", 0) >= 1
-                else 4.0 * d * c["examined"])
+    rr_bytes = rerank_bytes_of(kw, c, d)
     nq = queries.shape[0]
     return {"queries_per_s": round(nq / (ms / 1e3), 1), "ms_per_step": round(ms, 3),
             "recall_at_k": round(rec, 4), "plain_ids_kept": same,
             "mean_verified": round(c["examined"] / nq, 1),
             "mean_float32_rows": round(c["refined"] / nq, 1),
             "mean_candidates": round(c["n_cand"] / nq, 1),
+            "mean_row_bytes_read": round(c["row_bytes"] / nq, 1),
             "rerank_algorithmic_gb_s": round(rr_bytes / 1e9 / (st1["rerank"]["ms"] / 1e3), 1),
             "max_rel_err_vs_fp64": fp64_error(base, qrot, ids, dists),
             "_kw": kw, "_counts": c}
@@ -367,6 +382,11 @@ def measure(args, pool):
         if args.scoring:
             # and with the half distances pre-scored on bfloat16 matrix cores (same results)
             forms[f"bf16_scored_pf{args.tuned_patience}"] = dict(precision=2, patience_factor=args.tuned_patience)
+    if args.mode == 1 and args.ads:
+        # ADSampling verification (float32 rows read only as far as Eq. (2) needs)
+        forms["ads"] = dict(precision=0, verify=1)
+        if args.tuned_patience > 0:
+            forms[f"ads_pf{args.tuned_patience}"] = dict(precision=0, verify=1, patience_factor=args.tuned_patience)
     if args.mode == 1:
         for pf in [int(v) for v in args.patience_sweep.split(",") if v.strip()]:
             forms.setdefault(f"bf16_pf{pf}", dict(precision=1, patience_factor=pf))
@@ -403,7 +423,7 @@ def measure(args, pool):
     # ---- roofline of each stage (algorithmic bytes / flops per step) --------
     d = w.d
     bf16 = kw.get("precision", 0) >= 1
-    rerank_bytes = ((2.0 * d + 4.0) * c["examined"] + 4.0 * d * c["refined"]) if bf16 else 4.0 * d * c["examined"]
+    rerank_bytes = rerank_bytes_of(kw, c, d)
     per_step = {
         "rotate": ("mfma", 2.0 * d * d * w.n_query / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"),
         # first counting pass: every retrieved id read once, every candidate (id, score) written once

@@ -169,7 +169,14 @@ crisp_status crisp_index_enable_bf16(crisp_index *index, void *buffer, size_t by
  *                      it needs a rank the bounds leave open.  Same ids,
  *                      distances and stage outputs; half_dist is only filled
  *                      for every centroid when that tap is requested (which
- *                      then takes the exact path).
+ *                      then takes the exact path).  3: as 2 with the
+ *                      pre-scoring on FP8 (OCP e4m3) matrix cores: per
+ *                      (query, half) and per half-codebook power-of-two
+ *                      scales, each coordinate split into two e4m3 terms,
+ *                      three v_mfma_f32_16x16x32_fp8_fp8 per 32 coordinates,
+ *                      float32 accumulation, the same kind of certified
+ *                      bound; wider bounds, so more subspaces take the exact
+ *                      path (the score_fallback tap counts them).
  *   persistent      -- 0: the re-rank launches one block per query.  1: it
  *                      launches about as many blocks as fit on the chip,
  *                      each pulling queries from a device-side counter (same
@@ -238,6 +245,9 @@ typedef struct {
  *                                      verify 1: those ADSampling did not prune)
  *   row_bytes   int64  [nq]            bytes of stored rows the verification read
  *                                      (rows of a walk chunk past the stop included)
+ *   score_fallback int32 [nq]          precision 2 and 3: subspaces whose cell
+ *                                      selection the certified bounds did not
+ *                                      decide (computed on the exact path)
  *   score_lb    float32 [nq][M][2][K]  precision 2, K <= 64: certified lower and
  *   score_ub    float32 [nq][M][2][K]  upper bounds of Dist_1 / Dist_2 from the
  *                                      bfloat16 matrix-core scoring
@@ -264,6 +274,7 @@ typedef struct {
   float *score_lb;
   float *score_ub;
   int64_t *row_bytes;
+  int32_t *score_fallback;
 } crisp_taps;
 
 /* Bytes of workspace crisp_search needs for this index, batch and parameters. */

@@ -46,7 +46,7 @@ STAGES = ["rotate", "hamming_place", "select", "count", "hamming_dist", "rerank"
 
 TAP_FIELDS = ["q_rot", "half_dist", "n_cells", "cells", "retrieved", "hist", "tau_eff", "n_cand",
               "cand", "cand_score", "order", "hamming", "examined", "last_update", "stopped", "features",
-              "limits", "refined", "score_lb", "score_ub", "row_bytes"]
+              "limits", "refined", "score_lb", "score_ub", "row_bytes", "score_fallback"]
 
 
 class Taps(ctypes.Structure):

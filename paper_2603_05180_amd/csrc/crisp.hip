@@ -179,7 +179,7 @@ struct StageTimer {
 struct Layout {
   size_t qrot, hdist, ptab, ncell, cells, retr, tilecnt, hist, flag, taueff, ncand, segids, segscore, cand,
       score, regA, regB, regC, examined, lastupd, stopped, refined, sstat, feat, lim, queue, order, sclb, scub,
-      flist, nflag, rbytes, total;
+      flist, nflag, rbytes, sfall, total;
 };
 
 static Layout make_layout(const crisp_index *ix, long long qc) {
@@ -219,6 +219,7 @@ static Layout make_layout(const crisp_index *ix, long long qc) {
   L.flist = take(qc * 4);
   L.nflag = take(4);
   L.rbytes = take(qc * 8);
+  L.sfall = take(qc * 4);
   L.total = o;
   return L;
 }
@@ -391,9 +392,9 @@ static crisp_status check_params(const crisp_index *ix, int64_t nq, int32_t k, c
   if (p->budget_source != 0 && p->budget_source != 1) return fail(CRISP_E_INVALID, "budget_source must be 0 or 1");
   if (p->budget_source == 1 && p->mode != 1) return fail(CRISP_E_INVALID, "the learned budget applies to Optimized Mode");
   if (p->budget_source == 1 && !ix->mlp_params) return fail(CRISP_E_INVALID, "no budget model set");
-  if (p->precision < 0 || p->precision > 2) return fail(CRISP_E_INVALID, "precision must be 0, 1 or 2");
+  if (p->precision < 0 || p->precision > 3) return fail(CRISP_E_INVALID, "precision must be 0, 1, 2 or 3");
   if (p->precision >= 1 && !ix->base16)
-    return fail(CRISP_E_INVALID, "precision 1 and 2 need crisp_index_enable_bf16");
+    return fail(CRISP_E_INVALID, "precision 1, 2 and 3 need crisp_index_enable_bf16");
   if (p->persistent != 0 && p->persistent != 1) return fail(CRISP_E_INVALID, "persistent must be 0 or 1");
   if (p->overlap != 0 && p->overlap != 1) return fail(CRISP_E_INVALID, "overlap must be 0 or 1");
   if (p->walk_order != 0 && p->walk_order != 1) return fail(CRISP_E_INVALID, "walk_order must be 0 or 1");
@@ -453,7 +454,7 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
   // precision 2: certified bfloat16 matrix-core pre-scoring of the half
   // distances (K <= 64); the selection ignores it while the exact half
   // distances are tapped
-  const bool score = p->precision == 2 && ix->k <= kWave;
+  const bool score = p->precision >= 2 && ix->k <= kWave;
   const bool score_used = score && !(taps && taps->half_dist);
   const size_t rr_lds = rerank_lds(d, k, bf16).total;
   // float32 error factor of the bfloat16 row distance: gamma_{L+10}, L = terms per lane
@@ -506,6 +507,7 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
     float *feat = reinterpret_cast<float *>(ws + L.feat);
     int32_t *llim = reinterpret_cast<int32_t *>(ws + L.lim);
     long long *rbytes = reinterpret_cast<long long *>(ws + L.rbytes);
+    int32_t *sfall = reinterpret_cast<int32_t *>(ws + L.sfall);
     const int cq = static_cast<int>(std::min<long long>(qc, nq - q0));
     const float *qin = queries + q0 * d;
     const int32_t *lv = live_base ? live_base + q0 / qc : nullptr;
@@ -525,14 +527,21 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
     {
       StageTimer t2(ix, 2, st);
       if (score) {
-        k_score_bf16x3<<<dim3((cq + 15) / 16, m), 64, 0, st>>>(qrot, d, ix->cent_t, m, kh, ix->h, cq, sclb, scub, lv);
-        LAUNCH_TRY("k_score_bf16x3");
+        k_fill<int32_t><<<grid1(cq, 256), 256, 0, st>>>(sfall, cq, 0);
+        LAUNCH_TRY("k_fill");
+        if (p->precision == 3) {
+          k_score_fp8<<<dim3((cq + 15) / 16, m), 64, 0, st>>>(qrot, d, ix->cent_t, m, kh, ix->h, cq, sclb, scub, lv);
+          LAUNCH_TRY("k_score_fp8");
+        } else {
+          k_score_bf16x3<<<dim3((cq + 15) / 16, m), 64, 0, st>>>(qrot, d, ix->cent_t, m, kh, ix->h, cq, sclb, scub, lv);
+          LAUNCH_TRY("k_score_bf16x3");
+        }
       }
       dim3 g(m, cq);
       k_select_cells<<<g, 64, select_lds_bytes(kh, ix->h), st>>>(qrot, d, ix->cent_t, m, kh, ix->h, ix->off,
                                                                   budget, k, p->mode, hdist, ptab, ncell, cells,
                                                                   retr, sstat, lv, score_used ? sclb : nullptr,
-                                                                  score_used ? scub : nullptr);
+                                                                  score_used ? scub : nullptr, sfall);
       LAUNCH_TRY("k_select_cells");
       t2.stop();
     }
@@ -664,6 +673,8 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       if ((s = tap_copy(taps->stopped ? taps->stopped + q0 : nullptr, stopd, size_t(cq) * 4, st))) return s;
       if ((s = tap_copy(taps->refined ? taps->refined + q0 : nullptr, refd, size_t(cq) * 4, st))) return s;
       if ((s = tap_copy(taps->row_bytes ? taps->row_bytes + q0 : nullptr, rbytes, size_t(cq) * 8, st))) return s;
+      if (score_used && (s = tap_copy(taps->score_fallback ? taps->score_fallback + q0 : nullptr, sfall,
+                                      size_t(cq) * 4, st))) return s;
       if (score) {
         const size_t sb = size_t(cq) * m * 2 * kh * 4;
         if ((s = tap_copy(taps->score_lb ? taps->score_lb + q0 * m * 2 * kh : nullptr, sclb, sb, st))) return s;

@@ -305,6 +305,151 @@ __global__ void __launch_bounds__(64) k_score_bf16x3(const float *__restrict__ q
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same certified pre-scoring on FP8 (OCP e4m3) matrix cores (precision 3,
+// K <= 64).  Per (query, half) and per half-codebook a power-of-two scale
+// maps the largest magnitude to [128, 256) (exact), each scaled coordinate is
+// split into two e4m3 terms, x = x_hi + x_lo + r_x (x_hi = e4m3(x), x_lo =
+// e4m3(x - x_hi), both round to nearest even; r_x exact in float32), and q.c
+// is approximated by q_hi.c_hi + q_lo.c_hi + q_hi.c_lo with three
+// v_mfma_f32_16x16x32_fp8_fp8 per 32-coordinate step (products of two e4m3
+// values are exact in float32).  The bound has the form of the bfloat16
+// kernel's: the omitted terms |q_lo.c_lo| + |(q_hi + q_lo).r_c| + |r_q.c| by
+// Cauchy-Schwarz from the exact residual norms, the float32 sum errors of
+// the three products ((3 * 32 nks + 32) 2^-22 per unit of the products'
+// absolute sum, nks = 32-coordinate steps), the float32 norms and the final
+// expression; doubled, plus 2^-40 of the scale for the canonical float64
+// half distance.  One wavefront per (16 queries, subspace); lane l holds
+// query row l & 15 (A) and centroid column l & 15 (B), coordinates
+// 8 (l >> 4) .. + 7 of each 32-coordinate step.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float pow2_scale_for(float amax) {
+  // 2^e with amax * 2^e in [128, 256); 1 when amax is 0 or not finite
+  if (!(amax > 0.f) || !(amax < 3.0e38f)) return 1.f;
+  const int e = 7 - ilogbf(amax);
+  return ldexpf(1.f, max(-60, min(60, e)));  // two scales multiply without overflow
+}
+
+// Two e4m3 terms of one float (already scaled): bytes hi, lo; their float
+// values hf, lf (exact).
+__device__ __forceinline__ void split_fp8(float x, int &hb, int &lb, float &hf, float &lf) {
+  const int ph = __builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false);
+  hf = __builtin_amdgcn_cvt_f32_fp8(ph, 0);
+  const int pl = __builtin_amdgcn_cvt_pk_fp8_f32(x - hf, 0.f, 0, false);
+  lf = __builtin_amdgcn_cvt_f32_fp8(pl, 0);
+  hb = ph & 0xff;
+  lb = pl & 0xff;
+}
+
+__global__ void __launch_bounds__(64) k_score_fp8(const float *__restrict__ qrot, int d,
+                                                  const float *__restrict__ cent_t, int m, int k, int h, int cq,
+                                                  float *__restrict__ out_lb, float *__restrict__ out_ub,
+                                                  const int32_t *__restrict__ live) {
+  const int lane = threadIdx.x, r = lane & 15, kq = lane >> 4;
+  const int q0 = blockIdx.x * 16, sub = blockIdx.y;
+  const int nl = live ? min(cq, *live) : cq;
+  if (q0 >= nl) return;
+  const int nks = (h + 31) / 32;
+  const int qa = q0 + r;
+  const float *qrow = qrot + static_cast<long long>(min(qa, nl - 1)) * d + sub * 2 * h;
+  // Sum error of the FP8 matrix-core products: the 32-product dot of one
+  // instruction is not exact in float32 on gfx950 (measured up to 1.1e-4 of
+  // the products' absolute sum); 2^-9 of it per instruction, plus the float32
+  // accumulation over the 3 nks instructions.
+  const float sacc = 0x1p-9f + static_cast<float>(3 * nks + 4) * 0x1p-22f;
+  const float snorm = static_cast<float>(4 * nks + 4) * 0x1p-23f;
+  for (int s = 0; s < 2; ++s) {
+    const float *ct = cent_t + static_cast<long long>(sub * 2 + s) * h * k;
+    // scales: this lane's query row (its four lanes share the row), the codebook
+    float aq = 0.f;
+    for (int t = kq; t < h; t += 4) aq = fmaxf(aq, fabsf(qa < nl ? qrow[s * h + t] : 0.f));
+    aq = fmaxf(aq, __shfl_xor(aq, 16, kWave));
+    aq = fmaxf(aq, __shfl_xor(aq, 32, kWave));
+    float ac = 0.f;
+    for (int t = lane; t < h * k; t += kWave) ac = fmaxf(ac, fabsf(ct[t]));
+#pragma unroll
+    for (int sh = 32; sh >= 1; sh >>= 1) ac = fmaxf(ac, __shfl_xor(ac, sh, kWave));
+    const float sq = pow2_scale_for(aq), sc = pow2_scale_for(ac);
+    for (int c0 = 0; c0 < k; c0 += 16) {
+      const int c = c0 + r;
+      score_f4 acc = score_f4{0.f, 0.f, 0.f, 0.f};
+      float nq = 0.f, nqlo = 0.f, nqr = 0.f, nqt = 0.f;
+      float nc = 0.f, nclo = 0.f, ncr = 0.f, nct = 0.f;
+      for (int ks = 0; ks < nks; ++ks) {
+        long qh = 0, ql = 0, ch = 0, cl = 0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int dd = ks * 32 + 8 * kq + e;
+          const float xq = (dd < h && qa < nl) ? qrow[s * h + dd] : 0.f;
+          const float xc = (dd < h && c < k) ? ct[static_cast<long long>(dd) * k + c] : 0.f;
+          int hb, lb;
+          float hf, lf;
+          split_fp8(xq * sq, hb, lb, hf, lf);
+          qh |= static_cast<long>(hb) << (8 * e);
+          ql |= static_cast<long>(lb) << (8 * e);
+          // unscaled terms (power-of-two scale: exact)
+          float uh = hf / sq, ul = lf / sq;
+          float rr = (xq - uh) - ul;
+          nq = fmaf(xq, xq, nq);
+          nqlo = fmaf(ul, ul, nqlo);
+          nqr = fmaf(rr, rr, nqr);
+          nqt = fmaf(uh + ul, uh + ul, nqt);
+          split_fp8(xc * sc, hb, lb, hf, lf);
+          ch |= static_cast<long>(hb) << (8 * e);
+          cl |= static_cast<long>(lb) << (8 * e);
+          uh = hf / sc;
+          ul = lf / sc;
+          rr = (xc - uh) - ul;
+          nc = fmaf(xc, xc, nc);
+          nclo = fmaf(ul, ul, nclo);
+          ncr = fmaf(rr, rr, ncr);
+          nct = fmaf(uh + ul, uh + ul, nct);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(qh, ch, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ql, ch, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(qh, cl, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int sh = 16; sh <= 32; sh <<= 1) {
+        nq += __shfl_xor(nq, sh, kWave);
+        nqlo += __shfl_xor(nqlo, sh, kWave);
+        nqr += __shfl_xor(nqr, sh, kWave);
+        nqt += __shfl_xor(nqt, sh, kWave);
+        nc += __shfl_xor(nc, sh, kWave);
+        nclo += __shfl_xor(nclo, sh, kWave);
+        ncr += __shfl_xor(ncr, sh, kWave);
+        nct += __shfl_xor(nct, sh, kWave);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 4 * kq + i;
+        const float vq = __shfl(nq, row, kWave), vqlo = __shfl(nqlo, row, kWave);
+        const float vqr = __shfl(nqr, row, kWave), vqt = __shfl(nqt, row, kWave);
+        const float vs = __shfl(sq, row, kWave);
+        const int qq = q0 + row;
+        if (qq < nl && c < k) {
+          const float dot = acc[i] / (vs * sc);   // power-of-two unscaling: exact
+          const float dt = vq + nc - 2.f * dot;
+          const float omit = sqrtf(vqlo * nclo) + sqrtf(vqt * ncr) + sqrtf(vqr * nc);
+          const float sums = sacc * (sqrtf(vqt) + sqrtf(vqlo)) * (sqrtf(nct) + sqrtf(nclo));
+          const float scale = vq + nc + 2.f * fabsf(dot);
+          const double e = 2.0 * (2.0 * (static_cast<double>(omit) + sums) + static_cast<double>(snorm) * (vq + nc) +
+                                  0x1p-21 * scale) +
+                           0x1p-40 * scale + 1e-300;
+          const double lo = fmax(0.0, static_cast<double>(dt) - e);
+          const double hi = static_cast<double>(dt) + e;
+          float lf = static_cast<float>(lo), hf = static_cast<float>(hi);
+          if (static_cast<double>(lf) > lo) lf = nextafterf(lf, 0.f);
+          if (static_cast<double>(hf) < hi) hf = nextafterf(hf, __int_as_float(0x7f800000));
+          const long long o = (static_cast<long long>(qq) * m + sub) * 2 * k + s * k + c;
+          out_lb[o] = lf;
+          out_ub[o] = hf;
+        }
+      }
+    }
+  }
+}
+
 __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ qrot, int d,
                                                      const float *__restrict__ cent_t, int m, int k, int h,
                                                      const int32_t *__restrict__ offsets, int budget, int ksize,
@@ -314,7 +459,8 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
                                                      int32_t *__restrict__ retrieved,
                                                      double *__restrict__ sstat, const int32_t *__restrict__ live,
                                                      const float *__restrict__ sc_lb,
-                                                     const float *__restrict__ sc_ub) {
+                                                     const float *__restrict__ sc_ub,
+                                                     int32_t *__restrict__ sfall) {
   extern __shared__ __align__(16) unsigned char dyn[];
   SelectLds S;
   {
@@ -485,6 +631,8 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
     }
   }
 
+  // the certified path did not decide this subspace: count it
+  if (sc_lb != nullptr && sfall != nullptr && lane == 0) atomicAdd(&sfall[q], 1);
   // ---- Dist_1 / Dist_2 -----------------------------------------------------
   double *hout = hdist_out + (static_cast<long long>(q) * m + sub) * 2 * k;
   for (int s = 0; s < 2; ++s) {

@@ -239,11 +239,12 @@ class Index:
             "score_lb": (torch.float32, (nq, m, 2, kh)),
             "score_ub": (torch.float32, (nq, m, 2, kh)),
             "row_bytes": (torch.int64, (nq,)),
+            "score_fallback": (torch.int32, (nq,)),
         }
 
     def alloc_taps(self, nq: int, mode: int) -> dict:
         only1 = {"order", "hamming", "features", "limits"}
-        skip = {"score_lb", "score_ub"}
+        skip = {"score_lb", "score_ub", "score_fallback"}
         return {name: torch.empty(shape, dtype=dt, device=self.device)
                 for name, (dt, shape) in self.tap_specs(nq).items()
                 if name not in skip and (mode == 1 or name not in only1)}

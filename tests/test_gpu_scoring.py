@@ -1,10 +1,10 @@
-"""Certified bfloat16 matrix-core pre-scoring of the half distances
-(precision 2, needs an MI355X).  The scoring kernel's bounds must contain
-the exact float64 half distances; and a search with precision 2 must return
-exactly what precision 0 and the oracle return, with the same activated
-cells, candidates and walk, both when the cell walk stays inside the
-certified ranks and when it needs the exact path (hundreds of cells per
-subspace)."""
+"""Certified matrix-core pre-scoring of the half distances (needs an
+MI355X): bfloat16 (precision 2) and FP8 e4m3 (precision 3).  The scoring
+kernel's bounds must contain the exact float64 half distances; and a search
+with precision 2 or 3 must return exactly what precision 0 and the oracle
+return, with the same activated cells, candidates and walk, both when the
+cell walk stays inside the certified ranks and when it needs the exact path
+(hundreds of cells per subspace)."""
 import numpy as np
 import pytest
 import torch
@@ -37,7 +37,8 @@ def case(request):
     return request.param, w, q, idx, g, kw
 
 
-def test_bounds_contain_the_exact_half_distances(case):
+@pytest.mark.parametrize("precision", [2, 3])
+def test_bounds_contain_the_exact_half_distances(case, precision):
     name, w, q, idx, g, kw = case
     nq, m, kh = q.shape[0], idx["m"], idx["k_half"]
     z = dict(device=g.device)
@@ -45,8 +46,8 @@ def test_bounds_contain_the_exact_half_distances(case):
             "score_lb": torch.empty(nq, m, 2, kh, dtype=torch.float32, **z),
             "score_ub": torch.empty(nq, m, 2, kh, dtype=torch.float32, **z)}
     qt = torch.from_numpy(np.ascontiguousarray(q)).to(g.device)
-    print(f"{name}: bounds", flush=True)
-    g.search(qt, 10, precision=2, taps=taps, **kw)
+    print(f"{name}: bounds, precision {precision}", flush=True)
+    g.search(qt, 10, precision=precision, taps=taps, **kw)
     torch.cuda.synchronize()
     hd = taps["half_dist"].cpu().numpy()
     lb = taps["score_lb"].cpu().numpy().astype(np.float64)
@@ -55,21 +56,27 @@ def test_bounds_contain_the_exact_half_distances(case):
     assert np.all(lb <= hd), (name, float((lb - hd).max()))
     assert np.all(hd <= ub), (name, float((hd - ub).max()))
     # the bounds are tight enough to certify (reported, not asserted)
-    print(f"{name}: median relative width {float(np.median((ub - lb) / np.maximum(hd, 1e-30))):.2e}")
+    print(f"{name}: precision {precision}, median relative width "
+          f"{float(np.median((ub - lb) / np.maximum(hd, 1e-30))):.2e}")
 
 
-def test_results_equal_precision_0_and_the_oracle(case):
+@pytest.mark.parametrize("precision", [2, 3])
+def test_results_equal_precision_0_and_the_oracle(case, precision):
     name, w, q, idx, g, kw = case
     k = 10
-    print(f"{name}: precision 0 vs 2", flush=True)
+    print(f"{name}: precision 0 vs {precision}", flush=True)
     i0, d0, t0 = run_gpu(g, q, k, precision=0, **kw)
     taps = g.alloc_taps(q.shape[0], kw["mode"])
     del taps["half_dist"]            # with it the selection takes the exact path
     qt = torch.from_numpy(np.ascontiguousarray(q)).to(g.device)
-    ids, d = g.search(qt, k, precision=2, taps=taps, **kw)
+    taps["score_fallback"] = torch.empty(q.shape[0], dtype=torch.int32, device=g.device)
+    ids, d = g.search(qt, k, precision=precision, taps=taps, **kw)
     torch.cuda.synchronize()
     i2, d2 = ids.cpu().numpy(), d.cpu().numpy()
     t2 = {key: v.cpu().numpy() for key, v in taps.items()}
+    fb = t2["score_fallback"]
+    assert np.all((fb >= 0) & (fb <= idx["m"]))
+    print(f"{name}: precision {precision}, exact-path subspaces {int(fb.sum())} of {fb.size * idx['m']}")
     assert np.array_equal(i2, i0)
     assert np.array_equal(d2.view(np.uint32), d0.view(np.uint32))
     keys = ["n_cells", "retrieved", "hist", "tau_eff", "n_cand", "examined", "last_update", "stopped"]
