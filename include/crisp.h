@@ -204,6 +204,11 @@ crisp_status crisp_index_enable_bf16(crisp_index *index, void *buffer, size_t by
  *                      the k-th key at that moment (the product in float64);
  *                      a pruned candidate counts as a non-update, the others
  *                      are verified exactly.  Needs precision 0.
+ *   order_prefix    -- Optimized Mode: positions of the Hamming order placed
+ *                      before the walk (whole distance bins covering them;
+ *                      0 = 2 P + 1024, P the patience).  A walk that reaches
+ *                      their end without stopping is walked again on the
+ *                      full order, so results never depend on it.
  */
 typedef struct {
   int32_t mode;
@@ -218,6 +223,7 @@ typedef struct {
   int32_t overlap;
   int32_t walk_order;
   int32_t verify;
+  int32_t order_prefix;
 } crisp_search_params;
 
 /*

@@ -92,7 +92,8 @@ __device__ __forceinline__ double from_dbits(unsigned long long b) {
   return __longlong_as_double(static_cast<long long>(b));
 }
 
-// Block-wide exclusive scan of `n` ints held in LDS (in place), n <= 4096.
+// Block-wide exclusive scan of `n` ints held in LDS (in place); each thread
+// scans ceil(n / blockDim) consecutive entries.
 // Returns the total.  All threads of the block must call it.
 __device__ inline int block_exclusive_scan(int *a, int n, int *tmp /* >= blockDim/64 + 1 ints */) {
   const int tid = threadIdx.x;

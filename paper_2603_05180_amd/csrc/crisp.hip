@@ -179,7 +179,7 @@ struct StageTimer {
 struct Layout {
   size_t qrot, hdist, ptab, ncell, cells, retr, tilecnt, hist, flag, taueff, ncand, segids, segscore, cand,
       score, regA, regB, regC, examined, lastupd, stopped, refined, sstat, feat, lim, queue, order, sclb, scub,
-      flist, nflag, rbytes, sfall, total;
+      flist, nflag, rbytes, sfall, avail, hstat, redo, nredo, total;
 };
 
 static Layout make_layout(const crisp_index *ix, long long qc) {
@@ -220,6 +220,10 @@ static Layout make_layout(const crisp_index *ix, long long qc) {
   L.nflag = take(4);
   L.rbytes = take(qc * 8);
   L.sfall = take(qc * 4);
+  L.avail = take(qc * 4);
+  L.hstat = take(qc * kHamStats * 4);
+  L.redo = take(qc * 4);
+  L.nredo = take(4);
   L.total = o;
   return L;
 }
@@ -401,6 +405,7 @@ static crisp_status check_params(const crisp_index *ix, int64_t nq, int32_t k, c
   if (p->walk_order == 1 && p->budget_source == 1)
     return fail(CRISP_E_INVALID, "the learned budget's features need the Hamming order (walk_order 0)");
   if (p->verify != 0 && p->verify != 1) return fail(CRISP_E_INVALID, "verify must be 0 or 1");
+  if (p->order_prefix < 0) return fail(CRISP_E_INVALID, "order_prefix must be >= 0");
   if (p->verify == 1 && p->mode != 1) return fail(CRISP_E_INVALID, "ADSampling (verify 1) is for Optimized Mode");
   if (p->verify == 1 && p->precision != 0) return fail(CRISP_E_INVALID, "ADSampling (verify 1) needs precision 0");
   return CRISP_OK;
@@ -457,6 +462,13 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
   const bool score = p->precision >= 2 && ix->k <= kWave;
   const bool score_used = score && !(taps && taps->half_dist);
   const size_t rr_lds = rerank_lds(d, k, bf16).total;
+  // Hamming order: positions placed before the walk (whole distance bins
+  // covering them); all of them when the order or its distances are tapped
+  const bool full_order = taps && (taps->order || taps->hamming);
+  const long long plen_auto = 2ll * patience + 1024;
+  const int plen = full_order ? INT32_MAX
+                              : static_cast<int>(std::min<long long>(p->order_prefix > 0 ? p->order_prefix : plen_auto,
+                                                                     INT32_MAX));
   // float32 error factor of the bfloat16 row distance: gamma_{L+10}, L = terms per lane
   const double lterms = static_cast<double>((d / 8 + kWave - 1) / kWave * 8 + 10) * 5.9604644775390625e-08;
   const double gam = lterms / (1.0 - lterms);
@@ -508,6 +520,10 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
     int32_t *llim = reinterpret_cast<int32_t *>(ws + L.lim);
     long long *rbytes = reinterpret_cast<long long *>(ws + L.rbytes);
     int32_t *sfall = reinterpret_cast<int32_t *>(ws + L.sfall);
+    int32_t *avail = reinterpret_cast<int32_t *>(ws + L.avail);
+    int32_t *hstat = reinterpret_cast<int32_t *>(ws + L.hstat);
+    int32_t *redo = reinterpret_cast<int32_t *>(ws + L.redo);
+    int32_t *nredo = reinterpret_cast<int32_t *>(ws + L.nredo);
     const int cq = static_cast<int>(std::min<long long>(qc, nq - q0));
     const float *qin = queries + q0 * d;
     const int32_t *lv = live_base ? live_base + q0 / qc : nullptr;
@@ -606,16 +622,18 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       }
       t4.stop();
       StageTimer t1(ix, 1, st);  // order
-      k_hamming_place<<<cq, kOrderThreads, 0, st>>>(d, ncand, cand, n, regA, reinterpret_cast<long long *>(regC),
-                                                     segids, regB, lv);
-      LAUNCH_TRY("k_hamming_place");
+      k_fill<int32_t><<<1, 64, 0, st>>>(nredo, 1, 0);
+      LAUNCH_TRY("k_fill");
+      k_hamming_order<<<cq, kOrderThreads, hamming_order_lds(d), st>>>(d, ncand, cand, n, regA, plen, segids, regB,
+                                                                       avail, hstat, lv, nullptr, nullptr);
+      LAUNCH_TRY("k_hamming_order");
       t1.stop();
     }
     if (p->mode == 1) {
       // learned budget: features, then bfloat16 MFMA inference -> limits
       if (ham && (p->budget_source == 1 || (taps && taps->features))) {
         StageTimer t6(ix, 6, st);
-        k_features<<<grid1(cq, 256), 256, 0, st>>>(cq, m, d, k, 1, ncand, hist, taueff, sstat, regB, n, feat, lv);
+        k_features<<<grid1(cq, 256), 256, 0, st>>>(cq, m, d, k, 1, ncand, hist, taueff, sstat, hstat, feat, lv);
         LAUNCH_TRY("k_features");
         if (p->budget_source == 1) {
           k_mlp_limits<<<(cq + 15) / 16, 64, 0, st>>>(cq, nf, feat, ix->mlp_mean, ix->mlp_std, ix->mlp_params,
@@ -635,8 +653,21 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
                                                         ham ? segids : cand, n, k, patience, lim, regC, nullptr, nullptr,
                                                         ids + q0 * k,
                                                         dists + q0 * k, exam, lastu, stopd, refd, ix->ads_fac,
-                                                        rbytes, lv, cq, p->persistent ? queue : nullptr, qord);
+                                                        rbytes, ham ? avail : nullptr, ham ? redo : nullptr, nredo,
+                                                        lv, cq, p->persistent ? queue : nullptr, qord);
       LAUNCH_TRY("k_rerank");
+      if (ham && plen < n) {
+        // walks that reached the end of the placed prefix: full order, walk again
+        k_hamming_order<<<std::min(cq, 256), kOrderThreads, hamming_order_lds(d), st>>>(
+            d, ncand, cand, n, regA, INT32_MAX, segids, regB, avail, hstat, lv, redo, nredo);
+        LAUNCH_TRY("k_hamming_order (redo)");
+        rerank1<<<xcd_pad(cq), kRerankThreads, rr_lds, st>>>(qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
+                                                             segids, n, k, patience, lim, regC, nullptr, nullptr,
+                                                             ids + q0 * k, dists + q0 * k, exam, lastu, stopd, refd,
+                                                             ix->ads_fac, rbytes, nullptr, nullptr, nullptr, nredo,
+                                                             cq, nullptr, redo);
+        LAUNCH_TRY("k_rerank (redo)");
+      }
       t5.stop();
     } else {
       StageTimer t5(ix, 5, st);
@@ -648,7 +679,8 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
                                                         cand, n, k, patience, lim, regC,
                                                         reinterpret_cast<float *>(regA), regB, ids + q0 * k,
                                                         dists + q0 * k, exam, lastu, stopd, refd, ix->ads_fac,
-                                                        rbytes, lv, cq, p->persistent ? queue : nullptr, qord);
+                                                        rbytes, nullptr, nullptr, nullptr, lv, cq,
+                                                        p->persistent ? queue : nullptr, qord);
       LAUNCH_TRY("k_rerank");
       t5.stop();
     }

@@ -18,10 +18,12 @@ constexpr int kHamPos = 12;  // Hamming distances at positions 1, 2, 4, ..., 204
 __host__ __device__ inline int n_features(int m) { return 1 + 16 + 3 * m + kHamPos + 1; }
 
 // One thread per query.  sstat [q][m][4] = (c1, c2, c_cut, size of the
-// cheapest cell); hist [q][2M+1]; ham_sorted [q][n] (Hamming order).
+// cheapest cell); hist [q][2M+1]; hstat [q][kHamPos + 1] = the Hamming
+// distances at positions 1, 2, 4, ..., 2048 (clipped to |C|) and at the
+// median of the Hamming order.
 __global__ void k_features(int nq, int m, int d, int k, int have_ham, const int32_t *__restrict__ ncand,
                            const int32_t *__restrict__ hist, const int32_t *__restrict__ tau_eff,
-                           const double *__restrict__ sstat, const int32_t *__restrict__ ham_sorted, long long n,
+                           const double *__restrict__ sstat, const int32_t *__restrict__ hstat,
                            float *__restrict__ feat, const int32_t *__restrict__ live) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq || (live && q >= *live)) return;
@@ -45,10 +47,8 @@ __global__ void k_features(int nq, int m, int d, int k, int have_ham, const int3
   }
   const int base = 17 + 3 * m;
   if (have_ham && nc > 0) {
-    const int32_t *hm = ham_sorted + static_cast<long long>(q) * n;
-    for (int j = 0; j < kHamPos; ++j)
-      f[base + j] = static_cast<float>(static_cast<double>(hm[min(1 << j, nc) - 1]) / d);
-    f[base + kHamPos] = static_cast<float>(static_cast<double>(hm[(nc + 1) / 2 - 1]) / d);
+    const int32_t *hs = hstat + static_cast<long long>(q) * (kHamPos + 1);
+    for (int j = 0; j <= kHamPos; ++j) f[base + j] = static_cast<float>(static_cast<double>(hs[j]) / d);
   } else {
     for (int j = 0; j <= kHamPos; ++j) f[base + j] = 0.0f;
   }

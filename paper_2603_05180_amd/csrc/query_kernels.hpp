@@ -7,8 +7,8 @@
 //   k_count         (A3/A4) LDS collision counters per (query, id tile),
 //                   threshold, ordered compaction, score histogram
 //   k_flag / k_tau_eff / k_compact (A4) fallback rule and candidate lists
-//   k_hamming_dist / k_hamming_place (A5) Hamming distances, then a stable
-//                   counting sort per query
+//   k_hamming_dist / k_hamming_order (A5) Hamming distances, then the
+//                   (distance, id) order placed as far as the walk reads it
 //   k_rerank        (A6/A7) exact float64 keys, top-k / patience walk; the
 //                   bfloat16 variant first bounds every row from a bfloat16
 //                   copy and reads float32 rows only where the bound matters
@@ -356,7 +356,7 @@ __global__ void __launch_bounds__(64) k_score_fp8(const float *__restrict__ qrot
   // instruction is not exact in float32 on gfx950 (measured up to 1.1e-4 of
   // the products' absolute sum); 2^-9 of it per instruction, plus the float32
   // accumulation over the 3 nks instructions.
-  const float sacc = 0x1p-9f + static_cast<float>(3 * nks + 4) * 0x1p-22f;
+  const float sacc = 0x1p-8f + static_cast<float>(3 * nks + 4) * 0x1p-22f;
   const float snorm = static_cast<float>(4 * nks + 4) * 0x1p-23f;
   for (int s = 0; s < 2; ++s) {
     const float *ct = cent_t + static_cast<long long>(sub * 2 + s) * h * k;
@@ -1297,9 +1297,7 @@ __global__ void __launch_bounds__(kQueryOrderThreads) k_query_order(int cq, cons
 // four loads per lane are in flight per batch, and the partial popcounts are
 // reduced over the row's L lanes.
 //
-// k_hamming_place: one block per query sorts the candidates by distance with
-// a two-pass stable LSD radix sort (7-bit digits) spread over its four
-// wavefronts.
+// k_hamming_order (below) places the candidates in (distance, id) order.
 // ---------------------------------------------------------------------------
 constexpr int kOrderThreads = 256;
 constexpr int kOrderWaves = kOrderThreads / kWave;
@@ -1391,105 +1389,120 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_dist(
   }
 }
 
-// One pass of a stable LSD radix sort by 7-bit digits: the four wavefronts
-// take contiguous quarters of the input in order; per-wave digit counts give
-// each (wave, digit) its start, and inside a 64-lane step a lane's rank among
-// lower lanes with the same digit comes from 7 ballots.  Input element i is
-// (key[i], val[i]) or, when packed, the int64 (key << 32 | val).
-constexpr int kPlaceU = 8;  // elements per lane loaded together (loads in flight)
+// Candidates in ascending (Hamming distance, id) order, placed only as far
+// as the walk is expected to read.  One block per query (or per entry of a
+// query list): a histogram of the distances over all candidates (LDS, D + 1
+// bins) and its exclusive scan give every bin's first position; the order
+// statistics the learned budget uses are read from it (the distance at
+// positions 1, 2, 4, ..., 2048 and at the median); then the candidates of
+// the bins that cover the first `plen` positions (whole bins) are placed,
+// stably: one wave walks the candidate list (ascending id) 64 at a time, a
+// lane's rank among the lanes with the same distance from ballots over the
+// distance's bits, each bin's cursor in LDS.  avail[q] = positions placed.
+constexpr int kHamStats = 13;  // positions 1, 2, 4, ..., 2048, then the median
 
-template <bool kPackedIn, bool kPackedOut>
-__device__ __forceinline__ void radix_pass(int nc, int shift, const int32_t *__restrict__ key_in,
-                                           const int32_t *__restrict__ val_in, const long long *__restrict__ pk_in,
-                                           int32_t *__restrict__ key_out, int32_t *__restrict__ val_out,
-                                           long long *__restrict__ pk_out, int (*cnt)[128]) {
-  const int lane = lane_id(), wv = wave_id();
-  const int per = ((nc + kOrderWaves - 1) / kOrderWaves + kWave - 1) / kWave * kWave;
-  const int b0 = min(nc, wv * per), b1 = min(nc, b0 + per);
-  auto load = [&](int i, int &k, int &v) {
-    if constexpr (kPackedIn) {
-      const long long e = pk_in[i];
-      k = static_cast<int>(e >> 32);
-      v = static_cast<int>(e & 0xffffffffll);
-    } else {
-      k = key_in[i];
-      v = val_in[i];
-    }
-  };
-  for (int t = threadIdx.x; t < kOrderWaves * 128; t += kOrderThreads) cnt[t >> 7][t & 127] = 0;
-  __syncthreads();
-  for (int i0 = b0; i0 < b1; i0 += kPlaceU * kWave) {
-    int k[kPlaceU], v[kPlaceU];
+__global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
+    int d, const int32_t *__restrict__ ncand, const int32_t *__restrict__ cand, long long n,
+    const int32_t *__restrict__ hm_tmp, int plen, int32_t *__restrict__ order, int32_t *__restrict__ ham_sorted,
+    int32_t *__restrict__ avail, int32_t *__restrict__ hstat, const int32_t *__restrict__ live,
+    const int32_t *__restrict__ qlist, const int32_t *__restrict__ qcount) {
+  extern __shared__ __align__(16) int hist[];  // d + 1 bins, then the scan's scratch
+  int *tmp = hist + d + 1;
+  const int nl = live ? *live : 0x7fffffff;
+  const int nitems = qcount ? *qcount : static_cast<int>(gridDim.x);
+  const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int q = qlist ? qlist[item] : item;
+    if (q >= nl) return;                  // uniform over the block
+    const int nc = ncand[q];
+    const long long qo = static_cast<long long>(q) * n;
+    const int32_t *hq = hm_tmp + qo;
+    for (int h = tid; h <= d; h += kOrderThreads) hist[h] = 0;
+    __syncthreads();
+    // histogram: the lanes of a step holding equal distances add once (their
+    // count), so that a crowded bin is not hit by 64 atomics at once
+    {
+      int nbits_all = 0;
+      while ((1 << nbits_all) <= d) ++nbits_all;
+      const unsigned long long below = lanes_below_mask();
+      constexpr int U = 4;
+      for (int i0 = wv * kWave * U; i0 < nc; i0 += kOrderThreads * U) {
+        int hv[U];
 #pragma unroll
-    for (int u = 0; u < kPlaceU; ++u) load(min(i0 + u * kWave + lane, b1 - 1), k[u], v[u]);  // clamped
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * kWave + lane;
+          hv[u] = hq[i < nc ? i : nc - 1];  // clamped: every load is issued
+        }
 #pragma unroll
-    for (int u = 0; u < kPlaceU; ++u)
-      if (i0 + u * kWave + lane < b1) atomicAdd(&cnt[wv][(k[u] >> shift) & 127], 1);
-  }
-  __syncthreads();
-  // start of (wave w, digit g) = (elements of smaller digits) + (digit g in waves < w)
-  if (wv == 0) {
-    int t0 = 0, t1 = 0;
-    for (int w = 0; w < kOrderWaves; ++w) { t0 += cnt[w][2 * lane]; t1 += cnt[w][2 * lane + 1]; }
-    const int incl = wave_incl_scan_i32(t0 + t1);
-    int run0 = incl - t0 - t1, run1 = incl - t1;
-    for (int w = 0; w < kOrderWaves; ++w) {
-      const int c0 = cnt[w][2 * lane], c1 = cnt[w][2 * lane + 1];
-      cnt[w][2 * lane] = run0;
-      cnt[w][2 * lane + 1] = run1;
-      run0 += c0;
-      run1 += c1;
-    }
-  }
-  __syncthreads();
-  const unsigned long long below = lanes_below_mask();
-  for (int s0 = b0; s0 < b1; s0 += kPlaceU * kWave) {
-    int kk[kPlaceU], vv[kPlaceU];
-#pragma unroll
-    for (int u = 0; u < kPlaceU; ++u) load(min(s0 + u * kWave + lane, b1 - 1), kk[u], vv[u]);  // clamped
-#pragma unroll
-    for (int u = 0; u < kPlaceU; ++u) {
-      const bool valid = s0 + u * kWave + lane < b1;
-      const int k = kk[u], v = vv[u];
-      const int g = (k >> shift) & 127;
-      unsigned long long same = __ballot(valid);
-#pragma unroll
-      for (int bit = 0; bit < 7; ++bit) {
-        const bool on = (g >> bit) & 1;
-        const unsigned long long bb = __ballot(on);
-        same &= on ? bb : ~bb;
-      }
-      if (valid) {
-        const int pos = cnt[wv][g] + __popcll(same & below);
-        if constexpr (kPackedOut) {
-          pk_out[pos] = (static_cast<long long>(k) << 32) | static_cast<unsigned int>(v);
-        } else {
-          key_out[pos] = k;
-          val_out[pos] = v;
+        for (int u = 0; u < U; ++u) {
+          const bool ok = i0 + u * kWave + lane < nc;
+          unsigned long long same = __ballot(ok);
+          for (int bit = 0; bit < nbits_all; ++bit) {
+            const bool on = (hv[u] >> bit) & 1;
+            const unsigned long long bb = __ballot(on);
+            same &= on ? bb : ~bb;
+          }
+          if (ok && (same & below) == 0) atomicAdd(&hist[hv[u]], __popcll(same));
         }
       }
-      __builtin_amdgcn_wave_barrier();
-      if (valid && (same & below) == 0) cnt[wv][g] += __popcll(same);
-      __builtin_amdgcn_wave_barrier();
     }
+    __syncthreads();
+    block_exclusive_scan(hist, d + 1, tmp);  // hist[h] = first position of bin h
+    // order statistics: the bin holding position p - 1 (largest h with start <= p - 1)
+    if (tid < kHamStats) {
+      int v = 0;
+      if (nc > 0) {
+        const int p = tid < kHamStats - 1 ? min(1 << tid, nc) : (nc + 1) / 2;
+        v = upper_bound_minus1(hist, d + 1, p - 1);
+      }
+      hstat[static_cast<long long>(q) * kHamStats + tid] = v;
+    }
+    const int want = min(nc, plen);
+    const int hcut = want > 0 ? upper_bound_minus1(hist, d + 1, want - 1) : -1;
+    const int placed = hcut < 0 ? 0 : (hcut < d ? hist[hcut + 1] : nc);
+    if (tid == 0) avail[q] = placed;
+    __syncthreads();
+    if (wv == 0 && hcut >= 0) {
+      int nbits = 0;
+      while ((1 << nbits) <= hcut) ++nbits;
+      const unsigned long long below = lanes_below_mask();
+      constexpr int U = 8;  // steps whose distances and ids are loaded together
+      for (int i0 = 0; i0 < nc; i0 += kWave * U) {
+        int hv[U], iv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = min(i0 + u * kWave + lane, nc - 1);  // clamped: every load is issued
+          hv[u] = hq[i];
+          iv[u] = cand[qo + i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int h = hv[u];
+          const bool in = i0 + u * kWave + lane < nc && h <= hcut;
+          unsigned long long same = __ballot(in);
+          if (same == 0ull) continue;  // wave-uniform
+          for (int bit = 0; bit < nbits; ++bit) {
+            const bool on = (h >> bit) & 1;
+            const unsigned long long bb = __ballot(on);
+            same &= on ? bb : ~bb;
+          }
+          if (in) {
+            const int pos = hist[h] + __popcll(same & below);
+            order[qo + pos] = iv[u];
+            ham_sorted[qo + pos] = h;
+          }
+          __builtin_amdgcn_wave_barrier();
+          if (in && (same & below) == 0) hist[h] += __popcll(same);
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
-// Candidates in ascending (Hamming distance, id) order: the candidate list
-// is in ascending id order, so two stable 7-bit passes (low digit, then high
-// digit; distances <= 8192 < 2^14) give the order.  tmp: int64 per candidate.
-__global__ void __launch_bounds__(kOrderThreads) k_hamming_place(
-    int d, const int32_t *__restrict__ ncand, const int32_t *__restrict__ cand, long long n,
-    const int32_t *__restrict__ hm_tmp, long long *__restrict__ tmp, int32_t *__restrict__ order,
-    int32_t *__restrict__ ham_sorted, const int32_t *__restrict__ live) {
-  __shared__ int cnt[kOrderWaves][128];
-  const int q = blockIdx.x;
-  if (live && q >= *live) return;
-  const int nc = ncand[q];
-  const long long qo = static_cast<long long>(q) * n;
-  radix_pass<false, true>(nc, 0, hm_tmp + qo, cand + qo, nullptr, nullptr, nullptr, tmp + qo, cnt);
-  radix_pass<true, false>(nc, 7, nullptr, nullptr, tmp + qo, ham_sorted + qo, order + qo, nullptr, cnt);
+__host__ __device__ inline size_t hamming_order_lds(int d) {
+  return (static_cast<size_t>(d) + 1 + kOrderThreads / kWave + 1) * sizeof(int);
 }
 
 // ---------------------------------------------------------------------------
@@ -2067,10 +2080,11 @@ __device__ inline void select_topk(double *__restrict__ keys, const int32_t *__r
       double *__restrict__ dkey, float *__restrict__ lbuf, int32_t *__restrict__ rbuf,                        \
       int64_t *__restrict__ out_ids, float *__restrict__ out_d, int32_t *__restrict__ examined,              \
       int32_t *__restrict__ last_upd, int32_t *__restrict__ stopped, int32_t *__restrict__ refined,           \
-      const double *__restrict__ ads_fac, long long *__restrict__ row_bytes
+      const double *__restrict__ ads_fac, long long *__restrict__ row_bytes, const int32_t *__restrict__ avail, \
+      int32_t *__restrict__ redo, int32_t *__restrict__ nredo
 #define CRISP_RERANK_ARGS                                                                                 \
   qrot, d, base, base16, rerr, gam, ncand, list, n, k, patience, limits, dkey, lbuf, rbuf, out_ids, out_d, \
-      examined, last_upd, stopped, refined, ads_fac, row_bytes
+      examined, last_upd, stopped, refined, ads_fac, row_bytes, avail, redo, nredo
 
 // One query, whole block.  kAds (Optimized Mode, float32 rows): walked
 // candidates are verified with ADSampling.
@@ -2169,11 +2183,14 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
 
   if constexpr (kMode == 1) {
     // ---- Optimized: Hamming order with patience ------------------------------
-    int lim = nc;
+    int lim0 = nc;
     if (limits != nullptr) {
       const int l = limits[q];
-      if (l > 0 && l < lim) lim = l;
+      if (l > 0 && l < lim0) lim0 = l;
     }
+    // only the first avail[q] positions of the order are placed; a walk that
+    // reaches them without stopping is redone on the full order
+    const int lim = avail != nullptr ? min(lim0, avail[q]) : lim0;
     if (tid == 0) {
       S.misc[2] = 0; S.misc[3] = 0; S.misc[4] = 0; S.misc[5] = 0; S.misc[6] = 0; S.misc[8] = 0;
       S.rbytes = 0;
@@ -2393,6 +2410,7 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
     __syncthreads();
     // The top-k is in (key, id) order; write_topk fixes the float32 values.
     write_topk(S.misc[2], k, cb, sq, base, d, top_d, top_i, top_x, oi, od);
+    if (tid == 0 && redo != nullptr && lim < lim0 && !S.misc[5]) redo[atomicAdd(nredo, 1)] = q;
     if (tid == 0) {
       examined[q] = S.misc[6];
       last_upd[q] = S.misc[4];

@@ -81,6 +81,22 @@ def compare(idx, q, k, *, mode, alpha, tau, patience_factor=40, limits=None, gpu
                 assert int(tp["stopped"][qi]) == (0 if t["stop"] is None else 1), f"stopped q={qi}"
     assert np.array_equal(gi, oi), "ids"
     assert np.array_equal(gd.view(np.uint32), od.view(np.uint32)), "dists"
+    if mode == 1 and walk_order == 0:
+        # without the order taps only a prefix of the Hamming order is placed
+        # before the walk (order_prefix 0: automatic; 1: every walk that goes
+        # past its first candidate is redone on the full order)
+        qt = torch.from_numpy(np.ascontiguousarray(q, dtype=np.float32)).to(g.device)
+        lim = None if limits is None else torch.from_numpy(np.asarray(limits, dtype=np.int32)).to(g.device)
+        for op in (0, 1):
+            small = {"examined": torch.empty(q.shape[0], dtype=torch.int32, device=g.device),
+                     "last_update": torch.empty(q.shape[0], dtype=torch.int32, device=g.device)}
+            pi, pd = g.search(qt, k, mode=mode, alpha=alpha, tau=tau, patience_factor=patience_factor, limits=lim,
+                              max_chunk=max_chunk, precision=precision, verify=verify, order_prefix=op, taps=small)
+            torch.cuda.synchronize()
+            assert np.array_equal(pi.cpu().numpy(), oi), f"ids, order prefix {op}"
+            assert np.array_equal(pd.cpu().numpy().view(np.uint32), od.view(np.uint32)), f"dists, order prefix {op}"
+            assert np.array_equal(small["examined"].cpu().numpy(), tp["examined"]), f"examined, order prefix {op}"
+            assert np.array_equal(small["last_update"].cpu().numpy(), tp["last_update"]), f"L*, order prefix {op}"
     return {"n_cand": [t["candidates"].size for t in tr], "gpu": g, "taps": tp, "ids": gi, "dists": gd}
 
 
