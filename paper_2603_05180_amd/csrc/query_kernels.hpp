@@ -25,21 +25,26 @@ namespace crisp {
 // values are exact in float64; so chaining the instructions in ascending k
 // gives every output exactly the ascending-k float64 sum of its definition.
 // 128x64 output tile per 256-thread block, 64x32 per wavefront (4x2 tiles of
-// 16x16); the k dimension is staged through LDS 32 at a time, converted to
-// float64 on the way in, with the next slab prefetched into registers.
+// 16x16).  The k dimension goes through LDS in 8-deep float32 slabs, double
+// buffered (one barrier per slab: the next slab is loaded into registers
+// while the current one feeds the matrix cores, then stored to the other
+// buffer); fragments are widened to float64 after the LDS read.  Small
+// slabs and float32 staging keep the kernel at 110 registers, four waves per
+// SIMD (measured against 16- and 32-deep slabs, float64 staging, 128x128
+// block tiles and two or three waves per SIMD: 55-60 TF/s, this one at the
+// top).  Rows padded by 16 floats: the four k of a fragment fall in
+// different banks.
 // ---------------------------------------------------------------------------
-constexpr int kRotBM = 128, kRotBN = 64, kRotBK = 32;
+constexpr int kRotBM = 128, kRotBN = 64, kRotBK = 8, kRotPad = 16;
 constexpr int kRotEA = kRotBM * kRotBK / 256, kRotEB = kRotBK * kRotBN / 256;  // staged floats per thread
 typedef double rot_acc_t __attribute__((ext_vector_type(4)));
 
 // live: NULL, or a device count of the rows to produce (rows beyond it are skipped).
-__global__ void __launch_bounds__(256) k_rotate_rows(const float *__restrict__ x, long long rows, int d,
-                                                     const float *__restrict__ r, float *__restrict__ out,
-                                                     const int32_t *__restrict__ live) {
-  // [k][row] / [k][col]: the 16 lanes of one k read 16 consecutive doubles;
-  // rows padded by two doubles so the four k of a fragment use other banks.
-  __shared__ __align__(16) double sa[kRotBK][kRotBM + 2];
-  __shared__ __align__(16) double sb[kRotBK][kRotBN + 2];
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_rotate_rows(const float *__restrict__ x, long long rows, int d, const float *__restrict__ r,
+              float *__restrict__ out, const int32_t *__restrict__ live) {
+  __shared__ __align__(16) float sa[2][kRotBK][kRotBM + kRotPad];
+  __shared__ __align__(16) float sb[2][kRotBK][kRotBN + kRotPad];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int fi = lane & 15, fk = lane >> 4;          // fragment row / k of this lane
   const int wr = (wv >> 1) * 64, wc = (wv & 1) * 32; // the wavefront's 64x32 sub-tile
@@ -69,32 +74,38 @@ __global__ void __launch_bounds__(256) k_rotate_rows(const float *__restrict__ x
       rb[e] = r[static_cast<long long>(k0 + kk) * d + col0 + cc];
     }
   };
-  gload(0);
-  for (int k0 = 0; k0 < d; k0 += kRotBK) {
+  auto store = [&](int b) {
 #pragma unroll
     for (int e = 0; e < kRotEA; ++e) {
       const int idx = tid + e * 256;
-      sa[idx % kRotBK][idx / kRotBK] = static_cast<double>(ra[e]);
+      sa[b][idx % kRotBK][idx / kRotBK] = ra[e];
     }
 #pragma unroll
     for (int e = 0; e < kRotEB; ++e) {
       const int idx = tid + e * 256;
-      sb[idx / kRotBN][idx % kRotBN] = static_cast<double>(rb[e]);
+      sb[b][idx / kRotBN][idx % kRotBN] = rb[e];
     }
-    __syncthreads();
-    if (k0 + kRotBK < d) gload(k0 + kRotBK);
+  };
+  const int nslab = d / kRotBK;
+  gload(0);
+  store(0);
+  __syncthreads();
+  for (int s = 0; s < nslab; ++s) {
+    const int cur = s & 1;
+    if (s + 1 < nslab) gload((s + 1) * kRotBK);
 #pragma unroll
     for (int kk = 0; kk < kRotBK; kk += 4) {
       double a[4], b[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = sa[kk + fk][wr + i * 16 + fi];
+      for (int i = 0; i < 4; ++i) a[i] = static_cast<double>(sa[cur][kk + fk][wr + i * 16 + fi]);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = sb[kk + fk][wc + j * 16 + fi];
+      for (int j = 0; j < 2; ++j) b[j] = static_cast<double>(sb[cur][kk + fk][wc + j * 16 + fi]);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    if (s + 1 < nslab) store(cur ^ 1);
     __syncthreads();
   }
   // Accumulator element v of lane l holds row fk + 4v, column fi of its tile.
