@@ -426,8 +426,9 @@ def measure(args, pool):
     rerank_bytes = rerank_bytes_of(kw, c, d)
     per_step = {
         "rotate": ("mfma", 2.0 * d * d * w.n_query / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"),
-        # first counting pass: every retrieved id read once, every candidate (id, score) written once
-        "count": ("hbm", (4.0 * c["retrieved"] + 5.0 * c["n_cand"]) / 1e9, HBM_PEAK_GBS, "GB/s"),
+        # first counting pass: every retrieved posting entry read once (its
+        # 2-byte counter position), every candidate (id, score) written once
+        "count": ("hbm", (2.0 * c["retrieved"] + 5.0 * c["n_cand"]) / 1e9, HBM_PEAK_GBS, "GB/s"),
         "hamming_dist": ("hbm", (d / 8.0 + 8.0) * c["n_cand"] / 1e9, HBM_PEAK_GBS, "GB/s"),
         "rerank": ("hbm", rerank_bytes / 1e9, HBM_PEAK_GBS, "GB/s"),
     }

@@ -101,9 +101,10 @@ typedef struct {
 
 /*
  * Bytes of the device buffer crisp_index_load needs for derived per-index
- * tables (per cell and id tile, where each posting list crosses tile
- * boundaries).  tile_ids: ids per collision-counting tile (a power of two in
- * [4096, 131072]; 0 = library default).
+ * tables: per cell and id tile, where each posting list crosses tile
+ * boundaries; and the posting lists in the counting kernel's form, 2 bytes
+ * per entry (M x N entries).  tile_ids: ids per collision-counting tile (a
+ * power of two in [4096, 65536]; 0 = library default).
  */
 crisp_status crisp_index_derived_bytes(const crisp_index_desc *desc, int32_t tile_ids,
                                        size_t *bytes);

@@ -67,6 +67,7 @@ crisp_status check_shape(int64_t n, int32_t d, int32_t m, int32_t k) {
   if (d % 64 != 0) return fail(CRISP_E_UNSUPPORTED, "D must be a multiple of 64");
   if (d > 8192) return fail(CRISP_E_UNSUPPORTED, "D must be <= 8192");
   if (m > 127) return fail(CRISP_E_UNSUPPORTED, "M must be <= 127");
+  if (static_cast<int64_t>(m) * n >= (int64_t(1) << 31)) return fail(CRISP_E_UNSUPPORTED, "M x N must be < 2^31");
   if (d % (2 * m) != 0) return fail(CRISP_E_UNSUPPORTED, "D must be a multiple of 2M");
   if (k > 256) return fail(CRISP_E_UNSUPPORTED, "K must be <= 256");
   // The selection's path for K > 64 (prefix-size tables in device memory)
@@ -131,6 +132,7 @@ struct crisp_index {
   const uint16_t *base16 = nullptr;  // bfloat16 copy of the rows (crisp_index_enable_bf16)
   const float *rerr = nullptr;       // per-row bound of the bfloat16 rounding error
   int32_t *tile_off;
+  uint16_t *pos16;  // counter byte position of every posting-list entry (load-time form)
   float *cent_t;  // [M][2][h][K]
   double *ads_fac;  // ADSampling factors (t/D)(1 + eps_0/sqrt(t))^2, t = 32, 64, ... < D
   int ncu = 256;  // compute units of the device the index was loaded on
@@ -243,14 +245,15 @@ crisp_status crisp_index_derived_bytes(const crisp_index_desc *desc, int32_t til
   crisp_status s = check_shape(desc->n, desc->d, desc->m, desc->k_half);
   if (s != CRISP_OK) return s;
   int tile = resolve_tile(tile_ids);
-  if (tile < 4096 || tile > 131072 || (tile & (tile - 1)))
-    return fail(CRISP_E_INVALID, "tile_ids must be a power of two in [4096, 131072]");
+  if (tile < 4096 || tile > 65536 || (tile & (tile - 1)))
+    return fail(CRISP_E_INVALID, "tile_ids must be a power of two in [4096, 65536]");
   long long ntiles = (desc->n + tile - 1) / tile;
   if (ntiles > 1024) return fail(CRISP_E_UNSUPPORTED, "N / tile_ids must be <= 1024");
   long long ncells = static_cast<long long>(desc->k_half) * desc->k_half;
   const size_t h = static_cast<size_t>(desc->d) / (2 * desc->m);
   *bytes = align_up(static_cast<size_t>(desc->m) * ncells * (ntiles + 1) * 4) +
-           align_up(static_cast<size_t>(desc->m) * 2 * desc->k_half * h * 4) + ads_table_bytes(desc->d) + 256;
+           align_up(static_cast<size_t>(desc->m) * 2 * desc->k_half * h * 4) + ads_table_bytes(desc->d) +
+           align_up(static_cast<size_t>(desc->m) * desc->n * 2) + 256;
   return CRISP_OK;
 }
 
@@ -292,17 +295,32 @@ crisp_status crisp_index_load(const crisp_index_desc *desc, int32_t tile_ids, vo
   // correctly rounded square root each); the copy completes before returning.
   double *ads_fac = reinterpret_cast<double *>(reinterpret_cast<char *>(cent_t) +
                                                align_up(static_cast<size_t>(desc->m) * 2 * desc->k_half * hh * 4));
+  // Counter positions of the posting-list entries (uint16 each).
+  uint16_t *pos16 = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(ads_fac) + ads_table_bytes(desc->d));
+  const long long npos = static_cast<long long>(desc->m) * desc->n;
+  k_count_positions<<<grid_stride(npos, 256), 256, 0, st>>>(desc->ids, npos, pos16);
+  LAUNCH_TRY("k_count_positions");
   std::vector<double> fac = ads_factors(desc->d);
   if (!fac.empty()) {
     HIP_TRY(hipMemcpyAsync(ads_fac, fac.data(), fac.size() * sizeof(double), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
   }
+  {
+    // the counting kernels address their counters from LDS address 0
+    const void *kc[3] = {reinterpret_cast<const void *>(&k_count<0>), reinterpret_cast<const void *>(&k_count<1>),
+                         reinterpret_cast<const void *>(&k_count<2>)};
+    for (int i = 0; i < 3; ++i) {
+      hipFuncAttributes fa{};
+      HIP_TRY(hipFuncGetAttributes(&fa, kc[i]));
+      if (fa.sharedSizeBytes != 0) return fail(CRISP_E_HIP, "k_count<%d> has %zu bytes of static LDS", i, fa.sharedSizeBytes);
+    }
+  }
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_count<0>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              tile));
+                              tile + static_cast<int>(sizeof(CountShared))));
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_count<1>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              tile));
+                              tile + static_cast<int>(sizeof(CountShared))));
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_count<2>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              tile));
+                              tile + static_cast<int>(sizeof(CountShared))));
   {
     const void *rr[5] = {reinterpret_cast<const void *>(&k_rerank<0, false>),
                          reinterpret_cast<const void *>(&k_rerank<0, true>),
@@ -319,6 +337,7 @@ crisp_status crisp_index_load(const crisp_index_desc *desc, int32_t tile_ids, vo
   ix->h = desc->d / (2 * desc->m); ix->ncells = ncells; ix->tile = tile; ix->ntiles = ntiles;
   ix->rot = desc->rotation; ix->cent = desc->centroids; ix->base = desc->base;
   ix->off = desc->offsets; ix->ids = desc->ids; ix->codes = desc->codes; ix->tile_off = tile_off;
+  ix->pos16 = pos16;
   ix->cent_t = cent_t;
   ix->ads_fac = ads_fac;
   {
@@ -453,7 +472,7 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
   const int budget = static_cast<int>(std::max<double>(1.0, std::ceil(p->alpha * static_cast<double>(n))));
   const int patience =
       p->mode == 1 ? static_cast<int>(std::min<long long>(static_cast<long long>(p->patience_factor) * k, INT32_MAX)) : 0;
-  const size_t count_lds = static_cast<size_t>(ix->tile);
+  const size_t count_lds = static_cast<size_t>(ix->tile) + sizeof(CountShared);
   const int nseg = ix->ntiles * kCountWaves;
   const bool bf16 = p->precision >= 1;
   // precision 2: certified bfloat16 matrix-core pre-scoring of the half
@@ -574,7 +593,7 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
     {
       dim3 g(ix->ntiles, cq);
       StageTimer t3(ix, 3, st);
-      k_count<0><<<g, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
+      k_count<0><<<g, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->pos16, n, ix->tile_off,
                                                       ix->ntiles, ix->tile, p->tau, flag, taueff, segids, segscore,
                                                       tilecnt, hist, lv, flist, nflag);
       LAUNCH_TRY("k_count pass 0");
@@ -584,13 +603,13 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       LAUNCH_TRY("k_flag");
       // the fallback passes walk the flagged queries' list
       const dim3 gf(ix->ntiles, std::min(cq, 256));
-      k_count<1><<<gf, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
+      k_count<1><<<gf, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->pos16, n, ix->tile_off,
                                                       ix->ntiles, ix->tile, p->tau, flag, taueff, segids, segscore,
                                                       tilecnt, hist, lv, flist, nflag);
       LAUNCH_TRY("k_count pass 1");
       k_tau_eff<<<grid1(cq, 256), 256, 0, st>>>(flag, cq, k, p->tau, nb, hist, taueff, tilecnt, nseg, lv);
       LAUNCH_TRY("k_tau_eff");
-      k_count<2><<<gf, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->off, ix->ids, n, ix->tile_off,
+      k_count<2><<<gf, kCountThreads, count_lds, st>>>(ncell, cells, m, ix->ncells, ix->pos16, n, ix->tile_off,
                                                       ix->ntiles, ix->tile, p->tau, flag, taueff, segids, segscore,
                                                       tilecnt, hist, lv, flist, nflag);
       LAUNCH_TRY("k_count pass 2");

@@ -924,10 +924,20 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
 // exceed 2M <= 254.  Within each group of 32 ids, id 8j + i (j < 4, i < 8)
 // is byte j of the group's dword i, so that the threshold test of a dword
 // lands, with one shift, on the bits that keep a lane's 64 counters in id
-// order.  Work items are (subspace, activated cell) pairs; each
-// contributes the slice of the cell's posting list inside the tile (from the
-// load-time cell x tile table); waves take whole slices round robin and
-// stride them with four coalesced id loads in flight per lane.
+// order.  The posting lists are read in a load-time form: per entry, the
+// uint16 byte position of its id's counter inside a 65,536-id tile (the
+// layout above, which permutes only within groups of 32, so the position in
+// a tile of 2^t <= 65,536 ids is the low t bits); a counter update is then an
+// AND, two shifts and the atomic.  Work items are (subspace, activated cell)
+// pairs; each contributes the slice of the cell's posting list inside the
+// tile (from the load-time cell x tile table).  The block cuts the slices
+// into sub-slices of at most 64 entries and lists them in LDS; waves take
+// eight consecutive sub-slices at a time, round robin, with each record in
+// scalar registers, and issue the eight 64-lane loads before the first
+// counter update, so that a wave waits for memory once per eight
+// sub-slices.  The block's setup costs two dependent round trips to memory
+// when every subspace activates at most 1024 / M cells (counts and cells
+// loaded together, then the table), three otherwise.
 // Each of the 16 waves then scans its sixteenth of the counters (64 per lane
 // per step, four bytes of a dword tested by one 32-bit add when 2M < 128,
 // else in two 16-bit fields) and writes the ids reaching the threshold, in
@@ -940,40 +950,99 @@ __global__ void __launch_bounds__(64) k_select_cells(const float *__restrict__ q
 // ---------------------------------------------------------------------------
 constexpr int kCountThreads = 1024;
 constexpr int kCountWaves = kCountThreads / kWave;
-constexpr int kItems = 1024;
-
-// A pointer into global memory (read back from LDS, the compiler would
-// otherwise treat it as generic and use flat loads).
-typedef const int32_t __attribute__((address_space(1))) *global_i32_ptr;
+constexpr int kSub = 1280;    // sub-slices (<= 64 entries) per batch
+constexpr int kG = 8;         // sub-slices per wave per round (loads in flight)
+static_assert(kG > 0 && kG <= kWave && (kG & (kG - 1)) == 0, "a wave's lanes u < kG read its kG records");
 
 // LDS byte offset of the counter of tile-local id loc (the layout above).
 __device__ __forceinline__ int cnt_dword_bytes(int loc) { return (loc & ~31) | ((loc << 2) & 31); }
 __device__ __forceinline__ int cnt_byte(int loc) { return cnt_dword_bytes(loc) | ((loc >> 3) & 3); }
 
+// A posting-list entry in global memory (a pointer formed from values read
+// back from LDS would otherwise be treated as generic and loaded with flat
+// instructions).
+typedef const uint16_t __attribute__((address_space(1))) *global_u16_ptr;
+typedef uint32_t __attribute__((address_space(3))) *lds_u32_ptr;
+
+// Adds v to the LDS dword at byte address addr.
+__device__ __forceinline__ void lds_add(uint32_t addr, uint32_t v) {
+  __hip_atomic_fetch_add(reinterpret_cast<lds_u32_ptr>(static_cast<uintptr_t>(addr)), v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 struct CountShared {
-  global_i32_ptr ptr[kItems];  // first id of the item's slice (ids itself for an empty slice)
-  int lw[kItems];              // slice length << 8 | rank weight
+  // per sub-slice: element offset of its first entry in the position array;
+  // length << 8 | rank weight.  kG empty entries follow the last one.
+  uint32_t soff[kSub + kG], slw[kSub + kG];
   int mbase[129];
   int hist[256];
   int tmp[kCountWaves + 1];
+  int wide[kCountWaves];
+  int misc;
 };
 
-#define CRISP_COUNT_PARAMS                                                                                    \
-  const int32_t *__restrict__ ncell, const int32_t *__restrict__ cells, int m, int ncells,                    \
-      const int32_t *__restrict__ offsets, const int32_t *__restrict__ ids, long long n,                      \
-      const int32_t *__restrict__ tile_off, int ntiles, int tile_ids, int tau, const int32_t *__restrict__ flag, \
-      const int32_t *__restrict__ tau_eff, int32_t *__restrict__ seg_ids, uint8_t *__restrict__ seg_score,    \
-      int32_t *__restrict__ seg_cnt, int32_t *__restrict__ hist, const int32_t *__restrict__ live
-#define CRISP_COUNT_ARGS                                                                                  \
-  ncell, cells, m, ncells, offsets, ids, n, tile_off, ntiles, tile_ids, tau, flag, tau_eff, seg_ids, seg_score, \
-      seg_cnt, hist, live
+#define CRISP_COUNT_PARAMS                                                                                      \
+  const int32_t *__restrict__ ncell, const int32_t *__restrict__ cells, int m, int ncells,                      \
+      const uint16_t *__restrict__ pos, long long n, const int32_t *__restrict__ tile_off, int ntiles,         \
+      int tile_ids, int tau, const int32_t *__restrict__ flag, const int32_t *__restrict__ tau_eff,            \
+      int32_t *__restrict__ seg_ids, uint8_t *__restrict__ seg_score, int32_t *__restrict__ seg_cnt,           \
+      int32_t *__restrict__ hist, const int32_t *__restrict__ live
+#define CRISP_COUNT_ARGS                                                                                 \
+  ncell, cells, m, ncells, pos, n, tile_off, ntiles, tile_ids, tau, flag, tau_eff, seg_ids, seg_score, seg_cnt, \
+      hist, live
+
+// The block's counting rounds over the sub-slice list (total_sub records in
+// S.soff / S.slw, followed by kG empty ones).  Waves take kG consecutive
+// sub-slices at a time, round robin; lane u < kG reads record c0 + u, which
+// then goes to scalar registers.  All kG loads are issued before the first
+// counter update; they are unconditional (a lane past the end of its
+// sub-slice reads the last entry again, an empty record reads position 0),
+// so that no value register carries over between rounds and the loads
+// overlap.
+template <typename Shared>
+__device__ __forceinline__ void count_rounds(const Shared &S, int total_sub, const uint16_t *__restrict__ pos,
+                                             uint32_t amask) {
+  const int lane = lane_id();
+  const int wave0 = __builtin_amdgcn_readfirstlane(wave_id());
+  for (int c0 = wave0 * kG; c0 < total_sub; c0 += kG * kCountWaves) {
+    const int mi = c0 + (lane & (kG - 1));
+    const int moff = static_cast<int>(S.soff[mi]), mlw = static_cast<int>(S.slw[mi]);
+    uint32_t pv[kG];
+#pragma unroll
+    for (int u = 0; u < kG; ++u) {
+      const uint32_t o = static_cast<uint32_t>(__builtin_amdgcn_readlane(moff, u));
+      const int len = static_cast<int>(static_cast<uint32_t>(__builtin_amdgcn_readlane(mlw, u)) >> 8);
+      const uint32_t e = static_cast<uint32_t>(min(lane, max(len - 1, 0)));
+      pv[u] = *(global_u16_ptr)(reinterpret_cast<const char *>(pos) + 2u * (o + e));
+    }
+#pragma unroll
+    for (int u = 0; u < kG; ++u) {
+      const uint32_t l = static_cast<uint32_t>(__builtin_amdgcn_readlane(mlw, u));
+      if (lane < static_cast<int>(l >> 8)) lds_add(pv[u] & amask, (l & 255u) << ((pv[u] << 3) & 31));
+    }
+  }
+}
+
+// Writes the sub-slices of one activated cell's slice (element offset off,
+// length len, rank weight w) from record index at.
+template <typename Shared>
+__device__ __forceinline__ void put_subslices(Shared &S, int at, uint32_t off, int len, uint32_t w) {
+  for (int k = 0; k * kWave < len; ++k) {
+    S.soff[at + k] = off + static_cast<uint32_t>(k * kWave);
+    S.slw[at + k] = (static_cast<uint32_t>(min(kWave, len - k * kWave)) << 8) | w;
+  }
+}
 
 // One (id tile, query) block's work; every early return is uniform over the block.
 template <int kPass>
 __device__ __forceinline__ void count_block(const int tile, const int q, CRISP_COUNT_PARAMS) {
   constexpr int pass = kPass;
+  // dynamic LDS: the tile's counters first, then the block's shared records.
+  // The kernel has no static LDS (checked on the host at index load), so the
+  // counters start at LDS address 0 and a counter's byte position within the
+  // tile is its LDS address.
   extern __shared__ __align__(16) uint32_t cnt[];
-  __shared__ CountShared S;
+  CountShared &S = *reinterpret_cast<CountShared *>(reinterpret_cast<char *>(cnt) + tile_ids);
   const int tid = threadIdx.x;
   if (live && q >= *live) return;
   if (pass != 0 && flag[q] == 0) return;
@@ -982,92 +1051,128 @@ __device__ __forceinline__ void count_block(const int tile, const int q, CRISP_C
   const int ndw = tile_ids >> 2;  // counters allocated for a full tile
   const int thr = (pass == 0) ? tau : (pass == 1 ? 1 : tau_eff[q]);
   const int lane = lane_id();
+  const int wv0 = wave_id();
+  const long long qm = static_cast<long long>(q) * m;
+  // Counter dword of a position: its low t bits with the byte bits cleared;
+  // the byte's shift (8 x its low two bits) is what a 32-bit shift keeps of
+  // the position times 8.
+  const uint32_t amask = static_cast<uint32_t>(tile_ids - 1) & ~3u;
+  // Direct slots: thread t stands for cell t % J of subspace t / J, with J =
+  // 1024 / m rounded down to a power of two.  Its subspace's count and the
+  // cell are loaded together (the cell speculatively: in bounds, used only
+  // when t % J is below the count), then the cell's slice in the tile.
+  const int jl = 31 - __builtin_clz(static_cast<unsigned>(kCountThreads / m));   // log2 J
+  const int fs = tid >> jl, fj = tid & ((1 << jl) - 1);
+  int nco = 0, fpk = 0;
+  if (fs < m) {
+    nco = ncell[qm + fs];
+    if (fj < ncells) fpk = cells[(qm + fs) * ncells + fj];
+  }
   uint4 *cnt4 = reinterpret_cast<uint4 *>(cnt);
   for (int i = tid; i < (ndw >> 2); i += kCountThreads) cnt4[i] = make_uint4(0u, 0u, 0u, 0u);
   for (int i = tid; i < 256; i += kCountThreads) S.hist[i] = 0;
-  {
-    // Per-subspace activated-cell counts -> prefix mbase[0..m] (m <= 127:
-    // waves 0 and 1 load and scan them in parallel).
-    const int v = (tid < m) ? ncell[static_cast<long long>(q) * m + tid] : 0;
-    const int incl = wave_incl_scan_i32(v);
-    if (tid == kWave - 1) S.tmp[0] = incl;
-    __syncthreads();
-    if (tid < 2 * kWave) S.mbase[tid + 1] = incl + (tid >= kWave ? S.tmp[0] : 0);
-    if (tid == 0) S.mbase[0] = 0;
-    __syncthreads();
+  uint32_t off = 0, lw = 0;
+  int nsub = 0;
+  if (fs < m && fj < nco) {
+    const int cell = fpk & 0xFFFFFF;
+    const int32_t *to = tile_off + (static_cast<long long>(fs) * ncells + cell) * (ntiles + 1);
+    const int a = to[tile];
+    const int len = to[tile + 1] - a;
+    off = static_cast<uint32_t>(static_cast<long long>(fs) * n + a);   // M x N < 2^31
+    lw = (static_cast<uint32_t>(len) << 8) | (static_cast<uint32_t>(fpk) >> 24);
+    nsub = (len + kWave - 1) / kWave;
   }
-  const int total_items = S.mbase[m];
-  for (int b0 = 0; b0 < total_items; b0 += kItems) {
-    const int nb = min(kItems, total_items - b0);
-    for (int it = tid; it < kItems; it += kCountThreads) {
-      int len = 0;
-      global_i32_ptr ptr = (global_i32_ptr)(ids);
-      int w = 0;
-      if (it < nb) {
-        int g = b0 + it;
-        int s = upper_bound_minus1(S.mbase, m + 1, g);
-        int packed = cells[(static_cast<long long>(q) * m + s) * ncells + (g - S.mbase[s])];
-        int cell = packed & 0xFFFFFF;
-        w = packed >> 24;
-        const int32_t *to = tile_off + (static_cast<long long>(s) * ncells + cell) * (ntiles + 1);
-        const int a = to[tile];
-        len = to[tile + 1] - a;
-        if (len > 0) ptr = (global_i32_ptr)(ids + static_cast<long long>(s) * n + a);
-      }
-      S.ptr[it] = ptr;
-      S.lw[it] = (len << 8) | w;
-    }
+  {
+    const int incl = wave_incl_scan_i32(nsub);
+    const bool wide = __builtin_amdgcn_ballot_w64(fs < m && fj == 0 && nco > (1 << jl)) != 0;
+    if (lane == kWave - 1) S.tmp[wv0] = incl;
+    if (lane == 0) S.wide[wv0] = wide;
     __syncthreads();
-    // Waves take whole items (posting-list slices, a few dozen ids each on
-    // average) round robin, kG at a time: the first 64 ids of kG slices are
-    // loaded together, then any longer slice is strided with four coalesced
-    // loads in flight per lane.  Item reads are unconditional (an item past
-    // the batch reads as an empty slice) so that no lane mask is set up per
-    // slice.
-    constexpr int kG = 8;
-    const int wave0 = __builtin_amdgcn_readfirstlane(wave_id());
-    for (int it0 = wave0; it0 < nb; it0 += kG * kCountWaves) {
-      int idv[kG], lenv[kG];
-      global_i32_ptr ptrv[kG];
-      uint32_t wgv[kG];
+    int total = 0, excl = incl - nsub, anywide = 0;
 #pragma unroll
-      for (int u = 0; u < kG; ++u) {
-        const int it = it0 + u * kCountWaves;
-        const int itc = min(it, kItems - 1);
-        const int lw = S.lw[itc];
-        lenv[u] = it < nb ? (lw >> 8) : 0;
-        wgv[u] = static_cast<uint32_t>(lw & 255);
-        ptrv[u] = S.ptr[itc];
-        // clamped: every load is issued, an empty slice reads its first element
-        idv[u] = ptrv[u][min(lane, max(lenv[u] - 1, 0))];
-      }
-#pragma unroll
-      for (int u = 0; u < kG; ++u) {
-        const int loc = idv[u] - static_cast<int>(t0);
-        if (lane < lenv[u] && static_cast<unsigned>(loc) < static_cast<unsigned>(tlen))
-          atomicAdd(&cnt[cnt_dword_bytes(loc) >> 2], wgv[u] << (loc & 0x18));
-      }
-#pragma unroll 1
-      for (int u = 0; u < kG; ++u) {
-        const global_i32_ptr sp = ptrv[u];
-        const int len = lenv[u];
-        for (int p0 = kWave + lane; p0 < len; p0 += 4 * kWave) {
-          int iv[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int p = p0 + e * kWave;
-            iv[e] = sp[p < len ? p : len - 1];   // clamped: every load is issued
-          }
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int loc = iv[e] - static_cast<int>(t0);
-            if (p0 + e * kWave < len && static_cast<unsigned>(loc) < static_cast<unsigned>(tlen))
-              atomicAdd(&cnt[cnt_dword_bytes(loc) >> 2], wgv[u] << (loc & 0x18));
+    for (int j = 0; j < kCountWaves; ++j) {
+      const int t = S.tmp[j];
+      total += t;
+      excl += j < wv0 ? t : 0;
+      anywide |= S.wide[j];
+    }
+    // Common case: every activated cell has a direct slot and all
+    // sub-slices fit in the list (one round of the loop below).  Otherwise
+    // the activated cells are taken in subspace order (item g lies in
+    // subspace s with mbase[s] <= g < mbase[s + 1]), in batches whose
+    // sub-slices fit in the list.
+    const bool general = anywide || total > kSub;
+    int total_items = 0;
+    if (general) {
+      __syncthreads();                                     // every wave has read S.tmp and S.wide
+      // Per-subspace counts -> prefix mbase[0..m] (m <= 127: waves 0 and 1
+      // load and scan them in parallel).
+      const int v = (tid < m) ? ncell[qm + tid] : 0;
+      const int inc = wave_incl_scan_i32(v);
+      if (tid == kWave - 1) S.tmp[0] = inc;
+      __syncthreads();
+      if (tid < 2 * kWave) S.mbase[tid + 1] = inc + (tid >= kWave ? S.tmp[0] : 0);
+      if (tid == 0) S.mbase[0] = 0;
+      __syncthreads();
+      total_items = S.mbase[m];
+    }
+    for (int b0 = 0;;) {
+      int total_sub = total, taken = 0;
+      if (!general) {
+        if (nsub > 0) put_subslices(S, excl, off, static_cast<int>(lw >> 8), lw & 255u);
+        if (tid < kG) {
+          S.soff[total + tid] = 0;
+          S.slw[total + tid] = 0;
+        }
+        __syncthreads();
+      } else {
+        if (b0 >= total_items) break;
+        // Items b0 .. b0 + nb - 1, one per thread; the items whose
+        // sub-slices fit in the list are taken (at least the first: a slice
+        // has at most 65,536 / 64 = 1,024 <= kSub of them).
+        const int nb = min(kCountThreads, total_items - b0);
+        uint32_t goff = 0, glw = 0;
+        int gsub = 0;
+        if (tid < nb) {
+          const int g = b0 + tid;
+          const int s = upper_bound_minus1(S.mbase, m + 1, g);
+          const int packed = cells[(qm + s) * ncells + (g - S.mbase[s])];
+          const int32_t *to = tile_off + (static_cast<long long>(s) * ncells + (packed & 0xFFFFFF)) * (ntiles + 1);
+          const int a = to[tile];
+          const int len = to[tile + 1] - a;
+          goff = static_cast<uint32_t>(static_cast<long long>(s) * n + a);
+          glw = (static_cast<uint32_t>(len) << 8) | (static_cast<uint32_t>(packed) >> 24);
+          gsub = (len + kWave - 1) / kWave;
+        }
+        const int inc = wave_incl_scan_i32(gsub);
+        if (lane == kWave - 1) S.tmp[wv0] = inc;
+        __syncthreads();
+        int gex = inc - gsub;
+        for (int j = 0; j < wv0; ++j) gex += S.tmp[j];
+        const bool fits = tid < nb && gex + gsub <= kSub;
+        const unsigned long long fb = __builtin_amdgcn_ballot_w64(fits);
+        __syncthreads();                                   // every wave has read S.tmp
+        if (lane == 0) S.tmp[wv0] = __popcll(fb);
+        __syncthreads();
+        for (int j = 0; j < kCountWaves; ++j) taken += S.tmp[j];
+        if (fits) {
+          if (gsub > 0) put_subslices(S, gex, goff, static_cast<int>(glw >> 8), glw & 255u);
+          if (tid == taken - 1) {                          // the last item taken closes the list
+            S.misc = gex + gsub;
+            for (int k = 0; k < kG; ++k) {
+              S.soff[gex + gsub + k] = 0;
+              S.slw[gex + gsub + k] = 0;
+            }
           }
         }
+        __syncthreads();
+        total_sub = S.misc;
       }
+      count_rounds(S, total_sub, pos, amask);
+      __syncthreads();
+      if (!general) break;
+      b0 += taken;
     }
-    __syncthreads();
   }
 
   // ---- scan: threshold, histogram, ordered per-wave compaction --------------
@@ -1150,8 +1255,13 @@ __device__ __forceinline__ void count_block(const int tile, const int q, CRISP_C
 // pass 0: grid (tiles, queries).  Passes 1 and 2 concern the queries k_flag
 // listed (flist[0 .. *nflag)), usually none: a grid of (tiles, a few hundred)
 // blocks walks the list instead of launching a block for every query.
+// At most 80 scalar registers: with more, two 16-wave blocks do not fit on a
+// compute unit together (measured: 96 registers left one resident block per
+// unit and took 1.5x as long; the few values over the budget go to lanes of
+// a vector register).
 template <int kPass>
-__global__ void __launch_bounds__(kCountThreads) k_count(CRISP_COUNT_PARAMS, const int32_t *__restrict__ flist,
+__global__ void __launch_bounds__(kCountThreads) __attribute__((amdgpu_num_sgpr(80)))
+k_count(CRISP_COUNT_PARAMS, const int32_t *__restrict__ flist,
                                                           const int32_t *__restrict__ nflag) {
   if constexpr (kPass == 0) {
     count_block<0>(blockIdx.x, blockIdx.y, CRISP_COUNT_ARGS);
@@ -2520,6 +2630,14 @@ __global__ void k_tile_offsets(const int32_t *__restrict__ offsets, const int32_
     }
     dst[tt] = off[c] + lo;  // position in the subspace's id array
   }
+}
+
+// Per posting-list entry: the uint16 byte position of its id's collision
+// counter inside a 65,536-id tile (the counting kernel's layout).
+__global__ void k_count_positions(const int32_t *__restrict__ ids, long long total, uint16_t *__restrict__ pos) {
+  for (long long j = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; j < total;
+       j += static_cast<long long>(gridDim.x) * blockDim.x)
+    pos[j] = static_cast<uint16_t>(cnt_byte(ids[j] & 0xFFFF));
 }
 
 }  // namespace crisp

@@ -121,3 +121,21 @@ def test_codebooks_above_64_are_refused():
     assert b"K > 64" in _lib.lib.crisp_last_error()
     desc = _lib.IndexDesc(1000, 128, 4, 64, None, None, None, None, None, None)
     assert _lib.lib.crisp_index_derived_bytes(ctypes.byref(desc), 0, ctypes.byref(size)) == 0
+
+
+def test_tile_and_posting_size_limits():
+    """Collision-counting tiles hold at most 65,536 ids (a posting entry's
+    counter position is 16 bits) and the posting lists at most 2^31 entries
+    in all (their byte offsets are 32-bit); the derived buffer holds 2 bytes
+    per posting entry."""
+    from paper_2603_05180_amd import _lib
+    size = ctypes.c_size_t(0)
+    desc = _lib.IndexDesc(100_000, 128, 4, 8, None, None, None, None, None, None)
+    assert _lib.lib.crisp_index_derived_bytes(ctypes.byref(desc), 65536, ctypes.byref(size)) == 0
+    small = size.value
+    assert small >= 4 * 100_000 * 2
+    assert _lib.lib.crisp_index_derived_bytes(ctypes.byref(desc), 131072, ctypes.byref(size)) == -1
+    assert b"65536" in _lib.lib.crisp_last_error()
+    desc = _lib.IndexDesc(40_000_000, 128, 64, 8, None, None, None, None, None, None)
+    assert _lib.lib.crisp_index_derived_bytes(ctypes.byref(desc), 65536, ctypes.byref(size)) == -5
+    assert b"M x N" in _lib.lib.crisp_last_error()

@@ -114,7 +114,7 @@ def test_results_do_not_depend_on_tiles_or_chunks(d128, mode):
     w, x, q, idx, g = d128
     kw = dict(mode=mode, alpha=0.05, tau=4)
     ref = g.search(q, 10, **kw)
-    for tile in (4096, 8192, 131072):
+    for tile in (4096, 8192, 65536):
         print(f"tile={tile} mode={mode}", flush=True)
         gt = engine.Index(g.arrays | {"n": g.n, "d": g.d, "m": g.m, "k_half": g.k_half}, tile_ids=tile)
         for chunk in (0, 7, 64):
