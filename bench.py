@@ -689,7 +689,7 @@ def uneven_batches(args):
     sp = dict(kw, mode=1, precision=1, budget_source=1 if model is not None else 0)
     t = time.time()
     srv = autotune.Server(None, index, sp, max_batch=4096, ks=(1, 10, 100), tiles=(16384, 65536),
-                          chunks=(512, 1024))
+                          chunks=(512, 1024), count_tiles=(1, 4))
     choice = srv.tune(queries, [1 << i for i in range(13)], reps=2, cache=args.autotune_cache or None)
     torch.cuda.synchronize()
     log(f"uneven: tuned {len(choice)} (k, bucket) pairs in {time.time() - t:.1f}s")
@@ -713,8 +713,8 @@ def uneven_batches(args):
             tot += m * 10
         o += nq
     tuned = {}
-    for (k, b), (tile, chunk, pers) in sorted(choice.items()):
-        tuned[f"k{k}_b{b}"] = [tile, chunk, pers]
+    for (k, b), setting in sorted(choice.items()):
+        tuned[f"k{k}_b{b}"] = list(setting)
     out = {"workload": f"{w.name}: N={w.n} D={w.d} correlated Gaussian mixture ({w.kind} rank {w.rank}, "
                        f"{w.n_comp} comps), M={w.m} K={w.k_half}",
            "queries": int(sum(sizes)), "batches": len(sizes), "batch_sizes": "log-uniform in [1, 4096]",
@@ -725,7 +725,7 @@ def uneven_batches(args):
            "p99_batch_ms": round(float(np.percentile(lat, 99)), 4),
            "max_batch_ms": round(float(lat.max()), 4),
            "recall_at_10_sample": round(hit / max(1, tot), 4),
-           "tuned_tile_chunk_persistent": tuned}
+           "tuned_tile_chunk_persistent_counttiles": tuned}
     log(f"uneven: {out['queries_per_s']} q/s, p50 {out['p50_batch_ms']} ms, p99 {out['p99_batch_ms']} ms")
     srv.free()
     index.free()

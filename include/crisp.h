@@ -210,6 +210,11 @@ crisp_status crisp_index_enable_bf16(crisp_index *index, void *buffer, size_t by
  *                      0 = 2 P + 1024, P the patience).  A walk that reaches
  *                      their end without stopping is walked again on the
  *                      full order, so results never depend on it.
+ *   count_tiles     -- id tiles that one block of the collision-counting
+ *                      stage counts in turn (the activated cells are read
+ *                      once for them; 0 = chosen from the chunk size and the
+ *                      number of compute units).  Results do not depend on
+ *                      it.
  */
 typedef struct {
   int32_t mode;
@@ -225,6 +230,7 @@ typedef struct {
   int32_t walk_order;
   int32_t verify;
   int32_t order_prefix;
+  int32_t count_tiles;
 } crisp_search_params;
 
 /*

@@ -10,6 +10,8 @@ distribution and keeps the fastest:
   max_chunk  -- queries per internal chunk (bounded by workspace memory)
   persistent -- re-rank with one block per query, or a persistent grid
                 pulling queries from a device-side counter
+  count_tiles -- id tiles counted in turn by one collision-counting block
+                (0: the library's choice)
 
 Every candidate returns identical results (results do not depend on tiles,
 chunks or the re-rank grid), so the choice only affects time.  Results are
@@ -48,11 +50,13 @@ def _key(index: engine.Index, k: int, bucket: int, params: dict) -> str:
 class Server:
     """Indexes per tile over the same arrays, plans per setting, one shared buffer."""
 
-    def __init__(self, arrays: dict, base: engine.Index, params: dict, max_batch: int, ks, tiles, chunks):
+    def __init__(self, arrays: dict, base: engine.Index, params: dict, max_batch: int, ks, tiles, chunks,
+                 count_tiles=(0,)):
         self.arrays = {name: base.arrays[name] for name in base.arrays} | {
             "n": base.n, "d": base.d, "m": base.m, "k_half": base.k_half}
         self.base, self.params, self.max_batch = base, dict(params), int(max_batch)
         self.ks, self.tiles, self.chunks = list(ks), list(tiles), list(chunks)
+        self.count_tiles = list(count_tiles)
         self.indexes = {}
         self.plans = {}
         self.choice = {}
@@ -78,12 +82,13 @@ class Server:
             self.indexes[tile] = ix
         return self.indexes[tile]
 
-    def plan(self, k: int, tile: int, chunk: int, persistent: int):
-        key = (k, tile, chunk, persistent)
+    def plan(self, k: int, tile: int, chunk: int, persistent: int, count_tiles: int = 0):
+        key = (k, tile, chunk, persistent, count_tiles)
         if key not in self.plans:
             ix = self.index(tile)
             pl = engine.Plan.__new__(engine.Plan)
-            pl._p = ix.params(**(self.params | {"max_chunk": chunk, "persistent": persistent}))
+            pl._p = ix.params(**(self.params | {"max_chunk": chunk, "persistent": persistent,
+                                                "count_tiles": count_tiles}))
             h = ctypes.c_void_p(0)
             check(lib.crisp_plan_create(ix._h, self.max_batch, int(k), ctypes.byref(pl._p), engine._ptr(self.buf),
                                         self.buf.numel(), ctypes.byref(h)))
@@ -97,7 +102,8 @@ class Server:
                 if chunk > max(bucket, min(self.chunks)) and chunk != min(self.chunks):
                     continue
                 for persistent in (0, 1):
-                    yield tile, chunk, persistent
+                    for ct in self.count_tiles:
+                        yield tile, chunk, persistent, ct
 
     def tune(self, queries: torch.Tensor, buckets, reps: int = 3, cache: str | None = None, log=None):
         """Fastest setting per (k, bucket); reuses and extends the JSON cache."""
@@ -129,10 +135,10 @@ class Server:
                         best = (ms, cand)
                 self.choice[(k, b)] = best[1]
                 saved[key] = {"setting": list(best[1]), "ms": round(best[0], 4),
-                              "fields": ["tile_ids", "max_chunk", "persistent"]}
+                              "fields": ["tile_ids", "max_chunk", "persistent", "count_tiles"]}
                 if log:
                     log(f"tuned k={k} bucket={b}: tile={best[1][0]} chunk={best[1][1]} "
-                        f"persistent={best[1][2]} {best[0]:.3f} ms")
+                        f"persistent={best[1][2]} count_tiles={best[1][3]} {best[0]:.3f} ms")
         if cache:
             with open(cache, "w") as f:
                 json.dump(saved, f, indent=1, sort_keys=True)
@@ -145,8 +151,7 @@ class Server:
         o = 0
         for nq, k in zip(sizes, ks):
             b = bucket_of(nq)
-            tile, chunk, persistent = self.choice[(k, b)]
-            pl = self.plan(k, tile, chunk, persistent)
+            pl = self.plan(k, *self.choice[(k, b)])
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
             ids, d = pl.search(queries[o:o + nq])

@@ -996,9 +996,9 @@ struct CountShared {
 // sub-slices at a time, round robin; lane u < kG reads record c0 + u, which
 // then goes to scalar registers.  All kG loads are issued before the first
 // counter update; they are unconditional (a lane past the end of its
-// sub-slice reads the last entry again, an empty record reads position 0),
-// so that no value register carries over between rounds and the loads
-// overlap.
+// sub-slice reads the entries that follow, which exist: the position array
+// ends with 64 spare entries; an empty record reads the first 64), so that
+// no value register carries over between rounds and the loads overlap.
 template <typename Shared>
 __device__ __forceinline__ void count_rounds(const Shared &S, int total_sub, const uint16_t *__restrict__ pos,
                                              uint32_t amask) {
@@ -1011,9 +1011,7 @@ __device__ __forceinline__ void count_rounds(const Shared &S, int total_sub, con
 #pragma unroll
     for (int u = 0; u < kG; ++u) {
       const uint32_t o = static_cast<uint32_t>(__builtin_amdgcn_readlane(moff, u));
-      const int len = static_cast<int>(static_cast<uint32_t>(__builtin_amdgcn_readlane(mlw, u)) >> 8);
-      const uint32_t e = static_cast<uint32_t>(min(lane, max(len - 1, 0)));
-      pv[u] = *(global_u16_ptr)(reinterpret_cast<const char *>(pos) + 2u * (o + e));
+      pv[u] = *(global_u16_ptr)(reinterpret_cast<const char *>(pos) + 2u * (o + static_cast<uint32_t>(lane)));
     }
 #pragma unroll
     for (int u = 0; u < kG; ++u) {
@@ -1021,6 +1019,16 @@ __device__ __forceinline__ void count_rounds(const Shared &S, int total_sub, con
       if (lane < static_cast<int>(l >> 8)) lds_add(pv[u] & amask, (l & 255u) << ((pv[u] << 3) & 31));
     }
   }
+}
+
+// Sum of v[0 .. 15] (the block's per-wave values) and of v[0 .. w - 1], w
+// uniform over the wave: lane j < 16 reads v[j], then a wave scan.
+__device__ __forceinline__ int2 waves_total_and_before(const int *v, int w) {
+  const int lane = lane_id();
+  const int sc = wave_incl_scan_i32(lane < kCountWaves ? v[lane] : 0);
+  const int total = __builtin_amdgcn_readlane(sc, kCountWaves - 1);
+  const int before = w > 0 ? __builtin_amdgcn_readlane(sc, w - 1) : 0;
+  return make_int2(total, before);
 }
 
 // Writes the sub-slices of one activated cell's slice (element offset off,
@@ -1033,9 +1041,88 @@ __device__ __forceinline__ void put_subslices(Shared &S, int at, uint32_t off, i
   }
 }
 
-// One (id tile, query) block's work; every early return is uniform over the block.
+// Threshold scan of one tile's counters: each of the 16 waves scans its
+// sixteenth (64 counters per lane per step, four bytes of a dword tested by
+// one 32-bit add when 2M < 128, else in two 16-bit fields), counts the scores
+// >= 1 reached into the block's histogram (passes 0 and 1) and writes the ids
+// reaching the threshold, in ascending order, to its own segment (passes 0
+// and 2); returns the wave's candidate count.
+template <int kPass, typename Shared>
+__device__ __forceinline__ int scan_tile(Shared &S, const uint32_t *cnt, int q, long long t0, int tlen, int ndw,
+                                         int m, int thr, long long n, int32_t *__restrict__ seg_ids,
+                                         uint8_t *__restrict__ seg_score) {
+  constexpr int pass = kPass;
+  const int lane = lane_id();
+  const int wv = __builtin_amdgcn_readfirstlane(wave_id());
+  const int per_wave = ndw / kCountWaves;            // dwords per wave (tiles of 2^12..2^16 ids: a multiple of 256)
+  const int dw0 = wv * per_wave;
+  // The wave's segment; candidates are stored at 32-bit offsets from it.
+  char *dst = reinterpret_cast<char *>(seg_ids + static_cast<long long>(q) * n + t0 + static_cast<long long>(dw0) * 4);
+  char *dsc = reinterpret_cast<char *>(seg_score + static_cast<long long>(q) * n + t0 + static_cast<long long>(dw0) * 4);
+  int run = 0;
+  // Bytes >= thr, four at a time.  When 2M < 128 adding 128 - thr to every
+  // byte of a dword sets each byte's bit 7 exactly when the byte is >= thr
+  // (no carry leaves a byte).  Otherwise the even and odd bytes sit in
+  // 16-bit fields, and adding 256 - thr to a field sets its bit 8 exactly
+  // when the byte is >= thr.
+  const bool narrow = 2 * m < 128;
+  const uint32_t add4 = static_cast<uint32_t>(0x80 - thr) * 0x01010101u;
+  const uint32_t add = static_cast<uint32_t>(0x100 - thr) * 0x00010001u;
+  const uint8_t *cnt8 = reinterpret_cast<const uint8_t *>(cnt);
+  const uint4 *cnt4 = reinterpret_cast<const uint4 *>(cnt);
+  constexpr int kScanDw = 8;                         // dwords (32 counters, one group of 32 ids) per lane per step
+  for (int v0 = 0; v0 < per_wave; v0 += kScanDw * kWave) {
+    const int dwl = v0 + kScanDw * lane;             // this lane's first dword within the wave range
+    uint32_t words[kScanDw];
+#pragma unroll
+    for (int u = 0; u < kScanDw / 4; ++u) {
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (dwl < per_wave) v = cnt4[((dw0 + dwl) >> 2) + u];
+      words[4 * u] = v.x; words[4 * u + 1] = v.y; words[4 * u + 2] = v.z; words[4 * u + 3] = v.w;
+    }
+    const int idbase = (dw0 + dwl) * 4;              // tile-local id of the first counter (a multiple of 32)
+    // Bit 8j + i of sel (dword i, byte j) is the counter of id idbase + 8j + i.
+    uint32_t sel = 0u;
+    if (narrow) {
+#pragma unroll
+      for (int j = 0; j < kScanDw; ++j) sel |= ((words[j] + add4) >> (7 - j)) & (0x01010101u << j);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kScanDw; ++j) {
+        const uint32_t ge = (words[j] & 0x00FF00FFu) + add;           // bytes 0, 2 -> bits 8, 24
+        const uint32_t go = ((words[j] >> 8) & 0x00FF00FFu) + add;    // bytes 1, 3 -> bits 8, 24
+        sel |= ((ge >> (8 - j)) & (0x00010001u << j)) | ((go << j) & (0x01000100u << j));
+      }
+    }
+    const int nvalid = (dwl < per_wave) ? min(max(tlen - idbase, 0), 4 * kScanDw) : 0;
+    sel &= (nvalid >= 32) ? ~0u : ((1u << nvalid) - 1u);
+    const int c = __popc(sel);
+    int pos = run;
+    if (pass != 1) {
+      // exclusive prefix of c over the lanes, and the step's total
+      const int incl = wave_incl_scan_dpp(c);
+      pos += incl - c;
+      run += __builtin_amdgcn_readlane(incl, kWave - 1);
+    }
+    while (sel) {
+      const int e = __builtin_ctz(sel);               // id idbase + e: dword e & 7, byte e >> 3 of the group
+      sel &= sel - 1u;
+      const int sc = cnt8[idbase + ((e & 7) << 2) + (e >> 3)];
+      if (pass != 2 && sc >= 1) atomicAdd(&S.hist[sc], 1);
+      if (pass != 1) {
+        *reinterpret_cast<int32_t *>(dst + 4u * static_cast<uint32_t>(pos)) = static_cast<int32_t>(t0) + idbase + e;
+        *reinterpret_cast<uint8_t *>(dsc + static_cast<uint32_t>(pos)) = static_cast<uint8_t>(sc);
+        ++pos;
+      }
+    }
+  }
+  return run;
+}
+
+// One block's work: tiles tile_lo .. tile_hi - 1 of query q, in turn; every
+// early return is uniform over the block.
 template <int kPass>
-__device__ __forceinline__ void count_block(const int tile, const int q, CRISP_COUNT_PARAMS) {
+__device__ __forceinline__ void count_block(const int tile_lo, const int tile_hi, const int q, CRISP_COUNT_PARAMS) {
   constexpr int pass = kPass;
   // dynamic LDS: the tile's counters first, then the block's shared records.
   // The kernel has no static LDS (checked on the host at index load), so the
@@ -1046,8 +1133,6 @@ __device__ __forceinline__ void count_block(const int tile, const int q, CRISP_C
   const int tid = threadIdx.x;
   if (live && q >= *live) return;
   if (pass != 0 && flag[q] == 0) return;
-  const long long t0 = static_cast<long long>(tile) * tile_ids;
-  const int tlen = static_cast<int>(min(static_cast<long long>(tile_ids), n - t0));
   const int ndw = tile_ids >> 2;  // counters allocated for a full tile
   const int thr = (pass == 0) ? tau : (pass == 1 ? 1 : tau_eff[q]);
   const int lane = lane_id();
@@ -1060,7 +1145,8 @@ __device__ __forceinline__ void count_block(const int tile, const int q, CRISP_C
   // Direct slots: thread t stands for cell t % J of subspace t / J, with J =
   // 1024 / m rounded down to a power of two.  Its subspace's count and the
   // cell are loaded together (the cell speculatively: in bounds, used only
-  // when t % J is below the count), then the cell's slice in the tile.
+  // when t % J is below the count), then the cell's row of the cell x tile
+  // table, whose entry for the next tile is always loaded one tile ahead.
   const int jl = 31 - __builtin_clz(static_cast<unsigned>(kCountThreads / m));   // log2 J
   const int fs = tid >> jl, fj = tid & ((1 << jl) - 1);
   int nco = 0, fpk = 0;
@@ -1068,58 +1154,63 @@ __device__ __forceinline__ void count_block(const int tile, const int q, CRISP_C
     nco = ncell[qm + fs];
     if (fj < ncells) fpk = cells[(qm + fs) * ncells + fj];
   }
-  uint4 *cnt4 = reinterpret_cast<uint4 *>(cnt);
-  for (int i = tid; i < (ndw >> 2); i += kCountThreads) cnt4[i] = make_uint4(0u, 0u, 0u, 0u);
-  for (int i = tid; i < 256; i += kCountThreads) S.hist[i] = 0;
-  uint32_t off = 0, lw = 0;
-  int nsub = 0;
-  if (fs < m && fj < nco) {
-    const int cell = fpk & 0xFFFFFF;
-    const int32_t *to = tile_off + (static_cast<long long>(fs) * ncells + cell) * (ntiles + 1);
-    const int a = to[tile];
-    const int len = to[tile + 1] - a;
-    off = static_cast<uint32_t>(static_cast<long long>(fs) * n + a);   // M x N < 2^31
-    lw = (static_cast<uint32_t>(len) << 8) | (static_cast<uint32_t>(fpk) >> 24);
-    nsub = (len + kWave - 1) / kWave;
+  const bool valid = fs < m && fj < nco;
+  // the slot's row of the cell x tile table (an element index)
+  const uint32_t row = valid ? static_cast<uint32_t>((fs * ncells + (fpk & 0xFFFFFF)) * (ntiles + 1)) : 0u;
+  int ta = 0, tb = 0;                                      // the slot's slice of the current tile
+  if (valid) {
+    ta = tile_off[row + tile_lo];
+    tb = tile_off[row + tile_lo + 1];
   }
-  {
+  for (int i = tid; i < 256; i += kCountThreads) S.hist[i] = 0;
+  bool general = false, have_mbase = false;
+  for (int tile = tile_lo; tile < tile_hi; ++tile) {
+    const long long t0 = static_cast<long long>(tile) * tile_ids;
+    const int tlen = static_cast<int>(min(static_cast<long long>(tile_ids), n - t0));
+    const int tn = (valid && tile + 2 <= ntiles) ? tile_off[row + tile + 2] : 0;   // next tile's end, loaded ahead
+    uint4 *cnt4 = reinterpret_cast<uint4 *>(cnt);
+    for (int i = tid; i < (ndw >> 2); i += kCountThreads) cnt4[i] = make_uint4(0u, 0u, 0u, 0u);
+    const int len = tb - ta;
+    const int nsub = valid ? (len + kWave - 1) / kWave : 0;
     const int incl = wave_incl_scan_i32(nsub);
-    const bool wide = __builtin_amdgcn_ballot_w64(fs < m && fj == 0 && nco > (1 << jl)) != 0;
-    if (lane == kWave - 1) S.tmp[wv0] = incl;
-    if (lane == 0) S.wide[wv0] = wide;
-    __syncthreads();
-    int total = 0, excl = incl - nsub, anywide = 0;
-#pragma unroll
-    for (int j = 0; j < kCountWaves; ++j) {
-      const int t = S.tmp[j];
-      total += t;
-      excl += j < wv0 ? t : 0;
-      anywide |= S.wide[j];
+    if (tile == tile_lo) {
+      const bool wide = __builtin_amdgcn_ballot_w64(fs < m && fj == 0 && nco > (1 << jl)) != 0;
+      if (lane == 0) S.wide[wv0] = wide;
     }
-    // Common case: every activated cell has a direct slot and all
-    // sub-slices fit in the list (one round of the loop below).  Otherwise
-    // the activated cells are taken in subspace order (item g lies in
-    // subspace s with mbase[s] <= g < mbase[s + 1]), in batches whose
+    if (lane == kWave - 1) S.tmp[wv0] = incl;
+    __syncthreads();
+    const int2 tb2 = waves_total_and_before(S.tmp, wv0);
+    const int total = tb2.x, excl = incl - nsub + tb2.y;
+    if (tile == tile_lo) general = __builtin_amdgcn_ballot_w64(lane < kCountWaves && S.wide[lane] != 0) != 0;
+    // Common case: every activated cell has a direct slot and all the
+    // tile's sub-slices fit in the list (one round of the loop below).
+    // Otherwise the activated cells are taken in subspace order (item g lies
+    // in subspace s with mbase[s] <= g < mbase[s + 1]), in batches whose
     // sub-slices fit in the list.
-    const bool general = anywide || total > kSub;
+    const bool batched = general || total > kSub;
     int total_items = 0;
-    if (general) {
-      __syncthreads();                                     // every wave has read S.tmp and S.wide
-      // Per-subspace counts -> prefix mbase[0..m] (m <= 127: waves 0 and 1
-      // load and scan them in parallel).
-      const int v = (tid < m) ? ncell[qm + tid] : 0;
-      const int inc = wave_incl_scan_i32(v);
-      if (tid == kWave - 1) S.tmp[0] = inc;
-      __syncthreads();
-      if (tid < 2 * kWave) S.mbase[tid + 1] = inc + (tid >= kWave ? S.tmp[0] : 0);
-      if (tid == 0) S.mbase[0] = 0;
-      __syncthreads();
+    if (batched) {
+      __syncthreads();                                     // every wave has read S.tmp
+      if (!have_mbase) {
+        // Per-subspace counts -> prefix mbase[0..m] (m <= 127: waves 0 and
+        // 1 load and scan them in parallel).
+        const int v = (tid < m) ? ncell[qm + tid] : 0;
+        const int inc = wave_incl_scan_i32(v);
+        if (tid == kWave - 1) S.tmp[0] = inc;
+        __syncthreads();
+        if (tid < 2 * kWave) S.mbase[tid + 1] = inc + (tid >= kWave ? S.tmp[0] : 0);
+        if (tid == 0) S.mbase[0] = 0;
+        __syncthreads();
+        have_mbase = true;
+      }
       total_items = S.mbase[m];
     }
     for (int b0 = 0;;) {
       int total_sub = total, taken = 0;
-      if (!general) {
-        if (nsub > 0) put_subslices(S, excl, off, static_cast<int>(lw >> 8), lw & 255u);
+      if (!batched) {
+        if (nsub > 0)
+          put_subslices(S, excl, static_cast<uint32_t>(static_cast<long long>(fs) * n + ta), len,
+                        static_cast<uint32_t>(fpk) >> 24);
         if (tid < kG) {
           S.soff[total + tid] = 0;
           S.slw[total + tid] = 0;
@@ -1137,24 +1228,23 @@ __device__ __forceinline__ void count_block(const int tile, const int q, CRISP_C
           const int g = b0 + tid;
           const int s = upper_bound_minus1(S.mbase, m + 1, g);
           const int packed = cells[(qm + s) * ncells + (g - S.mbase[s])];
-          const int32_t *to = tile_off + (static_cast<long long>(s) * ncells + (packed & 0xFFFFFF)) * (ntiles + 1);
-          const int a = to[tile];
-          const int len = to[tile + 1] - a;
-          goff = static_cast<uint32_t>(static_cast<long long>(s) * n + a);
-          glw = (static_cast<uint32_t>(len) << 8) | (static_cast<uint32_t>(packed) >> 24);
-          gsub = (len + kWave - 1) / kWave;
+          const int32_t *gto = tile_off + (static_cast<long long>(s) * ncells + (packed & 0xFFFFFF)) * (ntiles + 1);
+          const int a = gto[tile];
+          const int gl = gto[tile + 1] - a;
+          goff = static_cast<uint32_t>(static_cast<long long>(s) * n + a);   // M x N < 2^31
+          glw = (static_cast<uint32_t>(gl) << 8) | (static_cast<uint32_t>(packed) >> 24);
+          gsub = (gl + kWave - 1) / kWave;
         }
         const int inc = wave_incl_scan_i32(gsub);
         if (lane == kWave - 1) S.tmp[wv0] = inc;
         __syncthreads();
-        int gex = inc - gsub;
-        for (int j = 0; j < wv0; ++j) gex += S.tmp[j];
+        const int gex = inc - gsub + waves_total_and_before(S.tmp, wv0).y;
         const bool fits = tid < nb && gex + gsub <= kSub;
         const unsigned long long fb = __builtin_amdgcn_ballot_w64(fits);
         __syncthreads();                                   // every wave has read S.tmp
         if (lane == 0) S.tmp[wv0] = __popcll(fb);
         __syncthreads();
-        for (int j = 0; j < kCountWaves; ++j) taken += S.tmp[j];
+        taken = waves_total_and_before(S.tmp, 0).x;
         if (fits) {
           if (gsub > 0) put_subslices(S, gex, goff, static_cast<int>(glw >> 8), glw & 255u);
           if (tid == taken - 1) {                          // the last item taken closes the list
@@ -1170,105 +1260,43 @@ __device__ __forceinline__ void count_block(const int tile, const int q, CRISP_C
       }
       count_rounds(S, total_sub, pos, amask);
       __syncthreads();
-      if (!general) break;
+      if (!batched) break;
       b0 += taken;
     }
+    const int run = scan_tile<kPass>(S, cnt, q, t0, tlen, ndw, m, thr, n, seg_ids, seg_score);
+    if (pass != 1 && lane == 0) seg_cnt[(static_cast<long long>(q) * ntiles + tile) * kCountWaves + wv0] = run;
+    __syncthreads();                                       // the counters are read before the next tile clears them
+    ta = tb;
+    tb = tn;
   }
-
-  // ---- scan: threshold, histogram, ordered per-wave compaction --------------
-  const int wv = wave_id();
-  const int per_wave = ndw / kCountWaves;            // dwords per wave (tiles of 2^12..2^17 ids: a multiple of 64)
-  const int dw0 = wv * per_wave;
-  int32_t *dst = seg_ids + static_cast<long long>(q) * n + t0 + static_cast<long long>(dw0) * 4;
-  uint8_t *dsc = seg_score + static_cast<long long>(q) * n + t0 + static_cast<long long>(dw0) * 4;
-  int run = 0;
-  // Bytes >= thr, four at a time.  When 2M < 128 adding 128 - thr to every
-  // byte of a dword sets each byte's bit 7 exactly when the byte is >= thr
-  // (no carry leaves a byte).  Otherwise the even and odd bytes sit in
-  // 16-bit fields, and adding 256 - thr to a field sets its bit 8 exactly
-  // when the byte is >= thr.
-  const bool narrow = 2 * m < 128;
-  const uint32_t add4 = static_cast<uint32_t>(0x80 - thr) * 0x01010101u;
-  const uint32_t add = static_cast<uint32_t>(0x100 - thr) * 0x00010001u;
-  const uint8_t *cnt8 = reinterpret_cast<const uint8_t *>(cnt);
-  constexpr int kScanDw = 16;                      // dwords (64 counters) per lane per step
-  for (int v0 = 0; v0 < per_wave; v0 += kScanDw * kWave) {
-    const int dwl = v0 + kScanDw * lane;           // this lane's first dword within the wave range
-    uint32_t words[kScanDw];
-#pragma unroll
-    for (int u = 0; u < kScanDw / 4; ++u) {
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (dwl < per_wave) v = cnt4[((dw0 + dwl) >> 2) + u];
-      words[4 * u] = v.x; words[4 * u + 1] = v.y; words[4 * u + 2] = v.z; words[4 * u + 3] = v.w;
-    }
-    const int idbase = (dw0 + dwl) * 4;            // tile-local id of the first counter
-    // Bit 32g + 8j + i of sel (dword 8g + i of the lane's 16, byte j) is
-    // the counter of id idbase + 32g + 8j + i.
-    uint32_t half[2] = {0u, 0u};
-    if (narrow) {
-#pragma unroll
-      for (int j = 0; j < kScanDw; ++j) {
-        const int i = j & 7;
-        half[j >> 3] |= ((words[j] + add4) >> (7 - i)) & (0x01010101u << i);
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < kScanDw; ++j) {
-        const int i = j & 7;
-        const uint32_t ge = (words[j] & 0x00FF00FFu) + add;           // bytes 0, 2 -> bits 8, 24
-        const uint32_t go = ((words[j] >> 8) & 0x00FF00FFu) + add;    // bytes 1, 3 -> bits 8, 24
-        half[j >> 3] |= ((ge >> (8 - i)) & (0x00010001u << i)) | ((go << i) & (0x01000100u << i));
-      }
-    }
-    unsigned long long sel = (static_cast<unsigned long long>(half[1]) << 32) | half[0];
-    const int nvalid = (dwl < per_wave) ? min(max(tlen - idbase, 0), 64) : 0;
-    sel &= (nvalid >= 64) ? ~0ull : ((1ull << nvalid) - 1ull);
-    const int c = __popcll(sel);
-    int pos = run;
-    if (pass != 1) {
-      // exclusive prefix of c over the lanes, and the step's total
-      const int incl = wave_incl_scan_dpp(c);
-      pos += incl - c;
-      run += __builtin_amdgcn_readlane(incl, kWave - 1);
-    }
-    while (sel) {
-      const int e = __ffsll(static_cast<long long>(sel)) - 1;
-      sel &= sel - 1ull;
-      const int sc = cnt8[cnt_byte(idbase + e)];
-      if (pass != 2 && sc >= 1) atomicAdd(&S.hist[sc], 1);
-      if (pass != 1) {
-        dst[pos] = static_cast<int32_t>(t0) + idbase + e;
-        dsc[pos] = static_cast<uint8_t>(sc);
-        ++pos;
-      }
-    }
-  }
-  if (pass != 1 && lane == 0) seg_cnt[(static_cast<long long>(q) * ntiles + tile) * kCountWaves + wv] = run;
   if (pass != 2) {
-    __syncthreads();
     const int nb = 2 * m + 1;
     for (int s = tid; s < nb; s += kCountThreads)
       if (S.hist[s]) atomicAdd(&hist[static_cast<long long>(q) * nb + s], S.hist[s]);
   }
 }
 
-// pass 0: grid (tiles, queries).  Passes 1 and 2 concern the queries k_flag
-// listed (flist[0 .. *nflag)), usually none: a grid of (tiles, a few hundred)
-// blocks walks the list instead of launching a block for every query.
+// pass 0: grid (tile groups, queries), each block counting tiles_per_block
+// consecutive tiles of its query.  Passes 1 and 2 concern the queries k_flag
+// listed (flist[0 .. *nflag)), usually none: a grid of (tile groups, a few
+// hundred) blocks walks the list instead of launching a block for every
+// query.
 // At most 80 scalar registers: with more, two 16-wave blocks do not fit on a
 // compute unit together (measured: 96 registers left one resident block per
 // unit and took 1.5x as long; the few values over the budget go to lanes of
 // a vector register).
 template <int kPass>
 __global__ void __launch_bounds__(kCountThreads) __attribute__((amdgpu_num_sgpr(80)))
-k_count(CRISP_COUNT_PARAMS, const int32_t *__restrict__ flist,
-                                                          const int32_t *__restrict__ nflag) {
+k_count(CRISP_COUNT_PARAMS, const int32_t *__restrict__ flist, const int32_t *__restrict__ nflag,
+        int tiles_per_block) {
+  const int tile_lo = blockIdx.x * tiles_per_block;
+  const int tile_hi = min(tile_lo + tiles_per_block, ntiles);
   if constexpr (kPass == 0) {
-    count_block<0>(blockIdx.x, blockIdx.y, CRISP_COUNT_ARGS);
+    count_block<0>(tile_lo, tile_hi, blockIdx.y, CRISP_COUNT_ARGS);
   } else {
     const int nf = *nflag;
     for (int i = blockIdx.y; i < nf; i += gridDim.y) {
-      count_block<kPass>(blockIdx.x, flist[i], CRISP_COUNT_ARGS);
+      count_block<kPass>(tile_lo, tile_hi, flist[i], CRISP_COUNT_ARGS);
       __syncthreads();
     }
   }

@@ -119,6 +119,16 @@ def test_results_do_not_depend_on_tiles_or_chunks(d128, mode):
         gt = engine.Index(g.arrays | {"n": g.n, "d": g.d, "m": g.m, "k_half": g.k_half}, tile_ids=tile)
         for chunk in (0, 7, 64):
             _same(gt.search(q, 10, max_chunk=chunk, **kw), ref)
+        if tile == 4096:
+            # three tiles: counted one, two or three per block
+            for ct in (1, 2, 3, 5):
+                _same(gt.search(q, 10, count_tiles=ct, **kw), ref)
+            # every cell activated: each tile's sub-slices overflow the
+            # block's list and are counted in several batches
+            wide = dict(kw, alpha=1.0, tau=8)
+            ref1 = g.search(q[:8].contiguous(), 10, **wide)
+            for ct in (1, 3):
+                _same(gt.search(q[:8].contiguous(), 10, count_tiles=ct, **wide), ref1)
         gt.free()
 
 
@@ -139,7 +149,8 @@ def test_tuned_runner_serves_uneven_batches(d128, tmp_path):
     from paper_2603_05180_amd import autotune
     w, x, q, idx, g = d128
     params = dict(mode=1, alpha=0.05, tau=4, precision=1)
-    srv = autotune.Server(None, g, params, max_batch=64, ks=(1, 10), tiles=(4096, 16384), chunks=(16, 64))
+    srv = autotune.Server(None, g, params, max_batch=64, ks=(1, 10), tiles=(4096, 16384), chunks=(16, 64),
+                          count_tiles=(0, 2))
     cache = str(tmp_path / "tune.json")
     choice = srv.tune(q, [1, 2, 4, 8, 16, 32, 64], reps=1, cache=cache)
     assert len(choice) == 14
@@ -153,7 +164,8 @@ def test_tuned_runner_serves_uneven_batches(d128, tmp_path):
         _same((ids, d), g.search(q[o:o + nq].contiguous(), k, **params))
         o += nq
     # the cache is reused
-    srv2 = autotune.Server(None, g, params, max_batch=64, ks=(1, 10), tiles=(4096, 16384), chunks=(16, 64))
+    srv2 = autotune.Server(None, g, params, max_batch=64, ks=(1, 10), tiles=(4096, 16384), chunks=(16, 64),
+                           count_tiles=(0, 2))
     assert srv2.tune(q, [1, 2, 4, 8, 16, 32, 64], cache=cache) == choice
     srv.free()
     srv2.free()
