@@ -5,11 +5,13 @@
   python -m paper_2603_05180_amd.rocprof_summary dispatches <kernel_trace.csv> <kernel> [last]
       one kernel's dispatch durations grouped by grid size (from --kernel-trace),
       and the average of its last `last` dispatches
-  python -m paper_2603_05180_amd.rocprof_summary traffic <fetch.csv> <write.csv> <kernel> <workload> <out.json> [last]
+  python -m paper_2603_05180_amd.rocprof_summary traffic <fetch.csv> <write.csv> <kernel> <workload> <out.json> [last] [launches]
       HBM bytes per launch of <kernel> from two `--pmc FETCH_SIZE` / `--pmc
       WRITE_SIZE` runs, each scaled by what the same counter reads for the
       run's k_copy_probe dispatch (a plain copy: 1 GiB read, 1 GiB written);
-      with `last`, over the kernel's last `last` dispatches only
+      with `last`, over the kernel's last `last` dispatches only; with
+      `launches`, their total divided by that many launches (a stage that
+      dispatches the kernel more than once per launch)
 """
 from __future__ import annotations
 
@@ -78,9 +80,10 @@ def _per_dispatch(path: str, counter: str):
 
 
 def traffic(fetch_csv: str, write_csv: str, kernel: str, workload: str, out_json: str, last: int = 0,
-            copy_bytes=1 << 30):
+            copy_bytes=1 << 30, launches: int = 0):
     """HBM bytes per launch of `kernel`: over its last `last` dispatches (in
-    dispatch order; 0 = all of them)."""
+    dispatch order; 0 = all of them), their total divided by `launches`
+    (0 = one launch per dispatch)."""
     from .provenance import source_hash
     res = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
@@ -95,7 +98,8 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, workload: str, out_json
             ks = ks[-last:]
         if not ks:
             raise SystemExit(f"no {kernel} dispatch in {path}")
-        res[counter] = {"kib_per_launch": sum(ks) / len(ks), "launches": len(ks), "copy_kib": ref_kib,
+        nl = launches if launches else len(ks)
+        res[counter] = {"kib_per_launch": sum(ks) / nl, "launches": nl, "dispatches": len(ks), "copy_kib": ref_kib,
                         "factor": factor}
     t = json.load(open(out_json)) if os.path.exists(out_json) else {}
     t[kernel] = {"workload": workload, "source_hash": source_hash(),
@@ -113,6 +117,7 @@ if __name__ == "__main__":
     elif sys.argv[1] == "dispatches":
         sys.stdout.write(dispatches(sys.argv[2], sys.argv[3], int(sys.argv[4]) if len(sys.argv) > 4 else 0))
     elif sys.argv[1] == "traffic":
-        print(json.dumps(traffic(*sys.argv[2:7], last=int(sys.argv[7]) if len(sys.argv) > 7 else 0), indent=1))
+        print(json.dumps(traffic(*sys.argv[2:7], last=int(sys.argv[7]) if len(sys.argv) > 7 else 0,
+                                 launches=int(sys.argv[8]) if len(sys.argv) > 8 else 0), indent=1))
     else:
         raise SystemExit(__doc__)

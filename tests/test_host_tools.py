@@ -68,6 +68,12 @@ def test_traffic_scales_each_counter_by_the_copy_probe(tmp_path):
     # every dispatch when `last` is 0
     ent = rs.traffic(fetch, write, "k_count<0>", "d4096", str(out))
     assert ent["fetch_bytes_per_launch"] == pytest.approx(250.0 * 1024 * 2.0)
+    # a stage that dispatches the kernel twice per launch: the last four
+    # dispatches are two launches
+    ent = rs.traffic(fetch, write, "k_count<0>", "d4096", str(out), last=4, launches=2)
+    assert ent["counters"]["FETCH_SIZE"]["launches"] == 2
+    assert ent["counters"]["FETCH_SIZE"]["dispatches"] == 4
+    assert ent["fetch_bytes_per_launch"] == pytest.approx(500.0 * 1024 * 2.0)
 
 
 def test_traffic_needs_exactly_one_copy_probe(tmp_path):
