@@ -181,6 +181,9 @@ def counts(index, queries, k, kw):
             "n_cand": torch.empty(nq, dtype=torch.int32, device=dev),
             "retrieved": torch.empty(nq, m, dtype=torch.int32, device=dev),
             "row_bytes": torch.empty(nq, dtype=torch.int64, device=dev)}
+    if kw.get("precision", 0) >= 2:
+        # subspaces whose centroid scores could not be certified (exact path)
+        taps["score_fallback"] = torch.empty(nq, dtype=torch.int32, device=dev)
     index.search(queries, k, taps=taps, **kw)
     torch.cuda.synchronize()
     return {key: int(v.long().sum()) for key, v in taps.items()}
@@ -272,6 +275,8 @@ def run_form(index, queries, truth, k, kw, args, ids, dists, plain_ids, base, qr
             "mean_row_bytes_read": round(c["row_bytes"] / nq, 1),
             "rerank_algorithmic_gb_s": round(rr_bytes / 1e9 / (st1["rerank"]["ms"] / 1e3), 1),
             "max_rel_err_vs_fp64": fp64_error(base, qrot, ids, dists),
+            **({"exact_scoring_subspace_frac": round(c["score_fallback"] / (nq * index.m), 5)}
+               if "score_fallback" in c else {}),
             "_kw": kw, "_counts": c}
 
 
@@ -382,6 +387,8 @@ def measure(args, pool):
         if args.scoring:
             # and with the half distances pre-scored on bfloat16 matrix cores (same results)
             forms[f"bf16_scored_pf{args.tuned_patience}"] = dict(precision=2, patience_factor=args.tuned_patience)
+            # and on FP8 (e4m3) matrix cores, two-term split (same results; more exact-path subspaces)
+            forms[f"fp8_scored_pf{args.tuned_patience}"] = dict(precision=3, patience_factor=args.tuned_patience)
     if args.mode == 1 and args.ads:
         # ADSampling verification (float32 rows read only as far as Eq. (2) needs)
         forms["ads"] = dict(precision=0, verify=1)

@@ -364,9 +364,10 @@ __global__ void __launch_bounds__(64) k_score_fp8(const float *__restrict__ qrot
   const int qa = q0 + r;
   const float *qrow = qrot + static_cast<long long>(min(qa, nl - 1)) * d + sub * 2 * h;
   // Sum error of the FP8 matrix-core products: the 32-product dot of one
-  // instruction is not exact in float32 on gfx950 (measured up to 1.1e-4 of
-  // the products' absolute sum); 2^-9 of it per instruction, plus the float32
-  // accumulation over the 3 nks instructions.
+  // instruction is not exact in float32 on gfx950 (measured up to 4.1e-4,
+  // 2^-11.2, of the products' absolute sum over 131,072 tiles of random
+  // codes and of two-term splits); 2^-8 of it per instruction, plus the
+  // float32 accumulation over the 3 nks instructions.
   const float sacc = 0x1p-8f + static_cast<float>(3 * nks + 4) * 0x1p-22f;
   const float snorm = static_cast<float>(4 * nks + 4) * 0x1p-23f;
   for (int s = 0; s < 2; ++s) {
