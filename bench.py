@@ -693,10 +693,13 @@ def uneven_batches(args):
     queries = sg.rows(w, w.seed_query, 0, args.uneven_queries, params)
     sizes = synth.batch_sizes(w.seed_query, args.uneven_queries, max_batch=4096)
     ks = synth.batch_ks(w.seed_query, len(sizes))
-    sp = dict(kw, mode=1, precision=1, budget_source=1 if model is not None else 0)
+    # candidate lists capped at 65,536 per query (queries with more are
+    # searched again uncapped, same results): 11.4 MB of workspace per query
+    # instead of 52 MB, so chunks of 2,048 fit with two pipelines
+    sp = dict(kw, mode=1, precision=1, budget_source=1 if model is not None else 0, max_candidates=65536)
     t = time.time()
     srv = autotune.Server(None, index, sp, max_batch=4096, ks=(1, 10, 100), tiles=(16384, 65536),
-                          chunks=(512, 1024), count_tiles=(1, 4))
+                          chunks=(512, 1024, 2048), count_tiles=(1, 4))
     choice = srv.tune(queries, [1 << i for i in range(13)], reps=2, cache=args.autotune_cache or None)
     torch.cuda.synchronize()
     log(f"uneven: tuned {len(choice)} (k, bucket) pairs in {time.time() - t:.1f}s")
@@ -732,6 +735,7 @@ def uneven_batches(args):
            "p99_batch_ms": round(float(np.percentile(lat, 99)), 4),
            "max_batch_ms": round(float(lat.max()), 4),
            "recall_at_10_sample": round(hit / max(1, tot), 4),
+           "max_candidates": 65536,
            "tuned_tile_chunk_persistent_counttiles": tuned}
     log(f"uneven: {out['queries_per_s']} q/s, p50 {out['p50_batch_ms']} ms, p99 {out['p99_batch_ms']} ms")
     srv.free()

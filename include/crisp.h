@@ -215,6 +215,18 @@ crisp_status crisp_index_enable_bf16(crisp_index *index, void *buffer, size_t by
  *                      once for them; 0 = chosen from the chunk size and the
  *                      number of compute units).  Results do not depend on
  *                      it.
+ *   max_candidates  -- capacity of a query's candidate list in the workspace
+ *                      (0, or N or more: N, uncapped).  The candidate-indexed
+ *                      buffers (candidates, their scores, Hamming distances
+ *                      and order, float64 keys: 21 bytes per entry) shrink
+ *                      from N to this many entries per query; the per-tile
+ *                      counting segments stay N (5 bytes per id).  A query
+ *                      with more candidates is searched again, alone, with
+ *                      N-entry lists in a reserved part of the workspace,
+ *                      after the batch (crisp_search waits for the batch to
+ *                      find them: one host synchronisation per call, and
+ *                      one per crisp_plan_search).  Results and taps do not
+ *                      depend on it.
  */
 typedef struct {
   int32_t mode;
@@ -231,6 +243,7 @@ typedef struct {
   int32_t verify;
   int32_t order_prefix;
   int32_t count_tiles;
+  int32_t max_candidates;
 } crisp_search_params;
 
 /*

@@ -36,7 +36,7 @@ class SearchParams(ctypes.Structure):
                 ("patience_factor", c_int32), ("limits", c_void_p), ("max_chunk", c_int32),
                 ("budget_source", c_int32), ("precision", c_int32), ("persistent", c_int32),
                 ("overlap", c_int32), ("walk_order", c_int32), ("verify", c_int32), ("order_prefix", c_int32),
-                ("count_tiles", c_int32)]
+                ("count_tiles", c_int32), ("max_candidates", c_int32)]
 
 
 class Profile(ctypes.Structure):

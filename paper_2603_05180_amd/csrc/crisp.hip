@@ -184,7 +184,9 @@ struct Layout {
       flist, nflag, rbytes, sfall, avail, hstat, redo, nredo, total;
 };
 
-static Layout make_layout(const crisp_index *ix, long long qc) {
+// cap: capacity of each query's candidate list (entries of cand, score,
+// the Hamming distances and order, the float64 keys); n when uncapped.
+static Layout make_layout(const crisp_index *ix, long long qc, long long cap) {
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
@@ -200,13 +202,13 @@ static Layout make_layout(const crisp_index *ix, long long qc) {
   L.flag = take(qc * 4);
   L.taueff = take(qc * 4);
   L.ncand = take(qc * 4);
-  L.segids = take(qc * n * 4);     // per-tile segments; later the Hamming order
+  L.segids = take(qc * n * 4);     // per-tile segments; later the Hamming order (stride cap)
   L.segscore = take(qc * n);
-  L.cand = take(qc * n * 4);
-  L.score = take(qc * n);
-  L.regA = take(qc * n * 4);       // mode 1: Hamming distance per candidate
-  L.regB = take(qc * n * 4);       // mode 1: Hamming distances in order
-  L.regC = take(qc * n * 8);       // mode 0: float64 keys of the candidates
+  L.cand = take(qc * cap * 4);
+  L.score = take(qc * cap);
+  L.regA = take(qc * cap * 4);     // mode 1: Hamming distance per candidate
+  L.regB = take(qc * cap * 4);     // mode 1: Hamming distances in order
+  L.regC = take(qc * cap * 8);     // mode 0: float64 keys of the candidates
   L.examined = take(qc * 4);
   L.lastupd = take(qc * 4);
   L.stopped = take(qc * 4);
@@ -233,6 +235,30 @@ static Layout make_layout(const crisp_index *ix, long long qc) {
 static long long chunk_of(const crisp_search_params *p, long long nq) {
   long long c = (p && p->max_chunk > 0) ? p->max_chunk : kDefaultChunk;
   return std::max<long long>(1, std::min<long long>(c, std::max<long long>(nq, 1)));
+}
+
+static long long cap_of(const crisp_index *ix, const crisp_search_params *p) {
+  return (p && p->max_candidates > 0 && p->max_candidates < ix->n) ? p->max_candidates : ix->n;
+}
+
+// Workspace of one search of nq queries: the chunk pipelines (two with
+// overlap), the list of queries whose candidates overflowed the cap (a count,
+// then their indexes), and, with a cap, one uncapped query's workspace in
+// which those queries are searched again.
+struct SearchWs {
+  Layout L;
+  size_t ovf, retry, retry_bytes, total;
+};
+static size_t retry_bytes_of(const crisp_index *ix) { return make_layout(ix, 1, ix->n).total + align_up(8); }
+static SearchWs search_ws(const crisp_index *ix, long long nq, const crisp_search_params *p) {
+  SearchWs W{};
+  const long long cap = cap_of(ix, p);
+  W.L = make_layout(ix, chunk_of(p, nq), cap);
+  W.ovf = W.L.total * (p->overlap == 1 ? 2 : 1);
+  W.retry = W.ovf + align_up(4 + 4 * static_cast<size_t>(std::max<long long>(nq, 1)));
+  W.retry_bytes = cap < ix->n ? retry_bytes_of(ix) : 0;
+  W.total = W.retry + W.retry_bytes;
+  return W;
 }
 
 extern "C" {
@@ -428,6 +454,7 @@ static crisp_status check_params(const crisp_index *ix, int64_t nq, int32_t k, c
   if (p->verify != 0 && p->verify != 1) return fail(CRISP_E_INVALID, "verify must be 0 or 1");
   if (p->order_prefix < 0) return fail(CRISP_E_INVALID, "order_prefix must be >= 0");
   if (p->count_tiles < 0) return fail(CRISP_E_INVALID, "count_tiles must be >= 0");
+  if (p->max_candidates < 0) return fail(CRISP_E_INVALID, "max_candidates must be >= 0");
   if (p->verify == 1 && p->mode != 1) return fail(CRISP_E_INVALID, "ADSampling (verify 1) is for Optimized Mode");
   if (p->verify == 1 && p->precision != 0) return fail(CRISP_E_INVALID, "ADSampling (verify 1) needs precision 0");
   return CRISP_OK;
@@ -438,7 +465,7 @@ crisp_status crisp_search_workspace_bytes(const crisp_index *index, int64_t nq, 
   if (!bytes) return fail(CRISP_E_INVALID, "null argument");
   crisp_status s = check_params(index, nq, k, params);
   if (s != CRISP_OK) return s;
-  *bytes = make_layout(index, chunk_of(params, nq)).total * (params->overlap == 1 ? 2 : 1);
+  *bytes = search_ws(index, nq, params).total;
   return CRISP_OK;
 }
 
@@ -448,23 +475,88 @@ static crisp_status tap_copy(void *dst, const void *src, size_t bytes, hipStream
   return CRISP_OK;
 }
 
+// rows of `width` bytes from a pitch of spitch to one of dpitch
+static crisp_status tap_copy_rows(void *dst, size_t dpitch, const void *src, size_t spitch, size_t width,
+                                  size_t rows, hipStream_t st) {
+  if (!dst || width == 0 || rows == 0) return CRISP_OK;
+  HIP_TRY(hipMemcpy2DAsync(dst, dpitch, src, spitch, width, rows, hipMemcpyDeviceToDevice, st));
+  return CRISP_OK;
+}
+
+// The taps of query qi of a batch (each array advanced by qi rows).
+static const crisp_taps *taps_at(crisp_taps *t, const crisp_taps *src, const crisp_index *ix, long long qi) {
+  *t = *src;
+  const long long n = ix->n, hk = 2LL * ix->m * ix->k;
+  auto adv = [qi](auto *&ptr, long long row) {
+    if (ptr) ptr += qi * row;
+  };
+  adv(t->q_rot, ix->d); adv(t->half_dist, hk); adv(t->n_cells, ix->m);
+  adv(t->cells, static_cast<long long>(ix->m) * ix->ncells); adv(t->retrieved, ix->m); adv(t->hist, 2LL * ix->m + 1);
+  adv(t->tau_eff, 1); adv(t->n_cand, 1); adv(t->cand, n); adv(t->cand_score, n); adv(t->order, n);
+  adv(t->hamming, n); adv(t->examined, 1); adv(t->last_update, 1); adv(t->stopped, 1);
+  adv(t->features, n_features(ix->m)); adv(t->limits, 1); adv(t->refined, 1); adv(t->score_lb, hk);
+  adv(t->score_ub, hk); adv(t->row_bytes, 1); adv(t->score_fallback, 1);
+  return t;
+}
+
 }  // extern "C"
 
 // The search pipeline.  live: NULL, or a device array with one count per
 // chunk of qc queries; kernels then skip the queries of chunk c at or beyond
 // live[c] (a captured graph sized for a batch-size bucket runs any smaller
 // batch this way).
+// redo: search the queries whose candidates overflowed max_candidates again
+// (host-synchronous); a graph capture passes false and its caller redoes
+// them after the replay (plan_redo).
 static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t nq, int32_t k,
                                 const crisp_search_params *p, int64_t *ids, float *dists, void *workspace,
-                                size_t ws_bytes, const crisp_taps *taps, hipStream_t st0, const int32_t *live_base) {
+                                size_t ws_bytes, const crisp_taps *taps, hipStream_t st0, const int32_t *live_base,
+                                bool redo_overflow);
+static crisp_status redo_overflow(crisp_index *ix, const float *queries, int64_t nq, int32_t k,
+                                  const crisp_search_params *p, int64_t *ids, float *dists, void *workspace,
+                                  const crisp_taps *taps, hipStream_t st) {
+  const SearchWs W = search_ws(ix, nq, p);
+  if (W.retry_bytes == 0) return CRISP_OK;
+  const int32_t *count = reinterpret_cast<const int32_t *>(static_cast<char *>(workspace) + W.ovf);
+  int32_t h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, count, 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h <= 0) return CRISP_OK;
+  std::vector<int32_t> list(static_cast<size_t>(h));
+  HIP_TRY(hipMemcpyAsync(list.data(), count + 1, 4 * static_cast<size_t>(h), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  crisp_search_params p1 = *p;
+  p1.max_chunk = 1;
+  p1.overlap = 0;
+  p1.max_candidates = 0;
+  for (const int32_t qi : list) {
+    p1.limits = p->limits ? p->limits + qi : nullptr;
+    crisp_taps t1{};
+    const crisp_taps *tp = taps ? taps_at(&t1, taps, ix, qi) : nullptr;
+    crisp_status s = search_impl(ix, queries + static_cast<long long>(qi) * ix->d, 1, k, &p1,
+                                 ids + static_cast<long long>(qi) * k, dists + static_cast<long long>(qi) * k,
+                                 static_cast<char *>(workspace) + W.retry, W.retry_bytes, tp, st, nullptr, false);
+    if (s != CRISP_OK) return s;
+  }
+  return CRISP_OK;
+}
+
+static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t nq, int32_t k,
+                                const crisp_search_params *p, int64_t *ids, float *dists, void *workspace,
+                                size_t ws_bytes, const crisp_taps *taps, hipStream_t st0, const int32_t *live_base,
+                                bool redo_overflow_now) {
   crisp_status s = CRISP_OK;
   const long long qc = chunk_of(p, nq);
-  const Layout L = make_layout(ix, qc);
+  const SearchWs W = search_ws(ix, nq, p);
+  const Layout &L = W.L;
+  const long long cap = cap_of(ix, p);
   // Two chunk pipelines (this stream and the index's second stream, each
   // with its own workspace) when the batch has more than one chunk.
   const bool two = p->overlap == 1 && nq > qc;
-  if (ws_bytes < (p->overlap == 1 ? 2 : 1) * L.total)
-    return fail(CRISP_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, (p->overlap == 1 ? 2 : 1) * L.total);
+  if (ws_bytes < W.total) return fail(CRISP_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, W.total);
+  int32_t *ovf_count = reinterpret_cast<int32_t *>(static_cast<char *>(workspace) + W.ovf);
+  k_fill<int32_t><<<1, 64, 0, st0>>>(ovf_count, 1, 0);
+  LAUNCH_TRY("k_fill");
   if (two) {
     HIP_TRY(hipEventRecord(ix->ev_fork, st0));
     HIP_TRY(hipStreamWaitEvent(ix->aux, ix->ev_fork, 0));
@@ -628,11 +720,11 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
                                                       ix->ntiles, ix->tile, p->tau, flag, taueff, segids, segscore,
                                                       tilecnt, hist, lv, flist, nflag, 1);
       LAUNCH_TRY("k_count pass 2");
-      k_compact<<<cq, kCompactThreads, 0, st>>>(segids, segscore, tilecnt, nseg, ix->tile / kCountWaves, n, cand,
-                                                 score, ncand, lv);
+      k_compact<<<cq, kCompactThreads, 0, st>>>(segids, segscore, tilecnt, nseg, ix->tile / kCountWaves, n, cap,
+                                                 cand, score, ncand, lv, ovf_count, ovf_count + 1, q0);
       LAUNCH_TRY("k_compact");
       if (cq <= kQueryOrderMax) {
-        k_query_order<<<1, kQueryOrderThreads, 0, st>>>(cq, ncand, cand, n, qord, lv);
+        k_query_order<<<1, kQueryOrderThreads, 0, st>>>(cq, ncand, cand, n, cap, qord, lv);
         LAUNCH_TRY("k_query_order");
       } else {
         qord = nullptr;
@@ -649,16 +741,16 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
         const int gx = static_cast<int>(std::max(1, std::min(64, (4096 + cq - 1) / cq)));
         const int g = xcd_pad(gx * cq);
         if (hamming_vec(d / 64) == 2)
-          k_hamming_dist<2><<<g, kOrderThreads, 0, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, lv, qord, gx, cq);
+          k_hamming_dist<2><<<g, kOrderThreads, 0, st>>>(qrot, d, ix->codes, ncand, cand, cap, regA, lv, qord, gx, cq);
         else
-          k_hamming_dist<1><<<g, kOrderThreads, 0, st>>>(qrot, d, ix->codes, ncand, cand, n, regA, lv, qord, gx, cq);
+          k_hamming_dist<1><<<g, kOrderThreads, 0, st>>>(qrot, d, ix->codes, ncand, cand, cap, regA, lv, qord, gx, cq);
         LAUNCH_TRY("k_hamming_dist");
       }
       t4.stop();
       StageTimer t1(ix, 1, st);  // order
       k_fill<int32_t><<<1, 64, 0, st>>>(nredo, 1, 0);
       LAUNCH_TRY("k_fill");
-      k_hamming_order<<<cq, kOrderThreads, hamming_order_lds(d), st>>>(d, ncand, cand, n, regA, plen, segids, regB,
+      k_hamming_order<<<cq, kOrderThreads, hamming_order_lds(d), st>>>(d, ncand, cand, cap, regA, plen, segids, regB,
                                                                        avail, hstat, lv, nullptr, nullptr);
       LAUNCH_TRY("k_hamming_order");
       t1.stop();
@@ -684,19 +776,19 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
         LAUNCH_TRY("k_fill");
       }
       rerank1<<<p->persistent ? std::min(cq, rr_resident) : xcd_pad(cq), kRerankThreads, rr_lds, st>>>(qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
-                                                        ham ? segids : cand, n, k, patience, lim, regC, nullptr, nullptr,
+                                                        ham ? segids : cand, cap, k, patience, lim, regC, nullptr, nullptr,
                                                         ids + q0 * k,
                                                         dists + q0 * k, exam, lastu, stopd, refd, ix->ads_fac,
                                                         rbytes, ham ? avail : nullptr, ham ? redo : nullptr, nredo,
                                                         lv, cq, p->persistent ? queue : nullptr, qord);
       LAUNCH_TRY("k_rerank");
-      if (ham && plen < n) {
+      if (ham && plen < cap) {
         // walks that reached the end of the placed prefix: full order, walk again
         k_hamming_order<<<std::min(cq, 256), kOrderThreads, hamming_order_lds(d), st>>>(
-            d, ncand, cand, n, regA, INT32_MAX, segids, regB, avail, hstat, lv, redo, nredo);
+            d, ncand, cand, cap, regA, INT32_MAX, segids, regB, avail, hstat, lv, redo, nredo);
         LAUNCH_TRY("k_hamming_order (redo)");
         rerank1<<<xcd_pad(cq), kRerankThreads, rr_lds, st>>>(qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
-                                                             segids, n, k, patience, lim, regC, nullptr, nullptr,
+                                                             segids, cap, k, patience, lim, regC, nullptr, nullptr,
                                                              ids + q0 * k, dists + q0 * k, exam, lastu, stopd, refd,
                                                              ix->ads_fac, rbytes, nullptr, nullptr, nullptr, nredo,
                                                              cq, nullptr, redo);
@@ -710,7 +802,7 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
         LAUNCH_TRY("k_fill");
       }
       rerank0<<<p->persistent ? std::min(cq, rr_resident) : xcd_pad(cq), kRerankThreads, rr_lds, st>>>(qrot, d, ix->base, ix->base16, ix->rerr, gam, ncand,
-                                                        cand, n, k, patience, lim, regC,
+                                                        cand, cap, k, patience, lim, regC,
                                                         reinterpret_cast<float *>(regA), regB, ids + q0 * k,
                                                         dists + q0 * k, exam, lastu, stopd, refd, ix->ads_fac,
                                                         rbytes, nullptr, nullptr, nullptr, lv, cq,
@@ -719,7 +811,7 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       t5.stop();
     }
     if (taps) {
-      const size_t qn = static_cast<size_t>(cq) * static_cast<size_t>(n);
+      const size_t un = static_cast<size_t>(n), uc = static_cast<size_t>(cap);
       if ((s = tap_copy(taps->q_rot ? taps->q_rot + q0 * d : nullptr, qrot, size_t(cq) * d * 4, st))) return s;
       if ((s = tap_copy(taps->half_dist ? taps->half_dist + q0 * m * 2 * kh : nullptr, hdist, size_t(cq) * m * 2 * kh * 8, st))) return s;
       if ((s = tap_copy(taps->n_cells ? taps->n_cells + q0 * m : nullptr, ncell, size_t(cq) * m * 4, st))) return s;
@@ -728,11 +820,15 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       if ((s = tap_copy(taps->hist ? taps->hist + q0 * nb : nullptr, hist, size_t(cq) * nb * 4, st))) return s;
       if ((s = tap_copy(taps->tau_eff ? taps->tau_eff + q0 : nullptr, taueff, size_t(cq) * 4, st))) return s;
       if ((s = tap_copy(taps->n_cand ? taps->n_cand + q0 : nullptr, ncand, size_t(cq) * 4, st))) return s;
-      if ((s = tap_copy(taps->cand ? taps->cand + q0 * n : nullptr, cand, qn * 4, st))) return s;
-      if ((s = tap_copy(taps->cand_score ? taps->cand_score + q0 * n : nullptr, score, qn, st))) return s;
+      // candidate-indexed taps: rows of n entries, filled up to the cap
+      if ((s = tap_copy_rows(taps->cand ? taps->cand + q0 * n : nullptr, un * 4, cand, uc * 4, uc * 4, cq, st))) return s;
+      if ((s = tap_copy_rows(taps->cand_score ? taps->cand_score + q0 * n : nullptr, un, score, uc, uc, cq, st)))
+        return s;
       if (p->mode == 1 && ham) {
-        if ((s = tap_copy(taps->order ? taps->order + q0 * n : nullptr, segids, qn * 4, st))) return s;
-        if ((s = tap_copy(taps->hamming ? taps->hamming + q0 * n : nullptr, regB, qn * 4, st))) return s;
+        if ((s = tap_copy_rows(taps->order ? taps->order + q0 * n : nullptr, un * 4, segids, uc * 4, uc * 4, cq, st)))
+          return s;
+        if ((s = tap_copy_rows(taps->hamming ? taps->hamming + q0 * n : nullptr, un * 4, regB, uc * 4, uc * 4, cq, st)))
+          return s;
       }
       if ((s = tap_copy(taps->examined ? taps->examined + q0 : nullptr, exam, size_t(cq) * 4, st))) return s;
       if ((s = tap_copy(taps->last_update ? taps->last_update + q0 : nullptr, lastu, size_t(cq) * 4, st))) return s;
@@ -756,6 +852,7 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
     HIP_TRY(hipEventRecord(ix->ev_join, ix->aux));
     HIP_TRY(hipStreamWaitEvent(st0, ix->ev_join, 0));
   }
+  if (redo_overflow_now) return redo_overflow(ix, queries, nq, k, p, ids, dists, workspace, taps, st0);
   return CRISP_OK;
 }
 
@@ -789,7 +886,7 @@ PlanLayout plan_layout(const crisp_index *ix, int max_batch, int k, const crisp_
   const long long qc = chunk_of(p, max_batch);
   const long long nch = (max_batch + qc - 1) / qc;
   L.ws = 0;
-  L.q = align_up(make_layout(ix, qc).total * (p->overlap == 1 ? 2 : 1));
+  L.q = align_up(search_ws(ix, max_batch, p).total);
   L.ids = L.q + align_up(static_cast<size_t>(max_batch) * ix->d * 4);
   L.dists = L.ids + align_up(static_cast<size_t>(max_batch) * k * 8);
   L.live = L.dists + align_up(static_cast<size_t>(max_batch) * k * 4);
@@ -814,7 +911,7 @@ crisp_status crisp_search(crisp_index *ix, const float *queries, int64_t nq, int
   if (nq == 0) return CRISP_OK;
   if (!queries || !ids || !dists || !workspace) return fail(CRISP_E_INVALID, "null argument");
   return search_impl(ix, queries, nq, k, p, ids, dists, workspace, ws_bytes, taps,
-                     static_cast<hipStream_t>(hip_stream), nullptr);
+                     static_cast<hipStream_t>(hip_stream), nullptr, true);
 }
 
 crisp_status crisp_search_static(crisp_index *ix, const float *queries, int64_t nq, int32_t k,
@@ -822,23 +919,25 @@ crisp_status crisp_search_static(crisp_index *ix, const float *queries, int64_t 
   crisp_status s = check_params(ix, nq, k, p);
   if (s != CRISP_OK) return s;
   if (!ix->scratch) return fail(CRISP_E_HIP, "static scratch unavailable: %s", ix->scratch_err.c_str());
-  const size_t cap = CRISP_STATIC_SCRATCH_BYTES;
-  const size_t one = make_layout(ix, 1).total;
-  if (one > cap)
-    return fail(CRISP_E_WORKSPACE, "one query needs %zu bytes of workspace; the static scratch holds %zu", one, cap);
+  const size_t room = CRISP_STATIC_SCRATCH_BYTES;
+  crisp_search_params q = *p;
+  q.overlap = 0;
+  q.max_chunk = 1;
+  const size_t one = search_ws(ix, nq, &q).total;
+  if (one > room)
+    return fail(CRISP_E_WORKSPACE, "one query needs %zu bytes of workspace; the static scratch holds %zu", one, room);
   if (nq == 0) return CRISP_OK;
   if (!queries || !ids || !dists) return fail(CRISP_E_INVALID, "null argument");
   // Largest chunk (up to the requested one) whose workspace fits.
   long long lo = 1, hi = chunk_of(p, nq);
   while (lo < hi) {
     const long long mid = (lo + hi + 1) / 2;
-    if (make_layout(ix, mid).total <= cap) lo = mid; else hi = mid - 1;
+    q.max_chunk = static_cast<int32_t>(mid);
+    if (search_ws(ix, nq, &q).total <= room) lo = mid; else hi = mid - 1;
   }
-  crisp_search_params q = *p;
-  q.overlap = 0;
   q.max_chunk = static_cast<int32_t>(lo);
-  return search_impl(ix, queries, nq, k, &q, ids, dists, ix->scratch, cap, nullptr,
-                     static_cast<hipStream_t>(hip_stream), nullptr);
+  return search_impl(ix, queries, nq, k, &q, ids, dists, ix->scratch, room, nullptr,
+                     static_cast<hipStream_t>(hip_stream), nullptr, true);
 }
 
 crisp_status crisp_plan_bytes(const crisp_index *ix, int32_t max_batch, int32_t k, const crisp_search_params *p,
@@ -889,7 +988,7 @@ static crisp_status plan_capture(crisp_plan *pl, int b) {
   ix->prof_on = false;
   HIP_TRY(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
   crisp_status s = search_impl(ix, pl->q_stage, nb, pl->k, &pl->p, pl->id_stage, pl->d_stage, pl->ws, pl->ws_bytes,
-                               nullptr, pl->cap, pl->live);
+                               nullptr, pl->cap, pl->live, false);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(pl->cap, &g);
   ix->prof_on = prof;
@@ -939,7 +1038,10 @@ crisp_status crisp_plan_search(crisp_plan *pl, const float *queries, int64_t nq,
   HIP_TRY(hipGraphLaunch(pl->exec[b], st));
   HIP_TRY(hipMemcpyAsync(ids, pl->id_stage, static_cast<size_t>(nq) * k * 8, hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipMemcpyAsync(dists, pl->d_stage, static_cast<size_t>(nq) * k * 4, hipMemcpyDeviceToDevice, st));
-  return CRISP_OK;
+  // queries whose candidates overflowed max_candidates: searched again,
+  // uncapped, into the caller's outputs (the replay's overflow list is in
+  // the workspace laid out for the bucket)
+  return redo_overflow(pl->ix, queries, bucket_size(pl, b), k, &pl->p, ids, dists, pl->ws, nullptr, st);
 }
 
 crisp_status crisp_plan_free(crisp_plan *pl) {

@@ -1348,16 +1348,22 @@ __global__ void k_tau_eff(const int32_t *__restrict__ flag, int nq, int k, int t
 // Concatenate the per-(tile, wave) candidate segments into one ascending list.
 constexpr int kCompactThreads = 256;
 
+// cap: capacity of a query's candidate list (its stride in cand / score);
+// a query with more candidates keeps the first cap, and its index in the
+// batch (q_base + q) is appended to ovf_list (count in *ovf_count, which the
+// caller clears) to be searched again with lists of n entries.
 __global__ void __launch_bounds__(kCompactThreads) k_compact(
     const int32_t *__restrict__ seg_ids, const uint8_t *__restrict__ seg_score, const int32_t *__restrict__ seg_cnt,
-    int nseg, int seg_len, long long n, int32_t *__restrict__ cand, uint8_t *__restrict__ score,
-    int32_t *__restrict__ ncand, const int32_t *__restrict__ live) {
+    int nseg, int seg_len, long long n, long long cap, int32_t *__restrict__ cand, uint8_t *__restrict__ score,
+    int32_t *__restrict__ ncand, const int32_t *__restrict__ live, int32_t *__restrict__ ovf_count,
+    int32_t *__restrict__ ovf_list, long long q_base) {
   __shared__ int base[kCompactThreads + 1];
   __shared__ int tmp[kCompactThreads / kWave + 1];
   __shared__ int carry;
   const int q = blockIdx.x, tid = threadIdx.x;
   if (live && q >= *live) return;
-  const long long qo = static_cast<long long>(q) * n;
+  const long long qs = static_cast<long long>(q) * n;     // the query's segments
+  const long long qo = static_cast<long long>(q) * cap;   // its candidate list
   const int32_t *sc = seg_cnt + static_cast<long long>(q) * nseg;
   if (tid == 0) carry = 0;
   __syncthreads();
@@ -1369,18 +1375,22 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(
     // copy the ns segments: each wave takes segments round robin
     for (int s = wave_id(); s < ns; s += kCompactThreads / kWave) {
       const int c = (s + 1 < kCompactThreads ? base[s + 1] : tot) - base[s];
-      const long long src = qo + static_cast<long long>(s0 + s) * seg_len;
-      const long long dpos = qo + carry + base[s];
-      for (int i = lane_id(); i < c; i += kWave) {
-        cand[dpos + i] = seg_ids[src + i];
-        score[dpos + i] = seg_score[src + i];
+      const long long src = qs + static_cast<long long>(s0 + s) * seg_len;
+      const long long at = static_cast<long long>(carry) + base[s];     // position in the list
+      const int cw = static_cast<int>(max(0ll, min(static_cast<long long>(c), cap - at)));
+      for (int i = lane_id(); i < cw; i += kWave) {
+        cand[qo + at + i] = seg_ids[src + i];
+        score[qo + at + i] = seg_score[src + i];
       }
     }
     __syncthreads();
     if (tid == 0) carry += tot;
     __syncthreads();
   }
-  if (tid == 0) ncand[q] = carry;
+  if (tid == 0) {
+    ncand[q] = static_cast<int32_t>(min(static_cast<long long>(carry), cap));
+    if (carry > cap) ovf_list[atomicAdd(ovf_count, 1)] = static_cast<int32_t>(q_base + q);
+  }
 }
 
 // Run order of a chunk's queries for the stages that read candidate rows
@@ -1396,9 +1406,10 @@ constexpr int kQueryOrderThreads = 1024;
 constexpr int kQueryOrderBits = 12;
 static_assert(kQueryOrderMax <= (1 << kQueryOrderBits), "query index must fit its field");
 
+// cap: the stride of a query's candidate list; n: a key above every id.
 __global__ void __launch_bounds__(kQueryOrderThreads) k_query_order(int cq, const int32_t *__restrict__ ncand,
                                                                     const int32_t *__restrict__ cand, long long n,
-                                                                    int32_t *__restrict__ order,
+                                                                    long long cap, int32_t *__restrict__ order,
                                                                     const int32_t *__restrict__ live) {
   __shared__ long long key[kQueryOrderMax];
   int n2 = 2;
@@ -1407,7 +1418,7 @@ __global__ void __launch_bounds__(kQueryOrderThreads) k_query_order(int cq, cons
   for (int i = threadIdx.x; i < n2; i += kQueryOrderThreads) {
     long long v = 0x7fffffffffffffffll;
     if (i < cq) {
-      const long long first = (i < nl && ncand[i] > 0) ? cand[static_cast<long long>(i) * n] : n;
+      const long long first = (i < nl && ncand[i] > 0) ? cand[static_cast<long long>(i) * cap] : n;
       v = (first << kQueryOrderBits) | i;
     }
     key[i] = v;
@@ -1474,7 +1485,7 @@ constexpr int kHamRows = 4, kHamLoads = 4;  // code rows per lane step, loads pe
 template <int kVec>
 __global__ void __launch_bounds__(kOrderThreads) k_hamming_dist(
     const float *__restrict__ qrot, int d, const uint64_t *__restrict__ codes, const int32_t *__restrict__ ncand,
-    const int32_t *__restrict__ cand, long long n, int32_t *__restrict__ hm_tmp, const int32_t *__restrict__ live,
+    const int32_t *__restrict__ cand, long long cap, int32_t *__restrict__ hm_tmp, const int32_t *__restrict__ live,
     const int32_t *__restrict__ order, int gx, int cq) {
   using V = typename CodeVec<kVec>::T;
   __shared__ uint64_t qc[128];
@@ -1485,7 +1496,7 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_dist(
   if (live && q >= *live) return;
   const int words = d / 64;
   const int nc = ncand[q];
-  const long long qo = static_cast<long long>(q) * n;
+  const long long qo = static_cast<long long>(q) * cap;
   for (int w = wv; w < words; w += kOrderWaves) {
     unsigned long long b = __ballot(qrot[static_cast<long long>(q) * d + w * 64 + lane] > 0.0f);
     if (lane == 0) qc[w] = b;
@@ -1552,7 +1563,7 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_dist(
 constexpr int kHamStats = 13;  // positions 1, 2, 4, ..., 2048, then the median
 
 __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
-    int d, const int32_t *__restrict__ ncand, const int32_t *__restrict__ cand, long long n,
+    int d, const int32_t *__restrict__ ncand, const int32_t *__restrict__ cand, long long cap,
     const int32_t *__restrict__ hm_tmp, int plen, int32_t *__restrict__ order, int32_t *__restrict__ ham_sorted,
     int32_t *__restrict__ avail, int32_t *__restrict__ hstat, const int32_t *__restrict__ live,
     const int32_t *__restrict__ qlist, const int32_t *__restrict__ qcount) {
@@ -1565,7 +1576,7 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
     const int q = qlist ? qlist[item] : item;
     if (q >= nl) return;                  // uniform over the block
     const int nc = ncand[q];
-    const long long qo = static_cast<long long>(q) * n;
+    const long long qo = static_cast<long long>(q) * cap;
     const int32_t *hq = hm_tmp + qo;
     for (int h = tid; h <= d; h += kOrderThreads) hist[h] = 0;
     __syncthreads();
@@ -2226,14 +2237,14 @@ __device__ inline void select_topk(double *__restrict__ keys, const int32_t *__r
 #define CRISP_RERANK_PARAMS                                                                              \
   const float *__restrict__ qrot, int d, const float *__restrict__ base, const uint16_t *__restrict__ base16, \
       const float *__restrict__ rerr, double gam, const int32_t *__restrict__ ncand,                          \
-      const int32_t *__restrict__ list, long long n, int k, int patience, const int32_t *__restrict__ limits,  \
+      const int32_t *__restrict__ list, long long cap, int k, int patience, const int32_t *__restrict__ limits,\
       double *__restrict__ dkey, float *__restrict__ lbuf, int32_t *__restrict__ rbuf,                        \
       int64_t *__restrict__ out_ids, float *__restrict__ out_d, int32_t *__restrict__ examined,              \
       int32_t *__restrict__ last_upd, int32_t *__restrict__ stopped, int32_t *__restrict__ refined,           \
       const double *__restrict__ ads_fac, long long *__restrict__ row_bytes, const int32_t *__restrict__ avail, \
       int32_t *__restrict__ redo, int32_t *__restrict__ nredo
 #define CRISP_RERANK_ARGS                                                                                 \
-  qrot, d, base, base16, rerr, gam, ncand, list, n, k, patience, limits, dkey, lbuf, rbuf, out_ids, out_d, \
+  qrot, d, base, base16, rerr, gam, ncand, list, cap, k, patience, limits, dkey, lbuf, rbuf, out_ids, out_d, \
       examined, last_upd, stopped, refined, ads_fac, row_bytes, avail, redo, nredo
 
 // One query, whole block.  kAds (Optimized Mode, float32 rows): walked
@@ -2251,7 +2262,7 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
   int *xpc = reinterpret_cast<int *>(dyn + LL.pc);
   __shared__ RerankShared S;
   const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
-  const long long qo = static_cast<long long>(q) * n;
+  const long long qo = static_cast<long long>(q) * cap;
   const double cb = key_band(d);
   for (int i = tid; i < d; i += kRerankThreads) sq[i] = qrot[static_cast<long long>(q) * d + i];
   const int nc = ncand[q];

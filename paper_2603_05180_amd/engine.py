@@ -152,10 +152,11 @@ class Index:
             {"dropped": pr.dropped}
 
     def params(self, *, mode=0, alpha=0.01, tau=1, patience_factor=40, limits=None, max_chunk=0, budget_source=0,
-               precision=0, persistent=0, overlap=0, walk_order=0, verify=0, order_prefix=0, count_tiles=0):
+               precision=0, persistent=0, overlap=0, walk_order=0, verify=0, order_prefix=0, count_tiles=0,
+               max_candidates=0):
         return SearchParams(int(mode), float(alpha), int(tau), int(patience_factor), _ptr(limits), int(max_chunk),
                             int(budget_source), int(precision), int(persistent), int(overlap), int(walk_order),
-                            int(verify), int(order_prefix), int(count_tiles))
+                            int(verify), int(order_prefix), int(count_tiles), int(max_candidates))
 
     def enable_bf16(self, stream=None, buffer: torch.Tensor | None = None) -> torch.Tensor:
         """bfloat16 copy of the rows + per-row error bounds for precision=1
@@ -253,7 +254,7 @@ class Index:
                patience_factor: int = 40, limits: torch.Tensor | None = None, max_chunk: int = 0,
                budget_source: int = 0, precision: int = 0, persistent: int = 0, overlap: int = 0,
                walk_order: int = 0, verify: int = 0, order_prefix: int = 0, count_tiles: int = 0,
-               taps: dict | None = None,
+               max_candidates: int = 0, taps: dict | None = None,
                out: tuple | None = None, stream=None):
         """Algorithm 1 for a batch; returns (ids int64 [nq, k], dists f32 [nq, k])."""
         _check_queries(queries, self.d, self.device)
@@ -264,7 +265,7 @@ class Index:
         p = self.params(mode=mode, alpha=alpha, tau=tau, patience_factor=patience_factor,
                         limits=limits, max_chunk=max_chunk, budget_source=budget_source, precision=precision,
                         persistent=persistent, overlap=overlap, walk_order=walk_order, verify=verify,
-                        order_prefix=order_prefix, count_tiles=count_tiles)
+                        order_prefix=order_prefix, count_tiles=count_tiles, max_candidates=max_candidates)
         ids, dists = _outputs(out, nq, int(k), self.device)
         tp = None
         if taps is not None:

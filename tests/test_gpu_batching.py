@@ -216,3 +216,61 @@ def test_stage_profile_intervals(d128):
         assert st[name]["intervals"] == 3 and st[name]["ms"] > 0, (name, st[name])
     assert st["candidates"]["intervals"] == 6 and st["candidates"]["ms"] > 0
     assert st["budget"]["intervals"] == 0
+
+
+@pytest.mark.parametrize("mode,precision", [(0, 1), (1, 0), (1, 1)])
+def test_capped_candidate_lists_match(d128, mode, precision):
+    """max_candidates caps each query's candidate-indexed buffers; queries
+    with more candidates are searched again uncapped after the batch.  Ids,
+    distances and every stage tap equal the uncapped search, with chunks and
+    two pipelines, through a plan's graph replays and through the static
+    scratch; the capped workspace is smaller."""
+    import ctypes
+    from paper_2603_05180_amd import engine
+    from paper_2603_05180_amd._lib import check, lib
+    w, x, q, idx, g = d128
+    kw = dict(mode=mode, alpha=0.05, tau=4, precision=precision)
+    nq = q.shape[0]
+    t0 = g.alloc_taps(nq, mode)
+    ref = g.search(q, 10, taps=t0, **kw)
+    torch.cuda.synchronize()
+    nc = t0["n_cand"].cpu().numpy()
+    cap = int(np.percentile(nc, 60))           # about 40% of the queries overflow
+    assert 0 < cap < nc.max() and (nc > cap).sum() > 0
+    print(f"cap {cap}, {(nc > cap).sum()} of {nq} queries above it", flush=True)
+    for extra in (dict(), dict(max_chunk=37), dict(max_chunk=64, overlap=1)):
+        t1 = g.alloc_taps(nq, mode)
+        _same(g.search(q, 10, taps=t1, max_candidates=cap, **kw, **extra), ref)
+        for key in t0:
+            if key == "limits":                  # written only with a budget model
+                continue
+            a, b = t0[key].cpu().numpy(), t1[key].cpu().numpy()
+            if key in ("cand", "cand_score", "order", "hamming"):
+                for qi in range(nq):
+                    assert np.array_equal(a[qi, :nc[qi]], b[qi, :nc[qi]]), (key, qi, extra)
+            elif key == "cells":                 # each subspace's activated cells only
+                ncl = t0["n_cells"].cpu().numpy()
+                for qi in range(nq):
+                    for sub in range(ncl.shape[1]):
+                        assert np.array_equal(a[qi, sub, :ncl[qi, sub]], b[qi, sub, :ncl[qi, sub]]), (key, qi, extra)
+            else:
+                assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), (key, extra)
+    # a cap above every candidate list changes nothing either
+    _same(g.search(q, 10, max_candidates=int(nc.max()) + 1, **kw), ref)
+    # the workspace shrinks: 21 bytes fewer per entry and query
+    sizes = []
+    for c in (0, cap):
+        b = ctypes.c_size_t(0)
+        p = g.params(max_candidates=c, max_chunk=256, **kw)
+        check(lib.crisp_search_workspace_bytes(g._h, 256, 10, ctypes.byref(p), ctypes.byref(b)))
+        sizes.append(b.value)
+    assert sizes[1] < sizes[0]
+    # plan replays (the overflowing queries redone after each replay)
+    pl = engine.Plan(g, 300, 10, max_candidates=cap, **kw)
+    for rep in range(2):
+        _same(pl.search(q), ref)
+        sub = q[:70].contiguous()
+        _same(pl.search(sub), g.search(sub, 10, **kw))
+    pl.free()
+    # the static scratch
+    _same(g.search_static(q, 10, max_candidates=cap, **kw), ref)
