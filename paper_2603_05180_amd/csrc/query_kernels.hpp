@@ -1461,6 +1461,7 @@ __global__ void __launch_bounds__(kQueryOrderThreads) k_query_order(int cq, cons
 // k_hamming_order (below) places the candidates in (distance, id) order.
 // ---------------------------------------------------------------------------
 constexpr int kOrderThreads = 256;
+constexpr int kOrderSpan = 1024;  // distance bins placed by all four waves (per-wave counts)
 constexpr int kOrderWaves = kOrderThreads / kWave;
 
 template <int kVec>
@@ -1567,8 +1568,10 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
     const int32_t *__restrict__ hm_tmp, int plen, int32_t *__restrict__ order, int32_t *__restrict__ ham_sorted,
     int32_t *__restrict__ avail, int32_t *__restrict__ hstat, const int32_t *__restrict__ live,
     const int32_t *__restrict__ qlist, const int32_t *__restrict__ qcount) {
-  extern __shared__ __align__(16) int hist[];  // d + 1 bins, then the scan's scratch
-  int *tmp = hist + d + 1;
+  // d + 1 bins (or the per-wave counts and starts of the placed bins), then
+  // the scan's scratch
+  extern __shared__ __align__(16) int hist[];
+  int *tmp = hist + max(d + 1, (kOrderWaves + 1) * kOrderSpan);
   const int nl = live ? *live : 0x7fffffff;
   const int nitems = qcount ? *qcount : static_cast<int>(gridDim.x);
   const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
@@ -1623,7 +1626,84 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
     const int placed = hcut < 0 ? 0 : (hcut < d ? hist[hcut + 1] : nc);
     if (tid == 0) avail[q] = placed;
     __syncthreads();
-    if (wv == 0 && hcut >= 0) {
+    // Placement of bins hmin .. hcut in (h, id) order.  When they span at
+    // most kOrderSpan distances the four waves place four contiguous ranges
+    // of the candidates (in id order) at once: each counts its range per
+    // bin, a prefix over the waves gives each wave its first position in
+    // every bin, then each places its range in order.  Otherwise wave 0
+    // places all of them.
+    const int hmin = hcut >= 0 ? upper_bound_minus1(hist, d + 1, 0) : 0;   // the first non-empty bin
+    const int span = hcut - hmin + 1;
+    if (hcut >= 0 && span <= kOrderSpan) {
+      int *wcnt = hist;                        // [kOrderWaves][kOrderSpan]: counts, then first positions
+      int *bst = hist + kOrderWaves * kOrderSpan;   // [kOrderSpan]: first position of each bin
+      int sv[kOrderSpan / kOrderThreads];
+#pragma unroll
+      for (int u = 0; u < kOrderSpan / kOrderThreads; ++u) {
+        const int j = tid + u * kOrderThreads;
+        sv[u] = j < span ? hist[hmin + j] : 0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kOrderSpan / kOrderThreads; ++u) bst[tid + u * kOrderThreads] = sv[u];
+      for (int j = tid; j < kOrderWaves * kOrderSpan; j += kOrderThreads) wcnt[j] = 0;
+      __syncthreads();
+      const int per = (nc + kOrderWaves * kWave - 1) / (kOrderWaves * kWave) * kWave;
+      const int r0 = wv * per, r1 = min(nc, r0 + per);
+      int *mine = wcnt + wv * kOrderSpan;
+      for (int i0 = r0; i0 < r1; i0 += kWave * 8) {
+        int hv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) hv[u] = hq[min(i0 + u * kWave + lane, r1 - 1)];  // clamped: every load is issued
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (i0 + u * kWave + lane < r1 && hv[u] <= hcut) atomicAdd(&mine[hv[u] - hmin], 1);
+      }
+      __syncthreads();
+      for (int j = tid; j < span; j += kOrderThreads) {
+        int run = bst[j];
+#pragma unroll
+        for (int w = 0; w < kOrderWaves; ++w) {
+          const int c = wcnt[w * kOrderSpan + j];
+          wcnt[w * kOrderSpan + j] = run;
+          run += c;
+        }
+      }
+      __syncthreads();
+      int nbits = 0;
+      while ((1 << nbits) < span) ++nbits;
+      const unsigned long long below = lanes_below_mask();
+      constexpr int U = 8;  // steps whose distances and ids are loaded together
+      for (int i0 = r0; i0 < r1; i0 += kWave * U) {
+        int hv[U], iv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = min(i0 + u * kWave + lane, r1 - 1);  // clamped: every load is issued
+          hv[u] = hq[i];
+          iv[u] = cand[qo + i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int b = hv[u] - hmin;
+          const bool in = i0 + u * kWave + lane < r1 && hv[u] <= hcut;
+          unsigned long long same = __ballot(in);
+          if (same == 0ull) continue;  // wave-uniform
+          for (int bit = 0; bit < nbits; ++bit) {
+            const bool on = (b >> bit) & 1;
+            const unsigned long long bb = __ballot(on);
+            same &= on ? bb : ~bb;
+          }
+          if (in) {
+            const int pos = mine[b] + __popcll(same & below);
+            order[qo + pos] = iv[u];
+            ham_sorted[qo + pos] = hv[u];
+          }
+          __builtin_amdgcn_wave_barrier();
+          if (in && (same & below) == 0) mine[b] += __popcll(same);
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+    } else if (wv == 0 && hcut >= 0) {
       int nbits = 0;
       while ((1 << nbits) <= hcut) ++nbits;
       const unsigned long long below = lanes_below_mask();
@@ -1663,7 +1743,8 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
 }
 
 __host__ __device__ inline size_t hamming_order_lds(int d) {
-  return (static_cast<size_t>(d) + 1 + kOrderThreads / kWave + 1) * sizeof(int);
+  const size_t bins = static_cast<size_t>(d) + 1, part = static_cast<size_t>(kOrderWaves + 1) * kOrderSpan;
+  return ((bins > part ? bins : part) + kOrderWaves + 1) * sizeof(int);
 }
 
 // ---------------------------------------------------------------------------

@@ -145,9 +145,8 @@ def test_code_widths_not_a_power_of_two(d, m):
 
 def test_hamming_order_wide_ranges():
     """Every point a candidate (alpha = 1, tau = 1) at D = 1024: each query's
-    Hamming distances span several hundred values, so both digits of the
-    two-pass placement vary, and the (h, id) order must still equal the
-    oracle's."""
+    Hamming distances span several hundred values, and the (h, id) order must
+    still equal the oracle's."""
     from oracle import query as oquery
     w, x, q = make_workload("d4096", n=3000, d=1024, m=8, k_half=6, rank=16, n_query=6)
     idx = oracle_index(w, x)
@@ -158,6 +157,29 @@ def test_hamming_order_wide_ranges():
     print("D=1024 alpha=1 spans", spans, flush=True)
     assert min(spans) >= 256, spans
     compare(idx, q, 10, mode=1, alpha=1.0, tau=1)
+
+
+@pytest.mark.parametrize("pf", [40, 300])
+def test_hamming_order_placed_span_above_1024(pf):
+    """D = 2048, every point a candidate, base rows among the queries (a
+    Hamming distance of 0 to themselves): the placed bins of those queries
+    span more than 1,024 distances (the placement by one wave) while the
+    others span fewer (the placement by all waves of the block); with patience
+    300 * k every candidate is placed, with 40 * k a prefix."""
+    from oracle import query as oquery
+    w, x, q = make_workload("d128", n=3000, d=2048, m=8, k_half=6, n_query=3)
+    q = np.ascontiguousarray(np.concatenate([x[[0, 7, 1500]], q]), dtype=np.float32)
+    idx = oracle_index(w, x, force_rotation=False)
+    spans = []
+    for qi in range(q.shape[0]):
+        _, _, tr = oquery.search_one(idx, q[qi], 10, mode=1, alpha=1.0, tau=1, trace=True)
+        h = np.sort(tr["hamming"])
+        plen = min(h.size, 2 * pf * 10 + 1024)
+        spans.append(int(h[plen - 1] - h[0]))
+    print(f"D=2048 patience={pf} placed spans", spans, flush=True)
+    if pf == 300:
+        assert max(spans) > 1024 and min(spans) <= 1024, spans
+    compare(idx, q, 10, mode=1, alpha=1.0, tau=1, patience_factor=pf)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
