@@ -469,6 +469,22 @@ crisp_status crisp_search_workspace_bytes(const crisp_index *index, int64_t nq, 
   return CRISP_OK;
 }
 
+// A0 launch.  The direct-to-LDS kernel needs 16-byte aligned rows and pays
+// off once its 128x128 tiles give every compute unit a block; smaller grids
+// (few rows, small D) run the small-tile kernel, which has twice the blocks.
+static void launch_rotate(const float *x, long long rows, int d, const float *r, float *out, const int32_t *live,
+                          int ncu, hipStream_t st) {
+  const long long tiles = static_cast<long long>((d + kRotBN - 1) / kRotBN) * ((rows + kRotBM - 1) / kRotBM);
+  const bool aligned = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(r)) & 15u) == 0;
+  if (aligned && tiles >= ncu) {
+    dim3 g((d + kRotBN - 1) / kRotBN, static_cast<unsigned>((rows + kRotBM - 1) / kRotBM));
+    k_rotate_rows<<<g, 256, 0, st>>>(x, rows, d, r, out, live);
+  } else {
+    dim3 g(d / kRotSmBN, static_cast<unsigned>((rows + kRotSmBM - 1) / kRotSmBM));
+    k_rotate_rows_small<<<g, 256, 0, st>>>(x, rows, d, r, out, live);
+  }
+}
+
 static crisp_status tap_copy(void *dst, const void *src, size_t bytes, hipStream_t st) {
   if (!dst || bytes == 0) return CRISP_OK;
   HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
@@ -644,8 +660,7 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
     // A0
     StageTimer t0(ix, 0, st);
     if (ix->rot) {
-      dim3 g(d / kRotBN, (cq + kRotBM - 1) / kRotBM);
-      k_rotate_rows<<<g, 256, 0, st>>>(qin, cq, d, ix->rot, qrot, lv);
+      launch_rotate(qin, cq, d, ix->rot, qrot, lv, ix->ncu, st);
       LAUNCH_TRY("k_rotate_rows");
     } else {
       k_copy_f32<<<grid1(static_cast<long long>(cq) * d, 256), 256, 0, st>>>(qin, qrot, static_cast<long long>(cq) * d,
@@ -1163,8 +1178,11 @@ crisp_status crisp_rotate_rows(const float *x, int64_t rows, int32_t d, const fl
   if (rows == 0) return CRISP_OK;
   if ((rows + kRotBM - 1) / kRotBM > 65535) return fail(CRISP_E_UNSUPPORTED, "too many rows for one call");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  dim3 g(d / kRotBN, static_cast<unsigned>((rows + kRotBM - 1) / kRotBM));
-  k_rotate_rows<<<g, 256, 0, st>>>(x, rows, d, r, out, nullptr);
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      ncu < 1)
+    ncu = 256;
+  launch_rotate(x, rows, d, r, out, nullptr, ncu, st);
   LAUNCH_TRY("k_rotate_rows");
   return CRISP_OK;
 }

@@ -24,32 +24,139 @@ namespace crisp {
 // each addition (checked bit for bit on gfx950), and products of two float32
 // values are exact in float64; so chaining the instructions in ascending k
 // gives every output exactly the ascending-k float64 sum of its definition.
-// 128x64 output tile per 256-thread block, 64x32 per wavefront (4x2 tiles of
-// 16x16).  The k dimension goes through LDS in 8-deep float32 slabs, double
-// buffered (one barrier per slab: the next slab is loaded into registers
-// while the current one feeds the matrix cores, then stored to the other
-// buffer); fragments are widened to float64 after the LDS read.  Small
-// slabs and float32 staging keep the kernel at 110 registers, four waves per
-// SIMD (measured against 16- and 32-deep slabs, float64 staging, 128x128
-// block tiles and two or three waves per SIMD: 55-60 TF/s, this one at the
-// top).  Rows padded by 16 floats: the four k of a fragment fall in
-// different banks.
+// Two kernels compute the same values:
+//
+// k_rotate_rows: 128x128 output tile per 256-thread block, 64x64 per
+// wavefront (4x4 tiles of 16x16), two waves per SIMD.  The k dimension goes
+// through LDS in 16-deep float32 slabs loaded by global_load_lds_dwordx4
+// straight into LDS (no staging registers), double buffered: after the
+// barrier each wave reads all of its fragments of the slab into registers,
+// then issues the next slab's loads into the other buffer (so no LDS read
+// follows a load in flight), then runs its 64 matrix instructions; the loads
+// are waited for at the next barrier.  A lane's 16-byte load lands at a fixed
+// LDS position (lane x 16 bytes from the instruction's base), so the layout
+// is chosen through the source address: the four 16-byte chunks of an A row
+// and the 32 of a B row are XOR-swizzled by the row so that the fragment
+// reads (16 rows x 4 k, or 4 k x 16 columns) hit 64 different banks.  Needs
+// 16-byte aligned rows and enough blocks to fill the chip (the host picks).
+//
+// k_rotate_rows_small: 128x64 tile per block, 64x32 per wavefront, 8-deep
+// slabs staged through registers, four waves per SIMD: twice the blocks of
+// the kernel above for small grids (few rows, or D below 1,024).
 // ---------------------------------------------------------------------------
-constexpr int kRotBM = 128, kRotBN = 64, kRotBK = 8, kRotPad = 16;
-constexpr int kRotEA = kRotBM * kRotBK / 256, kRotEB = kRotBK * kRotBN / 256;  // staged floats per thread
+constexpr int kRotBM = 128, kRotBN = 128, kRotBK = 16;
+constexpr int kRotCpr = kRotBK / 4, kRotRpl = 64 / kRotBK, kRotLoads = kRotBK / 8;  // chunks per A row, A rows per 64 banks, loads per wave per operand
 typedef double rot_acc_t __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void_t;
 
 // live: NULL, or a device count of the rows to produce (rows beyond it are skipped).
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_rotate_rows(const float *__restrict__ x, long long rows, int d, const float *__restrict__ r,
               float *__restrict__ out, const int32_t *__restrict__ live) {
-  __shared__ __align__(16) float sa[2][kRotBK][kRotBM + kRotPad];
-  __shared__ __align__(16) float sb[2][kRotBK][kRotBN + kRotPad];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int fi = lane & 15, fk = lane >> 4;          // fragment row / k of this lane
-  const int wr = (wv >> 1) * 64, wc = (wv & 1) * 32; // the wavefront's 64x32 sub-tile
+  __shared__ __align__(16) float sa[2][kRotBM * kRotBK];
+  __shared__ __align__(16) float sb[2][kRotBK * kRotBN];
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int fi = lane & 15, fk = lane >> 4;          // fragment row (column) / k of this lane
+  const int wr = (wv >> 1) * 64, wc = (wv & 1) * 64; // the wavefront's 64x64 sub-tile
   const long long row0 = static_cast<long long>(blockIdx.y) * kRotBM;
   const int col0 = blockIdx.x * kRotBN;
+  if (live) rows = min(rows, static_cast<long long>(*live));
+  if (row0 >= rows) return;
+  // Sources of this lane's loads.  A: load g covers rows 16g .. 16g + 15 of
+  // the tile, four lanes per row, LDS slot `slot` of row `row` holding k chunk
+  // slot ^ swizzle(row).  B: load g covers k rows 2g, 2g + 1, 32 lanes per
+  // row, slot holding column chunk slot ^ 4 (k & 3).  Rows past the last are
+  // clamped (never stored); columns past D are clamped (never stored).
+  const float *ga[kRotLoads], *gb[kRotLoads];
+#pragma unroll
+  for (int e = 0; e < kRotLoads; ++e) {
+    const int g = wv * kRotLoads + e;
+    const int row = g * (64 / kRotCpr) + lane / kRotCpr, slot = lane % kRotCpr;
+    const int chunk = slot ^ ((row / kRotRpl) % kRotCpr);
+    const long long gr = min(row0 + row, rows - 1);
+    ga[e] = x + gr * d + chunk * 4;
+    const int kr = g * 2 + (lane >> 5), bslot = lane & 31;
+    const int bchunk = bslot ^ ((kr & 3) << 2);
+    gb[e] = r + static_cast<long long>(kr) * d + min(col0 + bchunk * 4, d - 4);
+  }
+  auto issue = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < kRotLoads; ++e)
+      __builtin_amdgcn_global_load_lds(ga[e], (lds_void_t *)&sa[buf][(wv * kRotLoads + e) * 256], 16, 0, 0);
+#pragma unroll
+    for (int e = 0; e < kRotLoads; ++e)
+      __builtin_amdgcn_global_load_lds(gb[e], (lds_void_t *)&sb[buf][(wv * kRotLoads + e) * 256], 16, 0, 0);
+#pragma unroll
+    for (int e = 0; e < kRotLoads; ++e) {
+      ga[e] += kRotBK;
+      gb[e] += static_cast<long long>(kRotBK) * d;
+    }
+  };
+  rot_acc_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = rot_acc_t{0.0, 0.0, 0.0, 0.0};
+  const int swa = (fi / kRotRpl) % kRotCpr;          // swizzle of this lane's A rows
+  const int abase = (wr + fi) * kRotBK + fk;
+  int boff[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) boff[j] = fk * kRotBN + wc + ((j ^ fk) << 4) + fi;
+  const int nslab = d / kRotBK;
+  issue(0);
+  for (int s = 0; s < nslab; ++s) {
+    const int cur = s & 1;
+    __syncthreads();  // slab s is in LDS (each wave waits for its loads); every wave is done with slab s - 1
+    const float *A = sa[cur], *B = sb[cur];
+    float fa[kRotBK / 4][4], fb[kRotBK / 4][4];
+#pragma unroll
+    for (int t = 0; t < kRotBK / 4; ++t) {
+      const int ao = abase + ((t ^ swa) << 2);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) fa[t][i] = A[ao + i * 16 * kRotBK];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fb[t][j] = B[boff[j] + t * 4 * kRotBN];
+    }
+    if (s + 1 < nslab) issue(cur ^ 1);
+#pragma unroll
+    for (int t = 0; t < kRotBK / 4; ++t) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = static_cast<double>(fa[t][i]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = static_cast<double>(fb[t][j]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+  // Accumulator element v of lane l holds row fk + 4v, column fi of its tile.
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const long long gr = row0 + wr + i * 16 + fk + 4 * v;
+        const int gc = col0 + wc + j * 16 + fi;
+        if (gr < rows && gc < d) out[gr * d + gc] = static_cast<float>(acc[i][j][v]);
+      }
+}
+
+constexpr int kRotSmBM = 128, kRotSmBN = 64, kRotSmBK = 8, kRotSmPad = 16;
+constexpr int kRotSmEA = kRotSmBM * kRotSmBK / 256, kRotSmEB = kRotSmBK * kRotSmBN / 256;  // staged floats per thread
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_rotate_rows_small(const float *__restrict__ x, long long rows, int d, const float *__restrict__ r,
+                    float *__restrict__ out, const int32_t *__restrict__ live) {
+  __shared__ __align__(16) float sa[2][kRotSmBK][kRotSmBM + kRotSmPad];
+  __shared__ __align__(16) float sb[2][kRotSmBK][kRotSmBN + kRotSmPad];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int fi = lane & 15, fk = lane >> 4;
+  const int wr = (wv >> 1) * 64, wc = (wv & 1) * 32;  // the wavefront's 64x32 sub-tile
+  const long long row0 = static_cast<long long>(blockIdx.y) * kRotSmBM;
+  const int col0 = blockIdx.x * kRotSmBN;
   if (live) rows = min(rows, static_cast<long long>(*live));
   if (row0 >= rows) return;
   rot_acc_t acc[4][2];
@@ -57,44 +164,44 @@ k_rotate_rows(const float *__restrict__ x, long long rows, int d, const float *_
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = rot_acc_t{0.0, 0.0, 0.0, 0.0};
-  float ra[kRotEA], rb[kRotEB];
+  float ra[kRotSmEA], rb[kRotSmEB];
   auto gload = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < kRotEA; ++e) {
+    for (int e = 0; e < kRotSmEA; ++e) {
       const int idx = tid + e * 256;
-      const int rr = idx / kRotBK, kk = idx % kRotBK;
+      const int rr = idx / kRotSmBK, kk = idx % kRotSmBK;
       long long gr = row0 + rr;
       gr = gr < rows ? gr : rows - 1;            // clamped; such rows are never stored
       ra[e] = x[gr * d + k0 + kk];
     }
 #pragma unroll
-    for (int e = 0; e < kRotEB; ++e) {
+    for (int e = 0; e < kRotSmEB; ++e) {
       const int idx = tid + e * 256;
-      const int kk = idx / kRotBN, cc = idx % kRotBN;
+      const int kk = idx / kRotSmBN, cc = idx % kRotSmBN;
       rb[e] = r[static_cast<long long>(k0 + kk) * d + col0 + cc];
     }
   };
   auto store = [&](int b) {
 #pragma unroll
-    for (int e = 0; e < kRotEA; ++e) {
+    for (int e = 0; e < kRotSmEA; ++e) {
       const int idx = tid + e * 256;
-      sa[b][idx % kRotBK][idx / kRotBK] = ra[e];
+      sa[b][idx % kRotSmBK][idx / kRotSmBK] = ra[e];
     }
 #pragma unroll
-    for (int e = 0; e < kRotEB; ++e) {
+    for (int e = 0; e < kRotSmEB; ++e) {
       const int idx = tid + e * 256;
-      sb[b][idx / kRotBN][idx % kRotBN] = rb[e];
+      sb[b][idx / kRotSmBN][idx % kRotSmBN] = rb[e];
     }
   };
-  const int nslab = d / kRotBK;
+  const int nslab = d / kRotSmBK;
   gload(0);
   store(0);
   __syncthreads();
   for (int s = 0; s < nslab; ++s) {
     const int cur = s & 1;
-    if (s + 1 < nslab) gload((s + 1) * kRotBK);
+    if (s + 1 < nslab) gload((s + 1) * kRotSmBK);
 #pragma unroll
-    for (int kk = 0; kk < kRotBK; kk += 4) {
+    for (int kk = 0; kk < kRotSmBK; kk += 4) {
       double a[4], b[2];
 #pragma unroll
       for (int i = 0; i < 4; ++i) a[i] = static_cast<double>(sa[cur][kk + fk][wr + i * 16 + fi]);
@@ -108,7 +215,6 @@ k_rotate_rows(const float *__restrict__ x, long long rows, int d, const float *_
     if (s + 1 < nslab) store(cur ^ 1);
     __syncthreads();
   }
-  // Accumulator element v of lane l holds row fk + 4v, column fi of its tile.
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll

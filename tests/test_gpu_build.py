@@ -117,3 +117,26 @@ def test_sign_codes_of_every_row_at_full_size():
         assert torch.equal(bits, x[r] > 0), r
     del x, codes
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("rows,d,offset", [
+    (16500, 192, 0),   # 128x128 direct-to-LDS tiles: half-filled last column tile, ragged rows
+    (4100, 1024, 0),   # direct-to-LDS tiles, ragged rows
+    (16500, 192, 1),   # rows not 16-byte aligned: small-tile kernel
+    (300, 192, 0),     # too few tiles to fill the chip: small-tile kernel
+])
+def test_rotation_kernels_equal_oracle(rows, d, offset):
+    """x R through the C ABI on both rotation kernels equals the oracle's
+    ascending-i float64 sum rounded to float32, bit for bit (Section 3)."""
+    from paper_2603_05180_amd import engine
+    rng = np.random.default_rng(rows * 7 + d + offset)
+    x = (rng.standard_normal((rows, d)) * np.exp2(rng.integers(-6, 7, (rows, 1)))).astype(np.float32)
+    r = obuild.rotation_from_gaussian(rng.standard_normal((d, d)))
+    ref = obuild.rotate_rows(x, r)
+    buf = torch.zeros(rows * d + offset, dtype=torch.float32, device="cuda")
+    buf[offset:] = torch.from_numpy(x.reshape(-1)).cuda()
+    xt = buf[offset:].view(rows, d)
+    print(f"rotation rows={rows} d={d} offset={offset}", flush=True)
+    got = engine.rotate_rows(xt, torch.from_numpy(r).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy().view(np.uint32), ref.view(np.uint32))
