@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--max-chunk", type=int, default=4096,
                     help="queries per chunk (4096: two pipelines of N-sized per-query buffers fill most of HBM)")
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--max-candidates", type=int, default=0,
+                    help="candidate-list capacity per query (0: N); queries with more are searched again uncapped")
     ap.add_argument("--guaranteed", type=int, default=1, help="also time Guaranteed Mode (plain and bf16)")
     ap.add_argument("--scoring", type=int, default=1,
                     help="also time the tuned form with certified bfloat16 matrix-core pre-scoring (precision 2)")
@@ -356,7 +358,7 @@ def measure(args, pool):
     index.enable_bf16()
     k = w.k
     base_kw = dict(mode=args.mode, alpha=args.alpha, tau=args.tau, patience_factor=args.patience,
-                   max_chunk=args.max_chunk, overlap=args.overlap)
+                   max_chunk=args.max_chunk, overlap=args.overlap, max_candidates=args.max_candidates)
 
     # Rotated queries (same kernel as the search) for the exact ground truth.
     qrot = engine.rotate_rows(queries, arrays["rotation"]) if arrays["rotation"] is not None else queries

@@ -1674,10 +1674,10 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
     const int32_t *__restrict__ hm_tmp, int plen, int32_t *__restrict__ order, int32_t *__restrict__ ham_sorted,
     int32_t *__restrict__ avail, int32_t *__restrict__ hstat, const int32_t *__restrict__ live,
     const int32_t *__restrict__ qlist, const int32_t *__restrict__ qcount) {
-  // d + 1 bins (or the per-wave counts and starts of the placed bins), then
-  // the scan's scratch
+  // d + 1 bins (or, while placing, the per-wave counts and starts of the
+  // placed bins and the waves' staging lists), then the scan's scratch
   extern __shared__ __align__(16) int hist[];
-  int *tmp = hist + max(d + 1, (kOrderWaves + 1) * kOrderSpan);
+  int *tmp = hist + max(d + 1, (kOrderWaves + 2) * kOrderSpan);
   const int nl = live ? *live : 0x7fffffff;
   const int nitems = qcount ? *qcount : static_cast<int>(gridDim.x);
   const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
@@ -1689,31 +1689,22 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
     const int32_t *hq = hm_tmp + qo;
     for (int h = tid; h <= d; h += kOrderThreads) hist[h] = 0;
     __syncthreads();
-    // histogram: the lanes of a step holding equal distances add once (their
-    // count), so that a crowded bin is not hit by 64 atomics at once
+    // histogram: one LDS atomic per candidate (a crowded bin serializes its
+    // lanes, at most 64 per instruction)
     {
-      int nbits_all = 0;
-      while ((1 << nbits_all) <= d) ++nbits_all;
-      const unsigned long long below = lanes_below_mask();
-      constexpr int U = 4;
-      for (int i0 = wv * kWave * U; i0 < nc; i0 += kOrderThreads * U) {
-        int hv[U];
+      constexpr int U = 8;  // steps per batch; the next batch is loaded while this one is counted
+      int hv[U], hn[U];
+      const int first = wv * kWave * U;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int i = i0 + u * kWave + lane;
-          hv[u] = hq[i < nc ? i : nc - 1];  // clamped: every load is issued
-        }
+      for (int u = 0; u < U; ++u) hv[u] = nc > 0 ? hq[min(first + u * kWave + lane, nc - 1)] : 0;  // clamped
+      for (int i0 = first; i0 < nc; i0 += kOrderThreads * U) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const bool ok = i0 + u * kWave + lane < nc;
-          unsigned long long same = __ballot(ok);
-          for (int bit = 0; bit < nbits_all; ++bit) {
-            const bool on = (hv[u] >> bit) & 1;
-            const unsigned long long bb = __ballot(on);
-            same &= on ? bb : ~bb;
-          }
-          if (ok && (same & below) == 0) atomicAdd(&hist[hv[u]], __popcll(same));
-        }
+        for (int u = 0; u < U; ++u) hn[u] = hq[min(i0 + kOrderThreads * U + u * kWave + lane, nc - 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (i0 + u * kWave + lane < nc) atomicAdd(&hist[hv[u]], 1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) hv[u] = hn[u];
       }
     }
     __syncthreads();
@@ -1752,18 +1743,25 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < kOrderSpan / kOrderThreads; ++u) bst[tid + u * kOrderThreads] = sv[u];
-      for (int j = tid; j < kOrderWaves * kOrderSpan; j += kOrderThreads) wcnt[j] = 0;
-      __syncthreads();
       const int per = (nc + kOrderWaves * kWave - 1) / (kOrderWaves * kWave) * kWave;
       const int r0 = wv * per, r1 = min(nc, r0 + per);
       int *mine = wcnt + wv * kOrderSpan;
-      for (int i0 = r0; i0 < r1; i0 += kWave * 8) {
-        int hv[8];
+      for (int j = lane; j < span; j += kWave) mine[j] = 0;   // the wave's own counters
+      __builtin_amdgcn_wave_barrier();
+      if (r0 < r1) {
+        constexpr int U = 8;  // steps per batch; the next batch is loaded while this one is counted
+        int hv[U], hn[U];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) hv[u] = hq[min(i0 + u * kWave + lane, r1 - 1)];  // clamped: every load is issued
+        for (int u = 0; u < U; ++u) hv[u] = hq[min(r0 + u * kWave + lane, r1 - 1)];  // clamped: every load is issued
+        for (int i0 = r0; i0 < r1; i0 += kWave * U) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (i0 + u * kWave + lane < r1 && hv[u] <= hcut) atomicAdd(&mine[hv[u] - hmin], 1);
+          for (int u = 0; u < U; ++u) hn[u] = hq[min(i0 + kWave * U + u * kWave + lane, r1 - 1)];
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if (i0 + u * kWave + lane < r1 && hv[u] <= hcut) atomicAdd(&mine[hv[u] - hmin], 1);
+#pragma unroll
+          for (int u = 0; u < U; ++u) hv[u] = hn[u];
+        }
       }
       __syncthreads();
       for (int j = tid; j < span; j += kOrderThreads) {
@@ -1776,37 +1774,66 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
         }
       }
       __syncthreads();
+      // Each wave walks its range 256 candidates at a time: the placed ones
+      // (h <= hcut) are packed, in id order, into the wave's staging lists
+      // (bin offset and id, in the space the bin starts used), then ranked 64
+      // at a time among equal bins by ballots over the bin offset's bits.
       int nbits = 0;
       while ((1 << nbits) < span) ++nbits;
       const unsigned long long below = lanes_below_mask();
-      constexpr int U = 8;  // steps whose distances and ids are loaded together
-      for (int i0 = r0; i0 < r1; i0 += kWave * U) {
-        int hv[U], iv[U];
+      int *sbin = bst + wv * (kOrderSpan / kOrderWaves), *sid = bst + kOrderSpan + wv * (kOrderSpan / kOrderWaves);
+      constexpr int U = kOrderSpan / kOrderWaves / kWave;  // steps per batch (256 candidates)
+      int hv[U], iv[U], hn[U], in_[U];
+      if (r0 < r1) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int i = min(i0 + u * kWave + lane, r1 - 1);  // clamped: every load is issued
+          const int i = min(r0 + u * kWave + lane, r1 - 1);  // clamped: every load is issued
           hv[u] = hq[i];
           iv[u] = cand[qo + i];
         }
+      }
+      for (int i0 = r0; i0 < r1; i0 += kWave * U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {  // the next batch, loaded while this one is placed
+          const int i = min(i0 + kWave * U + u * kWave + lane, r1 - 1);
+          hn[u] = hq[i];
+          in_[u] = cand[qo + i];
+        }
+        int nin = 0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int b = hv[u] - hmin;
           const bool in = i0 + u * kWave + lane < r1 && hv[u] <= hcut;
-          unsigned long long same = __ballot(in);
-          if (same == 0ull) continue;  // wave-uniform
-          for (int bit = 0; bit < nbits; ++bit) {
-            const bool on = (b >> bit) & 1;
-            const unsigned long long bb = __ballot(on);
-            same &= on ? bb : ~bb;
-          }
+          const unsigned long long m = __ballot(in);
           if (in) {
-            const int pos = mine[b] + __popcll(same & below);
-            order[qo + pos] = iv[u];
-            ham_sorted[qo + pos] = hv[u];
+            const int at = nin + __popcll(m & below);
+            sbin[at] = hv[u] - hmin;
+            sid[at] = iv[u];
+          }
+          nin += __popcll(m);
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int j0 = 0; j0 < nin; j0 += kWave) {
+          const bool ok = j0 + lane < nin;
+          const int bb = ok ? sbin[j0 + lane] : 0, id = ok ? sid[j0 + lane] : 0;
+          unsigned long long same = __ballot(ok);
+          for (int bit = 0; bit < nbits; ++bit) {
+            const bool on = (bb >> bit) & 1;
+            const unsigned long long bm = __ballot(on);
+            same &= on ? bm : ~bm;
+          }
+          if (ok) {
+            const int pos = mine[bb] + __popcll(same & below);
+            order[qo + pos] = id;
+            ham_sorted[qo + pos] = bb + hmin;
           }
           __builtin_amdgcn_wave_barrier();
-          if (in && (same & below) == 0) mine[b] += __popcll(same);
+          if (ok && (same & below) == 0) mine[bb] += __popcll(same);
           __builtin_amdgcn_wave_barrier();
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          hv[u] = hn[u];
+          iv[u] = in_[u];
         }
       }
     } else if (wv == 0 && hcut >= 0) {
@@ -1849,7 +1876,7 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
 }
 
 __host__ __device__ inline size_t hamming_order_lds(int d) {
-  const size_t bins = static_cast<size_t>(d) + 1, part = static_cast<size_t>(kOrderWaves + 1) * kOrderSpan;
+  const size_t bins = static_cast<size_t>(d) + 1, part = static_cast<size_t>(kOrderWaves + 2) * kOrderSpan;
   return ((bins > part ? bins : part) + kOrderWaves + 1) * sizeof(int);
 }
 
