@@ -1907,6 +1907,7 @@ __host__ __device__ inline size_t hamming_order_lds(int d) {
 constexpr int kRerankThreads = 256;
 constexpr int kRerankWaves = kRerankThreads / kWave;
 constexpr int kChunk = 256;
+constexpr int kWalkGrain = 16;  // walk chunks are whole multiples of this many rows
 
 template <int B>
 __device__ __forceinline__ double canon_partial(const float4 *__restrict__ qq, const float4 *__restrict__ xr, int nv,
@@ -2573,10 +2574,10 @@ __device__ __forceinline__ void rerank_query(const int q, CRISP_RERANK_PARAMS) {
     __syncthreads();
     for (int c0 = 0, cnt = 0; c0 < lim; c0 += cnt) {
       // The walk cannot stop within the next patience - run candidates, so a
-      // chunk of that many (in whole wavefront widths, at most kChunk) is
+      // chunk of that many (rounded up to kWalkGrain rows, at most kChunk) is
       // always walked in full; fewer rows are read past the stopping point.
       const int need = max(patience - S.misc[3], 1);
-      cnt = min(min(kChunk, (need + kWave - 1) / kWave * kWave), lim - c0);
+      cnt = min(min(kChunk, (need + kWalkGrain - 1) / kWalkGrain * kWalkGrain), lim - c0);
       const int tn0 = S.misc[2];
       const int free_slots = max(0, k - tn0);
       // (a0) the chunk's ids (and row error bounds) staged in LDS by one
