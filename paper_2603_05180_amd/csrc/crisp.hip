@@ -755,10 +755,22 @@ static crisp_status search_impl(crisp_index *ix, const float *queries, int64_t n
       {
         const int gx = static_cast<int>(std::max(1, std::min(64, (4096 + cq - 1) / cq)));
         const int g = xcd_pad(gx * cq);
-        if (hamming_vec(d / 64) == 2)
-          k_hamming_dist<2><<<g, kOrderThreads, 0, st>>>(qrot, d, ix->codes, ncand, cand, cap, regA, lv, qord, gx, cq);
-        else
-          k_hamming_dist<1><<<g, kOrderThreads, 0, st>>>(qrot, d, ix->codes, ncand, cand, cap, regA, lv, qord, gx, cq);
+        const int vec = hamming_vec(d / 64), jl = hamming_loads(d / 64, vec);
+#define CRISP_HAM_ARGS qrot, d, ix->codes, ncand, cand, cap, regA, lv, qord, gx, cq
+        if (vec == 2) {
+          if (jl == 4) k_hamming_dist<2, 4><<<g, kOrderThreads, 0, st>>>(CRISP_HAM_ARGS);
+          else if (jl == 3) k_hamming_dist<2, 3><<<g, kOrderThreads, 0, st>>>(CRISP_HAM_ARGS);
+          else if (jl == 2) k_hamming_dist<2, 2><<<g, kOrderThreads, 0, st>>>(CRISP_HAM_ARGS);
+          else if (jl == 1) k_hamming_dist<2, 1><<<g, kOrderThreads, 0, st>>>(CRISP_HAM_ARGS);
+          else k_hamming_dist<2, 0><<<g, kOrderThreads, 0, st>>>(CRISP_HAM_ARGS);
+        } else {
+          if (jl == 4) k_hamming_dist<1, 4><<<g, kOrderThreads, 0, st>>>(CRISP_HAM_ARGS);
+          else if (jl == 3) k_hamming_dist<1, 3><<<g, kOrderThreads, 0, st>>>(CRISP_HAM_ARGS);
+          else if (jl == 2) k_hamming_dist<1, 2><<<g, kOrderThreads, 0, st>>>(CRISP_HAM_ARGS);
+          else if (jl == 1) k_hamming_dist<1, 1><<<g, kOrderThreads, 0, st>>>(CRISP_HAM_ARGS);
+          else k_hamming_dist<1, 0><<<g, kOrderThreads, 0, st>>>(CRISP_HAM_ARGS);
+        }
+#undef CRISP_HAM_ARGS
         LAUNCH_TRY("k_hamming_dist");
       }
       t4.stop();

@@ -1589,13 +1589,29 @@ __host__ __device__ inline int hamming_vec(int words) { return (words % 2 == 0) 
 
 constexpr int kHamRows = 4, kHamLoads = 4;  // code rows per lane step, loads per row in flight
 
-template <int kVec>
+// Lanes per code row and loads per row per lane for rows of `words` 64-bit
+// words read kVec at a time.
+__host__ __device__ inline int hamming_lanes(int words, int vec) {
+  const int span = words / vec;
+  return span >= 8 ? 8 : span >= 4 ? 4 : span >= 2 ? 2 : 1;
+}
+__host__ __device__ inline int hamming_loads(int words, int vec) {
+  const int span = words / vec, L = hamming_lanes(words, vec);
+  return (span + L - 1) / L;
+}
+
+// kJ > 0: every lane makes exactly kJ (at most kHamLoads) loads per row
+// (D <= 4096), so the lane's query words stay in registers and each row's
+// loads are issued unconditionally (a row past the list is read as a clamped
+// one and not stored; a load past the row's end is read clamped and not
+// counted).  kJ = 0: any row length.
+template <int kVec, int kJ>
 __global__ void __launch_bounds__(kOrderThreads) k_hamming_dist(
     const float *__restrict__ qrot, int d, const uint64_t *__restrict__ codes, const int32_t *__restrict__ ncand,
     const int32_t *__restrict__ cand, long long cap, int32_t *__restrict__ hm_tmp, const int32_t *__restrict__ live,
     const int32_t *__restrict__ order, int gx, int cq) {
   using V = typename CodeVec<kVec>::T;
-  __shared__ uint64_t qc[128];
+  __shared__ __align__(16) uint64_t qc[128];
   const int lb = xcd_major(blockIdx.x, gridDim.x);
   if (lb >= gx * cq) return;
   const int bx = lb % gx, pos = lb / gx;
@@ -1610,11 +1626,51 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_dist(
   }
   __syncthreads();
   const int span = words / kVec;                      // loads that cover a row
-  const int L = span >= 8 ? 8 : span >= 4 ? 4 : span >= 2 ? 2 : 1;
+  const int L = hamming_lanes(words, kVec);
   const int rows_per = kWave / L;
   const int sub = lane % L, rsel = lane / L;
   const int J = (span + L - 1) / L;                   // loads per row per lane
   const int stride = gx * kOrderWaves * kWave;
+  if constexpr (kJ > 0) {
+    V qv[kJ];
+    bool ve[kJ];
+    int vo[kJ];
+#pragma unroll
+    for (int e = 0; e < kJ; ++e) {
+      const int v = sub + e * L;
+      ve[e] = v < span;
+      vo[e] = min(v, span - 1);
+      qv[e] = reinterpret_cast<const V *>(qc)[vo[e]];
+    }
+    for (int base = (bx * kOrderWaves + wv) * kWave; base < nc; base += stride) {
+      const int my_id = cand[qo + min(base + lane, nc - 1)];
+      for (int s0 = 0; s0 < L; s0 += kHamRows) {
+        V cw[kHamRows][kJ];
+#pragma unroll
+        for (int u = 0; u < kHamRows; ++u) {
+          const int r = min(s0 + u, L - 1) * rows_per + rsel;
+          const V *row = reinterpret_cast<const V *>(codes + static_cast<long long>(__shfl(my_id, r, kWave)) * words);
+#pragma unroll
+          for (int e = 0; e < kJ; ++e) cw[u][e] = row[vo[e]];
+        }
+#pragma unroll
+        for (int u = 0; u < kHamRows; ++u) {
+          int h = 0;
+#pragma unroll
+          for (int e = 0; e < kJ; ++e) {
+            int c;
+            if constexpr (kVec == 2) c = __popcll(qv[e].x ^ cw[u][e].x) + __popcll(qv[e].y ^ cw[u][e].y);
+            else c = __popcll(qv[e] ^ cw[u][e]);
+            h += ve[e] ? c : 0;
+          }
+          for (int s2 = L >> 1; s2 >= 1; s2 >>= 1) h += __shfl_xor(h, s2, kWave);
+          const int row_at = base + (s0 + u) * rows_per + rsel;
+          if (sub == 0 && s0 + u < L && row_at < nc) hm_tmp[qo + row_at] = h;
+        }
+      }
+    }
+    return;
+  }
   for (int base = (bx * kOrderWaves + wv) * kWave; base < nc; base += stride) {
     const int my_id = cand[qo + min(base + lane, nc - 1)];
     for (int s0 = 0; s0 < L; s0 += kHamRows) {
