@@ -1478,15 +1478,29 @@ __global__ void __launch_bounds__(kCompactThreads) k_compact(
     base[tid] = (tid < ns) ? sc[s0 + tid] : 0;
     __syncthreads();
     const int tot = block_exclusive_scan(base, kCompactThreads, tmp);
-    // copy the ns segments: each wave takes segments round robin
-    for (int s = wave_id(); s < ns; s += kCompactThreads / kWave) {
-      const int c = (s + 1 < kCompactThreads ? base[s + 1] : tot) - base[s];
-      const long long src = qs + static_cast<long long>(s0 + s) * seg_len;
-      const long long at = static_cast<long long>(carry) + base[s];     // position in the list
-      const int cw = static_cast<int>(max(0ll, min(static_cast<long long>(c), cap - at)));
-      for (int i = lane_id(); i < cw; i += kWave) {
-        cand[qo + at + i] = seg_ids[src + i];
-        score[qo + at + i] = seg_score[src + i];
+    // copy the ns segments: thread t writes list positions carry + j for
+    // j = t, t + 256, ... (segment of j by binary search over the prefix),
+    // kU positions in flight per thread
+    const int lim = static_cast<int>(max(0ll, min(static_cast<long long>(tot), cap - carry)));
+    constexpr int kU = 8;
+    for (int j0 = 0; j0 < lim; j0 += kCompactThreads * kU) {
+      int32_t iv[kU];
+      uint8_t sv[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int j = min(j0 + u * kCompactThreads + tid, lim - 1);   // clamped: every load is issued
+        const int sg = upper_bound_minus1(base, ns, j);                // base[sg] <= j < base[sg + 1]
+        const long long src = qs + static_cast<long long>(s0 + sg) * seg_len + (j - base[sg]);
+        iv[u] = seg_ids[src];
+        sv[u] = seg_score[src];
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int j = j0 + u * kCompactThreads + tid;
+        if (j < lim) {
+          cand[qo + carry + j] = iv[u];
+          score[qo + carry + j] = sv[u];
+        }
       }
     }
     __syncthreads();
