@@ -1575,8 +1575,8 @@ __global__ void __launch_bounds__(kQueryOrderThreads) k_query_order(int cq, cons
 // read by L lanes (L = the largest power of two with kVec * L <= min(16,
 // words)), each reading kVec consecutive 64-bit words per load (kVec = 2,
 // 16-byte loads, when rows have an even number of words); four rows times
-// four loads per lane are in flight per batch, and the partial popcounts are
-// reduced over the row's L lanes.
+// up to four loads per lane are in flight per batch, and the partial
+// popcounts are reduced over the row's L lanes.
 //
 // k_hamming_order (below) places the candidates in (distance, id) order.
 // ---------------------------------------------------------------------------
@@ -1733,10 +1733,12 @@ __global__ void __launch_bounds__(kOrderThreads) k_hamming_dist(
 // bins) and its exclusive scan give every bin's first position; the order
 // statistics the learned budget uses are read from it (the distance at
 // positions 1, 2, 4, ..., 2048 and at the median); then the candidates of
-// the bins that cover the first `plen` positions (whole bins) are placed,
-// stably: one wave walks the candidate list (ascending id) 64 at a time, a
-// lane's rank among the lanes with the same distance from ballots over the
-// distance's bits, each bin's cursor in LDS.  avail[q] = positions placed.
+// the bins that cover the first `plen` positions (whole bins) are placed
+// stably, in id order within a bin: a lane's rank among the lanes with the
+// same distance comes from ballots over the distance's bits, each bin's
+// cursor is in LDS (the four waves take four contiguous id ranges when the
+// placed bins span at most kOrderSpan distances, else one wave places all).
+// avail[q] = positions placed.
 constexpr int kHamStats = 13;  // positions 1, 2, 4, ..., 2048, then the median
 
 __global__ void __launch_bounds__(kOrderThreads) k_hamming_order(
