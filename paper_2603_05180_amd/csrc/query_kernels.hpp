@@ -1527,39 +1527,63 @@ constexpr int kQueryOrderBits = 12;
 static_assert(kQueryOrderMax <= (1 << kQueryOrderBits), "query index must fit its field");
 
 // cap: the stride of a query's candidate list; n: a key above every id.
+// Bitonic network over kQueryOrderMax keys (padded with the largest key),
+// thread t holding keys 4t .. 4t + 3 in registers: exchanges at distance 1
+// and 2 stay in the thread, distances 4 .. 128 are lane shuffles within the
+// wavefront, and only the ten stages at distance >= 256 go through LDS.
 __global__ void __launch_bounds__(kQueryOrderThreads) k_query_order(int cq, const int32_t *__restrict__ ncand,
                                                                     const int32_t *__restrict__ cand, long long n,
                                                                     long long cap, int32_t *__restrict__ order,
                                                                     const int32_t *__restrict__ live) {
+  static_assert(kQueryOrderMax == 4 * kQueryOrderThreads, "four keys per thread");
   __shared__ long long key[kQueryOrderMax];
-  int n2 = 2;
-  while (n2 < cq) n2 <<= 1;
   const int nl = live ? min(cq, *live) : cq;
-  for (int i = threadIdx.x; i < n2; i += kQueryOrderThreads) {
-    long long v = 0x7fffffffffffffffll;
+  const int tid = threadIdx.x;
+  long long v[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int i = 4 * tid + e;
+    long long x = 0x7fffffffffffffffll;
     if (i < cq) {
       const long long first = (i < nl && ncand[i] > 0) ? cand[static_cast<long long>(i) * cap] : n;
-      v = (first << kQueryOrderBits) | i;
+      x = (first << kQueryOrderBits) | i;
     }
-    key[i] = v;
+    v[e] = x;
   }
-  __syncthreads();
-  for (int len = 2; len <= n2; len <<= 1)
+  // key i takes the smaller of (i, i ^ j) when i is the lower index of the
+  // pair in an ascending run (i & len == 0), or the higher one in a
+  // descending run; the larger otherwise
+  for (int len = 2; len <= kQueryOrderMax; len <<= 1) {
     for (int j = len >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n2; i += kQueryOrderThreads) {
-        const int p = i ^ j;
-        if (p > i) {
-          const long long a = key[i], b = key[p];
-          if ((a > b) == ((i & len) == 0)) {
-            key[i] = b;
-            key[p] = a;
-          }
-        }
+      long long w[4];
+      if (j >= 256) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) key[4 * tid + e] = v[e];
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w[e] = key[(4 * tid + e) ^ j];
+        __syncthreads();
+      } else if (j >= 4) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w[e] = __shfl_xor(v[e], j >> 2, kWave);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w[e] = v[e ^ j];
       }
-      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = 4 * tid + e;
+        const bool lower = (i & j) == 0, up = (i & len) == 0;
+        const bool take_min = lower == up;
+        v[e] = take_min ? min(v[e], w[e]) : max(v[e], w[e]);
+      }
     }
-  for (int i = threadIdx.x; i < cq; i += kQueryOrderThreads)
-    order[i] = static_cast<int32_t>(key[i] & ((1ll << kQueryOrderBits) - 1));
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int i = 4 * tid + e;
+    if (i < cq) order[i] = static_cast<int32_t>(v[e] & ((1ll << kQueryOrderBits) - 1));
+  }
 }
 
 // ---------------------------------------------------------------------------
