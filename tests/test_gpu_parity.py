@@ -83,6 +83,20 @@ def test_codebook_sizes(k_half):
         compare(idx, q, 10, mode=mode, alpha=0.03, tau=2)
 
 
+def test_tied_half_distances():
+    """Centroids 0 and 1 of every half made equal (and 2 equal to 3 in half
+    1): every query has tied half distances, which the (distance, index)
+    order breaks by index; the selection must rank them as the oracle does."""
+    w, x, q = make_workload("d128", n=4000, d=128, m=4, k_half=8, n_query=10)
+    idx = oracle_index(w, x)
+    cent = idx["centroids"].copy()
+    cent[:, :, 1] = cent[:, :, 0]
+    cent[:, 1, 3] = cent[:, 1, 2]
+    idx = dict(idx, centroids=cent)
+    for mode in (0, 1):
+        compare(idx, q, 10, mode=mode, alpha=0.03, tau=2)
+
+
 def test_cell_selection_beyond_direct_pops():
     """K = 32 (1,024 cells of about three ids) with half the points as the
     budget: several hundred cells per subspace, more than the direct
