@@ -99,10 +99,21 @@ __global__ void k_update(const float *__restrict__ x, int d, int col0, int h, co
   int c = t / h, i = t % h;
   int a = moff[c], b = moff[c + 1];
   if (b <= a) return;
+  // The members' values are loaded 16 at a time (their loads do not depend
+  // on the sum) and added in ascending member order, one at a time.
+  constexpr int U = 16;
   double acc = 0.0;
-  for (int p = a; p < b; ++p) {
-    long long r = rows ? rows[members[p]] : members[p];
-    acc = acc + static_cast<double>(x[r * d + col0 + i]);
+  for (int p0 = a; p0 < b; p0 += U) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = min(p0 + u, b - 1);  // clamped: every load is issued
+      const long long r = rows ? rows[members[p]] : members[p];
+      v[u] = x[r * d + col0 + i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (p0 + u < b) acc = acc + static_cast<double>(v[u]);
   }
   cent[t] = static_cast<float>(acc / static_cast<double>(b - a));
 }
