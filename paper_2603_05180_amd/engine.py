@@ -365,6 +365,9 @@ def sample_cev(x: torch.Tensor, rows: np.ndarray, stream=None) -> float:
     return float(lam[:top].sum() / lam.sum())
 
 
+BUILD_STREAMS = 8  # side streams for the half-codebook k-means of the index build
+
+
 def _csr(cell_of: torch.Tensor, cells: int, stream=None):
     n = cell_of.numel()
     off = torch.empty(cells + 1, dtype=torch.int32, device=cell_of.device)
@@ -434,16 +437,29 @@ def build_index(x: torch.Tensor, m: int, k_half: int, *, g, cev_rows: np.ndarray
     cent = torch.empty(m, 2, k_half, h, dtype=torch.float32, device=dev)
     offsets = torch.empty(m, k_half * k_half + 1, dtype=torch.int32, device=dev)
     ids = torch.empty(m, n, dtype=torch.int32, device=dev)
-    lab = [torch.empty(n, dtype=torch.int32, device=dev) for _ in range(2)]
+    lab = torch.empty(m, 2, n, dtype=torch.int32, device=dev)
     cell = torch.empty(n, dtype=torch.int32, device=dev)
-    for sub in range(m):
-        for s in range(2):
+    # The 2M half codebooks are independent and each one's launches are
+    # small, so they run on BUILD_STREAMS side streams (default priority),
+    # joined before the cells are formed; every kernel and input is the
+    # same as on one stream.
+    main = stream if stream is not None else torch.cuda.current_stream(dev)
+    side = [torch.cuda.Stream(device=dev) for _ in range(min(BUILD_STREAMS, 2 * m))]
+    for st in side:
+        st.wait_stream(main)
+    for j in range(2 * m):
+        sub, s = divmod(j, 2)
+        st = side[j % len(side)]
+        with torch.cuda.stream(st):
             col0 = sub * 2 * h + s * h
-            c = _kmeans_half(base, col0, h, rows_t, km_init, k_half, iters, stream)
+            c = _kmeans_half(base, col0, h, rows_t, km_init, k_half, iters, st)
             cent[sub, s].copy_(c)
             check(lib.crisp_build_assign(_ptr(base), n, d, col0, h, None, n, _ptr(cent[sub, s]), k_half,
-                                         _ptr(lab[s]), _stream(stream)))
-        check(lib.crisp_build_combine(_ptr(lab[0]), _ptr(lab[1]), n, k_half, _ptr(cell), _stream(stream)))
+                                         _ptr(lab[sub, s]), _stream(st)))
+    for st in side:
+        main.wait_stream(st)
+    for sub in range(m):
+        check(lib.crisp_build_combine(_ptr(lab[sub, 0]), _ptr(lab[sub, 1]), n, k_half, _ptr(cell), _stream(stream)))
         off_s, ids_s = _csr(cell, k_half * k_half, stream)
         offsets[sub].copy_(off_s)
         ids[sub].copy_(ids_s)
