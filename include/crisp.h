@@ -389,7 +389,11 @@ crisp_status crisp_plan_free(crisp_plan *plan);
  * Row rotation x' = x R with the float64 ascending-order definition above
  * (Section 3; used for queries, and for the data set when building).
  *   x -- device float32 [rows][d]; r -- device float32 [d][d]; out -- device
- *   float32 [rows][d] (must not alias x).
+ *   float32 [rows][d] (must not alias x).  Any 4-byte alignment is accepted;
+ *   x and r 16-byte aligned with at least one 128 x 128 output tile per
+ *   compute unit take the faster kernel (same results).
+ * Errors: CRISP_E_INVALID for a null pointer; CRISP_E_UNSUPPORTED when d is
+ * not a positive multiple of 64 or rows exceed 128 x 65,535 in one call.
  */
 crisp_status crisp_rotate_rows(const float *x, int64_t rows, int32_t d, const float *r,
                                float *out, void *hip_stream);
