@@ -38,7 +38,9 @@ float64, so fused and unfused evaluation agree) and rounded once to float32:
 
 with c the row's component label, z/eta/eps standard normals rounded to
 float32, mu = 2 N(0, I) (so means ~ N(0, 4I)), A ~ N(0, 1) unscaled,
-B = N(0, 1) / 8 (1/sqrt(64)), nu = 2 N(0, I).
+B = N(0, 1) / 8 (1/sqrt(64)), nu = s N(0, I) with s the workload's
+``center_scale`` (2 unless stated; a power of two keeps the float32 draw
+exact on both generators).
 """
 from __future__ import annotations
 
@@ -134,6 +136,7 @@ class Workload:
     k_half: int            # centroids per half-codebook K
     n_query: int
     k: int                 # neighbours per query
+    center_scale: float = 2.0  # global kind: component centres nu = center_scale * N(0, I)
 
     @property
     def sigma32(self) -> np.float32:
@@ -159,6 +162,10 @@ WORKLOADS = {
     # Uneven batching workload, D=3072.
     "d3072": Workload("d3072", 2_000_000, 3072, 200, 64, 0.05, "global",
                      1005, 2005, 4005, 32, 50, 50_000, 10),
+    # Overlapping components (centres at scale 0.5 against unit spread in the
+    # 64-dim latent space), D=1024: the candidate set depends on alpha and tau.
+    "d1024mix": Workload("d1024mix", 1_000_000, 1024, 100, 64, 0.05, "global",
+                         1006, 2006, 4006, 16, 50, 10_000, 10, center_scale=0.5),
 }
 
 
@@ -171,7 +178,7 @@ def mixture_params(w: Workload) -> dict:
         return {"mu": mu.reshape(w.n_comp, w.d), "a": a.reshape(w.n_comp, w.d, w.rank)}
     if w.kind == "global":
         b = (normals(s, TAG["factor"], np.arange(w.d * w.rank)) / 8.0).astype(np.float32)
-        nu = (2.0 * normals(s, TAG["center"], np.arange(w.n_comp * w.rank))).astype(np.float32)
+        nu = (w.center_scale * normals(s, TAG["center"], np.arange(w.n_comp * w.rank))).astype(np.float32)
         return {"b": b.reshape(w.d, w.rank), "nu": nu.reshape(w.n_comp, w.rank)}
     raise ValueError(w.kind)
 

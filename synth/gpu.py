@@ -55,7 +55,8 @@ def mixture_params(w: Workload, device="cuda") -> dict:
                 "a": normals_f32(s, TAG["factor"], w.n_comp * w.d * w.rank, 1.0, device)
                 .reshape(w.n_comp, w.d, w.rank)}
     return {"b": normals_f32(s, TAG["factor"], w.d * w.rank, 0.125, device).reshape(w.d, w.rank),
-            "nu": normals_f32(s, TAG["center"], w.n_comp * w.rank, 2.0, device).reshape(w.n_comp, w.rank)}
+            "nu": normals_f32(s, TAG["center"], w.n_comp * w.rank, float(w.center_scale), device)
+            .reshape(w.n_comp, w.rank)}
 
 
 def rows(w: Workload, seed: int, start: int, stop: int, params: dict, out: torch.Tensor | None = None):

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 def test_synth_gpu_twin_matches_numpy():
     import synth.gpu as sg
     for name, kw in (("d128", dict(n=3000)), ("d4096", dict(n=500, d=512, rank=64)),
-                     ("d960", dict(n=200, d=192, rank=32))):
+                     ("d960", dict(n=200, d=192, rank=32)), ("d1024mix", dict(n=500, d=256, rank=64))):
         w = synth.WORKLOADS[name].scaled(**kw)
         p = synth.mixture_params(w)
         pg = sg.mixture_params(w)
