@@ -50,3 +50,22 @@ def test_sample_indices_distinct_sorted():
 def test_batch_sizes_cover_total():
     b = synth.batch_sizes(5005, 20_000)
     assert sum(b) == 20_000 and min(b) >= 1 and max(b) <= 4096
+
+
+def test_center_scale_scales_the_centres_exactly():
+    """The component centres of a global mixture are center_scale x the same
+    normals: power-of-two scales give exact multiples, and the default (2)
+    reproduces the draw every other workload was generated with."""
+    import numpy as np
+    import synth
+    w = synth.WORKLOADS["d1024mix"].scaled(n=100, d=128, n_query=4)
+    p_half = synth.mixture_params(w)
+    p_two = synth.mixture_params(w.scaled(center_scale=2.0))
+    assert w.center_scale == 0.5
+    assert np.array_equal(p_half["nu"] * np.float32(4.0), p_two["nu"])
+    assert np.array_equal(p_half["b"], p_two["b"])
+    d4096 = synth.WORKLOADS["d4096"].scaled(n=100, d=128)
+    assert d4096.center_scale == 2.0
+    ref = (2.0 * synth.normals(d4096.seed_data, synth.TAG["center"],
+                               np.arange(d4096.n_comp * d4096.rank))).astype(np.float32)
+    assert np.array_equal(synth.mixture_params(d4096)["nu"].reshape(-1), ref)
